@@ -1,0 +1,304 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+Each test names the relation it checks.  None of them re-types the oracle's
+own formula: they use dense LU, scipy's GMRES, closed-form eigenvalues,
+brute-force least squares and exact invariants of the method.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as O
+import problems as P
+
+
+def _small(N=12, conv=(6.0, 3.0, 0.0), p=3, seed=0, cplx=False):
+    A = P.convdiff(N, 2, conv=conv)
+    if cplx:
+        A = (A.astype(np.complex128) + sp.identity(A.shape[0]) * (-30.0 + 15.0j)).tocsr()
+    rng = np.random.default_rng(seed)
+    B = rng.uniform(-1, 1, (A.shape[0], p))
+    if cplx:
+        B = B + 1j * rng.uniform(-1, 1, B.shape)
+    return A, B
+
+
+# ---- P1: dense LU (the plain definition X* = A^{-1} B) ---------------------
+
+def test_cfg1_sequence_matches_dense_lu():
+    w = P.cfg1()
+    U = None
+    for s in w.systems:
+        X, U, st = O.solve(s.A, s.B, s.X0, w.tol, w.m, w.k, U=U)
+        Ad = s.A.toarray()
+        Xs = np.linalg.solve(Ad, s.B)
+        kappa = np.linalg.cond(Ad)
+        assert st["rel_res"] <= w.tol
+        rel_err = np.linalg.norm(X - Xs) / np.linalg.norm(Xs)
+        # forward error bound: ||dx||/||x|| <= kappa ||r||/||b||
+        assert rel_err <= kappa * st["rel_res"] * 1.01
+        assert rel_err < 1e-6
+
+
+def test_complex_matches_dense_lu():
+    A, B = _small(N=10, cplx=True, p=2)
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-10, 6, 4)
+    Xs = np.linalg.solve(A.toarray(), B)
+    assert np.linalg.norm(X - Xs) / np.linalg.norm(Xs) < 1e-7
+    X2, U2, st2 = O.solve(A, B * 0.5, np.zeros_like(B), 1e-10, 6, 4, U=U)
+    assert np.linalg.norm(X2 - 0.5 * Xs) / np.linalg.norm(0.5 * Xs) < 1e-7
+
+
+# ---- P2/P3/P4: block modified Arnoldi relation, orthonormality, A U = C ----
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_modified_arnoldi_relation_and_orthonormality(cplx):
+    A, B = _small(cplx=cplx)
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-10, 5, 4, max_cycles=4, trace=True)
+    assert len(st["trace"]) >= 3
+    Ad = A.toarray()
+    for tr in st["trace"][1:]:
+        cyc, C = tr["cyc"], tr["C_in"]
+        V = cyc["V"]
+        me = cyc["m_eff"]
+        Wm1 = np.hstack(V)
+        Wm = Wm1[:, : me * B.shape[1]]
+        lhs = Ad @ Wm
+        rhs = C @ cyc["F"] + Wm1 @ cyc["H"]
+        # eq. block-modified-arnoldi: A W_m = C F_m + W_{m+1} H_m
+        assert np.linalg.norm(lhs - rhs) <= 1e-12 * np.linalg.norm(lhs)
+        I = np.eye(Wm1.shape[1])
+        assert np.linalg.norm(Wm1.conj().T @ Wm1 - I) < 1e-13
+        assert np.linalg.norm(C.conj().T @ C - np.eye(C.shape[1])) < 1e-13
+        assert np.linalg.norm(C.conj().T @ Wm1) < 1e-13
+        # subdiagonal blocks are upper triangular (Section 3.1)
+        p = B.shape[1]
+        H = cyc["H"]
+        for j in range(me):
+            blk = H[(j + 1) * p:(j + 2) * p, j * p:(j + 1) * p]
+            assert np.allclose(np.tril(blk, -1), 0)
+            # and every block below the subdiagonal is zero
+            assert np.allclose(H[(j + 2) * p:, j * p:(j + 1) * p], 0)
+    for tr in st["trace"]:
+        U_, C_ = tr["U"], tr["C"]
+        # A U = C with orthonormal C (Algorithm 1: C <- A U orthonormal)
+        assert np.linalg.norm(Ad @ U_ - C_) <= 1e-11 * np.linalg.norm(C_)
+        assert np.linalg.norm(C_.conj().T @ C_ - np.eye(C_.shape[1])) < 1e-12
+
+
+def test_recycle_import_gives_AU_equals_C():
+    A, B = _small()
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-9, 5, 4)
+    A2 = (A + sp.diags(np.linspace(0, 1, A.shape[0]))).tocsr()
+    U2, C2, X0, R0 = O.recycle_import(A2, U, np.zeros_like(B), B.copy())
+    assert np.linalg.norm(A2 @ U2 - C2) < 1e-11 * np.linalg.norm(C2)
+    assert np.linalg.norm(C2.T @ C2 - np.eye(C2.shape[1])) < 1e-13
+    # R0 <- (I - Phi) R0 is orthogonal to C and equals B - A X0
+    assert np.linalg.norm(C2.T @ R0) < 1e-12 * np.linalg.norm(B)
+    assert np.linalg.norm(R0 - (B - A2 @ X0)) < 1e-12 * np.linalg.norm(B)
+
+
+# ---- P5: residual equivalence (Proposition residual-equiv) ----------------
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_recurrence_residual_equals_true_residual(cplx):
+    A, B = _small(cplx=cplx, p=4)
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-10, 4, 5, max_cycles=8)
+    assert max(st["recur_drift"]) < 1e-12
+
+
+# ---- P6: monotone LSQ residual within a cycle (nested spaces) -------------
+
+def test_rho_monotone_within_cycle():
+    w = P.cfg1()
+    s = w.systems[0]
+    X, U, st = O.solve(s.A, s.B, s.X0, w.tol, w.m, w.k)
+    for rh in st["rho"]:
+        assert all(b <= a * (1 + 1e-12) for a, b in zip(rh, rh[1:]))
+
+
+# ---- P7: minimal residual over U + K_m by brute force ----------------------
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_cycle_is_minimal_residual_over_augmented_space(cplx):
+    A, B = _small(N=9, p=2, cplx=cplx)
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-12, 4, 3, max_cycles=4, trace=True)
+    Ad = A.toarray()
+    for i in range(1, len(st["trace"])):
+        prev, tr = st["trace"][i - 1], st["trace"][i]
+        R_prev = prev["R"]
+        U_in = tr["U_in"]
+        cyc = tr["cyc"]
+        Wm = np.hstack(cyc["V"][: cyc["m_eff"]])
+        basis = np.hstack([U_in, Wm])
+        AB = Ad @ basis
+        # columnwise min over span(basis) -- the block residual minimisation decouples
+        Zb, *_ = np.linalg.lstsq(AB, R_prev, rcond=None)
+        best = R_prev - AB @ Zb
+        assert np.linalg.norm(tr["R"]) == pytest.approx(np.linalg.norm(best), rel=1e-8)
+        assert np.linalg.norm(tr["R"] - best) < 1e-9 * np.linalg.norm(R_prev)
+
+
+# ---- P8: k = 0, p = 1 reduces to restarted GMRES(m) (scipy) ----------------
+
+@pytest.mark.parametrize("cycles", [1, 2, 4])
+def test_k0_p1_is_gmres_m(cycles):
+    A = P.convdiff(10, 2, conv=(5.0, 3.0, 0.0))
+    n = A.shape[0]
+    b = np.random.default_rng(1).uniform(-1, 1, (n, 1))
+    x, _ = spla.gmres(A, b[:, 0], x0=np.zeros(n), rtol=1e-300, atol=0.0, restart=7, maxiter=cycles)
+    X, U, st = O.solve(A, b, np.zeros((n, 1)), 1e-300, 7, 0, max_cycles=cycles)
+    assert st["cycles"] == cycles
+    assert np.linalg.norm(X[:, 0] - x) <= 1e-12 * np.linalg.norm(x)
+
+
+def test_k0_block_is_block_gmres_over_block_krylov_space():
+    """k=0, one cycle: the correction is the column-wise minimal residual over
+    blspan{R0, A R0, ..., A^{m-1} R0} (eq. block-Krylov-sum-space), built here
+    from explicit powers."""
+    A, B = _small(N=8, p=3)
+    m = 3
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-300, m, 0, max_cycles=1)
+    Ad = A.toarray()
+    K = [B]
+    for _ in range(m - 1):
+        K.append(Ad @ K[-1])
+    K = np.hstack(K)
+    Qk, _ = np.linalg.qr(K)
+    Zb, *_ = np.linalg.lstsq(Ad @ Qk, B, rcond=None)
+    Xb = Qk @ Zb
+    assert np.linalg.norm(X - Xb) < 1e-9 * np.linalg.norm(Xb)
+
+
+# ---- P10: harmonic Ritz ----------------------------------------------------
+
+def _toeplitz_tridiag(n, a, b, c):
+    return sp.diags([b * np.ones(n - 1), a * np.ones(n), c * np.ones(n - 1)], [-1, 0, 1]).tocsr()
+
+
+def test_harmonic_ritz_exact_when_krylov_space_is_whole_space():
+    """n = m p: the block Krylov space is C^n, harmonic Ritz values are the
+    eigenvalues of A (closed form for a tridiagonal Toeplitz matrix) and one
+    cycle solves exactly."""
+    n, p, m = 12, 3, 4
+    a, b, c = 4.0, 1.5, 0.6           # eigenvalues a + 2 sqrt(bc) cos(j pi/(n+1))
+    A = _toeplitz_tridiag(n, a, b, c)
+    B = np.random.default_rng(3).uniform(-1, 1, (n, p))
+    cyc = O.block_arnoldi_cycle(A, B, None, m, 0.0)
+    theta, T = O.harmonic_ritz_first(cyc["H"], p)
+    exact = a + 2 * np.sqrt(b * c) * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    assert np.allclose(np.sort(theta.real), np.sort(exact), atol=1e-9)
+    assert np.max(np.abs(theta.imag)) < 1e-9
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-300, m, 2, max_cycles=1)
+    Xs = np.linalg.solve(A.toarray(), B)
+    assert np.linalg.norm(X - Xs) < 1e-10 * np.linalg.norm(Xs)
+
+
+def test_harmonic_ritz_standard_equals_generalized_at_k0():
+    """Proposition block-harm-ritz vs eq. harm-ritz-gen-eig with no recycled space."""
+    A, B = _small(N=10, p=3)
+    cyc = O.block_arnoldi_cycle(A, B, None, 5, 0.0)
+    th1, _ = O.harmonic_ritz_first(cyc["H"], 3)
+    W = np.hstack(cyc["V"])
+    th2, _ = O.harmonic_ritz_augmented(cyc["H"], W, W[:, : cyc["H"].shape[1]])
+    th2 = th2[np.isfinite(th2)]
+    k1 = np.sort_complex(np.round(th1, 6))
+    k2 = np.sort_complex(np.round(th2, 6))
+    assert len(k1) == len(k2)
+    assert np.allclose(k1, k2, rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_harmonic_ritz_petrov_galerkin_bruteforce(cplx):
+    """(A y - theta y) orthogonal to A * span(W^_m) (harmonic Ritz condition,
+    Section 4.1), checked with explicit products for the augmented problem."""
+    A, B = _small(N=9, p=2, cplx=cplx)
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-12, 4, 3, max_cycles=3, trace=True)
+    tr = st["trace"][1]
+    Uin, Cin, cyc = tr["U_in"], tr["C_in"], tr["cyc"]
+    Ad = A.toarray()
+    d = 1.0 / np.linalg.norm(Uin, axis=0)
+    Ut = Uin * d
+    kk = Uin.shape[1]
+    H, F = cyc["H"], cyc["F"]
+    G = np.zeros((kk + H.shape[0], kk + H.shape[1]), dtype=H.dtype)
+    G[:kk, :kk] = np.diag(d)
+    G[:kk, kk:] = F
+    G[kk:, kk:] = H
+    Wh = np.hstack([Ut] + cyc["V"][:-1])
+    Wt = np.hstack([Cin] + cyc["V"])
+    # the compact relation A W^ = W~ G (eq. mod-arn-rel)
+    assert np.linalg.norm(Ad @ Wh - Wt @ G) < 1e-11 * np.linalg.norm(Ad @ Wh)
+    theta, T = O.harmonic_ritz_augmented(G, Wt, Wh)
+    AW = Ad @ Wh
+    ok = np.isfinite(theta)
+    for th, t in zip(theta[ok], T[:, ok].T):
+        y = Wh @ t
+        r = Ad @ y - th * y
+        assert np.linalg.norm(AW.conj().T @ r) <= 1e-8 * np.linalg.norm(AW) * np.linalg.norm(y) * max(1, abs(th))
+
+
+def test_select_ritz_keeps_conjugate_pairs_whole():
+    theta = np.array([1.0 + 0j, 2 + 1j, 2 - 1j, 5.0 + 0j, 0.5 + 0j])
+    T = np.eye(5, dtype=complex)
+    T[:, 1] = [0, 1, 1j, 0, 0]
+    T[:, 2] = [0, 1, -1j, 0, 0]
+    Pm, vals = O.select_ritz(theta, T, 2)
+    assert Pm.shape[1] == 2 and set(np.round(vals.real, 6)) == {0.5, 1.0}
+    Pm, vals = O.select_ritz(theta, T, 3)
+    # the third smallest |theta| is a member of a pair: both are kept, k_eff = 4
+    assert Pm.shape[1] == 4
+    assert np.isrealobj(Pm)
+    Pl, vl = O.select_ritz(theta, T, 1, largest=True)
+    assert vl[0] == 5.0
+    # infinite values are never kept
+    Pm, vals = O.select_ritz(np.array([np.inf, 3.0, 1.0]), np.eye(3), 2)
+    assert set(vals.real) == {1.0, 3.0}
+
+
+# ---- P11: Vital containment (Section 5) ------------------------------------
+
+def test_block_cycle_beats_single_vector_gmres_per_column():
+    A, B = _small(N=14, p=4, seed=5)
+    m = 5
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-300, m, 0, max_cycles=1)
+    Rb = B - A @ X
+    for i in range(B.shape[1]):
+        x, _ = spla.gmres(A, B[:, i], x0=np.zeros(A.shape[0]), rtol=1e-300, atol=0.0, restart=m, maxiter=1)
+        rs = np.linalg.norm(B[:, i] - A @ x)
+        assert np.linalg.norm(Rb[:, i]) <= rs * (1 + 1e-10)
+
+
+# ---- P12: equivariance -----------------------------------------------------
+
+def test_column_permutation_and_scaling_equivariance():
+    A, B = _small(N=10, p=4, seed=7)
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-10, 5, 4, max_cycles=3)
+    perm = [2, 0, 3, 1]
+    Xp, _, stp = O.solve(A, B[:, perm], np.zeros_like(B), 1e-10, 5, 4, max_cycles=3)
+    assert stp["block_steps"] == st["block_steps"]
+    assert np.linalg.norm(Xp - X[:, perm]) < 1e-8 * np.linalg.norm(X)
+    Xs, _, sts = O.solve(A, 3.0 * B, np.zeros_like(B), 1e-10, 5, 4, max_cycles=3)
+    assert np.linalg.norm(Xs - 3.0 * X) < 1e-8 * np.linalg.norm(3.0 * X)
+
+
+# ---- P13: degenerate inputs --------------------------------------------------
+
+def test_zero_rhs_and_exact_initial_guess():
+    A, B = _small(N=8, p=2)
+    X, U, st = O.solve(A, np.zeros_like(B), np.ones_like(B), 1e-8, 4, 3)
+    assert np.all(X == 0) and st["cycles"] == 0
+    Xs = np.linalg.solve(A.toarray(), B)
+    X, U, st = O.solve(A, B, Xs, 1e-8, 4, 3)
+    assert st["cycles"] == 0 and np.array_equal(X, Xs)
+
+
+def test_duplicate_rhs_columns_still_converge():
+    """A rank-deficient block R_0: the Householder QR gives an orthonormal V_1
+    whose extra column is an arbitrary direction; the solve still converges."""
+    A, B = _small(N=10, p=3)
+    B[:, 2] = B[:, 0]
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-9, 5, 4)
+    assert st["rel_res"] <= 1e-9
+    assert np.linalg.norm(X[:, 2] - X[:, 0]) < 1e-6 * np.linalg.norm(X[:, 0])
