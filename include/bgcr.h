@@ -1,0 +1,152 @@
+/*
+ * bgcr.h -- C ABI of the MI355X block GCRO-DR library (libbgcr.so).
+ *
+ * Block GCRO-DR (block recycled GMRES, Parks, Soodhalter and Szyld, Algorithm 1)
+ * solves a sequence of non-Hermitian sparse systems A^[i] X = B^[i] with p
+ * right-hand sides (Section 1, eq. (1.1)), keeping a recycled pair (U, C) with
+ * A U = C and orthonormal C on the device between calls (Algorithm 1, last line).
+ *
+ * Conventions for every entry point:
+ *   - Array arguments are DEVICE pointers (memory on the GPU the library runs
+ *     on) unless the comment says "host".  Sizes are in elements.
+ *   - Dense blocks are row-major n x p with a leading dimension ld >= p
+ *     (element (i, j) at ptr[i*ld + j]).  Complex data (BGCR_C128) is
+ *     interleaved (re, im) doubles.
+ *   - Sparse matrices are 0-based CSR with int32 row_ptr[n+1] and col_idx[nnz];
+ *     values are double (BGCR_F64) or interleaved complex double (BGCR_C128).
+ *   - The caller owns every array it passes in; the library never frees them
+ *     and keeps no pointer to them after the call returns.
+ *   - Every function returns a status code (BGCR_OK = 0, see bgcr_status);
+ *     no C++ exception crosses this boundary.
+ *   - Work is enqueued on the HIP stream given at creation (NULL = the legacy
+ *     default stream).  Calls on different sequences may run concurrently from
+ *     different host threads; one sequence is not re-entrant.
+ */
+#ifndef BGCR_H
+#define BGCR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BGCR_OK = 0,
+    BGCR_NOT_CONVERGED = 1,        /* max_cycles reached; X holds the last iterate */
+    BGCR_ERR_INVALID = -1,         /* NULL/ill-sized argument, n or p mismatch, tol <= 0 */
+    BGCR_ERR_NOMEM = -2,           /* device allocation failed */
+    BGCR_ERR_HIP = -3,             /* HIP runtime error, including no visible device */
+    BGCR_ERR_NONFINITE = -4,       /* NaN/Inf in B or X0, or produced during the solve */
+    BGCR_ERR_NUMERICAL = -5        /* rank-deficient Krylov block (Cholesky breakdown)
+                                      or eigensolver failure */
+} bgcr_status;
+
+typedef enum { BGCR_F64 = 0, BGCR_C128 = 1 } bgcr_dtype;
+
+typedef enum {
+    BGCR_PLAIN_FP64 = 0,           /* every step in FP64 (complex128 for BGCR_C128) */
+    BGCR_MIXED_FP32 = 1            /* FP32 SpMM/basis/BCGS2 cycles inside an FP64
+                                      iterative-refinement loop (real data only) */
+} bgcr_precision;
+
+typedef struct bgcr_sequence bgcr_sequence;   /* opaque; owns U, C and workspaces */
+
+typedef struct {
+    int32_t p;               /* number of right-hand sides = block size: 1, 2, 4, 8 or 16 */
+    int32_t m;               /* block Arnoldi steps per cycle (1..64) */
+    int32_t k;               /* recycled dimension (0..128); with real data k+1 columns
+                                are kept when a conjugate pair straddles the cut */
+    int32_t dtype;           /* bgcr_dtype */
+    int32_t precision;       /* bgcr_precision */
+    int32_t max_cycles;      /* restart cycles per solve before BGCR_NOT_CONVERGED (>= 1) */
+    int32_t select_largest;  /* 0: keep harmonic Ritz values of smallest modulus
+                                (Section 4.1 default); 1: largest */
+    int32_t reserved;        /* must be 0 */
+} bgcr_params;
+
+typedef struct {
+    int64_t n;               /* rows = columns */
+    int64_t nnz;
+    const int32_t* row_ptr;  /* device, n+1 entries */
+    const int32_t* col_idx;  /* device, nnz entries */
+    const void* values;      /* device, nnz entries (double or interleaved complex double) */
+} bgcr_csr;
+
+typedef struct {
+    int32_t status;          /* same as the return code of bgcr_solve */
+    int32_t cycles;          /* restart cycles, including the first-system block GMRES cycle */
+    int32_t block_steps;     /* block Arnoldi steps over all cycles */
+    int32_t spmm_calls;      /* block SpMMs (n x p) with A, any precision */
+    double rel_res;          /* ||B - A X||_F / ||B||_F at return (FP64) */
+    double rel_res_max_col;  /* max_j ||b_j - A x_j|| / ||b_j|| at return */
+    double seconds;          /* host wall time of the call */
+    double alg_bytes;        /* algorithmic HBM bytes of the block Arnoldi sweeps executed */
+    int32_t k_eff;           /* columns of the recycled space stored at return */
+    int32_t refine_steps;    /* FP64 refinement steps (BGCR_MIXED_FP32), else 0 */
+} bgcr_stats;
+
+/* Create a sequence for systems of order n (Algorithm 1 parameters m, k and
+ * block size p in prm).  Allocates the recycled pair, the block Arnoldi basis
+ * and every workspace on the current HIP device (size: bgcr_footprint_bytes).
+ * hip_stream: a hipStream_t all work of this sequence is enqueued on.
+ * out: host pointer receiving the handle.  Errors: INVALID, NOMEM, HIP. */
+int bgcr_create_sequence(const bgcr_params* prm, int64_t n, void* hip_stream,
+                         bgcr_sequence** out);
+
+/* Solve A X = B for the next system of the sequence (Algorithm 1).
+ * A: CSR of order n (device arrays; may differ at every call, Section 1).
+ * B: n x p right-hand sides with leading dimension ldb (read only).
+ * X: n x p, on entry the initial guess X0, on return the solution (ldx).
+ * tol: relative tolerance, stop when ||B - A X||_F <= tol ||B||_F.
+ * st: host pointer or NULL; receives the statistics of this call.
+ * The first call takes the no-U branch of Algorithm 1 (one block GMRES cycle,
+ * then harmonic Ritz selection); later calls import the stored U (A U = C S).
+ * Blocks the calling thread until the result is in X.
+ * Returns OK, NOT_CONVERGED (X holds the last iterate), INVALID, HIP,
+ * NONFINITE or NUMERICAL. */
+int bgcr_solve(bgcr_sequence* s, const bgcr_csr* A, const void* B, int64_t ldb,
+               void* X, int64_t ldx, double tol, bgcr_stats* st);
+
+/* Free U, C and every workspace of the sequence.  NULL is a no-op. */
+int bgcr_release(bgcr_sequence* s);
+
+/* Device bytes a sequence with these parameters allocates for order n and a
+ * matrix with nnz nonzeros (used for admission by HBM budget).  0 if prm is
+ * invalid. */
+size_t bgcr_footprint_bytes(const bgcr_params* prm, int64_t n, int64_t nnz);
+
+/* Number of recycled columns currently stored (0 before the first solve). */
+int bgcr_recycle_dim(const bgcr_sequence* s, int32_t* k_eff);
+
+/* Copy the stored recycled pair out (Algorithm 1: U is kept for the next
+ * call).  U_out and C_out: device, n x k_eff row-major with leading dimension
+ * ld >= k_eff, in the sequence's basis precision widened to FP64 (complex128
+ * for BGCR_C128).  Either pointer may be NULL. */
+int bgcr_get_recycle(const bgcr_sequence* s, void* U_out, void* C_out, int64_t ld);
+
+/* Replace the stored recycled space by the k_in columns of U_in (device,
+ * n x k_in, leading dimension ld, FP64 or complex128): the optional U input of
+ * Algorithm 1.  C is formed at the next solve by A U = C S.  k_in <= k+1. */
+int bgcr_set_recycle(bgcr_sequence* s, const void* U_in, int64_t ld, int32_t k_in);
+
+/* Per-cycle log of the last solve (host arrays of capacity cap): block steps
+ * of each cycle and the true relative residual ||B - A X||_F/||B||_F after it.
+ * *count receives the number of cycles (may exceed cap; only cap are written). */
+int bgcr_get_cycle_log(const bgcr_sequence* s, int32_t* steps, double* rel_res,
+                       int32_t cap, int32_t* count);
+
+/* Standalone block SpMM W = A V (the dominant kernel of the cycle, Section 6.3):
+ * V, W: device, n x p row-major, leading dimension p.  dtype BGCR_F64 or
+ * BGCR_C128, p in {1, 2, 4, 8, 16}.  hip_stream may be NULL. */
+int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* W,
+              void* hip_stream);
+
+/* Human-readable text of a status code (static storage). */
+const char* bgcr_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,127 @@
+// Internal declarations shared by the HIP kernels and the host driver of
+// libbgcr.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <complex>
+
+namespace bgcr {
+
+// Interleaved complex double, layout-compatible with std::complex<double>.
+struct zd {
+    double x, y;
+};
+
+__host__ __device__ inline zd operator+(zd a, zd b) { return {a.x + b.x, a.y + b.y}; }
+__host__ __device__ inline zd operator-(zd a, zd b) { return {a.x - b.x, a.y - b.y}; }
+__host__ __device__ inline zd operator-(zd a) { return {-a.x, -a.y}; }
+__host__ __device__ inline zd operator*(zd a, zd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__host__ __device__ inline zd operator*(double s, zd a) { return {s * a.x, s * a.y}; }
+__host__ __device__ inline zd& operator+=(zd& a, zd b) { a.x += b.x; a.y += b.y; return a; }
+__host__ __device__ inline zd& operator-=(zd& a, zd b) { a.x -= b.x; a.y -= b.y; return a; }
+
+__host__ __device__ inline double cj(double a) { return a; }
+__host__ __device__ inline float cj(float a) { return a; }
+__host__ __device__ inline zd cj(zd a) { return {a.x, -a.y}; }
+__host__ __device__ inline double absq(double a) { return a * a; }
+__host__ __device__ inline double absq(zd a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double re(double a) { return a; }
+__host__ __device__ inline double re(zd a) { return a.x; }
+
+// accumulation / coefficient type of a storage type: FP64 for real storage
+// (FP32 basis included), complex128 for complex storage
+template <class T> struct acc_of { using type = double; };
+template <> struct acc_of<zd> { using type = zd; };
+template <class T> using acc_t = typename acc_of<T>::type;
+
+template <class A> __host__ __device__ inline A zero();
+template <> __host__ __device__ inline double zero<double>() { return 0.0; }
+template <> __host__ __device__ inline zd zero<zd>() { return {0.0, 0.0}; }
+
+__host__ __device__ inline double widen(float v) { return (double)v; }
+__host__ __device__ inline double widen(double v) { return v; }
+__host__ __device__ inline zd widen(zd v) { return v; }
+
+template <class T> __host__ __device__ inline T narrow(acc_t<T> v);
+template <> __host__ __device__ inline float narrow<float>(double v) { return (float)v; }
+template <> __host__ __device__ inline double narrow<double>(double v) { return v; }
+template <> __host__ __device__ inline zd narrow<zd>(zd v) { return v; }
+
+// Pointers to column blocks (each n x P, row-major, leading dimension P).
+constexpr int MAXB = 64;
+struct BlockPtrs {
+    const void* p[MAXB];
+};
+
+constexpr int NT = 256;       // threads per workgroup of the streaming kernels
+constexpr int MAXI = 24;      // register accumulators per thread in the dot kernels
+constexpr int NWG_MAX = 1024; // workgroups of a streaming launch
+
+// control block written by the per-step kernel and read by every kernel of a cycle
+struct Ctl {
+    int active;   // 1 while the cycle keeps stepping
+    int meff;     // completed block steps of the current cycle
+    int status;   // 0 ok, 1 Cholesky breakdown
+    int pad;
+};
+
+inline int nwg_for(int64_t n, int P) {
+    int64_t rows = NT / P;
+    int64_t tiles = (n + rows - 1) / rows;
+    int64_t g = tiles < NWG_MAX ? tiles : NWG_MAX;
+    if (g >= 8) g -= g % 8;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// ---------------------------------------------------------------------------
+// launchers (kernels.hip); every one enqueues on `st` and returns a hipError_t
+// ---------------------------------------------------------------------------
+template <class T>
+struct Launch {
+    using A = acc_t<T>;
+    // W = (A Vin) Rinv; Vout = Vin Rinv (own rows); partial dots of [Q.., Vout]^H W
+    static hipError_t spmm_dot(hipStream_t st, int P, int64_t n, const int* rp, const int* ci,
+                               const T* av, const T* Vin, const A* Rinv, T* Vout, T* Wout,
+                               const BlockPtrs& Q, int nq, int with_self, A* part, int nwg,
+                               const Ctl* ctl);
+    // W' = W - Q S (S optional) then W' = W' Rmul (optional); store W' (optional);
+    // partials [Q^H W' (dot_q)] [W'^H W' (gram)]
+    static hipError_t update_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q,
+                                 int nq, const A* S, const A* Rmul, T* Wout, int dot_q, int gram,
+                                 A* part, int nwg, const Ctl* ctl);
+    // out_o (+)= sum_i in_i coef[i][o]   (coef: [nin][nout][P][P], FP64/complex128)
+    template <class TO>
+    static hipError_t combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin,
+                              const BlockPtrs& out, int nout, const A* coef, int accumulate);
+};
+
+// reduce partials: out[o] = (add ? add[o] : 0) + sum_w part[w*nout + o]
+template <class A>
+hipError_t reduce_partials(hipStream_t st, const A* part, int nwg, int nout, const A* add, A* out,
+                           const Ctl* ctl);
+
+// R = B - A X in FP64 (complex128); optional store of R narrowed to TR; per-WG
+// partial sums [|r_b|^2 (P)] [|b_b|^2 (P)] into part (double)
+template <class TA, class TR>
+hipError_t residual(hipStream_t st, int P, int64_t n, const int* rp, const int* ci, const TA* av,
+                    const TA* B, int64_t ldb, const TA* X, TR* Rout, double* part, int nwg);
+
+template <class A>
+hipError_t cholqr_first(hipStream_t st, int P, const A* part, int nwg, int nout, int off, A* Z1,
+                        A* Z1inv, Ctl* ctl);
+template <class A>
+hipError_t cholqr_second(hipStream_t st, int P, const A* part, int nwg, int nout, int off,
+                         const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl);
+template <class A>
+hipError_t step_small(hipStream_t st, int P, const A* gpart, int nwg, int gnout, int goff,
+                      const A* S, int KP, int j, int m, A* H, A* F, A* Rh, A* QH, A* g,
+                      A* RinvAll, double* rho, Ctl* ctl, double thresh);
+
+hipError_t cast_values(hipStream_t st, const double* in, float* out, int64_t nnz);
+template <class TI, class TO>
+hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ldi, TO* out,
+                      int64_t ldo, int zero_pad_to);
+
+}  // namespace bgcr

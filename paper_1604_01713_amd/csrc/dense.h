@@ -1,0 +1,71 @@
+// Small dense FP64 linear algebra on the host for the per-cycle problems of
+// block GCRO-DR: back substitution for the block GMRES least-squares solution,
+// thin QR with positive diagonal, Cholesky, and the harmonic-Ritz eigenproblem
+// (a complex Schur form by Hessenberg reduction and shifted QR iteration).
+// Everything works on column-major std::complex<double> matrices; real
+// problems are embedded.
+#pragma once
+
+#include <complex>
+#include <vector>
+
+namespace bgcr {
+namespace dense {
+
+using cd = std::complex<double>;
+
+struct Mat {
+    int r = 0, c = 0;
+    std::vector<cd> a;
+    Mat() = default;
+    Mat(int r_, int c_) : r(r_), c(c_), a((size_t)r_ * c_, cd(0.0, 0.0)) {}
+    cd& operator()(int i, int j) { return a[(size_t)i + (size_t)j * r]; }
+    const cd& operator()(int i, int j) const { return a[(size_t)i + (size_t)j * r]; }
+    static Mat eye(int n) {
+        Mat I(n, n);
+        for (int i = 0; i < n; ++i) I(i, i) = 1.0;
+        return I;
+    }
+    Mat block(int i0, int j0, int nr, int nc) const;
+    void set_block(int i0, int j0, const Mat& B);
+};
+
+Mat matmul(const Mat& A, const Mat& B);
+Mat adjoint(const Mat& A);
+double fro(const Mat& A);
+
+// G = R^H R, R upper triangular with real positive diagonal; false if G is
+// not numerically positive definite.
+bool chol_upper(const Mat& G, Mat& R);
+Mat tri_inv_upper(const Mat& R);
+// X with R X = B, R upper triangular (leading n x n of R is used)
+Mat solve_upper(const Mat& R, const Mat& B);
+// X with A X = B, Gaussian elimination with partial pivoting; false if singular
+bool solve_lu(const Mat& A, const Mat& B, Mat& X);
+// thin Householder QR, A = Q R with diag(R) real and >= 0
+void qr_pos(const Mat& A, Mat& Q, Mat& R);
+
+// complex Schur form A = Z T Z^H (T upper triangular)
+struct Schur {
+    Mat T, Z;
+    std::vector<cd> lam;
+    bool ok = false;
+};
+Schur schur(const Mat& A);
+// eigenvector of A for eigenvalue index i of the Schur form (unit 2-norm)
+std::vector<cd> schur_eigvec(const Schur& S, int i);
+
+// harmonic Ritz selection rules (Section 4.1): k values of smallest modulus
+// (largest with `largest`), order (|theta|, Re, Im, index), infinite or NaN
+// values never kept; `real` keeps a conjugate pair whole (k may grow by one)
+// and returns the basis [Re t, Im t] for it.  Returns the selected indices in
+// `idx` and, for real problems, whether index is the first of a pair.
+struct Selection {
+    std::vector<int> idx;        // eigenvalue indices, in selection order
+    std::vector<int> pair_first; // 1 if idx[i] opens a conjugate pair (real case)
+    int ncols = 0;               // columns of the real/complex basis
+};
+Selection select_ritz(const std::vector<cd>& theta, int k, bool largest, bool real);
+
+}  // namespace dense
+}  // namespace bgcr

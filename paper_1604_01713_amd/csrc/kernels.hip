@@ -1,0 +1,762 @@
+// HIP kernels of the block GCRO-DR restart cycle for gfx950 (MI355X).
+//
+// Data layout: every n x P block (basis block V_j, SpMM output W, recycled
+// column blocks of U and C, residual R) is row-major with leading dimension P,
+// so one row of a block is P contiguous scalars and a tile of NT/P rows of a
+// block is NT contiguous scalars.  A streaming kernel gives each workgroup a
+// contiguous range of row tiles; workgroups are renumbered so that each of the
+// 8 XCDs owns one contiguous slice of rows (L2 locality for the SpMM gathers).
+//
+// Reductions over rows are two-stage and deterministic: a workgroup writes
+// its partial sums to part[wg][*]; a second kernel sums them in fixed order.
+#include <mutex>
+
+#include "bgcr_internal.h"
+
+namespace bgcr {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+template <class T> __host__ __device__ inline T tz();
+template <> __host__ __device__ inline float tz<float>() { return 0.f; }
+template <> __host__ __device__ inline double tz<double>() { return 0.0; }
+template <> __host__ __device__ inline zd tz<zd>() { return {0.0, 0.0}; }
+
+__device__ inline double inv_real(double a) { return 1.0 / a; }
+__device__ inline double scale_by(double s, double a) { return s * a; }
+__device__ inline zd scale_by(double s, zd a) { return {s * a.x, s * a.y}; }
+template <class A> __device__ inline A from_real(double v);
+template <> __device__ inline double from_real<double>(double v) { return v; }
+template <> __device__ inline zd from_real<zd>(double v) { return {v, 0.0}; }
+
+template <class TO, class TI> __host__ __device__ inline TO conv(TI v);
+template <> __host__ __device__ inline double conv<double, double>(double v) { return v; }
+template <> __host__ __device__ inline float conv<float, double>(double v) { return (float)v; }
+template <> __host__ __device__ inline double conv<double, float>(float v) { return (double)v; }
+template <> __host__ __device__ inline float conv<float, float>(float v) { return v; }
+template <> __host__ __device__ inline zd conv<zd, zd>(zd v) { return v; }
+
+// Workgroup renumbering: hardware dispatches workgroup w to XCD w % 8; the
+// logical index gives XCD x the contiguous logical range [x G/8, (x+1) G/8).
+__device__ inline int logical_wg() {
+    const int w = blockIdx.x, G = gridDim.x;
+    if (G % 8 != 0) return w;
+    return (w % 8) * (G / 8) + (w / 8);
+}
+
+__device__ inline void tile_range(int64_t ntiles, int lw, int64_t& t0, int64_t& t1) {
+    const int64_t G = gridDim.x;
+    t0 = (int64_t)lw * ntiles / G;
+    t1 = (int64_t)(lw + 1) * ntiles / G;
+}
+
+// Contribution of one row tile to one output of a tall-skinny product.
+// Output o < ndot: (Q column c = o / P)^H (W column o % P) with the Q tile of
+// block c / P at Qs[(c/P)*NT ...]; o >= ndot: Gram entry (a, b) of the W tile.
+template <class T, int P>
+__device__ inline acc_t<T> tile_item(const T* Qs, const T* Ws, int ndot, int o, int g, int G) {
+    constexpr int ROWS = NT / P;
+    using A = acc_t<T>;
+    A s = zero<A>();
+    const int bb = o % P;
+    const T* x;
+    if (o < ndot) {
+        const int c = o / P;
+        x = Qs + (c / P) * NT + (c % P);
+    } else {
+        x = Ws + (o - ndot) / P;
+    }
+    const T* y = Ws + bb;
+    for (int rr = g; rr < ROWS; rr += G) s += cj(widen(x[rr * P])) * widen(y[rr * P]);
+    return s;
+}
+
+// Item bookkeeping shared by the dot kernels: nout outputs, G row groups per
+// output when nout < NT, thread t owns items t + NT*i.
+struct Items {
+    int nout, G, items;
+    __device__ Items(int nout_) : nout(nout_) {
+        G = (nout > 0 && nout < NT) ? NT / nout : 1;
+        items = nout * G;
+    }
+};
+
+template <class A>
+__device__ inline void write_partials(const Items& it, A (&acc)[MAXI], A* red, A* part, int lw) {
+    const int t = threadIdx.x;
+    if (it.nout == 0) return;
+    if (it.G == 1) {
+#pragma unroll
+        for (int i = 0; i < MAXI; ++i) {
+            const int id = t + NT * i;
+            if (id < it.items) part[(int64_t)lw * it.nout + id] = acc[i];
+        }
+        return;
+    }
+    __syncthreads();
+    if (t < it.items) red[t] = acc[0];
+    __syncthreads();
+    if (t < it.nout) {
+        A s = zero<A>();
+        for (int g = 0; g < it.G; ++g) s += red[g * it.nout + t];
+        part[(int64_t)lw * it.nout + t] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sweep 1: block SpMM fused with the first block-CGS dot products
+// ---------------------------------------------------------------------------
+// W = (A Vin) Rinv and Vout = Vin Rinv for the rows of each tile; the dot
+// part accumulates [Q_0 .. Q_{nq-1}, Vout]^H W (Vout from the tile itself).
+template <class T, int P>
+__global__ __launch_bounds__(NT) void k_spmm_dot(int64_t n, const int* __restrict__ rp,
+                                                 const int* __restrict__ ci, const T* __restrict__ av,
+                                                 const T* __restrict__ Vin,
+                                                 const acc_t<T>* __restrict__ Rinv, T* Vout, T* Wout,
+                                                 BlockPtrs Q, int nq, int with_self,
+                                                 acc_t<T>* __restrict__ part, const Ctl* ctl) {
+    using A = acc_t<T>;
+    if (ctl && ctl->active == 0) return;
+    constexpr int ROWS = NT / P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    A* raw = (A*)smem;
+    A* Rs = raw + NT;
+    T* Ws = (T*)(Rs + P * P);
+    T* Qs = Ws + NT;
+    const int t = threadIdx.x, r = t / P, b = t % P;
+    const int nqt = nq + with_self;
+    const Items it(nqt * P * P);
+    A acc[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) acc[i] = zero<A>();
+    if (Rinv && t < P * P) Rs[t] = Rinv[t];
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_range((n + ROWS - 1) / ROWS, lw, t0, t1);
+    __syncthreads();
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t row = tile * ROWS + r;
+        const bool ok = row < n;
+        A s = zero<A>();
+        if (ok) {
+            const int e = rp[row + 1];
+            for (int kk = rp[row]; kk < e; ++kk) s += widen(av[kk]) * widen(Vin[(int64_t)ci[kk] * P + b]);
+        }
+        A w = s;
+        if (Rinv) {
+            raw[t] = s;
+            __syncthreads();
+            w = zero<A>();
+#pragma unroll
+            for (int a = 0; a < P; ++a) w += raw[r * P + a] * Rs[a * P + b];
+        }
+        const T wt = narrow<T>(w);
+        Ws[t] = wt;
+        if (ok) Wout[row * P + b] = wt;
+        if (Vout) {
+            A v = zero<A>();
+            if (ok) {
+                if (Rinv) {
+#pragma unroll
+                    for (int a = 0; a < P; ++a) v += widen(Vin[row * P + a]) * Rs[a * P + b];
+                } else {
+                    v = widen(Vin[row * P + b]);
+                }
+            }
+            const T vt = narrow<T>(v);
+            if (ok) Vout[row * P + b] = vt;
+            if (with_self) Qs[nq * NT + t] = vt;
+        }
+        for (int i = 0; i < nq; ++i) Qs[i * NT + t] = ok ? ((const T*)Q.p[i])[row * P + b] : tz<T>();
+        __syncthreads();
+        if (it.nout) {
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i) {
+                const int id = t + NT * i;
+                if (id < it.items) acc[i] += tile_item<T, P>(Qs, Ws, it.nout, id % it.nout, id / it.nout, it.G);
+            }
+        }
+        __syncthreads();
+    }
+    write_partials(it, acc, raw, part, lw);
+}
+
+// ---------------------------------------------------------------------------
+// sweeps 2 and 3: W' = W - Q S (and/or W' = W Rmul), optional store, partial
+// Q^H W' and/or Gram W'^H W'
+// ---------------------------------------------------------------------------
+template <class T, int P>
+__global__ __launch_bounds__(NT) void k_update_dot(int64_t n, const T* __restrict__ Win, BlockPtrs Q,
+                                                   int nq, const acc_t<T>* __restrict__ S,
+                                                   const acc_t<T>* __restrict__ Rmul, T* Wout,
+                                                   int dot_q, int gram, acc_t<T>* __restrict__ part,
+                                                   const Ctl* ctl) {
+    using A = acc_t<T>;
+    if (ctl && ctl->active == 0) return;
+    constexpr int ROWS = NT / P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    A* raw = (A*)smem;
+    A* Rs = raw + NT;
+    A* Ss = Rs + P * P;
+    T* Ws = (T*)(Ss + (S ? nq * P * P : 0));
+    T* Qs = Ws + NT;
+    const int t = threadIdx.x, r = t / P, b = t % P;
+    const int ndot = dot_q ? nq * P * P : 0;
+    const Items it(ndot + (gram ? P * P : 0));
+    const bool needQ = nq > 0 && (S != nullptr || dot_q);
+    A acc[MAXI];
+#pragma unroll
+    for (int i = 0; i < MAXI; ++i) acc[i] = zero<A>();
+    if (Rmul && t < P * P) Rs[t] = Rmul[t];
+    if (S)
+        for (int e = t; e < nq * P * P; e += NT) Ss[e] = S[e];
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_range((n + ROWS - 1) / ROWS, lw, t0, t1);
+    __syncthreads();
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t row = tile * ROWS + r;
+        const bool ok = row < n;
+        A w = ok ? widen(Win[row * P + b]) : zero<A>();
+        if (needQ)
+            for (int i = 0; i < nq; ++i) Qs[i * NT + t] = ok ? ((const T*)Q.p[i])[row * P + b] : tz<T>();
+        __syncthreads();
+        if (S) {
+            for (int c = 0; c < nq * P; ++c) w -= widen(Qs[(c / P) * NT + r * P + (c % P)]) * Ss[c * P + b];
+        }
+        if (Rmul) {
+            raw[t] = w;
+            __syncthreads();
+            w = zero<A>();
+#pragma unroll
+            for (int a = 0; a < P; ++a) w += raw[r * P + a] * Rs[a * P + b];
+        }
+        const T wt = narrow<T>(w);
+        Ws[t] = wt;
+        if (ok && Wout) Wout[row * P + b] = wt;
+        __syncthreads();
+        if (it.nout) {
+#pragma unroll
+            for (int i = 0; i < MAXI; ++i) {
+                const int id = t + NT * i;
+                if (id < it.items) acc[i] += tile_item<T, P>(Qs, Ws, ndot, id % it.nout, id / it.nout, it.G);
+            }
+        }
+        __syncthreads();
+    }
+    write_partials(it, acc, raw, part, lw);
+}
+
+// ---------------------------------------------------------------------------
+// out_o (+)= sum_i in_i coef[i][o]  (basis updates: solution, residual, recycle refresh)
+// ---------------------------------------------------------------------------
+template <class TI, class TO, int P>
+__global__ __launch_bounds__(NT) void k_combine(int64_t n, BlockPtrs in, int nin, BlockPtrs out, int nout,
+                                                const acc_t<TI>* __restrict__ coef, int accumulate) {
+    using A = acc_t<TI>;
+    constexpr int ROWS = NT / P;
+    const int t = threadIdx.x, r = t / P, b = t % P;
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_range((n + ROWS - 1) / ROWS, lw, t0, t1);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t row = tile * ROWS + r;
+        if (row >= n) continue;
+        for (int o = 0; o < nout; ++o) {
+            TO* y = (TO*)out.p[o];
+            A v = accumulate ? widen(y[row * P + b]) : zero<A>();
+            for (int i = 0; i < nin; ++i) {
+                const TI* x = (const TI*)in.p[i] + row * P;
+                const A* cf = coef + ((int64_t)(i * nout + o) * P) * P + b;
+#pragma unroll
+                for (int a = 0; a < P; ++a) v += widen(x[a]) * cf[a * P];
+            }
+            y[row * P + b] = narrow<TO>(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// deterministic second-stage reduction
+// ---------------------------------------------------------------------------
+template <class A>
+__global__ void k_reduce(const A* __restrict__ part, int nwg, int nout, const A* __restrict__ add, A* out,
+                         const Ctl* ctl) {
+    if (ctl && ctl->active == 0) return;
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= nout) return;
+    A s = add ? add[o] : zero<A>();
+    for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * nout + o];
+    out[o] = s;
+}
+
+// ---------------------------------------------------------------------------
+// true residual R = B - A X (FP64 / complex128) with per-column norms
+// ---------------------------------------------------------------------------
+template <class TA, class TR, int P>
+__global__ __launch_bounds__(NT) void k_residual(int64_t n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const TA* __restrict__ av, const TA* __restrict__ B,
+                                                 int64_t ldb, const TA* __restrict__ X, TR* Rout,
+                                                 double* __restrict__ part) {
+    constexpr int ROWS = NT / P;
+    __shared__ double red[2 * NT];
+    const int t = threadIdx.x, r = t / P, b = t % P;
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_range((n + ROWS - 1) / ROWS, lw, t0, t1);
+    double rs = 0.0, bs = 0.0;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t row = tile * ROWS + r;
+        if (row >= n) continue;
+        TA s = tz<TA>();
+        const int e = rp[row + 1];
+        for (int kk = rp[row]; kk < e; ++kk) s += av[kk] * X[(int64_t)ci[kk] * P + b];
+        const TA bv = B[row * ldb + b];
+        const TA rv = bv - s;
+        if (Rout) Rout[row * P + b] = narrow<TR>(rv);
+        rs += absq(rv);
+        bs += absq(bv);
+    }
+    red[t] = rs;
+    red[NT + t] = bs;
+    __syncthreads();
+    if (t < P) {
+        double a = 0.0, c = 0.0;
+        for (int q = 0; q < ROWS; ++q) {
+            a += red[q * P + t];
+            c += red[NT + q * P + t];
+        }
+        part[(int64_t)lw * 2 * P + t] = a;
+        part[(int64_t)lw * 2 * P + P + t] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small FP64 problems on the device (one workgroup)
+// ---------------------------------------------------------------------------
+__device__ inline double dabs(double a) { return fabs(a); }
+__device__ inline double dabs(zd a) { return sqrt(a.x * a.x + a.y * a.y); }
+
+// G = R^H R with R upper triangular, positive diagonal.  Fails when a pivot is
+// not above 1e-24 of the largest diagonal entry of G (columns numerically
+// dependent to about 1e-12).
+template <class A>
+__device__ bool chol_upper(const A* G, A* R, int P) {
+    double maxd = 0.0;
+    for (int i = 0; i < P; ++i) maxd = fmax(maxd, re(G[i * P + i]));
+    if (!(maxd > 0.0) || !isfinite(maxd)) return false;
+    for (int i = 0; i < P; ++i) {
+        for (int j = 0; j < i; ++j) R[i * P + j] = zero<A>();
+        A d = G[i * P + i];
+        for (int l = 0; l < i; ++l) d -= cj(R[l * P + i]) * R[l * P + i];
+        const double dd = re(d);
+        if (!(dd > 1e-24 * maxd) || !isfinite(dd)) return false;
+        const double rii = sqrt(dd);
+        R[i * P + i] = from_real<A>(rii);
+        const double ir = 1.0 / rii;
+        for (int j = i + 1; j < P; ++j) {
+            A s = G[i * P + j];
+            for (int l = 0; l < i; ++l) s -= cj(R[l * P + i]) * R[l * P + j];
+            R[i * P + j] = scale_by(ir, s);
+        }
+    }
+    return true;
+}
+
+// inverse of an upper triangular matrix with real positive diagonal
+template <class A>
+__device__ void tri_inv_upper(const A* R, A* Ri, int P) {
+    for (int j = 0; j < P; ++j) {
+        for (int i = j + 1; i < P; ++i) Ri[i * P + j] = zero<A>();
+        Ri[j * P + j] = from_real<A>(1.0 / re(R[j * P + j]));
+        for (int i = j - 1; i >= 0; --i) {
+            A s = zero<A>();
+            for (int l = i + 1; l <= j; ++l) s += R[i * P + l] * Ri[l * P + j];
+            Ri[i * P + j] = scale_by(-1.0 / re(R[i * P + i]), s);
+        }
+    }
+}
+
+template <class A>
+__device__ void reduce_small(const A* part, int nwg, int nout, int off, A* out, int cnt) {
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+        A s = zero<A>();
+        for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * nout + off + e];
+        out[e] = s;
+    }
+}
+
+// first pass of CholQR of the cycle's starting block: Z1 = chol(Gram)
+template <class A, int P>
+__global__ void k_cholqr_first(const A* part, int nwg, int nout, int off, A* Z1, A* Z1inv, Ctl* ctl) {
+    __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
+    __shared__ int okf;
+    reduce_small(part, nwg, nout, off, Gs, P * P);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        okf = chol_upper(Gs, Rs, P);
+        if (okf) tri_inv_upper(Rs, Ri, P);
+    }
+    __syncthreads();
+    if (!okf) {
+        if (threadIdx.x == 0) {
+            ctl->active = 0;
+            ctl->meff = 0;
+            ctl->status = 1;
+        }
+        return;
+    }
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
+        Z1[e] = Rs[e];
+        Z1inv[e] = Ri[e];
+    }
+    if (threadIdx.x == 0) ctl->status = 0;
+}
+
+// second pass: Z2 = chol(Gram of R Z1^{-1}); Z = Z2 Z1; LSQ right-hand side
+// E Z (Algorithm 1) and the cycle control block are initialised here.
+template <class A, int P>
+__global__ void k_cholqr_second(const A* part, int nwg, int nout, int off, const A* Z1, A* Rinv0, A* g, int m,
+                                Ctl* ctl) {
+    __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
+    __shared__ int okf;
+    if (ctl->status != 0) return;
+    reduce_small(part, nwg, nout, off, Gs, P * P);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        okf = chol_upper(Gs, Rs, P);
+        if (okf) tri_inv_upper(Rs, Ri, P);
+    }
+    __syncthreads();
+    if (!okf) {
+        if (threadIdx.x == 0) {
+            ctl->active = 0;
+            ctl->meff = 0;
+            ctl->status = 1;
+        }
+        return;
+    }
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) Rinv0[e] = Ri[e];
+    for (int e = threadIdx.x; e < (m + 1) * P * P; e += blockDim.x) {
+        const int i = e / P, j = e % P;
+        A z = zero<A>();
+        if (i < P)
+            for (int l = 0; l < P; ++l) z += Rs[i * P + l] * Z1[l * P + j];
+        g[e] = z;
+    }
+    if (threadIdx.x == 0) {
+        ctl->active = 1;
+        ctl->meff = 0;
+        ctl->status = 0;
+    }
+}
+
+// Per block step j (1-based): CholQR factor of W'' from its Gram partials,
+// new column block of the block Hessenberg H (and of F = C^H A W), and the
+// progressive block-Householder triangularisation of H with the right-hand
+// side update (Section 4.1, Householder reflection storage): the reflectors
+// of block column j are accumulated into one 2P x 2P unitary QH_j that later
+// columns apply as a single matrix product.
+template <class A, int P>
+__global__ __launch_bounds__(NT) void k_step_small(const A* gpart, int nwg, int gnout, int goff, const A* S, int KP,
+                                                   int j, int m, A* H, A* F, A* Rh, A* QH, A* g, A* RinvAll,
+                                                   double* rho, Ctl* ctl, double thresh) {
+    if (ctl->active == 0) return;
+    constexpr int P2 = 2 * P;
+    __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
+    __shared__ A X[P2 * P], M[P2 * P2], tmp[P2 * P], V[P2];
+    __shared__ double vv, red[NT];
+    __shared__ int okf;
+    const int t = threadIdx.x;
+    const int jc = j - 1;
+    const int ldH = m * P;
+    reduce_small(gpart, nwg, gnout, goff, Gs, P * P);
+    __syncthreads();
+    if (t == 0) {
+        okf = chol_upper(Gs, Rs, P);
+        if (okf) tri_inv_upper(Rs, Ri, P);
+    }
+    __syncthreads();
+    if (!okf) {
+        if (t == 0) {
+            ctl->active = 0;
+            ctl->meff = j - 1;
+            ctl->status = 1;
+        }
+        return;
+    }
+    for (int e = t; e < P * P; e += NT) RinvAll[(int64_t)j * P * P + e] = Ri[e];
+    for (int e = t; e < (j + 1) * P * P; e += NT) {
+        const int i = e / P, bb = e % P;
+        const A v = (i < j * P) ? S[(KP + i) * P + bb] : Rs[(i - j * P) * P + bb];
+        H[(int64_t)i * ldH + jc * P + bb] = v;
+        Rh[(int64_t)i * ldH + jc * P + bb] = v;
+    }
+    for (int e = t; e < KP * P; e += NT) {
+        const int i = e / P, bb = e % P;
+        F[(int64_t)i * ldH + jc * P + bb] = S[i * P + bb];
+    }
+    __threadfence_block();
+    __syncthreads();
+    // apply the stored block reflectors of earlier block columns
+    for (int i = 1; i < j; ++i) {
+        const int r0 = (i - 1) * P;
+        for (int e = t; e < P2 * P; e += NT) tmp[e] = Rh[(int64_t)(r0 + e / P) * ldH + jc * P + e % P];
+        __syncthreads();
+        const A* Q = QH + (int64_t)(i - 1) * P2 * P2;
+        for (int e = t; e < P2 * P; e += NT) {
+            const int rr = e / P, bb = e % P;
+            A s = zero<A>();
+            for (int l = 0; l < P2; ++l) s += Q[rr * P2 + l] * tmp[l * P + bb];
+            Rh[(int64_t)(r0 + rr) * ldH + jc * P + bb] = s;
+        }
+        __threadfence_block();
+        __syncthreads();
+    }
+    // Householder QR of the 2P x P block in rows (j-1)P .. (j+1)P-1
+    const int r0 = (j - 1) * P;
+    for (int e = t; e < P2 * P; e += NT) X[e] = Rh[(int64_t)(r0 + e / P) * ldH + jc * P + e % P];
+    for (int e = t; e < P2 * P2; e += NT) M[e] = from_real<A>((e / P2) == (e % P2) ? 1.0 : 0.0);
+    __syncthreads();
+    for (int c = 0; c < P; ++c) {
+        if (t == 0) {
+            double al = 0.0;
+            for (int l = c; l < P2; ++l) al += absq(X[l * P + c]);
+            al = sqrt(al);
+            double s2 = 0.0;
+            if (al > 0.0) {
+                const A x0 = X[c * P + c];
+                const double ax = dabs(x0);
+                const A ph = ax > 0.0 ? scale_by(1.0 / ax, x0) : from_real<A>(1.0);
+                const A beta = scale_by(-al, ph);
+                for (int l = 0; l < P2; ++l) V[l] = l < c ? zero<A>() : (l == c ? x0 - beta : X[l * P + c]);
+                for (int l = c; l < P2; ++l) s2 += absq(V[l]);
+            }
+            vv = s2;
+        }
+        __syncthreads();
+        if (vv > 0.0) {
+            const double f = 2.0 / vv;
+            if (t < P) {
+                const int col = t;
+                if (col >= c) {
+                    A w = zero<A>();
+                    for (int l = c; l < P2; ++l) w += cj(V[l]) * X[l * P + col];
+                    for (int l = c; l < P2; ++l) X[l * P + col] -= scale_by(f, V[l] * w);
+                }
+            } else if (t < P + P2) {
+                const int col = t - P;
+                A w = zero<A>();
+                for (int l = c; l < P2; ++l) w += cj(V[l]) * M[l * P2 + col];
+                for (int l = c; l < P2; ++l) M[l * P2 + col] -= scale_by(f, V[l] * w);
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = t; e < P2 * P; e += NT) {
+        const int rr = e / P, bb = e % P;
+        Rh[(int64_t)(r0 + rr) * ldH + jc * P + bb] = (rr < P && bb >= rr) ? X[e] : zero<A>();
+    }
+    for (int e = t; e < P2 * P2; e += NT) QH[(int64_t)jc * P2 * P2 + e] = M[e];
+    for (int e = t; e < P2 * P; e += NT) tmp[e] = g[(int64_t)(r0 + e / P) * P + e % P];
+    __syncthreads();
+    for (int e = t; e < P2 * P; e += NT) {
+        const int rr = e / P, bb = e % P;
+        A s = zero<A>();
+        for (int l = 0; l < P2; ++l) s += M[rr * P2 + l] * tmp[l * P + bb];
+        g[(int64_t)(r0 + rr) * P + bb] = s;
+    }
+    __threadfence_block();
+    __syncthreads();
+    double v = 0.0;
+    if (t < P * P) v = absq(g[(int64_t)(j * P + t / P) * P + t % P]);
+    red[t] = v;
+    __syncthreads();
+    if (t == 0) {
+        double s = 0.0;
+        for (int q = 0; q < P * P && q < NT; ++q) s += red[q];
+        const double rh = sqrt(s);
+        rho[jc] = rh;
+        ctl->meff = j;
+        if (rh <= thresh || j == m) ctl->active = 0;
+    }
+}
+
+template <class TI, class TO>
+__global__ void k_copy_block(int64_t n, int p, const TI* __restrict__ in, int64_t ldi, TO* __restrict__ out,
+                             int64_t ldo, int padto) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * padto) return;
+    const int64_t i = e / padto;
+    const int j = (int)(e % padto);
+    out[i * ldo + j] = j < p ? conv<TO, TI>(in[i * ldi + j]) : conv<TO, TI>(tz<TI>());
+}
+
+__global__ void k_cast(const double* __restrict__ in, float* __restrict__ out, int64_t nnz) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nnz) out[e] = (float)in[e];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <class F>
+static void allow_big_lds(F* f) {
+    // gfx950 has 160 KB of LDS per CU; allow a workgroup to use it
+    (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+#define BGCR_DISPATCH_P(P, MACRO) \
+    switch (P) {                  \
+        case 1: MACRO(1); break;  \
+        case 2: MACRO(2); break;  \
+        case 4: MACRO(4); break;  \
+        case 8: MACRO(8); break;  \
+        case 16: MACRO(16); break; \
+        default: return hipErrorInvalidValue; \
+    }
+
+template <class T>
+hipError_t Launch<T>::spmm_dot(hipStream_t st, int P, int64_t n, const int* rp, const int* ci, const T* av,
+                               const T* Vin, const A* Rinv, T* Vout, T* Wout, const BlockPtrs& Q, int nq,
+                               int with_self, A* part, int nwg, const Ctl* ctl) {
+    const size_t lds = (size_t)NT * sizeof(A) + (size_t)P * P * sizeof(A) + (size_t)NT * sizeof(T) +
+                       (size_t)(nq + with_self) * NT * sizeof(T);
+    if ((nq + with_self) * P * P > MAXI * NT) return hipErrorInvalidValue;
+#define L(PP)                                                                                     \
+    {                                                                                             \
+        static std::once_flag fl;                                                                 \
+        std::call_once(fl, [] { allow_big_lds(k_spmm_dot<T, PP>); });                             \
+        hipLaunchKernelGGL((k_spmm_dot<T, PP>), dim3(nwg), dim3(NT), lds, st, n, rp, ci, av, Vin, \
+                           Rinv, Vout, Wout, Q, nq, with_self, part, ctl);                        \
+    }
+    BGCR_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t Launch<T>::update_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
+                                 const A* S, const A* Rmul, T* Wout, int dot_q, int gram, A* part, int nwg,
+                                 const Ctl* ctl) {
+    const size_t lds = (size_t)NT * sizeof(A) + (size_t)P * P * sizeof(A) +
+                       (S ? (size_t)nq * P * P * sizeof(A) : 0) + (size_t)NT * sizeof(T) +
+                       (size_t)nq * NT * sizeof(T);
+    if ((dot_q ? nq * P * P : 0) + (gram ? P * P : 0) > MAXI * NT) return hipErrorInvalidValue;
+#define L(PP)                                                                                      \
+    {                                                                                              \
+        static std::once_flag fl;                                                                  \
+        std::call_once(fl, [] { allow_big_lds(k_update_dot<T, PP>); });                            \
+        hipLaunchKernelGGL((k_update_dot<T, PP>), dim3(nwg), dim3(NT), lds, st, n, Win, Q, nq, S, \
+                           Rmul, Wout, dot_q, gram, part, ctl);                                    \
+    }
+    BGCR_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <class T>
+template <class TO>
+hipError_t Launch<T>::combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out,
+                              int nout, const A* coef, int accumulate) {
+    const int nwg = nwg_for(n, P);
+#define L(PP) hipLaunchKernelGGL((k_combine<T, TO, PP>), dim3(nwg), dim3(NT), 0, st, n, in, nin, out, nout, coef, accumulate);
+    BGCR_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <class A>
+hipError_t reduce_partials(hipStream_t st, const A* part, int nwg, int nout, const A* add, A* out, const Ctl* ctl) {
+    if (nout <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_reduce<A>), dim3((nout + 255) / 256), dim3(256), 0, st, part, nwg, nout, add, out, ctl);
+    return hipGetLastError();
+}
+
+template <class TA, class TR>
+hipError_t residual(hipStream_t st, int P, int64_t n, const int* rp, const int* ci, const TA* av, const TA* B,
+                    int64_t ldb, const TA* X, TR* Rout, double* part, int nwg) {
+#define L(PP) hipLaunchKernelGGL((k_residual<TA, TR, PP>), dim3(nwg), dim3(NT), 0, st, n, rp, ci, av, B, ldb, X, Rout, part);
+    BGCR_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <class A>
+hipError_t cholqr_first(hipStream_t st, int P, const A* part, int nwg, int nout, int off, A* Z1, A* Z1inv, Ctl* ctl) {
+#define L(PP) hipLaunchKernelGGL((k_cholqr_first<A, PP>), dim3(1), dim3(NT), 0, st, part, nwg, nout, off, Z1, Z1inv, ctl);
+    BGCR_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <class A>
+hipError_t cholqr_second(hipStream_t st, int P, const A* part, int nwg, int nout, int off, const A* Z1, A* Rinv0,
+                         A* g, int m, Ctl* ctl) {
+#define L(PP) hipLaunchKernelGGL((k_cholqr_second<A, PP>), dim3(1), dim3(NT), 0, st, part, nwg, nout, off, Z1, Rinv0, g, m, ctl);
+    BGCR_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <class A>
+hipError_t step_small(hipStream_t st, int P, const A* gpart, int nwg, int gnout, int goff, const A* S, int KP, int j,
+                      int m, A* H, A* F, A* Rh, A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl, double thresh) {
+#define L(PP) hipLaunchKernelGGL((k_step_small<A, PP>), dim3(1), dim3(NT), 0, st, gpart, nwg, gnout, goff, S, KP, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
+    BGCR_DISPATCH_P(P, L)
+#undef L
+    return hipGetLastError();
+}
+
+hipError_t cast_values(hipStream_t st, const double* in, float* out, int64_t nnz) {
+    if (nnz <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, in, out, nnz);
+    return hipGetLastError();
+}
+
+template <class TI, class TO>
+hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ldi, TO* out, int64_t ldo, int padto) {
+    const int64_t tot = n * padto;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_copy_block<TI, TO>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, p, in, ldi,
+                       out, ldo, padto);
+    return hipGetLastError();
+}
+
+// explicit instantiations
+template struct Launch<double>;
+template struct Launch<float>;
+template struct Launch<zd>;
+template hipError_t Launch<double>::combine<double>(hipStream_t, int, int64_t, const BlockPtrs&, int,
+                                                    const BlockPtrs&, int, const double*, int);
+template hipError_t Launch<float>::combine<float>(hipStream_t, int, int64_t, const BlockPtrs&, int,
+                                                  const BlockPtrs&, int, const double*, int);
+template hipError_t Launch<float>::combine<double>(hipStream_t, int, int64_t, const BlockPtrs&, int,
+                                                   const BlockPtrs&, int, const double*, int);
+template hipError_t Launch<zd>::combine<zd>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int,
+                                            const zd*, int);
+template hipError_t reduce_partials<double>(hipStream_t, const double*, int, int, const double*, double*, const Ctl*);
+template hipError_t reduce_partials<zd>(hipStream_t, const zd*, int, int, const zd*, zd*, const Ctl*);
+template hipError_t residual<double, double>(hipStream_t, int, int64_t, const int*, const int*, const double*,
+                                             const double*, int64_t, const double*, double*, double*, int);
+template hipError_t residual<double, float>(hipStream_t, int, int64_t, const int*, const int*, const double*,
+                                            const double*, int64_t, const double*, float*, double*, int);
+template hipError_t residual<zd, zd>(hipStream_t, int, int64_t, const int*, const int*, const zd*, const zd*, int64_t,
+                                     const zd*, zd*, double*, int);
+template hipError_t cholqr_first<double>(hipStream_t, int, const double*, int, int, int, double*, double*, Ctl*);
+template hipError_t cholqr_first<zd>(hipStream_t, int, const zd*, int, int, int, zd*, zd*, Ctl*);
+template hipError_t cholqr_second<double>(hipStream_t, int, const double*, int, int, int, const double*, double*,
+                                          double*, int, Ctl*);
+template hipError_t cholqr_second<zd>(hipStream_t, int, const zd*, int, int, int, const zd*, zd*, zd*, int, Ctl*);
+template hipError_t step_small<double>(hipStream_t, int, const double*, int, int, int, const double*, int, int, int,
+                                       double*, double*, double*, double*, double*, double*, double*, Ctl*, double);
+template hipError_t step_small<zd>(hipStream_t, int, const zd*, int, int, int, const zd*, int, int, int, zd*, zd*, zd*,
+                                   zd*, zd*, zd*, double*, Ctl*, double);
+template hipError_t copy_block<double, double>(hipStream_t, int64_t, int, const double*, int64_t, double*, int64_t,
+                                               int);
+template hipError_t copy_block<zd, zd>(hipStream_t, int64_t, int, const zd*, int64_t, zd*, int64_t, int);
+template hipError_t copy_block<float, double>(hipStream_t, int64_t, int, const float*, int64_t, double*, int64_t, int);
+template hipError_t copy_block<double, float>(hipStream_t, int64_t, int, const double*, int64_t, float*, int64_t, int);
+
+}  // namespace bgcr

@@ -1,0 +1,1000 @@
+// Host driver of block GCRO-DR (Algorithm 1) on one MI355X and the C ABI of
+// libbgcr.so.  Every n-sized operation runs in the HIP kernels of kernels.hip;
+// the host keeps only the small FP64 problems of each cycle (least-squares
+// back substitution, harmonic Ritz eigenproblem, QR of G P) whose size is
+// independent of n.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "bgcr.h"
+#include "bgcr_internal.h"
+#include "dense.h"
+
+using namespace bgcr;
+using dense::cd;
+using dense::Mat;
+
+struct bgcr_sequence {
+    virtual ~bgcr_sequence() {}
+    virtual int solve(const bgcr_csr* A, const void* B, int64_t ldb, void* X, int64_t ldx, double tol,
+                      bgcr_stats* st) = 0;
+    virtual int get_recycle(void* U, void* C, int64_t ld) const = 0;
+    virtual int set_recycle(const void* U, int64_t ld, int k_in) = 0;
+    virtual int recycle_dim() const = 0;
+    std::vector<int> log_steps;
+    std::vector<double> log_res;
+};
+
+namespace {
+
+inline cd to_cd(double v) { return cd(v, 0.0); }
+inline cd to_cd(zd v) { return cd(v.x, v.y); }
+template <class A> A from_cd(cd v);
+template <> double from_cd<double>(cd v) { return v.real(); }
+template <> zd from_cd<zd>(cd v) { return {v.real(), v.imag()}; }
+
+struct Fail {
+    int code;
+};
+#define HIPCHK(...)                                      \
+    do {                                                 \
+        hipError_t e_ = (__VA_ARGS__);                   \
+        if (e_ != hipSuccess) throw Fail{BGCR_ERR_HIP};  \
+    } while (0)
+
+bool valid_params(const bgcr_params* prm, int64_t n) {
+    if (!prm || n <= 0) return false;
+    const int p = prm->p;
+    if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16)) return false;
+    if (prm->m < 1 || prm->m > 64 || prm->k < 0 || prm->k > 128) return false;
+    if (prm->dtype != BGCR_F64 && prm->dtype != BGCR_C128) return false;
+    if (prm->precision != BGCR_PLAIN_FP64 && prm->precision != BGCR_MIXED_FP32) return false;
+    if (prm->dtype == BGCR_C128 && prm->precision != BGCR_PLAIN_FP64) return false;
+    if (prm->max_cycles < 1 || prm->reserved != 0) return false;
+    const int KB = (prm->k + (prm->dtype == BGCR_F64 ? 1 : 0) + p - 1) / p;
+    if (KB + prm->m + 1 > MAXB) return false;
+    if ((KB + prm->m) * p * p > MAXI * NT) return false;
+    return true;
+}
+
+struct Sizes {
+    int P, m, k, KB, KP;
+    size_t s, sa;  // bytes of a basis scalar, of an FP64 scalar
+    size_t basis, blk, recyc, small_, part, total_fixed;
+};
+
+Sizes sizes_of(const bgcr_params* prm, int64_t n) {
+    Sizes z;
+    z.P = prm->p;
+    z.m = prm->m;
+    z.k = prm->k;
+    const bool cplx = prm->dtype == BGCR_C128;
+    z.KB = z.k > 0 ? (z.k + (cplx ? 0 : 1) + z.P - 1) / z.P : 0;
+    z.KP = z.KB * z.P;
+    z.sa = cplx ? 16 : 8;
+    z.s = cplx ? 16 : (prm->precision == BGCR_MIXED_FP32 ? 4 : 8);
+    z.blk = (size_t)n * z.P * z.s;
+    z.basis = (size_t)z.m * z.blk;
+    z.recyc = 4 * (size_t)z.KB * z.blk;
+    const int qmax = (2 * z.KB + z.m + 1) * z.P;
+    const size_t nout = std::max((size_t)qmax * z.P, (size_t)z.KP * z.P);
+    z.part = (size_t)NWG_MAX * nout * z.sa;
+    const size_t mp = (size_t)z.m * z.P, m1p = (size_t)(z.m + 1) * z.P;
+    z.small_ = z.sa * (2 * (size_t)qmax * z.P + 2 * m1p * mp + (size_t)z.KP * mp + (size_t)z.m * 4 * z.P * z.P +
+                       m1p * z.P + (size_t)(z.m + 1) * z.P * z.P + 2 * (size_t)z.P * z.P +
+                       (size_t)(2 * z.KB + z.m + 1) * z.P * 2 * z.KP) +
+               sizeof(double) * ((size_t)z.m + (size_t)NWG_MAX * 2 * z.P) + sizeof(Ctl);
+    z.total_fixed = z.basis + 3 * z.blk /* W2, Wb, R */ + (size_t)n * z.P * z.sa /* X */ + z.recyc + z.part + z.small_;
+    return z;
+}
+
+}  // namespace
+
+template <class T>
+struct Seq final : bgcr_sequence {
+    using A = acc_t<T>;  // FP64 real or complex128: coefficients, solution, matrix for the residual
+    using L = Launch<T>;
+
+    bgcr_params prm;
+    int64_t n;
+    int P, m, k, KB, KP, nwg;
+    bool mixed, cplx;
+    hipStream_t st;
+    Sizes sz;
+
+    T *Vb = nullptr, *W2 = nullptr, *Wb = nullptr, *R = nullptr;
+    T* Ub[2] = {nullptr, nullptr};
+    T* Cb[2] = {nullptr, nullptr};
+    A* X = nullptr;
+    float* av32 = nullptr;
+    size_t av32_cap = 0;
+    A *part = nullptr, *S1 = nullptr, *Sf = nullptr, *H = nullptr, *F = nullptr, *Rh = nullptr, *QH = nullptr,
+      *g = nullptr, *RinvAll = nullptr, *Z1 = nullptr, *Z1i = nullptr, *coef = nullptr;
+    size_t coef_cap = 0;
+    double *rho = nullptr, *dpart = nullptr;
+    Ctl* ctl = nullptr;
+    unsigned char* hbuf = nullptr;
+    size_t hcap = 0, hoff = 0;
+    int cur = 0, keff = 0;
+    // per-solve counters
+    int n_spmm = 0, n_steps = 0, n_cycles = 0, n_refine = 0;
+    double alg_bytes = 0.0;
+    bool breakdown_seen = false;
+
+    std::vector<void*> allocs;
+
+    Seq(const bgcr_params* p_, int64_t n_, hipStream_t s_) : prm(*p_), n(n_), st(s_) {
+        P = prm.p;
+        m = prm.m;
+        k = prm.k;
+        cplx = prm.dtype == BGCR_C128;
+        mixed = prm.precision == BGCR_MIXED_FP32;
+        sz = sizes_of(&prm, n);
+        KB = sz.KB;
+        KP = sz.KP;
+        nwg = nwg_for(n, P);
+    }
+
+    ~Seq() override {
+        if (st) (void)hipStreamSynchronize(st);
+        for (void* p : allocs) (void)hipFree(p);
+        if (hbuf) (void)hipHostFree(hbuf);
+    }
+
+    template <class U_>
+    U_* dalloc(size_t count) {
+        if (count == 0) return nullptr;
+        void* p = nullptr;
+        if (hipMalloc(&p, count * sizeof(U_)) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
+        allocs.push_back(p);
+        return (U_*)p;
+    }
+
+    void allocate() {
+        const size_t blk = (size_t)n * P;
+        Vb = dalloc<T>((size_t)m * blk);
+        W2 = dalloc<T>(blk);
+        Wb = dalloc<T>(blk);
+        R = dalloc<T>(blk);
+        X = dalloc<A>(blk);
+        for (int i = 0; i < 2; ++i) {
+            Ub[i] = dalloc<T>((size_t)KB * blk);
+            Cb[i] = dalloc<T>((size_t)KB * blk);
+        }
+        const int qmax = (2 * KB + m + 1) * P;
+        const size_t nout = std::max((size_t)qmax * P, (size_t)KP * P);
+        part = dalloc<A>((size_t)NWG_MAX * nout);
+        S1 = dalloc<A>((size_t)qmax * P);
+        Sf = dalloc<A>((size_t)qmax * P);
+        const size_t mp = (size_t)m * P, m1p = (size_t)(m + 1) * P;
+        H = dalloc<A>(m1p * mp);
+        Rh = dalloc<A>(m1p * mp);
+        F = dalloc<A>(std::max<size_t>(1, (size_t)KP * mp));
+        QH = dalloc<A>((size_t)m * 4 * P * P);
+        g = dalloc<A>(m1p * P);
+        RinvAll = dalloc<A>((size_t)(m + 1) * P * P);
+        Z1 = dalloc<A>((size_t)P * P);
+        Z1i = dalloc<A>((size_t)P * P);
+        coef_cap = (size_t)(2 * KB + m + 1) * P * 2 * std::max(KP, P);
+        coef = dalloc<A>(coef_cap);
+        rho = dalloc<double>(m);
+        dpart = dalloc<double>((size_t)NWG_MAX * 2 * P);
+        ctl = dalloc<Ctl>(1);
+        hcap = std::max<size_t>((size_t)4 << 20, 2 * coef_cap * sizeof(A) + (64 << 10));
+        if (hipHostMalloc((void**)&hbuf, hcap, hipHostMallocDefault) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
+        HIPCHK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
+        HIPCHK(hipMemsetAsync(Ub[0], 0, (size_t)KB * blk * sizeof(T), st));
+        HIPCHK(hipMemsetAsync(Ub[1], 0, (size_t)KB * blk * sizeof(T), st));
+        HIPCHK(hipMemsetAsync(Cb[0], 0, (size_t)KB * blk * sizeof(T), st));
+        HIPCHK(hipMemsetAsync(Cb[1], 0, (size_t)KB * blk * sizeof(T), st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
+    T* vblk(int j) { return Vb + (size_t)j * n * P; }
+    T* ublk(int buf, int b) { return Ub[buf] + (size_t)b * n * P; }
+    T* cblk(int buf, int b) { return Cb[buf] + (size_t)b * n * P; }
+
+    // ---- host <-> device staging through pinned memory --------------------
+    void sync() {
+        HIPCHK(hipStreamSynchronize(st));
+        hoff = 0;
+    }
+    void d2h(void* dst, const void* src, size_t bytes) {
+        if (bytes == 0) return;
+        sync();
+        size_t done = 0;
+        while (done < bytes) {
+            const size_t c = std::min(bytes - done, hcap);
+            HIPCHK(hipMemcpyAsync(hbuf, (const char*)src + done, c, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::memcpy((char*)dst + done, hbuf, c);
+            done += c;
+        }
+    }
+    void h2d(void* dst, const void* src, size_t bytes) {
+        if (bytes == 0) return;
+        if (bytes > hcap) throw Fail{BGCR_ERR_INVALID};
+        const size_t al = (bytes + 255) & ~(size_t)255;
+        if (hoff + al > hcap) sync();
+        std::memcpy(hbuf + hoff, src, bytes);
+        HIPCHK(hipMemcpyAsync(dst, hbuf + hoff, bytes, hipMemcpyHostToDevice, st));
+        hoff += al;
+    }
+
+    static BlockPtrs bp(const std::vector<const void*>& v) {
+        BlockPtrs b;
+        std::memset(&b, 0, sizeof(b));
+        if (v.size() > (size_t)MAXB) throw Fail{BGCR_ERR_INVALID};
+        for (size_t i = 0; i < v.size(); ++i) b.p[i] = v[i];
+        return b;
+    }
+
+    // Upload a coefficient matrix K ((nin P) x (nout P)) for k_combine.
+    const A* upload_coef(const Mat& K, int nin, int nout, A* dst) {
+        const size_t cnt = (size_t)nin * nout * P * P;
+        std::vector<A> h(cnt);
+        for (int i = 0; i < nin; ++i)
+            for (int o = 0; o < nout; ++o)
+                for (int a = 0; a < P; ++a)
+                    for (int b = 0; b < P; ++b) {
+                        const int rr = i * P + a, cc = o * P + b;
+                        const cd v = (rr < K.r && cc < K.c) ? K(rr, cc) : cd(0.0, 0.0);
+                        h[((size_t)(i * nout + o) * P + a) * P + b] = from_cd<A>(v);
+                    }
+        h2d(dst, h.data(), cnt * sizeof(A));
+        return dst;
+    }
+
+    template <class TO>
+    void combine(const std::vector<const void*>& in, const std::vector<void*>& out, const Mat& K, int accumulate) {
+        const int nin = (int)in.size(), nout = (int)out.size();
+        if ((size_t)nin * nout * P * P > coef_cap) throw Fail{BGCR_ERR_INVALID};
+        std::vector<const void*> outc(out.begin(), out.end());
+        const A* cf = upload_coef(K, nin, nout, coef);
+        HIPCHK(L::template combine<TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate));
+    }
+
+    // Q^H W for a list of W blocks: returns Mat (nq P) x (nw P)
+    Mat multi_dot(const std::vector<const void*>& Q, const std::vector<const T*>& W) {
+        const int nq = (int)Q.size();
+        const int nw = (int)W.size();
+        Mat D(nq * P, nw * P);
+        const int chunk = std::max(1, (MAXI * NT) / (P * P));
+        std::vector<A> h;
+        for (int w = 0; w < nw; ++w) {
+            for (int q0 = 0; q0 < nq; q0 += chunk) {
+                const int qn = std::min(chunk, nq - q0);
+                std::vector<const void*> sub(Q.begin() + q0, Q.begin() + q0 + qn);
+                HIPCHK(L::update_dot(st, P, n, W[w], bp(sub), qn, nullptr, nullptr, nullptr, 1, 0, part, nwg, nullptr));
+                const int nout = qn * P * P;
+                HIPCHK(reduce_partials<A>(st, part, nwg, nout, nullptr, Sf, nullptr));
+                h.resize(nout);
+                d2h(h.data(), Sf, nout * sizeof(A));
+                for (int c = 0; c < qn * P; ++c)
+                    for (int b = 0; b < P; ++b) D(q0 * P + c, w * P + b) = to_cd(h[(size_t)c * P + b]);
+            }
+        }
+        return D;
+    }
+
+    // per-column ||B - A X||^2 and ||B||^2 (FP64); stores R (narrowed) if Rout
+    void residual_norms(const bgcr_csr* Am, const A* B, int64_t ldb, T* Rout, std::vector<double>& rn2,
+                        std::vector<double>& bn2) {
+        HIPCHK(residual<A, T>(st, P, n, Am->row_ptr, Am->col_idx, (const A*)Am->values, B, ldb, X, Rout, dpart,
+                              nwg));
+        std::vector<double> h((size_t)nwg * 2 * P);
+        d2h(h.data(), dpart, h.size() * sizeof(double));
+        rn2.assign(P, 0.0);
+        bn2.assign(P, 0.0);
+        for (int w = 0; w < nwg; ++w)
+            for (int b = 0; b < P; ++b) {
+                rn2[b] += h[(size_t)w * 2 * P + b];
+                bn2[b] += h[(size_t)w * 2 * P + P + b];
+            }
+        ++n_spmm;
+    }
+
+    // Algorithm 1, U available: A U = C S (CholQR2), U <- U S^{-1}
+    void import_basis(const bgcr_csr* Am, const T* avT) {
+        const int o = 1 - cur;
+        for (int b = 0; b < KB; ++b) {
+            HIPCHK(L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, ublk(cur, b), nullptr, nullptr, cblk(o, b),
+                               bp({}), 0, 0, part, nwg, nullptr));
+            ++n_spmm;
+        }
+        auto gram_of = [&](int buf) {
+            std::vector<const void*> Q;
+            std::vector<const T*> W;
+            for (int b = 0; b < KB; ++b) {
+                Q.push_back(cblk(buf, b));
+                W.push_back(cblk(buf, b));
+            }
+            return multi_dot(Q, W).block(0, 0, keff, keff);
+        };
+        Mat S1, S2;
+        if (!dense::chol_upper(gram_of(o), S1)) throw Fail{BGCR_ERR_NUMERICAL};
+        const Mat S1i = dense::tri_inv_upper(S1);
+        std::vector<const void*> inC, inU;
+        std::vector<void*> outCcur, outCo, outUo;
+        for (int b = 0; b < KB; ++b) {
+            inC.push_back(cblk(o, b));
+            outCcur.push_back(cblk(cur, b));
+        }
+        combine<T>(inC, outCcur, S1i, 0);
+        if (!dense::chol_upper(gram_of(cur), S2)) throw Fail{BGCR_ERR_NUMERICAL};
+        const Mat S2i = dense::tri_inv_upper(S2);
+        inC.clear();
+        for (int b = 0; b < KB; ++b) {
+            inC.push_back(cblk(cur, b));
+            inU.push_back(ublk(cur, b));
+            outCo.push_back(cblk(o, b));
+            outUo.push_back(ublk(o, b));
+        }
+        combine<T>(inC, outCo, S2i, 0);
+        const Mat Si = dense::matmul(S1i, S2i);  // S = S2 S1 -> S^{-1} = S1^{-1} S2^{-1}
+        combine<T>(inU, outUo, Si, 0);
+        cur = o;
+    }
+
+    // X += U C^H R, R -= C C^H R  (Algorithm 1 recycle import, and the start of
+    // every refinement step of the precision form)
+    void project() {
+        std::vector<const void*> Q;
+        for (int b = 0; b < KB; ++b) Q.push_back(cblk(cur, b));
+        Mat Tm = multi_dot(Q, {R});
+        for (int i = keff; i < KP; ++i)
+            for (int b = 0; b < P; ++b) Tm(i, b) = 0.0;
+        std::vector<const void*> inU, inC;
+        for (int b = 0; b < KB; ++b) {
+            inU.push_back(ublk(cur, b));
+            inC.push_back(cblk(cur, b));
+        }
+        combine<A>(inU, {X}, Tm, 1);
+        Mat mT = Tm;
+        for (cd& v : mT.a) v = -v;
+        combine<T>(inC, {R}, mT, 1);
+    }
+
+    struct CycleOut {
+        int meff = 0;
+        bool breakdown = false;
+        Mat H, F, Y, RinvLast;
+        const T* last = nullptr;  // block holding V_{meff+1} up to RinvLast
+    };
+
+    // One restart cycle: CholQR2 of R, m block Arnoldi steps on (I - C C^H) A
+    // with BCGS2 + CholQR and the progressive LSQ, then Y (Algorithm 1 loop body).
+    CycleOut cycle(const bgcr_csr* Am, const T* avT, bool withC, double thresh) {
+        const int P2 = P * P;
+        HIPCHK(L::update_dot(st, P, n, R, bp({}), 0, nullptr, nullptr, nullptr, 0, 1, part, nwg, nullptr));
+        HIPCHK(cholqr_first<A>(st, P, part, nwg, P2, 0, Z1, Z1i, ctl));
+        HIPCHK(L::update_dot(st, P, n, R, bp({}), 0, nullptr, Z1i, W2, 0, 1, part, nwg, nullptr));
+        HIPCHK(cholqr_second<A>(st, P, part, nwg, P2, 0, Z1, RinvAll, g, m, ctl));
+        const int ncb = withC ? KB : 0;
+        for (int j = 1; j <= m; ++j) {
+            std::vector<const void*> Q;
+            for (int b = 0; b < ncb; ++b) Q.push_back(cblk(cur, b));
+            for (int i = 0; i < j - 1; ++i) Q.push_back(vblk(i));
+            const int nq = (int)Q.size();
+            HIPCHK(L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
+                               vblk(j - 1), Wb, bp(Q), nq, 1, part, nwg, ctl));
+            const int nout = (nq + 1) * P2;
+            HIPCHK(reduce_partials<A>(st, part, nwg, nout, nullptr, S1, ctl));
+            Q.push_back(vblk(j - 1));
+            const BlockPtrs QB = bp(Q);
+            HIPCHK(L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, nwg, ctl));
+            HIPCHK(reduce_partials<A>(st, part, nwg, nout, S1, Sf, ctl));
+            HIPCHK(L::update_dot(st, P, n, Wb, QB, nq + 1, Sf, nullptr, W2, 0, 1, part, nwg, ctl));
+            HIPCHK(step_small<A>(st, P, part, nwg, P2, 0, Sf, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl,
+                                 thresh));
+        }
+        Ctl hc;
+        d2h(&hc, ctl, sizeof(Ctl));
+        CycleOut co;
+        co.meff = hc.meff;
+        co.breakdown = hc.status != 0;
+        if (co.meff == 0) throw Fail{BGCR_ERR_NUMERICAL};
+        const int me = co.meff, mp = me * P, ldH = m * P;
+        std::vector<A> hH((size_t)(m + 1) * P * ldH), hR((size_t)(m + 1) * P * ldH), hg((size_t)(m + 1) * P * P),
+            hRi((size_t)(m + 1) * P2), hF((size_t)std::max(1, KP) * ldH);
+        d2h(hH.data(), H, hH.size() * sizeof(A));
+        d2h(hR.data(), Rh, hR.size() * sizeof(A));
+        d2h(hg.data(), g, hg.size() * sizeof(A));
+        d2h(hRi.data(), RinvAll, hRi.size() * sizeof(A));
+        if (withC && KP > 0) d2h(hF.data(), F, (size_t)KP * ldH * sizeof(A));
+        co.H = Mat((me + 1) * P, mp);
+        for (int i = 0; i < (me + 1) * P; ++i)
+            for (int j = 0; j < mp; ++j) co.H(i, j) = to_cd(hH[(size_t)i * ldH + j]);
+        Mat Rt(mp, mp), gt(mp, P);
+        for (int i = 0; i < mp; ++i) {
+            for (int j = 0; j < mp; ++j) Rt(i, j) = to_cd(hR[(size_t)i * ldH + j]);
+            for (int b = 0; b < P; ++b) gt(i, b) = to_cd(hg[(size_t)i * P + b]);
+        }
+        co.Y = dense::solve_upper(Rt, gt);
+        co.F = Mat(withC ? KP : 0, mp);
+        if (withC)
+            for (int i = 0; i < KP; ++i)
+                for (int j = 0; j < mp; ++j) co.F(i, j) = to_cd(hF[(size_t)i * ldH + j]);
+        co.RinvLast = Mat(P, P);
+        if (co.breakdown) {
+            // step meff+1 failed its Cholesky: V_{meff+1} is the normalised block in slot meff
+            co.last = vblk(me);
+            co.RinvLast = Mat::eye(P);
+        } else {
+            co.last = W2;
+            for (int a = 0; a < P; ++a)
+                for (int b = 0; b < P; ++b) co.RinvLast(a, b) = to_cd(hRi[(size_t)me * P2 + a * P + b]);
+        }
+        if (co.breakdown) breakdown_seen = true;
+        // model-M algorithmic bytes of the executed Arnoldi sweeps
+        const double s = (double)sizeof(T), sA = (double)sizeof(T);
+        const double kc = withC ? (double)keff : 0.0;
+        for (int j = 1; j <= me; ++j)
+            alg_bytes += (sA + 4.0) * (double)Am->nnz + 4.0 * (double)(n + 1) + 5.0 * s * n * P +
+                         3.0 * s * n * (kc + (double)j * P);
+        n_spmm += me;
+        n_steps += me;
+        return co;
+    }
+
+    // X += W_m Y - U F Y ; (plain) R -= W_{m+1} H Y  (Algorithm 1)
+    void update_solution(const CycleOut& co, bool withC, bool update_R) {
+        const int me = co.meff, mp = me * P;
+        std::vector<const void*> in;
+        for (int i = 0; i < me; ++i) in.push_back(vblk(i));
+        Mat KX(mp + (withC ? KP : 0), P);
+        KX.set_block(0, 0, co.Y);
+        if (withC) {
+            Mat FY = dense::matmul(co.F, co.Y);
+            for (cd& v : FY.a) v = -v;
+            for (int i = keff; i < KP; ++i)
+                for (int b = 0; b < P; ++b) FY(i, b) = 0.0;
+            KX.set_block(mp, 0, FY);
+            for (int b = 0; b < KB; ++b) in.push_back(ublk(cur, b));
+        }
+        combine<A>(in, {X}, KX, 1);
+        if (update_R) {
+            Mat HY = dense::matmul(co.H, co.Y);
+            Mat KR((me + 1) * P, P);
+            for (int i = 0; i < mp; ++i)
+                for (int b = 0; b < P; ++b) KR(i, b) = -HY(i, b);
+            Mat last = dense::matmul(co.RinvLast, HY.block(mp, 0, P, P));
+            for (int i = 0; i < P; ++i)
+                for (int b = 0; b < P; ++b) KR(mp + i, b) = -last(i, b);
+            std::vector<const void*> inR;
+            for (int i = 0; i < me; ++i) inR.push_back(vblk(i));
+            inR.push_back(co.last);
+            combine<T>(inR, {R}, KR, 1);
+        }
+    }
+
+    // basis of the selected harmonic Ritz vectors: columns t (complex), or
+    // [Re t, Im t] / Re t for real problems
+    void ritz_basis(const dense::Selection& sel, const std::vector<std::vector<cd>>& vecs, Mat& Pm) {
+        const int dim = vecs.empty() ? 0 : (int)vecs[0].size();
+        Pm = Mat(dim, sel.ncols);
+        int col = 0;
+        for (size_t s = 0; s < sel.idx.size(); ++s) {
+            const std::vector<cd>& t = vecs[s];
+            if (cplx) {
+                for (int i = 0; i < dim; ++i) Pm(i, col) = t[i];
+                ++col;
+            } else if (sel.pair_first[s]) {
+                for (int i = 0; i < dim; ++i) {
+                    Pm(i, col) = t[i].real();
+                    Pm(i, col + 1) = t[i].imag();
+                }
+                col += 2;
+            } else {
+                int jm = 0;
+                for (int i = 1; i < dim; ++i)
+                    if (std::abs(t[i]) > std::abs(t[jm])) jm = i;
+                const cd ph = std::abs(t[jm]) > 0 ? std::conj(t[jm]) / std::abs(t[jm]) : cd(1.0, 0.0);
+                for (int i = 0; i < dim; ++i) Pm(i, col) = (t[i] * ph).real();
+                ++col;
+            }
+        }
+    }
+
+    // first system, no U (Algorithm 1 else-branch): Proposition block-harm-ritz
+    void refresh_first(const CycleOut& co) {
+        const int me = co.meff, mp = me * P;
+        const int kt = std::min(k, mp);
+        if (kt == 0) {
+            keff = 0;
+            return;
+        }
+        Mat Hm = co.H.block(0, 0, mp, mp);
+        Mat Hs = co.H.block(mp, mp - P, P, P);
+        Mat rhs(mp, P);
+        rhs.set_block(mp - P, 0, dense::matmul(dense::adjoint(Hs), Hs));
+        Mat Xs;
+        Mat K = Hm;
+        std::vector<cd> theta;
+        std::vector<std::vector<cd>> vecs;
+        dense::Selection sel;
+        if (dense::solve_lu(dense::adjoint(Hm), rhs, Xs)) {
+            for (int i = 0; i < mp; ++i)
+                for (int b = 0; b < P; ++b) K(i, mp - P + b) += Xs(i, b);
+            dense::Schur S = dense::schur(K);
+            if (!S.ok) throw Fail{BGCR_ERR_NUMERICAL};
+            theta = S.lam;
+            sel = dense::select_ritz(theta, kt, prm.select_largest != 0, !cplx);
+            for (int i : sel.idx) vecs.push_back(dense::schur_eigvec(S, i));
+        } else {
+            // singular H_m: generalized form with no recycled space
+            Mat M(co.H.r, mp);
+            for (int i = 0; i < mp; ++i) M(i, i) = 1.0;
+            gen_harmonic(co.H, M, kt, theta, sel, vecs);
+        }
+        Mat Pm;
+        ritz_basis(sel, vecs, Pm);
+        Mat Qg, rg;
+        dense::qr_pos(dense::matmul(co.H, Pm), Qg, rg);
+        const int kn = Pm.c;
+        if (kn > KP) throw Fail{BGCR_ERR_NUMERICAL};
+        Mat PR = dense::matmul(Pm, dense::tri_inv_upper(rg));
+        // inputs [V_1..V_meff, last]; outputs [U blocks, C blocks]
+        Mat K2((me + 1) * P, 2 * KP);
+        for (int i = 0; i < mp; ++i)
+            for (int c = 0; c < kn; ++c) {
+                K2(i, c) = PR(i, c);
+                K2(i, KP + c) = Qg(i, c);
+            }
+        Mat lastQ = dense::matmul(co.RinvLast, Qg.block(mp, 0, P, kn));
+        for (int i = 0; i < P; ++i)
+            for (int c = 0; c < kn; ++c) K2(mp + i, KP + c) = lastQ(i, c);
+        std::vector<const void*> in;
+        for (int i = 0; i < me; ++i) in.push_back(vblk(i));
+        in.push_back(co.last);
+        std::vector<void*> out;
+        for (int b = 0; b < KB; ++b) out.push_back(ublk(cur, b));
+        for (int b = 0; b < KB; ++b) out.push_back(cblk(cur, b));
+        combine<T>(in, out, K2, 0);
+        keff = kn;
+    }
+
+    // harmonic Ritz on the augmented space, eq. harm-ritz-gen-eig:
+    // G^H G t = theta G^H M t  with G = Qg Rg:  (Qg^H M Rg^{-1}) s = mu s,
+    // theta = 1/mu, t = Rg^{-1} s
+    void gen_harmonic(const Mat& G, const Mat& M, int kt, std::vector<cd>& theta, dense::Selection& sel,
+                      std::vector<std::vector<cd>>& vecs) {
+        Mat Qg, Rg;
+        dense::qr_pos(G, Qg, Rg);
+        const int nn = G.c;
+        for (int i = 0; i < nn; ++i)
+            if (!(std::abs(Rg(i, i)) > 0.0)) throw Fail{BGCR_ERR_NUMERICAL};
+        const Mat Rgi = dense::tri_inv_upper(Rg);
+        const Mat K = dense::matmul(dense::matmul(dense::adjoint(Qg), M), Rgi);
+        dense::Schur S = dense::schur(K);
+        if (!S.ok) throw Fail{BGCR_ERR_NUMERICAL};
+        theta.assign(nn, cd(0.0, 0.0));
+        for (int i = 0; i < nn; ++i) {
+            const cd mu = S.lam[i];
+            theta[i] = std::abs(mu) > 0.0 ? 1.0 / mu : cd(INFINITY, 0.0);
+        }
+        sel = dense::select_ritz(theta, kt, prm.select_largest != 0, !cplx);
+        vecs.clear();
+        for (int i : sel.idx) {
+            std::vector<cd> s = dense::schur_eigvec(S, i);
+            Mat sv(nn, 1);
+            for (int r = 0; r < nn; ++r) sv(r, 0) = s[r];
+            Mat t = dense::matmul(Rgi, sv);
+            std::vector<cd> tv(nn);
+            for (int r = 0; r < nn; ++r) tv[r] = t(r, 0);
+            vecs.push_back(tv);
+        }
+    }
+
+    // Algorithm 1, end of a cycle with recycling: D, G_m, harmonic Ritz on
+    // U + K_m, then C <- [C W_{m+1}] Q, U <- [U D  W_m] P rho^{-1}
+    void refresh_aug(const CycleOut& co) {
+        const int me = co.meff, mp = me * P;
+        // dots [U, C, V_1..V_meff, last]^H U
+        std::vector<const void*> Q;
+        std::vector<const T*> W;
+        for (int b = 0; b < KB; ++b) Q.push_back(ublk(cur, b));
+        for (int b = 0; b < KB; ++b) Q.push_back(cblk(cur, b));
+        for (int i = 0; i < me; ++i) Q.push_back(vblk(i));
+        Q.push_back(co.last);
+        for (int b = 0; b < KB; ++b) W.push_back(ublk(cur, b));
+        const Mat Dm = multi_dot(Q, W);
+        const int ke = keff;
+        std::vector<double> d(ke);
+        for (int i = 0; i < ke; ++i) {
+            const double nu = std::sqrt(std::max(Dm(i, i).real(), 0.0));
+            if (!(nu > 0.0)) throw Fail{BGCR_ERR_NUMERICAL};
+            d[i] = 1.0 / nu;
+        }
+        const int rows = ke + (me + 1) * P, cols = ke + mp;
+        Mat G(rows, cols), M(rows, cols);
+        for (int i = 0; i < ke; ++i) G(i, i) = d[i];
+        for (int i = 0; i < ke; ++i)
+            for (int j = 0; j < mp; ++j) G(i, ke + j) = co.F(i, j);
+        G.set_block(ke, ke, co.H);
+        // M = [C W_{m+1}]^H [U D  W_m] using C^H W = 0 and W^H W = I
+        for (int i = 0; i < ke; ++i)
+            for (int j = 0; j < ke; ++j) M(i, j) = Dm(KP + i, j) * d[j];
+        for (int i = 0; i < mp; ++i)
+            for (int j = 0; j < ke; ++j) M(ke + i, j) = Dm(2 * KP + i, j) * d[j];
+        Mat WlU = Dm.block(2 * KP + mp, 0, P, ke);
+        Mat VlU = dense::matmul(dense::adjoint(co.RinvLast), WlU);
+        for (int i = 0; i < P; ++i)
+            for (int j = 0; j < ke; ++j) M(ke + mp + i, j) = VlU(i, j) * d[j];
+        for (int i = 0; i < mp; ++i) M(ke + i, ke + i) = 1.0;
+        const int kt = std::min(k, cols);
+        std::vector<cd> theta;
+        dense::Selection sel;
+        std::vector<std::vector<cd>> vecs;
+        gen_harmonic(G, M, kt, theta, sel, vecs);
+        Mat Pm;
+        ritz_basis(sel, vecs, Pm);
+        const int kn = Pm.c;
+        if (kn > KP) throw Fail{BGCR_ERR_NUMERICAL};
+        Mat Qg, rg;
+        dense::qr_pos(dense::matmul(G, Pm), Qg, rg);
+        const Mat PR = dense::matmul(Pm, dense::tri_inv_upper(rg));
+        // inputs [U blocks, C blocks, V_1..V_meff, last]; outputs [U' blocks, C' blocks]
+        const int nin = 2 * KB + me + 1;
+        Mat K2(nin * P, 2 * KP);
+        for (int c = 0; c < kn; ++c) {
+            for (int i = 0; i < ke; ++i) {
+                K2(i, c) = d[i] * PR(i, c);          // U D part of [U D  W_m] P rho^{-1}
+                K2(KP + i, KP + c) = Qg(i, c);       // C part of [C W_{m+1}] Q
+            }
+            for (int i = 0; i < mp; ++i) {
+                K2(2 * KP + i, c) = PR(ke + i, c);
+                K2(2 * KP + i, KP + c) = Qg(ke + i, c);
+            }
+        }
+        Mat lastQ = dense::matmul(co.RinvLast, Qg.block(ke + mp, 0, P, kn));
+        for (int i = 0; i < P; ++i)
+            for (int c = 0; c < kn; ++c) K2(2 * KP + mp + i, KP + c) = lastQ(i, c);
+        std::vector<void*> out;
+        const int o = 1 - cur;
+        for (int b = 0; b < KB; ++b) out.push_back(ublk(o, b));
+        for (int b = 0; b < KB; ++b) out.push_back(cblk(o, b));
+        combine<T>(Q, out, K2, 0);
+        cur = o;
+        keff = kn;
+    }
+
+    void refresh(const CycleOut& co, bool withC) {
+        if (k == 0) return;
+        if (withC)
+            refresh_aug(co);
+        else
+            refresh_first(co);
+    }
+
+    int solve(const bgcr_csr* Am, const void* Bv, int64_t ldb, void* Xv, int64_t ldx, double tol,
+              bgcr_stats* stt) override {
+        const auto t0 = std::chrono::steady_clock::now();
+        n_spmm = n_steps = n_cycles = n_refine = 0;
+        alg_bytes = 0.0;
+        breakdown_seen = false;
+        log_steps.clear();
+        log_res.clear();
+        int status = BGCR_OK;
+        double rel = 0.0, relmax = 0.0;
+        try {
+            if (!Am || !Bv || !Xv || Am->n != n || !Am->row_ptr || !Am->col_idx || !Am->values || ldb < P ||
+                ldx < P || !(tol > 0.0) || Am->nnz < 0)
+                throw Fail{BGCR_ERR_INVALID};
+            const A* B = (const A*)Bv;
+            A* Xu = (A*)Xv;
+            const T* avT = (const T*)Am->values;
+            if (mixed) {
+                if ((size_t)Am->nnz > av32_cap) {
+                    if (av32) {
+                        sync();
+                        (void)hipFree(av32);
+                        allocs.erase(std::find(allocs.begin(), allocs.end(), (void*)av32));
+                    }
+                    av32 = dalloc<float>((size_t)Am->nnz);
+                    av32_cap = (size_t)Am->nnz;
+                }
+                HIPCHK(cast_values(st, (const double*)Am->values, av32, Am->nnz));
+                avT = (const T*)av32;
+            }
+            HIPCHK(copy_block<A, A>(st, n, P, Xu, ldx, X, P, P));
+            std::vector<double> rn2, bn2;
+            residual_norms(Am, B, ldb, R, rn2, bn2);
+            double bn = 0.0, rn = 0.0;
+            for (int b = 0; b < P; ++b) {
+                bn += bn2[b];
+                rn += rn2[b];
+            }
+            if (!std::isfinite(bn) || !std::isfinite(rn)) throw Fail{BGCR_ERR_NONFINITE};
+            bn = std::sqrt(bn);
+            rn = std::sqrt(rn);
+            auto finish_norms = [&](const std::vector<double>& r2, const std::vector<double>& b2) {
+                double s = 0.0;
+                relmax = 0.0;
+                for (int b = 0; b < P; ++b) {
+                    s += r2[b];
+                    if (b2[b] > 0.0) relmax = std::max(relmax, std::sqrt(r2[b] / b2[b]));
+                }
+                rel = bn > 0.0 ? std::sqrt(s) / bn : 0.0;
+            };
+            if (bn == 0.0) {
+                HIPCHK(hipMemsetAsync(X, 0, (size_t)n * P * sizeof(A), st));
+                rel = relmax = 0.0;
+            } else {
+                const double thresh = tol * bn;
+                finish_norms(rn2, bn2);
+                if (rn > thresh) {
+                    if (!mixed)
+                        status = run_plain(Am, avT, B, ldb, thresh, rn2, bn2, finish_norms);
+                    else
+                        status = run_mixed(Am, avT, B, ldb, thresh, rn2, bn2, finish_norms);
+                }
+            }
+            HIPCHK(copy_block<A, A>(st, n, P, X, P, Xu, ldx, P));
+            sync();
+            if (!std::isfinite(rel)) status = BGCR_ERR_NONFINITE;
+        } catch (const Fail& f) {
+            status = f.code;
+            (void)hipStreamSynchronize(st);
+            hoff = 0;
+        }
+        if (stt) {
+            std::memset(stt, 0, sizeof(*stt));
+            stt->status = status;
+            stt->cycles = n_cycles;
+            stt->block_steps = n_steps;
+            stt->spmm_calls = n_spmm;
+            stt->rel_res = rel;
+            stt->rel_res_max_col = relmax;
+            stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            stt->alg_bytes = alg_bytes;
+            stt->k_eff = keff;
+            stt->refine_steps = n_refine;
+        }
+        return status;
+    }
+
+    template <class FN>
+    int run_plain(const bgcr_csr* Am, const T* avT, const A* B, int64_t ldb, double thresh,
+                  std::vector<double>& rn2, std::vector<double>& bn2, FN& finish_norms) {
+        bool pending = false;  // the last cycle's true residual is still to be logged
+        if (keff > 0) {
+            import_basis(Am, avT);
+            project();
+        } else {
+            CycleOut co = cycle(Am, avT, false, thresh);
+            update_solution(co, false, true);
+            refresh(co, false);
+            ++n_cycles;
+            log_steps.push_back(co.meff);
+            log_res.push_back(0.0);
+            pending = true;
+        }
+        for (;;) {
+            residual_norms(Am, B, ldb, nullptr, rn2, bn2);
+            double s = 0.0;
+            for (double v : rn2) s += v;
+            if (!std::isfinite(s)) throw Fail{BGCR_ERR_NONFINITE};
+            finish_norms(rn2, bn2);
+            if (pending) log_res.back() = rel_now(rn2, bn2);
+            pending = false;
+            if (std::sqrt(s) <= thresh) return BGCR_OK;
+            if (n_cycles >= prm.max_cycles) return BGCR_NOT_CONVERGED;
+            const bool withC = keff > 0;
+            CycleOut co = cycle(Am, avT, withC, thresh);
+            update_solution(co, withC, true);
+            refresh(co, withC);
+            ++n_cycles;
+            log_steps.push_back(co.meff);
+            log_res.push_back(0.0);
+            pending = true;
+        }
+    }
+
+    static double rel_now(const std::vector<double>& r2, const std::vector<double>& b2) {
+        double a = 0.0, c = 0.0;
+        for (size_t i = 0; i < r2.size(); ++i) {
+            a += r2[i];
+            c += b2[i];
+        }
+        return c > 0.0 ? std::sqrt(a / c) : 0.0;
+    }
+
+    template <class FN>
+    int run_mixed(const bgcr_csr* Am, const T* avT, const A* B, int64_t ldb, double thresh,
+                  std::vector<double>& rn2, std::vector<double>& bn2, FN& finish_norms) {
+        if (keff > 0) import_basis(Am, avT);
+        bool first = true;
+        for (;;) {
+            if (!first) {
+                residual_norms(Am, B, ldb, R, rn2, bn2);
+                finish_norms(rn2, bn2);
+                if (!log_steps.empty()) log_res.back() = rel_now(rn2, bn2);
+            }
+            first = false;
+            double s = 0.0;
+            for (double v : rn2) s += v;
+            if (!std::isfinite(s)) throw Fail{BGCR_ERR_NONFINITE};
+            if (std::sqrt(s) <= thresh) return BGCR_OK;
+            if (n_cycles >= prm.max_cycles) return BGCR_NOT_CONVERGED;
+            const bool withC = keff > 0;
+            if (withC) project();
+            CycleOut co = cycle(Am, avT, withC, thresh);
+            update_solution(co, withC, false);
+            refresh(co, withC);
+            ++n_cycles;
+            ++n_refine;
+            log_steps.push_back(co.meff);
+            log_res.push_back(0.0);
+        }
+    }
+
+    int recycle_dim() const override { return keff; }
+
+    int get_recycle(void* Uo, void* Co, int64_t ld) const override {
+        if (ld < std::max(1, keff)) return BGCR_ERR_INVALID;
+        auto* self = const_cast<Seq*>(this);
+        try {
+            for (int b = 0; b < KB; ++b) {
+                const int cols = std::min(P, keff - b * P);
+                if (cols <= 0) break;
+                if (Uo)
+                    HIPCHK(copy_block<T, A>(self->st, n, cols, self->ublk(cur, b), P, (A*)Uo + (size_t)b * P, ld,
+                                            cols));
+                if (Co)
+                    HIPCHK(copy_block<T, A>(self->st, n, cols, self->cblk(cur, b), P, (A*)Co + (size_t)b * P, ld,
+                                            cols));
+            }
+            self->sync();
+        } catch (const Fail& f) {
+            return f.code;
+        }
+        return BGCR_OK;
+    }
+
+    int set_recycle(const void* Ui, int64_t ld, int k_in) override {
+        if (!Ui || k_in < 1 || k_in > KP || ld < k_in) return BGCR_ERR_INVALID;
+        try {
+            for (int b = 0; b < KB; ++b) {
+                const int cols = std::max(0, std::min(P, k_in - b * P));
+                if (cols > 0)
+                    HIPCHK(copy_block<A, T>(st, n, cols, (const A*)Ui + (size_t)b * P, ld, ublk(cur, b), P, P));
+                else
+                    HIPCHK(hipMemsetAsync(ublk(cur, b), 0, (size_t)n * P * sizeof(T), st));
+            }
+            sync();
+            keff = k_in;
+        } catch (const Fail& f) {
+            return f.code;
+        }
+        return BGCR_OK;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int bgcr_create_sequence(const bgcr_params* prm, int64_t n, void* hip_stream, bgcr_sequence** out) {
+    if (!out) return BGCR_ERR_INVALID;
+    *out = nullptr;
+    if (!valid_params(prm, n)) return BGCR_ERR_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BGCR_ERR_HIP;
+    bgcr_sequence* s = nullptr;
+    try {
+        hipStream_t st = (hipStream_t)hip_stream;
+        if (prm->dtype == BGCR_C128) {
+            auto* q = new Seq<zd>(prm, n, st);
+            s = q;
+            q->allocate();
+        } else if (prm->precision == BGCR_MIXED_FP32) {
+            auto* q = new Seq<float>(prm, n, st);
+            s = q;
+            q->allocate();
+        } else {
+            auto* q = new Seq<double>(prm, n, st);
+            s = q;
+            q->allocate();
+        }
+    } catch (const Fail& f) {
+        delete s;
+        return f.code;
+    } catch (...) {
+        delete s;
+        return BGCR_ERR_NOMEM;
+    }
+    *out = s;
+    return BGCR_OK;
+}
+
+int bgcr_solve(bgcr_sequence* s, const bgcr_csr* A, const void* B, int64_t ldb, void* X, int64_t ldx, double tol,
+               bgcr_stats* st) {
+    if (!s) return BGCR_ERR_INVALID;
+    try {
+        return s->solve(A, B, ldb, X, ldx, tol, st);
+    } catch (...) {
+        return BGCR_ERR_NOMEM;
+    }
+}
+
+int bgcr_release(bgcr_sequence* s) {
+    delete s;
+    return BGCR_OK;
+}
+
+size_t bgcr_footprint_bytes(const bgcr_params* prm, int64_t n, int64_t nnz) {
+    if (!valid_params(prm, n) || nnz < 0) return 0;
+    const Sizes z = sizes_of(prm, n);
+    size_t b = z.total_fixed;
+    if (prm->precision == BGCR_MIXED_FP32) b += (size_t)nnz * sizeof(float);
+    return b;
+}
+
+int bgcr_recycle_dim(const bgcr_sequence* s, int32_t* k_eff) {
+    if (!s || !k_eff) return BGCR_ERR_INVALID;
+    *k_eff = s->recycle_dim();
+    return BGCR_OK;
+}
+
+int bgcr_get_recycle(const bgcr_sequence* s, void* U_out, void* C_out, int64_t ld) {
+    if (!s) return BGCR_ERR_INVALID;
+    return s->get_recycle(U_out, C_out, ld);
+}
+
+int bgcr_set_recycle(bgcr_sequence* s, const void* U_in, int64_t ld, int32_t k_in) {
+    if (!s) return BGCR_ERR_INVALID;
+    return s->set_recycle(U_in, ld, k_in);
+}
+
+int bgcr_get_cycle_log(const bgcr_sequence* s, int32_t* steps, double* rel_res, int32_t cap, int32_t* count) {
+    if (!s || !count || cap < 0) return BGCR_ERR_INVALID;
+    const int c = (int)s->log_steps.size();
+    *count = c;
+    for (int i = 0; i < std::min(c, (int)cap); ++i) {
+        if (steps) steps[i] = s->log_steps[i];
+        if (rel_res) rel_res[i] = s->log_res[i];
+    }
+    return BGCR_OK;
+}
+
+int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* W, void* hip_stream) {
+    if (!A || !V || !W || A->n <= 0 || !A->row_ptr || !A->col_idx || !A->values) return BGCR_ERR_INVALID;
+    if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16)) return BGCR_ERR_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BGCR_ERR_HIP;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int nwg = nwg_for(A->n, p);
+    BlockPtrs none;
+    std::memset(&none, 0, sizeof(none));
+    hipError_t e;
+    if (dtype == BGCR_F64)
+        e = Launch<double>::spmm_dot(st, p, A->n, A->row_ptr, A->col_idx, (const double*)A->values,
+                                     (const double*)V, nullptr, nullptr, (double*)W, none, 0, 0, nullptr, nwg,
+                                     nullptr);
+    else if (dtype == BGCR_C128)
+        e = Launch<zd>::spmm_dot(st, p, A->n, A->row_ptr, A->col_idx, (const zd*)A->values, (const zd*)V, nullptr,
+                                 nullptr, (zd*)W, none, 0, 0, nullptr, nwg, nullptr);
+    else
+        return BGCR_ERR_INVALID;
+    return e == hipSuccess ? BGCR_OK : BGCR_ERR_HIP;
+}
+
+const char* bgcr_strerror(int status) {
+    switch (status) {
+        case BGCR_OK: return "ok";
+        case BGCR_NOT_CONVERGED: return "not converged within max_cycles";
+        case BGCR_ERR_INVALID: return "invalid argument";
+        case BGCR_ERR_NOMEM: return "device out of memory";
+        case BGCR_ERR_HIP: return "HIP runtime error";
+        case BGCR_ERR_NONFINITE: return "non-finite value";
+        case BGCR_ERR_NUMERICAL: return "numerical failure (rank-deficient block or eigensolver)";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, validates arguments without a GPU, and the input generators
+produce what their recipes say."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1604_01713_amd as bg
+import problems
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "bgcr.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|size_t|const char\*)\s+(bgcr_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_binding_symbols():
+    assert _header_functions() == sorted(bg.EXPORTED_SYMBOLS)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(bg.LIB_PATH):
+        from paper_1604_01713_amd.build import build
+        build()
+    return bg.lib()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_footprint_without_gpu(lib):
+    assert bg.bgcr_strerror(0) == "ok"
+    assert "invalid" in bg.bgcr_strerror(-1)
+    prm = bg.bgcr_params(8, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0)
+    n = 128**3
+    fb = bg.bgcr_footprint_bytes(prm, n, 7 * n)
+    # at least the basis (m blocks), U and C (double buffered) and W2, Wb, R, X
+    assert fb >= (10 + 4 * 3 + 4) * n * 8 * 8
+    assert fb < 8 * 1024**3
+    bad = bg.bgcr_params(3, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0)
+    assert bg.bgcr_footprint_bytes(bad, n, 7 * n) == 0
+    mixed_c = bg.bgcr_params(8, 10, 20, bg.BGCR_C128, bg.BGCR_MIXED_FP32, 100, 0, 0)
+    assert bg.bgcr_footprint_bytes(mixed_c, n, 7 * n) == 0
+    fm = bg.bgcr_footprint_bytes(bg.bgcr_params(8, 10, 20, bg.BGCR_F64, bg.BGCR_MIXED_FP32, 100, 0, 0), n, 7 * n)
+    assert fm < fb
+
+
+def test_invalid_arguments_are_rejected_without_a_gpu(lib):
+    h = ctypes.c_void_p()
+    assert lib.bgcr_create_sequence(None, 10, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID
+    prm = bg.bgcr_params(5, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0)
+    assert lib.bgcr_create_sequence(ctypes.byref(prm), 10, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID
+    assert lib.bgcr_solve(None, None, None, 0, None, 0, 1e-8, None) == bg.BGCR_ERR_INVALID
+    assert lib.bgcr_release(None) == 0
+    assert lib.bgcr_spmm(None, 0, 4, None, None, None) == bg.BGCR_ERR_INVALID
+
+
+def test_generators_follow_their_recipes():
+    A = problems.convdiff(4, 3, diff=(1.0, 0.1, 0.01), conv=(5.0, -5.0, 5.0))
+    n = 64
+    assert A.shape == (n, n) and A.nnz == 7 * 4**3 - 6 * 4**2
+    h = 1.0 / 5
+    # interior node (1,1,1): diagonal 2(a_x+a_y+a_z)/h^2 + (|b_x|+|b_y|+|b_z|)/h
+    i = 1 + 4 * 1 + 16 * 1
+    assert A[i, i] == pytest.approx(2 * 1.11 / h**2 + 15.0 / h)
+    assert A[i, i - 1] == pytest.approx(-1.0 / h**2 - 5.0 / h)     # upwind from -x for b_x > 0
+    assert A[i, i + 1] == pytest.approx(-1.0 / h**2)
+    assert A[i, i + 4] == pytest.approx(-0.1 / h**2 - 5.0 / h)     # b_y < 0: upwind from +y
+    assert A[i, i - 4] == pytest.approx(-0.1 / h**2)
+    w = problems.cfg1()
+    assert w.systems[0].A.shape == (1024, 1024) and w.systems[0].A.nnz == 5 * 32**2 - 4 * 32
+    d = (w.systems[1].A - w.systems[0].A).diagonal()
+    assert np.all(d >= 0) and np.all(d <= 0.01)
+    H = problems.helmholtz2d(8, 20.0)
+    assert H.dtype == np.complex128
+    assert H[0, 0] == pytest.approx(4 * 81 - 400 * (1 - 0.5j))

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Bar (stated by the method's target): relative difference of the solution
+||X_gpu - X_oracle||_F / ||X_oracle||_F <= 1e-6 at relative residual 1e-8,
+with cycle and block-step counts reported side by side.  Sizes are chosen so
+the row tiles of the kernels end in a ragged tail.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import problems
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PARITY = 1e-6
+
+
+def _bg():
+    import paper_1604_01713_amd as bg
+    bg.lib()
+    return bg
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    return torch.device("cuda:0")
+
+
+def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=1000):
+    bg = _bg()
+    dev = _dev()
+    n = systems[0][0].shape[0]
+    cplx = np.iscomplexobj(systems[0][1]) or np.iscomplexobj(systems[0][0].data)
+    dt = bg.BGCR_C128 if cplx else bg.BGCR_F64
+    seq = bg.Sequence(n, p, m, k, dtype=dt, precision=precision, max_cycles=max_cycles)
+    out = []
+    for (A, B, X0) in systems:
+        Ad = bg.DeviceCSR.from_scipy(A, dev)
+        Bd = torch.from_numpy(np.ascontiguousarray(B)).to(dev)
+        Xd = torch.from_numpy(np.ascontiguousarray(X0)).to(dev)
+        st = seq.solve(Ad, Bd, Xd, tol)
+        torch.cuda.synchronize()
+        out.append((Xd.cpu().numpy(), st.as_dict(), seq.cycle_log()))
+    return seq, out
+
+
+def _compare(name, systems, p, m, k, tol, precision=0, bar=PARITY):
+    seq, gpu = _run_sequence(systems, p, m, k, tol, precision=precision)
+    orc, _ = oracle.solve_sequence(systems, tol, m, k)
+    for i, ((Xg, st, log), (Xo, so)) in enumerate(zip(gpu, orc)):
+        A, B, _ = systems[i]
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+        print(f"{name} sys{i}: gpu cycles={st['cycles']} steps={st['block_steps']} relres={rg:.2e} "
+              f"| oracle cycles={so['cycles']} steps={so['block_steps']} | rel diff={rel:.2e}", flush=True)
+        assert st["status"] == 0, st
+        assert rg <= tol * 1.0001
+        assert rel <= bar
+    seq.release()
+    return gpu, orc
+
+
+# ---- kernel level ----------------------------------------------------------
+
+@pytest.mark.parametrize("p", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_block_spmm_matches_dense_product(p, cplx):
+    bg = _bg()
+    dev = _dev()
+    A = problems.convdiff(13, 3, diff=(1.0, 0.3, 0.1), conv=(4.0, -2.0, 1.0))  # n = 2197 (ragged tiles)
+    if cplx:
+        A = (A.astype(np.complex128) + sp.identity(A.shape[0]) * (1.0 + 2.0j)).tocsr()
+    rng = np.random.default_rng(p)
+    V = rng.uniform(-1, 1, (A.shape[0], p))
+    if cplx:
+        V = V + 1j * rng.uniform(-1, 1, V.shape)
+    Ad = bg.DeviceCSR.from_scipy(A, dev)
+    Vd = torch.from_numpy(V).to(dev)
+    Wd = torch.zeros_like(Vd)
+    bg.bgcr_spmm(Ad, Vd, Wd)
+    torch.cuda.synchronize()
+    W = Wd.cpu().numpy()
+    ref = A.toarray() @ V
+    assert np.linalg.norm(W - ref) <= 1e-14 * np.linalg.norm(ref) * 10
+
+
+# ---- whole method ------------------------------------------------------------
+
+def test_cfg1_sequence_parity():
+    w = problems.cfg1()
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    _compare("cfg1", systems, w.p, w.m, w.k, w.tol)
+
+
+def test_reduced_3d_convdiff_parity():
+    w = problems.cfg2(N=21, nsys=3)   # n = 9261, p = 8, m = 10, k = 20
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    _compare("cfg2-21^3", systems, w.p, w.m, w.k, w.tol)
+
+
+@pytest.mark.parametrize("p,m,k", [(1, 12, 6), (4, 6, 5), (16, 4, 8), (2, 5, 0)])
+def test_block_sizes_and_k0(p, m, k):
+    A = problems.convdiff(17, 2, conv=(8.0, -3.0, 0.0))  # n = 289
+    rng = np.random.default_rng(10 + p)
+    systems = []
+    for i in range(2):
+        Ai = (A + sp.diags(0.05 * i * np.ones(A.shape[0]))).tocsr()
+        B = rng.uniform(-1, 1, (A.shape[0], p))
+        systems.append((Ai, B, np.zeros_like(B)))
+    _compare(f"p{p}m{m}k{k}", systems, p, m, k, 1e-8)
+
+
+def test_complex_helmholtz_parity():
+    w = problems.cfg3(N=41, nsys=2, p=16, m=8, k=16, kappa0=6.0)   # n = 1681, complex128
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    _compare("cfg3-41^2", systems, w.p, w.m, w.k, w.tol)
+
+
+def test_mixed_precision_matches_fp64_oracle():
+    w = problems.cfg4(N=14, nsys=2, p=16, m=10, k=24)   # n = 2744, target 1e-10
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    seq, gpu = _run_sequence(systems, w.p, w.m, w.k, w.tol, precision=1)
+    orc, _ = oracle.solve_sequence(systems, w.tol, w.m, w.k)
+    for i, ((Xg, st, log), (Xo, so)) in enumerate(zip(gpu, orc)):
+        A, B, _ = systems[i]
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+        print(f"mixed sys{i}: gpu cycles={st['cycles']} refine={st['refine_steps']} relres={rg:.2e} | "
+              f"oracle cycles={so['cycles']} | rel diff vs FP64 oracle={rel:.2e}", flush=True)
+        assert st["status"] == 0
+        assert rg <= w.tol * 1.0001
+        assert rel <= PARITY
+    seq.release()
+
+
+def test_recycle_pair_satisfies_AU_equals_C():
+    bg = _bg()
+    dev = _dev()
+    w = problems.cfg2(N=15, nsys=2, p=4, m=6, k=9)
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    seq, gpu = _run_sequence(systems, w.p, w.m, w.k, w.tol)
+    ke = seq.recycle_dim()
+    assert ke in (9, 10)
+    n = systems[0][0].shape[0]
+    U = torch.zeros((n, ke), dtype=torch.float64, device=dev)
+    C = torch.zeros_like(U)
+    seq.get_recycle(U, C)
+    torch.cuda.synchronize()
+    U, C = U.cpu().numpy(), C.cpu().numpy()
+    A = systems[-1][0]
+    assert np.linalg.norm(A @ U - C) <= 1e-10 * np.linalg.norm(C)
+    assert np.linalg.norm(C.T @ C - np.eye(ke)) <= 1e-12
+    seq.release()
+
+
+def test_edge_cases_zero_rhs_exact_guess_and_limits():
+    bg = _bg()
+    dev = _dev()
+    A = problems.convdiff(9, 2, conv=(3.0, 1.0, 0.0))
+    n = A.shape[0]
+    B = np.random.default_rng(0).uniform(-1, 1, (n, 4))
+    Ad = bg.DeviceCSR.from_scipy(A, dev)
+    with bg.Sequence(n, 4, 5, 3) as seq:
+        Xd = torch.ones((n, 4), dtype=torch.float64, device=dev)
+        st = seq.solve(Ad, torch.zeros_like(Xd), Xd, 1e-8)
+        assert st.status == 0 and st.cycles == 0 and float(Xd.abs().max()) == 0.0
+        Xs = np.linalg.solve(A.toarray(), B)
+        Xd = torch.from_numpy(Xs).to(dev)
+        st = seq.solve(Ad, torch.from_numpy(B).to(dev), Xd, 1e-8)
+        assert st.status == 0 and st.cycles == 0
+        Xd = torch.zeros((n, 4), dtype=torch.float64, device=dev)
+        with pytest.raises(bg.BgcrError):
+            seq.solve(Ad, torch.from_numpy(B).to(dev), Xd, -1.0)
+    with bg.Sequence(n, 4, 3, 2, max_cycles=1) as seq:
+        Xd = torch.zeros((n, 4), dtype=torch.float64, device=dev)
+        st = seq.solve(Ad, torch.from_numpy(B).to(dev), Xd, 1e-14)
+        assert st.status == bg.BGCR_NOT_CONVERGED and st.cycles == 1
+    # leading dimensions larger than p
+    Bw = torch.zeros((n, 7), dtype=torch.float64, device=dev)
+    Bw[:, :4] = torch.from_numpy(B).to(dev)
+    Xw = torch.zeros((n, 6), dtype=torch.float64, device=dev)
+    with bg.Sequence(n, 4, 5, 3) as seq:
+        st = bg.bgcr_solve(seq.handle, Ad, Bw[:, :4], Xw[:, :4], 1e-9)
+        torch.cuda.synchronize()
+        Xg = Xw[:, :4].cpu().numpy()
+        assert np.linalg.norm(B - A @ Xg) <= 1e-9 * np.linalg.norm(B) * 1.0001
+        assert float(Xw[:, 4:].abs().max()) == 0.0
