@@ -150,6 +150,8 @@ struct Seq final : bgcr_sequence {
         void* p = nullptr;
         if (hipMalloc(&p, count * sizeof(U_)) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
         allocs.push_back(p);
+        // every workspace starts defined (zero)
+        HIPCHK(hipMemsetAsync(p, 0, count * sizeof(U_), st));
         return (U_*)p;
     }
 
@@ -369,6 +371,11 @@ struct Seq final : bgcr_sequence {
     // with BCGS2 + CholQR and the progressive LSQ, then Y (Algorithm 1 loop body).
     CycleOut cycle(const bgcr_csr* Am, const T* avT, bool withC, double thresh) {
         const int P2 = P * P;
+        // H and its triangularised copy are read below the block subdiagonal
+        // (block upper Hessenberg structure): those entries must be zero
+        const size_t hb = (size_t)(m + 1) * P * m * P * sizeof(A);
+        HIPCHK(hipMemsetAsync(H, 0, hb, st));
+        HIPCHK(hipMemsetAsync(Rh, 0, hb, st));
         HIPCHK(L::update_dot(st, P, n, R, bp({}), 0, nullptr, nullptr, nullptr, 0, 1, part, nwg, nullptr));
         HIPCHK(cholqr_first<A>(st, P, part, nwg, P2, 0, Z1, Z1i, ctl));
         HIPCHK(L::update_dot(st, P, n, R, bp({}), 0, nullptr, Z1i, W2, 0, 1, part, nwg, nullptr));
