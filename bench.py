@@ -1,0 +1,230 @@
+"""Benchmark: systems solved per second by block GCRO-DR on one MI355X.
+
+One step = one whole sequence of related systems solved from scratch (fresh
+recycle space, X0 = 0), which exercises every part of the restart cycle:
+recycle import, block residual QR, fused SpMM/BCGS2/CholQR sweeps, block
+Householder least squares, solution/residual update, true residual and the
+harmonic-Ritz refresh.
+
+Default workload: 3D convection-diffusion, 7-point upwind stencil on a 128^3
+grid (n = 2,097,152), convection (10,5,2)(1 + 0.5 sin 2 pi x), diffusion scaled
+by 1 + 0.02 i over a sequence of 10 systems, p = 8 right-hand sides U[-1,1],
+m = 10, k = 20, relative residual 1e-8, plain FP64.  Inputs are resident in
+HBM before the timed region starts.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "systems solved/s at rel.res 1e-8; Arnoldi HBM GB/s vs peak; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+ARNOLDI = ("spmm_dot", "proj_dot", "proj_gram")
+KERNEL_SYMBOL = {"spmm_dot": "k_spmm_dot", "proj_dot": "k_proj_dot", "proj_gram": "k_proj_gram"}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "bgcr_internal.h"):
+        with open(os.path.join(ROOT, "paper_1604_01713_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload):
+    """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get(workload, {}).get(kernel)
+        if not e or e.get("kernel_source_hash") != kernel_source_hash():
+            return None
+        return e.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(systems, m, k, tol, cycles_per_system):
+    """The FP64 oracle on a bounded sample: the first system of the sequence
+    for two restart cycles (the block GMRES cycle without U, then one cycle
+    with recycling), timed on the host cores; scaled to systems/s with the
+    GPU run's mean cycles per system."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([int(t.get("num_threads", 1)) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    A, B, X0 = systems[0]
+    t0 = time.perf_counter()
+    X, U, st = oracle.solve(A, B, X0, tol, m, k, max_cycles=2)
+    dt = time.perf_counter() - t0
+    per_cycle = dt / max(1, st["cycles"])
+    value = 1.0 / (per_cycle * cycles_per_system)
+    return {"value": value, "unit": "systems/s", "cores": cores, "kind": "oracle",
+            "sample": f"first system of the sequence, {st['cycles']} restart cycles in {dt:.1f} s "
+                      f"({per_cycle:.2f} s/cycle), scaled by the GPU run's {cycles_per_system:.1f} cycles/system",
+            "seconds_per_cycle": per_cycle}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--nsys", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import problems
+    import paper_1604_01713_amd as bg
+
+    bg.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    t0 = time.time()
+    w = problems.cfg2(N=args.grid, nsys=args.nsys)
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    n = systems[0][0].shape[0]
+    nnz = systems[0][0].nnz
+    log(f"[bench] generated {len(systems)} systems n={n} nnz={nnz} in {time.time() - t0:.1f}s")
+    dA = [bg.DeviceCSR.from_scipy(A, dev) for (A, _, _) in systems]
+    dB = [torch.from_numpy(B).to(dev) for (_, B, _) in systems]
+    dX = [torch.zeros_like(b) for b in dB]
+    torch.cuda.synchronize()
+    workload = f"convdiff3d_{args.grid}^3_seq{args.nsys}_p{w.p}_m{w.m}_k{w.k}"
+
+    def one_step(profile):
+        seq = bg.Sequence(n, w.p, w.m, w.k, max_cycles=2000)
+        if profile:
+            seq.set_profiling(True)
+        lat, cyc, steps, stats = [], [], [], []
+        for i in range(len(systems)):
+            dX[i].zero_()
+            ts = time.perf_counter()
+            st = seq.solve(dA[i], dB[i], dX[i], w.tol)
+            lat.append(time.perf_counter() - ts)
+            if st.status != 0:
+                raise RuntimeError(f"system {i}: {st.as_dict()}")
+            cyc.append(st.cycles)
+            steps.append(st.block_steps)
+            stats.append(st.as_dict())
+        prof = seq.profile() if profile else None
+        seq.release()
+        return lat, cyc, steps, stats, prof
+
+    for wi in range(args.warmup):
+        lat, cyc, steps, _, _ = one_step(False)
+        log(f"[bench] warmup {wi}: {sum(lat):.2f}s cycles/system={cyc}")
+
+    profile = not args.no_profile
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    all_lat, all_cyc, all_steps, prof_sum, last_stats = [], [], [], None, None
+    for si in range(args.steps):
+        lat, cyc, steps, stats, prof = one_step(profile)
+        all_lat += lat
+        all_cyc += cyc
+        all_steps += steps
+        last_stats = stats
+        if prof:
+            if prof_sum is None:
+                prof_sum = {k_: dict(v) for k_, v in prof.items()}
+            else:
+                for k_, v in prof.items():
+                    for f in v:
+                        prof_sum[k_][f] += v[f]
+        log(f"[bench] step {si}: {sum(lat):.2f}s cycles/system={cyc}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    nsolved = args.steps * len(systems)
+    value = nsolved / elapsed
+
+    # independent FP64 check of the last step's solutions on the host
+    worst = 0.0
+    for i, (A, B, _) in enumerate(systems):
+        Xg = dX[i].cpu().numpy()
+        worst = max(worst, float(np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)))
+
+    roof = None
+    arnoldi = None
+    if prof_sum:
+        dom = max(ARNOLDI, key=lambda c: prof_sum[c]["ms"])
+        d = prof_sum[dom]
+        ach = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] > 0 else 0.0
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": load_traffic(dom, workload),
+                "kernel": KERNEL_SYMBOL[dom], "launches": d["launches"],
+                "avg_launch_us": round(1e3 * d["ms"] / max(1, d["launches"]), 2),
+                "alg_bytes_per_launch": round(d["bytes"] / max(1, d["launches"]))}
+        tb = sum(prof_sum[c]["bytes"] for c in ARNOLDI)
+        tm = sum(prof_sum[c]["ms"] for c in ARNOLDI)
+        allms = sum(v["ms"] for v in prof_sum.values())
+        arnoldi = {"alg_GBs": round(tb / (tm * 1e-3) / 1e9, 1) if tm > 0 else 0.0,
+                   "frac": round(tb / (tm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tm > 0 else 0.0,
+                   "share_of_kernel_time": round(tm / allms, 3) if allms > 0 else 0.0,
+                   "kernel_ms": {c: round(v["ms"], 1) for c, v in prof_sum.items()}}
+
+    lat_sorted = np.sort(np.array(all_lat))
+    cps = float(np.mean(all_cyc))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on a bounded sample ...")
+        cpu = cpu_baseline(systems, w.m, w.k, w.tol, cps)
+        cpu.pop("seconds_per_cycle", None)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "systems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": n, "nnz": nnz, "systems": len(systems), "p": w.p, "m": w.m,
+                   "k": w.k, "tol": w.tol, "precision": "plain FP64"},
+        "p50_latency_s": round(float(np.percentile(lat_sorted, 50)), 4),
+        "p99_latency_s": round(float(np.percentile(lat_sorted, 99)), 4),
+        "cycles_per_system": round(cps, 2),
+        "block_steps_per_system": round(float(np.mean(all_steps)), 2),
+        "max_rel_res_fp64_check": worst,
+        "arnoldi_hbm": arnoldi,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -143,6 +143,31 @@ int bgcr_get_cycle_log(const bgcr_sequence* s, int32_t* steps, double* rel_res,
 int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* W,
               void* hip_stream);
 
+/* Kernel classes of the per-kernel profile. */
+typedef enum {
+    BGCR_K_SPMM_DOT = 0,     /* Arnoldi sweep 1: block SpMM + first block-CGS dots */
+    BGCR_K_PROJ_DOT = 1,     /* Arnoldi sweep 2: second block-CGS pass */
+    BGCR_K_PROJ_GRAM = 2,    /* Arnoldi sweep 3: W'' = W - Q S and its Gram */
+    BGCR_K_SMALL = 3,        /* partial reductions, Cholesky, block-Householder LSQ */
+    BGCR_K_COMBINE = 4,      /* basis updates: solution, residual, recycle refresh */
+    BGCR_K_RESIDUAL = 5,     /* FP64 true residual B - A X */
+    BGCR_K_TSDOT = 6,        /* other tall-skinny products (CholQR of R, recycle dots) */
+    BGCR_K_SPMM = 7,         /* plain block SpMM (recycle import A U) */
+    BGCR_K_NCLASS = 8
+} bgcr_kernel_class;
+
+/* Turn per-kernel timing on (1) or off (0) and reset the counters.  When on,
+ * every launch of the sequence is bracketed by HIP events on its stream and
+ * its algorithmic HBM bytes are counted (block steps skipped after an early
+ * exit of a cycle are not counted). */
+int bgcr_set_profiling(bgcr_sequence* s, int on);
+
+/* Accumulated profile since the last bgcr_set_profiling: per kernel class,
+ * total milliseconds, algorithmic bytes and launches (host arrays of nclass
+ * entries, any may be NULL). */
+int bgcr_get_profile(const bgcr_sequence* s, double* ms, double* bytes, int64_t* launches,
+                     int32_t nclass);
+
 /* Human-readable text of a status code (static storage). */
 const char* bgcr_strerror(int status);
 

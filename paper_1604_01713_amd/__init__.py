@@ -17,6 +17,7 @@ __all__ = [
     "BGCR_MIXED_FP32", "BgcrError", "bgcr_params", "bgcr_csr", "bgcr_stats", "lib", "LIB_PATH",
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_strerror",
+    "bgcr_set_profiling", "bgcr_get_profile", "KERNEL_CLASSES",
     "DeviceCSR", "Sequence", "EXPORTED_SYMBOLS",
 ]
 
@@ -36,8 +37,12 @@ BGCR_MIXED_FP32 = 1
 
 EXPORTED_SYMBOLS = [
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
-    "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_strerror",
+    "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_set_profiling",
+    "bgcr_get_profile", "bgcr_strerror",
 ]
+
+# kernel classes of the per-kernel profile (bgcr_kernel_class)
+KERNEL_CLASSES = ["spmm_dot", "proj_dot", "proj_gram", "small", "combine", "residual", "tsdot", "spmm"]
 
 
 class bgcr_params(ctypes.Structure):
@@ -90,10 +95,14 @@ def lib():
         L.bgcr_get_cycle_log.argtypes = [c.c_void_p, c.POINTER(c.c_int32), c.POINTER(c.c_double), c.c_int32,
                                          c.POINTER(c.c_int32)]
         L.bgcr_spmm.argtypes = [c.POINTER(bgcr_csr), c.c_int32, c.c_int32, c.c_void_p, c.c_void_p, c.c_void_p]
+        L.bgcr_set_profiling.argtypes = [c.c_void_p, c.c_int]
+        L.bgcr_get_profile.argtypes = [c.c_void_p, c.POINTER(c.c_double), c.POINTER(c.c_double),
+                                       c.POINTER(c.c_int64), c.c_int32]
         L.bgcr_strerror.argtypes = [c.c_int]
         L.bgcr_strerror.restype = c.c_char_p
         for name in ["bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_recycle_dim", "bgcr_get_recycle",
-                     "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm"]:
+                     "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_set_profiling",
+                     "bgcr_get_profile"]:
             getattr(L, name).restype = c.c_int
         _lib = L
     return _lib
@@ -174,6 +183,20 @@ def bgcr_spmm(A: "DeviceCSR", V, W, stream=None):
            "bgcr_spmm")
 
 
+def bgcr_set_profiling(seq, on: bool):
+    _check(lib().bgcr_set_profiling(seq, int(bool(on))), "bgcr_set_profiling")
+
+
+def bgcr_get_profile(seq):
+    """{class: {"ms": total ms, "bytes": algorithmic bytes, "launches": count}}"""
+    nc = len(KERNEL_CLASSES)
+    ms = (ctypes.c_double * nc)()
+    by = (ctypes.c_double * nc)()
+    ln = (ctypes.c_int64 * nc)()
+    _check(lib().bgcr_get_profile(seq, ms, by, ln, nc), "bgcr_get_profile")
+    return {name: {"ms": ms[i], "bytes": by[i], "launches": ln[i]} for i, name in enumerate(KERNEL_CLASSES)}
+
+
 class DeviceCSR:
     """CSR matrix resident on the device (int32 indices, FP64/complex128 values)."""
 
@@ -219,6 +242,12 @@ class Sequence:
 
     def cycle_log(self):
         return bgcr_get_cycle_log(self.handle)
+
+    def set_profiling(self, on=True):
+        bgcr_set_profiling(self.handle, on)
+
+    def profile(self):
+        return bgcr_get_profile(self.handle)
 
     def footprint(self, nnz):
         return bgcr_footprint_bytes(self.params, self.n, nnz)

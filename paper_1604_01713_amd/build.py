@@ -20,12 +20,13 @@ LIB = os.path.join(HERE, "libbgcr.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("BGCR_OFFLOAD_ARCH", "gfx950")
 
-HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
+HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-fcx-limited-range",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", INCLUDE, "-I", CSRC]
-CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-march=x86-64-v3", "-I", INCLUDE, "-I", CSRC]
+# complex products without the NaN-recovery path (operands are finite and checked)
+CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-march=x86-64-v3", "-fcx-limited-range", "-I", INCLUDE, "-I", CSRC]
 
-HIP_SOURCES = ["kernels.hip", "solver.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_mfma.hip", "solver.cpp"]
 CXX_SOURCES = ["dense.cpp"]
 
 

@@ -88,10 +88,11 @@ struct Launch {
                                const Ctl* ctl);
     // W' = W - Q S (S optional) then W' = W' Rmul (optional); store W' (optional);
     // partials [Q^H W' (dot_q)] [W'^H W' (gram)]
+    // kind: 1 = Arnoldi sweep 2 (k_proj_dot), 2 = Arnoldi sweep 3 (k_proj_gram), 0 = other (k_tsdot)
     static hipError_t update_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q,
                                  int nq, const A* S, const A* Rmul, T* Wout, int dot_q, int gram,
-                                 A* part, int nwg, const Ctl* ctl);
-    // out_o (+)= sum_i in_i coef[i][o]   (coef: [nin][nout][P][P], FP64/complex128)
+                                 A* part, int nwg, const Ctl* ctl, int kind = 0);
+    // out_o (+)= sum_i in_i coef[i][o]   (coef layout [nin][P][nout][P], FP64/complex128)
     template <class TO>
     static hipError_t combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin,
                               const BlockPtrs& out, int nout, const A* coef, int accumulate);
@@ -108,16 +109,30 @@ template <class TA, class TR>
 hipError_t residual(hipStream_t st, int P, int64_t n, const int* rp, const int* ci, const TA* av,
                     const TA* B, int64_t ldb, const TA* X, TR* Rout, double* part, int nwg);
 
+// small kernels read a reduced P x P Gram matrix
 template <class A>
-hipError_t cholqr_first(hipStream_t st, int P, const A* part, int nwg, int nout, int off, A* Z1,
-                        A* Z1inv, Ctl* ctl);
+hipError_t cholqr_first(hipStream_t st, int P, const A* gram, A* Z1, A* Z1inv, Ctl* ctl);
 template <class A>
-hipError_t cholqr_second(hipStream_t st, int P, const A* part, int nwg, int nout, int off,
-                         const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl);
+hipError_t cholqr_second(hipStream_t st, int P, const A* gram, const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl);
 template <class A>
-hipError_t step_small(hipStream_t st, int P, const A* gpart, int nwg, int gnout, int goff,
-                      const A* S, int KP, int j, int m, A* H, A* F, A* Rh, A* QH, A* g,
-                      A* RinvAll, double* rho, Ctl* ctl, double thresh);
+hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, int KP, int j, int m, A* H, A* F,
+                      A* Rh, A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl, double thresh);
+
+// matrix-core versions of the three Arnoldi sweeps (real FP64/FP32 storage,
+// P = 8 or 16); hipErrorNotSupported for other shapes.  nwg workgroups of
+// 64-row tiles (mfma_nwg gives the default).
+int mfma_nwg(int64_t n);
+hipError_t i_minus(hipStream_t st, const double* M, double* out, int P);
+template <class T>
+hipError_t mfma_spmm_dot(hipStream_t st, int P, int64_t n, const int* rp, const int* ci, const T* av, const T* Vin,
+                         const double* Rinv, T* Vout, T* Wout, const BlockPtrs& Q, int nq, double* part,
+                         const Ctl* ctl, int nwg);
+template <class T>
+hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
+                         double* part, const Ctl* ctl, int nwg);
+template <class T>
+hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
+                          const double* S, T* Wout, double* part, const Ctl* ctl, int nwg);
 
 hipError_t cast_values(hipStream_t st, const double* in, float* out, int64_t nnz);
 template <class TI, class TO>

@@ -204,59 +204,81 @@ static void givens(cd f, cd g, double& c, cd& s) {
     s = (f / af) * std::conj(g) / r;
 }
 
+// Complex Schur form by Householder reduction to Hessenberg form and the
+// explicitly shifted QR iteration (Wilkinson shift, exceptional shift every
+// 11th iteration without deflation).  T is kept row-major and Z transposed so
+// that every long loop runs over contiguous memory.
 Schur schur(const Mat& A0) {
     const int n = A0.r;
     Schur S;
-    S.T = A0;
-    S.Z = Mat::eye(n);
-    Mat& T = S.T;
-    Mat& Z = S.Z;
     S.lam.assign(n, cd(0.0, 0.0));
+    S.T = Mat(n, n);
+    S.Z = Mat(n, n);
     if (n == 0) {
         S.ok = true;
         return S;
     }
-    for (const cd& v : T.a)
-        if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return S;
-    // Hessenberg reduction by Householder reflections
-    std::vector<cd> v;
+    std::vector<cd> T((size_t)n * n), Zt((size_t)n * n, cd(0.0, 0.0));  // T[i*n+j], Zt[j*n+i] = Z(i, j)
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const cd v = A0(i, j);
+            if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return S;
+            T[(size_t)i * n + j] = v;
+        }
+    for (int i = 0; i < n; ++i) Zt[(size_t)i * n + i] = 1.0;
+    auto Tr = [&](int i) { return &T[(size_t)i * n]; };
+    auto Zr = [&](int j) { return &Zt[(size_t)j * n]; };
+    std::vector<cd> v, w(n);
     for (int k = 0; k + 2 < n; ++k) {
         const int len = n - k - 1;
         std::vector<cd> x(len);
-        for (int i = 0; i < len; ++i) x[i] = T(k + 1 + i, k);
+        for (int i = 0; i < len; ++i) x[i] = Tr(k + 1 + i)[k];
         const double vv = house(x.data(), len, v);
         if (vv == 0.0) continue;
         const double f = 2.0 / vv;
-        for (int j = k; j < n; ++j) {
-            cd w = 0.0;
-            for (int i = 0; i < len; ++i) w += std::conj(v[i]) * T(k + 1 + i, j);
-            w *= f;
-            for (int i = 0; i < len; ++i) T(k + 1 + i, j) -= v[i] * w;
+        // left: rows k+1.., w = v^H T_sub, T_sub -= f v w
+        std::fill(w.begin(), w.end(), cd(0.0, 0.0));
+        for (int i = 0; i < len; ++i) {
+            const cd cv = std::conj(v[i]);
+            const cd* row = Tr(k + 1 + i);
+            for (int j = k; j < n; ++j) w[j] += cv * row[j];
         }
+        for (int i = 0; i < len; ++i) {
+            const cd fv = f * v[i];
+            cd* row = Tr(k + 1 + i);
+            for (int j = k; j < n; ++j) row[j] -= fv * w[j];
+        }
+        // right: columns k+1.. of every row, and of Z
         for (int i = 0; i < n; ++i) {
-            cd w = 0.0;
-            for (int l = 0; l < len; ++l) w += T(i, k + 1 + l) * v[l];
-            w *= f;
-            for (int l = 0; l < len; ++l) T(i, k + 1 + l) -= w * std::conj(v[l]);
+            cd* row = Tr(i) + k + 1;
+            cd dot = 0.0;
+            for (int l = 0; l < len; ++l) dot += row[l] * v[l];
+            dot *= f;
+            for (int l = 0; l < len; ++l) row[l] -= dot * std::conj(v[l]);
         }
-        for (int i = 0; i < n; ++i) {
-            cd w = 0.0;
-            for (int l = 0; l < len; ++l) w += Z(i, k + 1 + l) * v[l];
-            w *= f;
-            for (int l = 0; l < len; ++l) Z(i, k + 1 + l) -= w * std::conj(v[l]);
+        // Z <- Z H: Zt rows k+1.. updated with Zt_sub -= f v^* (v^T Zt_sub)
+        std::fill(w.begin(), w.end(), cd(0.0, 0.0));
+        for (int l = 0; l < len; ++l) {
+            const cd vl = v[l];
+            const cd* zr = Zr(k + 1 + l);
+            for (int i = 0; i < n; ++i) w[i] += vl * zr[i];
         }
-        for (int i = k + 2; i < n; ++i) T(i, k) = 0.0;
+        for (int l = 0; l < len; ++l) {
+            const cd fc = f * std::conj(v[l]);
+            cd* zr = Zr(k + 1 + l);
+            for (int i = 0; i < n; ++i) zr[i] -= fc * w[i];
+        }
+        for (int i = k + 2; i < n; ++i) Tr(i)[k] = 0.0;
     }
-    // shifted QR iteration (Wilkinson shift, exceptional shifts on stagnation)
     int hi = n - 1, iter = 0, total = 0;
     std::vector<double> cs(n);
     std::vector<cd> ss(n);
     while (hi > 0) {
         int lo = hi;
         while (lo > 0) {
-            const double tst = std::abs(T(lo - 1, lo - 1)) + std::abs(T(lo, lo));
-            if (std::abs(T(lo, lo - 1)) <= EPS * (tst > 0.0 ? tst : 1.0)) {
-                T(lo, lo - 1) = 0.0;
+            const double tst = std::abs(Tr(lo - 1)[lo - 1]) + std::abs(Tr(lo)[lo]);
+            if (std::abs(Tr(lo)[lo - 1]) <= EPS * (tst > 0.0 ? tst : 1.0)) {
+                Tr(lo)[lo - 1] = 0.0;
                 break;
             }
             --lo;
@@ -270,46 +292,58 @@ Schur schur(const Mat& A0) {
         ++iter;
         cd mu;
         if (iter % 11 == 0) {
-            mu = T(hi, hi) + 0.75 * std::abs(T(hi, hi - 1));
+            mu = Tr(hi)[hi] + 0.75 * std::abs(Tr(hi)[hi - 1]);
         } else {
-            const cd a = T(hi - 1, hi - 1), b = T(hi - 1, hi), c = T(hi, hi - 1), d = T(hi, hi);
+            const cd a = Tr(hi - 1)[hi - 1], b = Tr(hi - 1)[hi], c = Tr(hi)[hi - 1], d = Tr(hi)[hi];
             const cd half = 0.5 * (a - d);
             const cd disc = std::sqrt(half * half + b * c);
             const cd m1 = 0.5 * (a + d) + disc, m2 = 0.5 * (a + d) - disc;
             mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
         }
-        for (int k = lo; k <= hi; ++k) T(k, k) -= mu;
+        for (int k = lo; k <= hi; ++k) Tr(k)[k] -= mu;
         for (int k = lo; k < hi; ++k) {
             double c;
             cd s;
-            givens(T(k, k), T(k + 1, k), c, s);
+            givens(Tr(k)[k], Tr(k + 1)[k], c, s);
             cs[k] = c;
             ss[k] = s;
+            cd* r0 = Tr(k);
+            cd* r1 = Tr(k + 1);
+            const cd sc = -std::conj(s);
             for (int j = k; j < n; ++j) {
-                const cd x = T(k, j), y = T(k + 1, j);
-                T(k, j) = c * x + s * y;
-                T(k + 1, j) = -std::conj(s) * x + c * y;
+                const cd x = r0[j], y = r1[j];
+                r0[j] = c * x + s * y;
+                r1[j] = sc * x + c * y;
             }
-            T(k + 1, k) = 0.0;
+            r1[k] = 0.0;
         }
         for (int k = lo; k < hi; ++k) {
             const double c = cs[k];
-            const cd s = ss[k];
+            const cd s = ss[k], scj = std::conj(s);
             const int rmax = std::min(k + 2, hi);
             for (int i = 0; i <= rmax; ++i) {
-                const cd x = T(i, k), y = T(i, k + 1);
-                T(i, k) = c * x + std::conj(s) * y;
-                T(i, k + 1) = -s * x + c * y;
+                cd* row = Tr(i);
+                const cd x = row[k], y = row[k + 1];
+                row[k] = c * x + scj * y;
+                row[k + 1] = -s * x + c * y;
             }
+            cd* z0 = Zr(k);
+            cd* z1 = Zr(k + 1);
             for (int i = 0; i < n; ++i) {
-                const cd x = Z(i, k), y = Z(i, k + 1);
-                Z(i, k) = c * x + std::conj(s) * y;
-                Z(i, k + 1) = -s * x + c * y;
+                const cd x = z0[i], y = z1[i];
+                z0[i] = c * x + scj * y;
+                z1[i] = -s * x + c * y;
             }
         }
-        for (int k = lo; k <= hi; ++k) T(k, k) += mu;
+        for (int k = lo; k <= hi; ++k) Tr(k)[k] += mu;
     }
-    for (int i = 0; i < n; ++i) S.lam[i] = T(i, i);
+    for (int i = 0; i < n; ++i) {
+        S.lam[i] = Tr(i)[i];
+        for (int j = 0; j < n; ++j) {
+            S.T(i, j) = Tr(i)[j];
+            S.Z(i, j) = Zr(j)[i];
+        }
+    }
     S.ok = true;
     return S;
 }
@@ -342,6 +376,310 @@ std::vector<cd> schur_eigvec(const Schur& S, int idx) {
     if (nr > 0.0)
         for (cd& v : y) v /= nr;
     return y;
+}
+
+// ---------------------------------------------------------------------------
+// eigenvalues (window-restricted QR) + inverse iteration
+// ---------------------------------------------------------------------------
+static bool eig_real_francis(std::vector<double>& H, int n, std::vector<cd>& lam) {
+    auto h = [&](int i, int j) -> double& { return H[(size_t)i * n + j]; };
+    double anorm = 0.0;
+    for (double v : H) anorm = std::max(anorm, std::fabs(v));
+    if (anorm == 0.0) anorm = 1.0;
+    int hi = n - 1, iter = 0, total = 0;
+    while (hi >= 0) {
+        if (hi == 0) {
+            lam[0] = h(0, 0);
+            break;
+        }
+        int lo = hi;
+        while (lo > 0) {
+            double s = std::fabs(h(lo - 1, lo - 1)) + std::fabs(h(lo, lo));
+            if (s == 0.0) s = anorm;
+            if (std::fabs(h(lo, lo - 1)) <= EPS * s) {
+                h(lo, lo - 1) = 0.0;
+                break;
+            }
+            --lo;
+        }
+        if (lo == hi) {
+            lam[hi] = h(hi, hi);
+            --hi;
+            iter = 0;
+            continue;
+        }
+        if (lo == hi - 1) {
+            const double a = h(hi - 1, hi - 1), b = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
+            const double p = 0.5 * (a - d), disc = p * p + b * c;
+            if (disc >= 0.0) {
+                const double r = std::sqrt(disc);
+                const double z = p >= 0.0 ? p + r : p - r;
+                lam[hi - 1] = d + z;
+                lam[hi] = z != 0.0 ? d - b * c / z : d + z;
+            } else {
+                const double r = std::sqrt(-disc);
+                lam[hi - 1] = cd(d + p, r);
+                lam[hi] = cd(d + p, -r);
+            }
+            hi -= 2;
+            iter = 0;
+            continue;
+        }
+        if (++total > 40 * n) return false;
+        ++iter;
+        double s, t;
+        if (iter % 10 == 0) {
+            // exceptional shift: a perturbed quadratic from the last subdiagonal entries
+            const double x = std::fabs(h(hi, hi - 1)) + std::fabs(h(hi - 1, hi - 2));
+            s = 1.5 * x + h(hi, hi);
+            t = x * x + h(hi, hi) * (1.5 * x);
+        } else {
+            s = h(hi - 1, hi - 1) + h(hi, hi);
+            t = h(hi - 1, hi - 1) * h(hi, hi) - h(hi - 1, hi) * h(hi, hi - 1);
+        }
+        // first column of H^2 - s H + t I at rows lo, lo+1, lo+2
+        double x = h(lo, lo) * h(lo, lo) + h(lo, lo + 1) * h(lo + 1, lo) - s * h(lo, lo) + t;
+        double y = h(lo + 1, lo) * (h(lo, lo) + h(lo + 1, lo + 1) - s);
+        double z = h(lo + 1, lo) * h(lo + 2, lo + 1);
+        for (int k = lo; k <= hi - 1; ++k) {
+            const int nr = (k < hi - 1) ? 3 : 2;  // reflector length
+            double v0 = x, v1 = y, v2 = nr == 3 ? z : 0.0;
+            const double al = std::sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+            if (al > 0.0) {
+                const double alpha = v0 >= 0.0 ? -al : al;
+                v0 -= alpha;
+                const double vv = v0 * v0 + v1 * v1 + v2 * v2;
+                if (vv > 0.0) {
+                    const double tau = 2.0 / vv;
+                    const int c0 = std::max(lo, k - 1);
+                    for (int j = c0; j <= hi; ++j) {
+                        double w = v0 * h(k, j) + v1 * h(k + 1, j) + (nr == 3 ? v2 * h(k + 2, j) : 0.0);
+                        w *= tau;
+                        h(k, j) -= w * v0;
+                        h(k + 1, j) -= w * v1;
+                        if (nr == 3) h(k + 2, j) -= w * v2;
+                    }
+                    const int r1 = std::min(k + 3, hi);
+                    for (int i = lo; i <= r1; ++i) {
+                        double w = v0 * h(i, k) + v1 * h(i, k + 1) + (nr == 3 ? v2 * h(i, k + 2) : 0.0);
+                        w *= tau;
+                        h(i, k) -= w * v0;
+                        h(i, k + 1) -= w * v1;
+                        if (nr == 3) h(i, k + 2) -= w * v2;
+                    }
+                }
+            }
+            if (k > lo) {
+                h(k + 1, k - 1) = 0.0;
+                if (nr == 3) h(k + 2, k - 1) = 0.0;
+            }
+            if (k < hi - 1) {
+                x = h(k + 1, k);
+                y = h(k + 2, k);
+                z = (k < hi - 2) ? h(k + 3, k) : 0.0;
+            }
+        }
+    }
+    return true;
+}
+
+static bool eig_complex_window(std::vector<cd>& T, int n, std::vector<cd>& lam) {
+    auto Tr = [&](int i) { return &T[(size_t)i * n]; };
+    int hi = n - 1, iter = 0, total = 0;
+    std::vector<double> cs(n);
+    std::vector<cd> ss(n);
+    while (hi > 0) {
+        int lo = hi;
+        while (lo > 0) {
+            const double tst = std::abs(Tr(lo - 1)[lo - 1]) + std::abs(Tr(lo)[lo]);
+            if (std::abs(Tr(lo)[lo - 1]) <= EPS * (tst > 0.0 ? tst : 1.0)) {
+                Tr(lo)[lo - 1] = 0.0;
+                break;
+            }
+            --lo;
+        }
+        if (lo == hi) {
+            lam[hi] = Tr(hi)[hi];
+            --hi;
+            iter = 0;
+            continue;
+        }
+        if (++total > 60 * n) return false;
+        ++iter;
+        cd mu;
+        if (iter % 11 == 0) {
+            mu = Tr(hi)[hi] + 0.75 * std::abs(Tr(hi)[hi - 1]);
+        } else {
+            const cd a = Tr(hi - 1)[hi - 1], b = Tr(hi - 1)[hi], c = Tr(hi)[hi - 1], d = Tr(hi)[hi];
+            const cd half = 0.5 * (a - d);
+            const cd disc = std::sqrt(half * half + b * c);
+            const cd m1 = 0.5 * (a + d) + disc, m2 = 0.5 * (a + d) - disc;
+            mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+        }
+        for (int k = lo; k <= hi; ++k) Tr(k)[k] -= mu;
+        for (int k = lo; k < hi; ++k) {
+            double c;
+            cd s;
+            givens(Tr(k)[k], Tr(k + 1)[k], c, s);
+            cs[k] = c;
+            ss[k] = s;
+            cd* r0 = Tr(k);
+            cd* r1 = Tr(k + 1);
+            const cd sc = -std::conj(s);
+            for (int j = k; j <= hi; ++j) {
+                const cd x = r0[j], y = r1[j];
+                r0[j] = c * x + s * y;
+                r1[j] = sc * x + c * y;
+            }
+            r1[k] = 0.0;
+        }
+        for (int k = lo; k < hi; ++k) {
+            const double c = cs[k];
+            const cd s = ss[k], scj = std::conj(s);
+            const int rmax = std::min(k + 2, hi);
+            for (int i = lo; i <= rmax; ++i) {
+                cd* row = Tr(i);
+                const cd x = row[k], y = row[k + 1];
+                row[k] = c * x + scj * y;
+                row[k + 1] = -s * x + c * y;
+            }
+        }
+        for (int k = lo; k <= hi; ++k) Tr(k)[k] += mu;
+    }
+    if (n > 0) lam[0] = Tr(0)[0];
+    return true;
+}
+
+void EigSolver::compute(const Mat& A, bool real_input) {
+    n = A.r;
+    real = real_input;
+    ok = false;
+    lam.assign(n, cd(0.0, 0.0));
+    Hh.assign((size_t)n * n, cd(0.0, 0.0));
+    refl.assign(n, {});
+    reflvv.assign(n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const cd v = A(i, j);
+            if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return;
+            Hh[(size_t)i * n + j] = real ? cd(v.real(), 0.0) : v;
+        }
+    auto Hr = [&](int i) { return &Hh[(size_t)i * n]; };
+    std::vector<cd> w(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int len = n - k - 1;
+        std::vector<cd> x(len);
+        for (int i = 0; i < len; ++i) x[i] = Hr(k + 1 + i)[k];
+        std::vector<cd>& v = refl[k];
+        const double vv = house(x.data(), len, v);
+        reflvv[k] = vv;
+        if (vv == 0.0) continue;
+        const double f = 2.0 / vv;
+        std::fill(w.begin(), w.end(), cd(0.0, 0.0));
+        for (int i = 0; i < len; ++i) {
+            const cd cv = std::conj(v[i]);
+            const cd* row = Hr(k + 1 + i);
+            for (int j = k; j < n; ++j) w[j] += cv * row[j];
+        }
+        for (int i = 0; i < len; ++i) {
+            const cd fv = f * v[i];
+            cd* row = Hr(k + 1 + i);
+            for (int j = k; j < n; ++j) row[j] -= fv * w[j];
+        }
+        for (int i = 0; i < n; ++i) {
+            cd* row = Hr(i) + k + 1;
+            cd dot = 0.0;
+            for (int l = 0; l < len; ++l) dot += row[l] * v[l];
+            dot *= f;
+            for (int l = 0; l < len; ++l) row[l] -= dot * std::conj(v[l]);
+        }
+        for (int i = k + 2; i < n; ++i) Hr(i)[k] = 0.0;
+    }
+    hnorm = 0.0;
+    for (const cd& v : Hh) hnorm = std::max(hnorm, std::abs(v));
+    if (real) {
+        std::vector<double> H((size_t)n * n);
+        for (size_t e = 0; e < H.size(); ++e) H[e] = Hh[e].real();
+        ok = eig_real_francis(H, n, lam);
+    } else {
+        std::vector<cd> T = Hh;
+        ok = eig_complex_window(T, n, lam);
+    }
+}
+
+std::vector<cd> EigSolver::vector_for(cd lambda, const std::vector<std::vector<cd>>& against) const {
+    // inverse iteration on the Hessenberg matrix with a slightly perturbed shift
+    const double pert = std::max(hnorm, 1e-300) * 1e-13;
+    const cd sh = lambda + cd(pert, 0.0);
+    std::vector<cd> U((size_t)n * n);
+    for (size_t e = 0; e < U.size(); ++e) U[e] = Hh[e];
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] -= sh;
+    // Hessenberg LU with partial pivoting (only rows k, k+1 compete); record ops
+    std::vector<int> swp(n, 0);
+    std::vector<cd> mult(n, cd(0.0, 0.0));
+    for (int k = 0; k + 1 < n; ++k) {
+        cd* rk = &U[(size_t)k * n];
+        cd* rk1 = &U[(size_t)(k + 1) * n];
+        if (std::abs(rk1[k]) > std::abs(rk[k])) {
+            for (int j = k; j < n; ++j) std::swap(rk[j], rk1[j]);
+            swp[k] = 1;
+        }
+        if (std::abs(rk[k]) == 0.0) rk[k] = pert;
+        const cd l = rk1[k] / rk[k];
+        mult[k] = l;
+        if (l != cd(0.0, 0.0))
+            for (int j = k; j < n; ++j) rk1[j] -= l * rk[j];
+    }
+    if (std::abs(U[(size_t)(n - 1) * n + n - 1]) == 0.0) U[(size_t)(n - 1) * n + n - 1] = pert;
+    auto solve = [&](std::vector<cd>& b) {
+        for (int k = 0; k + 1 < n; ++k) {
+            if (swp[k]) std::swap(b[k], b[k + 1]);
+            b[k + 1] -= mult[k] * b[k];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            const cd* row = &U[(size_t)i * n];
+            cd s = b[i];
+            for (int j = i + 1; j < n; ++j) s -= row[j] * b[j];
+            b[i] = s / row[i];
+        }
+    };
+    auto orth_normalize = [&](std::vector<cd>& x) {
+        for (const auto& a : against) {
+            cd d = 0.0;
+            for (int i = 0; i < n; ++i) d += std::conj(a[i]) * x[i];
+            for (int i = 0; i < n; ++i) x[i] -= d * a[i];
+        }
+        double nr = 0.0;
+        for (const cd& v : x) nr += std::norm(v);
+        nr = std::sqrt(nr);
+        if (nr > 0.0)
+            for (cd& v : x) v /= nr;
+    };
+    std::vector<cd> x(n);
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    for (int i = 0; i < n; ++i) {
+        st ^= st << 13;
+        st ^= st >> 7;
+        st ^= st << 17;
+        x[i] = cd(0.5 + (double)(st % 1000003) / 1000003.0, 0.0);
+    }
+    // vectors of nearby eigenvalues are carried in the Hessenberg basis
+    orth_normalize(x);
+    for (int it = 0; it < 3; ++it) {
+        solve(x);
+        orth_normalize(x);
+    }
+    // back to the basis of A: x <- H_0 H_1 ... H_{n-3} x
+    for (int k = n - 3; k >= 0; --k) {
+        if (reflvv[k] == 0.0) continue;
+        const std::vector<cd>& v = refl[k];
+        const int len = n - k - 1;
+        cd d = 0.0;
+        for (int l = 0; l < len; ++l) d += std::conj(v[l]) * x[k + 1 + l];
+        d *= 2.0 / reflvv[k];
+        for (int l = 0; l < len; ++l) x[k + 1 + l] -= d * v[l];
+    }
+    return x;
 }
 
 Selection select_ritz(const std::vector<cd>& theta, int k, bool largest, bool real) {

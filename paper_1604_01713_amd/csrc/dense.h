@@ -55,6 +55,26 @@ Schur schur(const Mat& A);
 // eigenvector of A for eigenvalue index i of the Schur form (unit 2-norm)
 std::vector<cd> schur_eigvec(const Schur& S, int i);
 
+// Eigenvalues by Hessenberg reduction and shifted QR restricted to the active
+// window (real Francis double shift for real input, complex single shift
+// otherwise), then eigenvectors for chosen eigenvalues only, by inverse
+// iteration on the Hessenberg matrix.
+struct EigSolver {
+    int n = 0;
+    bool real = true;
+    std::vector<cd> Hh;                 // Hessenberg form, row-major
+    std::vector<std::vector<cd>> refl;  // Householder vectors of the reduction
+    std::vector<double> reflvv;
+    std::vector<cd> lam;
+    double hnorm = 0.0;
+    bool ok = false;
+    // A: n x n; real selects the real double-shift path (A must be real)
+    void compute(const Mat& A, bool real_input);
+    // eigenvector for eigenvalue lambda (unit 2-norm, in the basis of A);
+    // `against`: vectors already chosen for nearby eigenvalues (kept apart)
+    std::vector<cd> vector_for(cd lambda, const std::vector<std::vector<cd>>& against) const;
+};
+
 // harmonic Ritz selection rules (Section 4.1): k values of smallest modulus
 // (largest with `largest`), order (|theta|, Re, Im, index), infinite or NaN
 // values never kept; `real` keeps a conjugate pair whole (k may grow by one)

@@ -110,12 +110,11 @@ __device__ inline void write_partials(const Items& it, A (&acc)[MAXI], A* red, A
 // W = (A Vin) Rinv and Vout = Vin Rinv for the rows of each tile; the dot
 // part accumulates [Q_0 .. Q_{nq-1}, Vout]^H W (Vout from the tile itself).
 template <class T, int P>
-__global__ __launch_bounds__(NT) void k_spmm_dot(int64_t n, const int* __restrict__ rp,
-                                                 const int* __restrict__ ci, const T* __restrict__ av,
-                                                 const T* __restrict__ Vin,
-                                                 const acc_t<T>* __restrict__ Rinv, T* Vout, T* Wout,
-                                                 BlockPtrs Q, int nq, int with_self,
-                                                 acc_t<T>* __restrict__ part, const Ctl* ctl) {
+__device__ __forceinline__ void spmm_dot_body(int64_t n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                              const T* __restrict__ av, const T* __restrict__ Vin,
+                                              const acc_t<T>* __restrict__ Rinv, T* Vout, T* Wout,
+                                              const BlockPtrs& Q, int nq, int with_self,
+                                              acc_t<T>* __restrict__ part, const Ctl* ctl) {
     using A = acc_t<T>;
     if (ctl && ctl->active == 0) return;
     constexpr int ROWS = NT / P;
@@ -182,16 +181,32 @@ __global__ __launch_bounds__(NT) void k_spmm_dot(int64_t n, const int* __restric
     write_partials(it, acc, raw, part, lw);
 }
 
+// sweep 1 of a block Arnoldi step
+template <class T, int P>
+__global__ __launch_bounds__(NT) void k_spmm_dot(int64_t n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                                 const T* __restrict__ av, const T* __restrict__ Vin,
+                                                 const acc_t<T>* __restrict__ Rinv, T* Vout, T* Wout, BlockPtrs Q,
+                                                 int nq, int with_self, acc_t<T>* __restrict__ part, const Ctl* ctl) {
+    spmm_dot_body<T, P>(n, rp, ci, av, Vin, Rinv, Vout, Wout, Q, nq, with_self, part, ctl);
+}
+
+// plain block SpMM W = A V (recycle import A U, standalone entry point)
+template <class T, int P>
+__global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int* __restrict__ rp, const int* __restrict__ ci,
+                                             const T* __restrict__ av, const T* __restrict__ Vin, T* Wout) {
+    BlockPtrs none;
+    spmm_dot_body<T, P>(n, rp, ci, av, Vin, nullptr, nullptr, Wout, none, 0, 0, nullptr, nullptr);
+}
+
 // ---------------------------------------------------------------------------
 // sweeps 2 and 3: W' = W - Q S (and/or W' = W Rmul), optional store, partial
 // Q^H W' and/or Gram W'^H W'
 // ---------------------------------------------------------------------------
 template <class T, int P>
-__global__ __launch_bounds__(NT) void k_update_dot(int64_t n, const T* __restrict__ Win, BlockPtrs Q,
-                                                   int nq, const acc_t<T>* __restrict__ S,
-                                                   const acc_t<T>* __restrict__ Rmul, T* Wout,
-                                                   int dot_q, int gram, acc_t<T>* __restrict__ part,
-                                                   const Ctl* ctl) {
+__device__ __forceinline__ void update_dot_body(int64_t n, const T* __restrict__ Win, const BlockPtrs& Q, int nq,
+                                                const acc_t<T>* __restrict__ S, const acc_t<T>* __restrict__ Rmul,
+                                                T* Wout, int dot_q, int gram, acc_t<T>* __restrict__ part,
+                                                const Ctl* ctl) {
     using A = acc_t<T>;
     if (ctl && ctl->active == 0) return;
     constexpr int ROWS = NT / P;
@@ -248,31 +263,70 @@ __global__ __launch_bounds__(NT) void k_update_dot(int64_t n, const T* __restric
     write_partials(it, acc, raw, part, lw);
 }
 
+#define BGCR_UPDATE_KERNEL(NAME)                                                                                   \
+    template <class T, int P>                                                                                      \
+    __global__ __launch_bounds__(NT) void NAME(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq,          \
+                                               const acc_t<T>* __restrict__ S, const acc_t<T>* __restrict__ Rmul,  \
+                                               T* Wout, int dot_q, int gram, acc_t<T>* __restrict__ part,           \
+                                               const Ctl* ctl) {                                                    \
+        update_dot_body<T, P>(n, Win, Q, nq, S, Rmul, Wout, dot_q, gram, part, ctl);                               \
+    }
+// sweep 2: second block-CGS pass, partial Q^H (W - Q S1)
+BGCR_UPDATE_KERNEL(k_proj_dot)
+// sweep 3: W'' = W - Q S stored, partial Gram of W''
+BGCR_UPDATE_KERNEL(k_proj_gram)
+// tall-skinny products outside the Arnoldi step (Gram/normalise of R, recycle dots)
+BGCR_UPDATE_KERNEL(k_tsdot)
+#undef BGCR_UPDATE_KERNEL
+
 // ---------------------------------------------------------------------------
 // out_o (+)= sum_i in_i coef[i][o]  (basis updates: solution, residual, recycle refresh)
 // ---------------------------------------------------------------------------
-template <class TI, class TO, int P>
+// One lane per row: the lane reads the P entries of its row of every input
+// block (a wave reads 64 consecutive rows: contiguous) and keeps the OC*P
+// outputs of its row in registers.  The coefficients are the same for every
+// row, so their loads are wave-uniform (scalar loads).  Layout of coef:
+// [nin][P][nout][P], i.e. for input i and its column a the nout*P
+// coefficients are contiguous.  Outputs are done in chunks of OC blocks.
+template <class TI, class TO, int P, int OC>
 __global__ __launch_bounds__(NT) void k_combine(int64_t n, BlockPtrs in, int nin, BlockPtrs out, int nout,
                                                 const acc_t<TI>* __restrict__ coef, int accumulate) {
     using A = acc_t<TI>;
-    constexpr int ROWS = NT / P;
-    const int t = threadIdx.x, r = t / P, b = t % P;
-    const int lw = logical_wg();
-    int64_t t0, t1;
-    tile_range((n + ROWS - 1) / ROWS, lw, t0, t1);
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t row = tile * ROWS + r;
-        if (row >= n) continue;
-        for (int o = 0; o < nout; ++o) {
-            TO* y = (TO*)out.p[o];
-            A v = accumulate ? widen(y[row * P + b]) : zero<A>();
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x; row < n; row += stride) {
+        for (int o0 = 0; o0 < nout; o0 += OC) {
+            A acc[OC * P];
+#pragma unroll
+            for (int e = 0; e < OC * P; ++e) acc[e] = zero<A>();
             for (int i = 0; i < nin; ++i) {
                 const TI* x = (const TI*)in.p[i] + row * P;
-                const A* cf = coef + ((int64_t)(i * nout + o) * P) * P + b;
+                A xv[P];
 #pragma unroll
-                for (int a = 0; a < P; ++a) v += widen(x[a]) * cf[a * P];
+                for (int a = 0; a < P; ++a) xv[a] = widen(x[a]);
+                const A* cf = coef + (int64_t)i * P * nout * P + (int64_t)o0 * P;
+#pragma unroll
+                for (int a = 0; a < P; ++a) {
+#pragma unroll
+                    for (int oo = 0; oo < OC; ++oo) {
+                        if (o0 + oo < nout) {
+#pragma unroll
+                            for (int b = 0; b < P; ++b) acc[oo * P + b] += xv[a] * cf[(int64_t)a * nout * P + oo * P + b];
+                        }
+                    }
+                }
             }
-            y[row * P + b] = narrow<TO>(v);
+#pragma unroll
+            for (int oo = 0; oo < OC; ++oo) {
+                if (o0 + oo < nout) {
+                    TO* y = (TO*)out.p[o0 + oo] + row * P;
+#pragma unroll
+                    for (int b = 0; b < P; ++b) {
+                        A v = acc[oo * P + b];
+                        if (accumulate) v += widen(y[b]);
+                        y[b] = narrow<TO>(v);
+                    }
+                }
+            }
         }
     }
 }
@@ -280,15 +334,33 @@ __global__ __launch_bounds__(NT) void k_combine(int64_t n, BlockPtrs in, int nin
 // ---------------------------------------------------------------------------
 // deterministic second-stage reduction
 // ---------------------------------------------------------------------------
+// out[o] = add[o] + sum_w part[w][o]: 16 outputs x 16 workgroup-groups per
+// block; each thread sums one residue class of w in order, then the 16 class
+// sums are added in order (deterministic).
 template <class A>
-__global__ void k_reduce(const A* __restrict__ part, int nwg, int nout, const A* __restrict__ add, A* out,
-                         const Ctl* ctl) {
+__global__ __launch_bounds__(256) void k_reduce(const A* __restrict__ part, int nwg, int nout,
+                                                const A* __restrict__ add, A* out, const Ctl* ctl) {
     if (ctl && ctl->active == 0) return;
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nout) return;
-    A s = add ? add[o] : zero<A>();
-    for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * nout + o];
-    out[o] = s;
+    __shared__ A red[256];
+    const int t = threadIdx.x;
+    const int o = blockIdx.x * 16 + (t % 16);
+    const int g = t / 16;
+    A s0 = zero<A>(), s1 = zero<A>();
+    if (o < nout) {
+        int w = g;
+        for (; w + 16 < nwg; w += 32) {
+            s0 += part[(int64_t)w * nout + o];
+            s1 += part[(int64_t)(w + 16) * nout + o];
+        }
+        if (w < nwg) s0 += part[(int64_t)w * nout + o];
+    }
+    red[t] = s0 + s1;
+    __syncthreads();
+    if (t < 16 && o < nout) {
+        A s = add ? add[o] : zero<A>();
+        for (int q = 0; q < 16; ++q) s += red[q * 16 + t];
+        out[o] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -389,10 +461,10 @@ __device__ void reduce_small(const A* part, int nwg, int nout, int off, A* out, 
 
 // first pass of CholQR of the cycle's starting block: Z1 = chol(Gram)
 template <class A, int P>
-__global__ void k_cholqr_first(const A* part, int nwg, int nout, int off, A* Z1, A* Z1inv, Ctl* ctl) {
+__global__ void k_cholqr_first(const A* gram, A* Z1, A* Z1inv, Ctl* ctl) {
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
     __shared__ int okf;
-    reduce_small(part, nwg, nout, off, Gs, P * P);
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) Gs[e] = gram[e];
     __syncthreads();
     if (threadIdx.x == 0) {
         okf = chol_upper(Gs, Rs, P);
@@ -417,12 +489,11 @@ __global__ void k_cholqr_first(const A* part, int nwg, int nout, int off, A* Z1,
 // second pass: Z2 = chol(Gram of R Z1^{-1}); Z = Z2 Z1; LSQ right-hand side
 // E Z (Algorithm 1) and the cycle control block are initialised here.
 template <class A, int P>
-__global__ void k_cholqr_second(const A* part, int nwg, int nout, int off, const A* Z1, A* Rinv0, A* g, int m,
-                                Ctl* ctl) {
+__global__ void k_cholqr_second(const A* gram, const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl) {
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
     __shared__ int okf;
     if (ctl->status != 0) return;
-    reduce_small(part, nwg, nout, off, Gs, P * P);
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) Gs[e] = gram[e];
     __syncthreads();
     if (threadIdx.x == 0) {
         okf = chol_upper(Gs, Rs, P);
@@ -459,9 +530,9 @@ __global__ void k_cholqr_second(const A* part, int nwg, int nout, int off, const
 // of block column j are accumulated into one 2P x 2P unitary QH_j that later
 // columns apply as a single matrix product.
 template <class A, int P>
-__global__ __launch_bounds__(NT) void k_step_small(const A* gpart, int nwg, int gnout, int goff, const A* S, int KP,
-                                                   int j, int m, A* H, A* F, A* Rh, A* QH, A* g, A* RinvAll,
-                                                   double* rho, Ctl* ctl, double thresh) {
+__global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, int KP, int j, int m, A* H, A* F,
+                                                   A* Rh, A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl,
+                                                   double thresh) {
     if (ctl->active == 0) return;
     constexpr int P2 = 2 * P;
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
@@ -471,7 +542,7 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gpart, int nwg, int 
     const int t = threadIdx.x;
     const int jc = j - 1;
     const int ldH = m * P;
-    reduce_small(gpart, nwg, gnout, goff, Gs, P * P);
+    for (int e = t; e < P * P; e += NT) Gs[e] = gram[e];
     __syncthreads();
     if (t == 0) {
         okf = chol_upper(Gs, Rs, P);
@@ -624,12 +695,16 @@ hipError_t Launch<T>::spmm_dot(hipStream_t st, int P, int64_t n, const int* rp, 
     const size_t lds = (size_t)NT * sizeof(A) + (size_t)P * P * sizeof(A) + (size_t)NT * sizeof(T) +
                        (size_t)(nq + with_self) * NT * sizeof(T);
     if ((nq + with_self) * P * P > MAXI * NT) return hipErrorInvalidValue;
-#define L(PP)                                                                                     \
-    {                                                                                             \
-        static std::once_flag fl;                                                                 \
-        std::call_once(fl, [] { allow_big_lds(k_spmm_dot<T, PP>); });                             \
-        hipLaunchKernelGGL((k_spmm_dot<T, PP>), dim3(nwg), dim3(NT), lds, st, n, rp, ci, av, Vin, \
-                           Rinv, Vout, Wout, Q, nq, with_self, part, ctl);                        \
+    const bool plain = !Rinv && !Vout && nq == 0 && !with_self;
+#define L(PP)                                                                                           \
+    {                                                                                                   \
+        static std::once_flag fl;                                                                       \
+        std::call_once(fl, [] { allow_big_lds(k_spmm_dot<T, PP>); allow_big_lds(k_spmm<T, PP>); });     \
+        if (plain)                                                                                      \
+            hipLaunchKernelGGL((k_spmm<T, PP>), dim3(nwg), dim3(NT), lds, st, n, rp, ci, av, Vin, Wout); \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_spmm_dot<T, PP>), dim3(nwg), dim3(NT), lds, st, n, rp, ci, av, Vin,    \
+                               Rinv, Vout, Wout, Q, nq, with_self, part, ctl);                          \
     }
     BGCR_DISPATCH_P(P, L)
 #undef L
@@ -639,17 +714,28 @@ hipError_t Launch<T>::spmm_dot(hipStream_t st, int P, int64_t n, const int* rp, 
 template <class T>
 hipError_t Launch<T>::update_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
                                  const A* S, const A* Rmul, T* Wout, int dot_q, int gram, A* part, int nwg,
-                                 const Ctl* ctl) {
+                                 const Ctl* ctl, int kind) {
     const size_t lds = (size_t)NT * sizeof(A) + (size_t)P * P * sizeof(A) +
                        (S ? (size_t)nq * P * P * sizeof(A) : 0) + (size_t)NT * sizeof(T) +
                        (size_t)nq * NT * sizeof(T);
     if ((dot_q ? nq * P * P : 0) + (gram ? P * P : 0) > MAXI * NT) return hipErrorInvalidValue;
-#define L(PP)                                                                                      \
-    {                                                                                              \
-        static std::once_flag fl;                                                                  \
-        std::call_once(fl, [] { allow_big_lds(k_update_dot<T, PP>); });                            \
-        hipLaunchKernelGGL((k_update_dot<T, PP>), dim3(nwg), dim3(NT), lds, st, n, Win, Q, nq, S, \
-                           Rmul, Wout, dot_q, gram, part, ctl);                                    \
+#define L(PP)                                                                                                 \
+    {                                                                                                         \
+        static std::once_flag fl;                                                                             \
+        std::call_once(fl, [] {                                                                               \
+            allow_big_lds(k_proj_dot<T, PP>);                                                                 \
+            allow_big_lds(k_proj_gram<T, PP>);                                                                \
+            allow_big_lds(k_tsdot<T, PP>);                                                                    \
+        });                                                                                                   \
+        if (kind == 1)                                                                                        \
+            hipLaunchKernelGGL((k_proj_dot<T, PP>), dim3(nwg), dim3(NT), lds, st, n, Win, Q, nq, S, Rmul,     \
+                               Wout, dot_q, gram, part, ctl);                                                 \
+        else if (kind == 2)                                                                                   \
+            hipLaunchKernelGGL((k_proj_gram<T, PP>), dim3(nwg), dim3(NT), lds, st, n, Win, Q, nq, S, Rmul,    \
+                               Wout, dot_q, gram, part, ctl);                                                 \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_tsdot<T, PP>), dim3(nwg), dim3(NT), lds, st, n, Win, Q, nq, S, Rmul, Wout,  \
+                               dot_q, gram, part, ctl);                                                       \
     }
     BGCR_DISPATCH_P(P, L)
 #undef L
@@ -660,8 +746,11 @@ template <class T>
 template <class TO>
 hipError_t Launch<T>::combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out,
                               int nout, const A* coef, int accumulate) {
-    const int nwg = nwg_for(n, P);
-#define L(PP) hipLaunchKernelGGL((k_combine<T, TO, PP>), dim3(nwg), dim3(NT), 0, st, n, in, nin, out, nout, coef, accumulate);
+    const int64_t blocks = (n + NT - 1) / NT;
+    const int nwg = (int)(blocks < 2048 ? blocks : 2048);
+    // output blocks per pass: 32 accumulators per lane (16 for complex)
+    constexpr int ACC = sizeof(A) == 16 ? 16 : 32;
+#define L(PP) hipLaunchKernelGGL((k_combine<T, TO, PP, (ACC / PP > 0 ? ACC / PP : 1)>), dim3(nwg), dim3(NT), 0, st, n, in, nin, out, nout, coef, accumulate);
     BGCR_DISPATCH_P(P, L)
 #undef L
     return hipGetLastError();
@@ -670,7 +759,7 @@ hipError_t Launch<T>::combine(hipStream_t st, int P, int64_t n, const BlockPtrs&
 template <class A>
 hipError_t reduce_partials(hipStream_t st, const A* part, int nwg, int nout, const A* add, A* out, const Ctl* ctl) {
     if (nout <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_reduce<A>), dim3((nout + 255) / 256), dim3(256), 0, st, part, nwg, nout, add, out, ctl);
+    hipLaunchKernelGGL((k_reduce<A>), dim3((nout + 15) / 16), dim3(256), 0, st, part, nwg, nout, add, out, ctl);
     return hipGetLastError();
 }
 
@@ -684,26 +773,25 @@ hipError_t residual(hipStream_t st, int P, int64_t n, const int* rp, const int* 
 }
 
 template <class A>
-hipError_t cholqr_first(hipStream_t st, int P, const A* part, int nwg, int nout, int off, A* Z1, A* Z1inv, Ctl* ctl) {
-#define L(PP) hipLaunchKernelGGL((k_cholqr_first<A, PP>), dim3(1), dim3(NT), 0, st, part, nwg, nout, off, Z1, Z1inv, ctl);
+hipError_t cholqr_first(hipStream_t st, int P, const A* gram, A* Z1, A* Z1inv, Ctl* ctl) {
+#define L(PP) hipLaunchKernelGGL((k_cholqr_first<A, PP>), dim3(1), dim3(NT), 0, st, gram, Z1, Z1inv, ctl);
     BGCR_DISPATCH_P(P, L)
 #undef L
     return hipGetLastError();
 }
 
 template <class A>
-hipError_t cholqr_second(hipStream_t st, int P, const A* part, int nwg, int nout, int off, const A* Z1, A* Rinv0,
-                         A* g, int m, Ctl* ctl) {
-#define L(PP) hipLaunchKernelGGL((k_cholqr_second<A, PP>), dim3(1), dim3(NT), 0, st, part, nwg, nout, off, Z1, Rinv0, g, m, ctl);
+hipError_t cholqr_second(hipStream_t st, int P, const A* gram, const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl) {
+#define L(PP) hipLaunchKernelGGL((k_cholqr_second<A, PP>), dim3(1), dim3(NT), 0, st, gram, Z1, Rinv0, g, m, ctl);
     BGCR_DISPATCH_P(P, L)
 #undef L
     return hipGetLastError();
 }
 
 template <class A>
-hipError_t step_small(hipStream_t st, int P, const A* gpart, int nwg, int gnout, int goff, const A* S, int KP, int j,
-                      int m, A* H, A* F, A* Rh, A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl, double thresh) {
-#define L(PP) hipLaunchKernelGGL((k_step_small<A, PP>), dim3(1), dim3(NT), 0, st, gpart, nwg, gnout, goff, S, KP, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
+hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, int KP, int j, int m, A* H, A* F, A* Rh,
+                      A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl, double thresh) {
+#define L(PP) hipLaunchKernelGGL((k_step_small<A, PP>), dim3(1), dim3(NT), 0, st, gram, S, KP, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
     BGCR_DISPATCH_P(P, L)
 #undef L
     return hipGetLastError();
@@ -744,15 +832,14 @@ template hipError_t residual<double, float>(hipStream_t, int, int64_t, const int
                                             const double*, int64_t, const double*, float*, double*, int);
 template hipError_t residual<zd, zd>(hipStream_t, int, int64_t, const int*, const int*, const zd*, const zd*, int64_t,
                                      const zd*, zd*, double*, int);
-template hipError_t cholqr_first<double>(hipStream_t, int, const double*, int, int, int, double*, double*, Ctl*);
-template hipError_t cholqr_first<zd>(hipStream_t, int, const zd*, int, int, int, zd*, zd*, Ctl*);
-template hipError_t cholqr_second<double>(hipStream_t, int, const double*, int, int, int, const double*, double*,
-                                          double*, int, Ctl*);
-template hipError_t cholqr_second<zd>(hipStream_t, int, const zd*, int, int, int, const zd*, zd*, zd*, int, Ctl*);
-template hipError_t step_small<double>(hipStream_t, int, const double*, int, int, int, const double*, int, int, int,
-                                       double*, double*, double*, double*, double*, double*, double*, Ctl*, double);
-template hipError_t step_small<zd>(hipStream_t, int, const zd*, int, int, int, const zd*, int, int, int, zd*, zd*, zd*,
-                                   zd*, zd*, zd*, double*, Ctl*, double);
+template hipError_t cholqr_first<double>(hipStream_t, int, const double*, double*, double*, Ctl*);
+template hipError_t cholqr_first<zd>(hipStream_t, int, const zd*, zd*, zd*, Ctl*);
+template hipError_t cholqr_second<double>(hipStream_t, int, const double*, const double*, double*, double*, int, Ctl*);
+template hipError_t cholqr_second<zd>(hipStream_t, int, const zd*, const zd*, zd*, zd*, int, Ctl*);
+template hipError_t step_small<double>(hipStream_t, int, const double*, const double*, int, int, int, double*, double*,
+                                       double*, double*, double*, double*, double*, Ctl*, double);
+template hipError_t step_small<zd>(hipStream_t, int, const zd*, const zd*, int, int, int, zd*, zd*, zd*, zd*, zd*, zd*,
+                                   double*, Ctl*, double);
 template hipError_t copy_block<double, double>(hipStream_t, int64_t, int, const double*, int64_t, double*, int64_t,
                                                int);
 template hipError_t copy_block<zd, zd>(hipStream_t, int64_t, int, const zd*, int64_t, zd*, int64_t, int);

@@ -6,7 +6,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "bgcr.h"
@@ -24,6 +26,8 @@ struct bgcr_sequence {
     virtual int get_recycle(void* U, void* C, int64_t ld) const = 0;
     virtual int set_recycle(const void* U, int64_t ld, int k_in) = 0;
     virtual int recycle_dim() const = 0;
+    virtual void set_profiling(int on) = 0;
+    virtual void get_profile(double* ms, double* bytes, int64_t* launches, int nclass) const = 0;
     std::vector<int> log_steps;
     std::vector<double> log_res;
 };
@@ -101,6 +105,8 @@ struct Seq final : bgcr_sequence {
     bgcr_params prm;
     int64_t n;
     int P, m, k, KB, KP, nwg;
+    int nwg_mx = 0;      // workgroups of the matrix-core sweeps (64-row tiles)
+    bool use_mx = false; // Arnoldi sweeps on matrix cores
     bool mixed, cplx;
     hipStream_t st;
     Sizes sz;
@@ -111,6 +117,8 @@ struct Seq final : bgcr_sequence {
     A* X = nullptr;
     float* av32 = nullptr;
     size_t av32_cap = 0;
+    A* dots = nullptr;
+    size_t dots_cap = 0;
     A *part = nullptr, *S1 = nullptr, *Sf = nullptr, *H = nullptr, *F = nullptr, *Rh = nullptr, *QH = nullptr,
       *g = nullptr, *RinvAll = nullptr, *Z1 = nullptr, *Z1i = nullptr, *coef = nullptr;
     size_t coef_cap = 0;
@@ -126,6 +134,69 @@ struct Seq final : bgcr_sequence {
 
     std::vector<void*> allocs;
 
+    // opt-in per-kernel-class timing with HIP events on this sequence's stream
+    struct Pend {
+        int cls, step;
+        double bytes;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> evfree;
+    std::vector<Pend> pend;
+    double pms[BGCR_K_NCLASS] = {}, pby[BGCR_K_NCLASS] = {};
+    long long pcnt[BGCR_K_NCLASS] = {};
+    int cur_step = 0;  // block step of the launches being enqueued (0: not a step kernel)
+
+    hipEvent_t ev_get() {
+        if (evfree.empty()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = evfree.back();
+        evfree.pop_back();
+        return e;
+    }
+    template <class FN>
+    void run(int cls, double bytes, FN&& launch) {
+        if (!prof) {
+            HIPCHK(launch());
+            return;
+        }
+        if (pend.size() > 16384) prof_resolve(1 << 30);
+        hipEvent_t a = ev_get(), b = ev_get();
+        HIPCHK(hipEventRecord(a, st));
+        HIPCHK(launch());
+        HIPCHK(hipEventRecord(b, st));
+        pend.push_back({cls, cur_step, bytes, a, b});
+    }
+    // accumulate finished launches; step kernels beyond `meff` were skipped on
+    // the device (early exit of the cycle) and are not counted
+    void prof_resolve(int meff) {
+        if (pend.empty()) return;
+        HIPCHK(hipStreamSynchronize(st));
+        for (const Pend& q : pend) {
+            if (q.step <= meff) {
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, q.a, q.b));
+                pms[q.cls] += ms;
+                pby[q.cls] += q.bytes;
+                pcnt[q.cls] += 1;
+            }
+            evfree.push_back(q.a);
+            evfree.push_back(q.b);
+        }
+        pend.clear();
+    }
+    void set_profiling(int on) override {
+        prof_resolve(1 << 30);
+        prof = on != 0;
+        for (int c = 0; c < BGCR_K_NCLASS; ++c) {
+            pms[c] = pby[c] = 0.0;
+            pcnt[c] = 0;
+        }
+    }
+
     Seq(const bgcr_params* p_, int64_t n_, hipStream_t s_) : prm(*p_), n(n_), st(s_) {
         P = prm.p;
         m = prm.m;
@@ -136,10 +207,19 @@ struct Seq final : bgcr_sequence {
         KB = sz.KB;
         KP = sz.KP;
         nwg = nwg_for(n, P);
+        nwg_mx = mfma_nwg(n);
+        const char* e = std::getenv("BGCR_NO_MFMA");
+        const bool off = e && e[0] == '1';
+        use_mx = !off && !std::is_same<T, zd>::value && (P == 8 || P == 16) && (KB + m) * P <= 256;
     }
 
     ~Seq() override {
-        if (st) (void)hipStreamSynchronize(st);
+        (void)hipStreamSynchronize(st);
+        for (const Pend& q : pend) {
+            (void)hipEventDestroy(q.a);
+            (void)hipEventDestroy(q.b);
+        }
+        for (hipEvent_t e : evfree) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
         if (hbuf) (void)hipHostFree(hbuf);
     }
@@ -170,6 +250,8 @@ struct Seq final : bgcr_sequence {
         const size_t nout = std::max((size_t)qmax * P, (size_t)KP * P);
         part = dalloc<A>((size_t)NWG_MAX * nout);
         S1 = dalloc<A>((size_t)qmax * P);
+        dots_cap = (size_t)qmax * P * std::max(KB, 1);
+        dots = dalloc<A>(dots_cap);
         Sf = dalloc<A>((size_t)qmax * P);
         const size_t mp = (size_t)m * P, m1p = (size_t)(m + 1) * P;
         H = dalloc<A>(m1p * mp);
@@ -203,6 +285,7 @@ struct Seq final : bgcr_sequence {
     void sync() {
         HIPCHK(hipStreamSynchronize(st));
         hoff = 0;
+        if (prof && cur_step == 0) prof_resolve(1 << 30);
     }
     void d2h(void* dst, const void* src, size_t bytes) {
         if (bytes == 0) return;
@@ -216,6 +299,33 @@ struct Seq final : bgcr_sequence {
             done += c;
         }
     }
+    // several device -> host copies with a single synchronisation
+    struct Copy {
+        void* dst;
+        const void* src;
+        size_t bytes;
+    };
+    void d2h_many(const std::vector<Copy>& cps) {
+        size_t tot = 0;
+        for (const Copy& c : cps) tot += (c.bytes + 255) & ~(size_t)255;
+        if (tot > hcap) {
+            for (const Copy& c : cps) d2h(c.dst, c.src, c.bytes);
+            return;
+        }
+        sync();
+        size_t off = 0;
+        for (const Copy& c : cps) {
+            if (c.bytes) HIPCHK(hipMemcpyAsync(hbuf + off, c.src, c.bytes, hipMemcpyDeviceToHost, st));
+            off += (c.bytes + 255) & ~(size_t)255;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        off = 0;
+        for (const Copy& c : cps) {
+            if (c.bytes) std::memcpy(c.dst, hbuf + off, c.bytes);
+            off += (c.bytes + 255) & ~(size_t)255;
+        }
+    }
+
     void h2d(void* dst, const void* src, size_t bytes) {
         if (bytes == 0) return;
         if (bytes > hcap) throw Fail{BGCR_ERR_INVALID};
@@ -244,7 +354,7 @@ struct Seq final : bgcr_sequence {
                     for (int b = 0; b < P; ++b) {
                         const int rr = i * P + a, cc = o * P + b;
                         const cd v = (rr < K.r && cc < K.c) ? K(rr, cc) : cd(0.0, 0.0);
-                        h[((size_t)(i * nout + o) * P + a) * P + b] = from_cd<A>(v);
+                        h[(((size_t)i * P + a) * nout + o) * P + b] = from_cd<A>(v);
                     }
         h2d(dst, h.data(), cnt * sizeof(A));
         return dst;
@@ -256,27 +366,44 @@ struct Seq final : bgcr_sequence {
         if ((size_t)nin * nout * P * P > coef_cap) throw Fail{BGCR_ERR_INVALID};
         std::vector<const void*> outc(out.begin(), out.end());
         const A* cf = upload_coef(K, nin, nout, coef);
-        HIPCHK(L::template combine<TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate));
+        const double by = (double)n * P * ((double)sizeof(T) * nin + (double)sizeof(TO) * nout * (accumulate ? 2 : 1));
+        run(BGCR_K_COMBINE, by, [&] { return L::template combine<TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate); });
     }
 
-    // Q^H W for a list of W blocks: returns Mat (nq P) x (nw P)
+    // Q^H W for a list of W blocks: returns Mat (nq P) x (nw P).  Every piece
+    // is reduced into its own slice of `dots`; one copy to the host at the end.
     Mat multi_dot(const std::vector<const void*>& Q, const std::vector<const T*>& W) {
         const int nq = (int)Q.size();
         const int nw = (int)W.size();
         Mat D(nq * P, nw * P);
-        const int chunk = std::max(1, (MAXI * NT) / (P * P));
-        std::vector<A> h;
+        const int chunk = use_mx ? std::max(1, 256 / P) : std::max(1, (MAXI * NT) / (P * P));
+        const int nr = use_mx ? nwg_mx : nwg;
+        if ((size_t)nq * P * P * nw > dots_cap) throw Fail{BGCR_ERR_INVALID};
+        size_t off = 0;
         for (int w = 0; w < nw; ++w) {
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = std::min(chunk, nq - q0);
                 std::vector<const void*> sub(Q.begin() + q0, Q.begin() + q0 + qn);
-                HIPCHK(L::update_dot(st, P, n, W[w], bp(sub), qn, nullptr, nullptr, nullptr, 1, 0, part, nwg, nullptr));
+                run(BGCR_K_TSDOT, (double)sizeof(T) * n * P * (1 + qn), [&] {
+                    if constexpr (!std::is_same<T, zd>::value) {
+                        if (use_mx) return mfma_proj_dot<T>(st, P, n, W[w], bp(sub), qn, nullptr, part, nullptr, nr);
+                    }
+                    return L::update_dot(st, P, n, W[w], bp(sub), qn, nullptr, nullptr, nullptr, 1, 0, part, nr, nullptr);
+                });
                 const int nout = qn * P * P;
-                HIPCHK(reduce_partials<A>(st, part, nwg, nout, nullptr, Sf, nullptr));
-                h.resize(nout);
-                d2h(h.data(), Sf, nout * sizeof(A));
+                run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nr, nout, nullptr, dots + off, nullptr); });
+                off += nout;
+            }
+        }
+        std::vector<A> h(off);
+        d2h(h.data(), dots, off * sizeof(A));
+        off = 0;
+        for (int w = 0; w < nw; ++w) {
+            for (int q0 = 0; q0 < nq; q0 += chunk) {
+                const int qn = std::min(chunk, nq - q0);
                 for (int c = 0; c < qn * P; ++c)
-                    for (int b = 0; b < P; ++b) D(q0 * P + c, w * P + b) = to_cd(h[(size_t)c * P + b]);
+                    for (int b = 0; b < P; ++b) D(q0 * P + c, w * P + b) = to_cd(h[off + (size_t)c * P + b]);
+                off += (size_t)qn * P * P;
             }
         }
         return D;
@@ -285,8 +412,11 @@ struct Seq final : bgcr_sequence {
     // per-column ||B - A X||^2 and ||B||^2 (FP64); stores R (narrowed) if Rout
     void residual_norms(const bgcr_csr* Am, const A* B, int64_t ldb, T* Rout, std::vector<double>& rn2,
                         std::vector<double>& bn2) {
-        HIPCHK(residual<A, T>(st, P, n, Am->row_ptr, Am->col_idx, (const A*)Am->values, B, ldb, X, Rout, dpart,
-                              nwg));
+        const double by = (double)(sizeof(A) + 4) * Am->nnz + 4.0 * (n + 1) + 2.0 * sizeof(A) * n * P +
+                          (Rout ? (double)sizeof(T) * n * P : 0.0);
+        run(BGCR_K_RESIDUAL, by, [&] {
+            return residual<A, T>(st, P, n, Am->row_ptr, Am->col_idx, (const A*)Am->values, B, ldb, X, Rout, dpart, nwg);
+        });
         std::vector<double> h((size_t)nwg * 2 * P);
         d2h(h.data(), dpart, h.size() * sizeof(double));
         rn2.assign(P, 0.0);
@@ -303,8 +433,10 @@ struct Seq final : bgcr_sequence {
     void import_basis(const bgcr_csr* Am, const T* avT) {
         const int o = 1 - cur;
         for (int b = 0; b < KB; ++b) {
-            HIPCHK(L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, ublk(cur, b), nullptr, nullptr, cblk(o, b),
-                               bp({}), 0, 0, part, nwg, nullptr));
+            run(BGCR_K_SPMM, (double)(sizeof(T) + 4) * Am->nnz + 4.0 * (n + 1) + 2.0 * sizeof(T) * n * P, [&] {
+                return L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, ublk(cur, b), nullptr, nullptr, cblk(o, b),
+                                   bp({}), 0, 0, part, nwg, nullptr);
+            });
             ++n_spmm;
         }
         auto gram_of = [&](int buf) {
@@ -376,30 +508,82 @@ struct Seq final : bgcr_sequence {
         const size_t hb = (size_t)(m + 1) * P * m * P * sizeof(A);
         HIPCHK(hipMemsetAsync(H, 0, hb, st));
         HIPCHK(hipMemsetAsync(Rh, 0, hb, st));
-        HIPCHK(L::update_dot(st, P, n, R, bp({}), 0, nullptr, nullptr, nullptr, 0, 1, part, nwg, nullptr));
-        HIPCHK(cholqr_first<A>(st, P, part, nwg, P2, 0, Z1, Z1i, ctl));
-        HIPCHK(L::update_dot(st, P, n, R, bp({}), 0, nullptr, Z1i, W2, 0, 1, part, nwg, nullptr));
-        HIPCHK(cholqr_second<A>(st, P, part, nwg, P2, 0, Z1, RinvAll, g, m, ctl));
+        const double sT = (double)sizeof(T), blkb = sT * (double)n * P;
+        // CholQR2 of the cycle's starting block R = V_1 Z (Algorithm 1)
+        const int nr = use_mx ? nwg_mx : nwg;
+        run(BGCR_K_TSDOT, blkb, [&] {
+            if constexpr (!std::is_same<T, zd>::value) {
+                if (use_mx) return mfma_proj_gram<T>(st, P, n, R, bp({}), 0, nullptr, nullptr, part, nullptr, nr);
+            }
+            return L::update_dot(st, P, n, R, bp({}), 0, nullptr, nullptr, nullptr, 0, 1, part, nr, nullptr);
+        });
+        run(BGCR_K_SMALL, 0.0, [&] {
+            HIPCHK(reduce_partials<A>(st, part, nr, P2, nullptr, Sf, nullptr));
+            return cholqr_first<A>(st, P, Sf, Z1, Z1i, ctl);
+        });
+        run(BGCR_K_TSDOT, 2.0 * blkb, [&] {
+            if constexpr (!std::is_same<T, zd>::value) {
+                if (use_mx) {
+                    // R Z1^{-1} = R - R (I - Z1^{-1})
+                    HIPCHK(i_minus(st, Z1i, S1, P));
+                    return mfma_proj_gram<T>(st, P, n, R, bp({R}), 1, S1, W2, part, nullptr, nr);
+                }
+            }
+            return L::update_dot(st, P, n, R, bp({}), 0, nullptr, Z1i, W2, 0, 1, part, nr, nullptr);
+        });
+        run(BGCR_K_SMALL, 0.0, [&] {
+            HIPCHK(reduce_partials<A>(st, part, nr, P2, nullptr, Sf, nullptr));
+            return cholqr_second<A>(st, P, Sf, Z1, RinvAll, g, m, ctl);
+        });
         const int ncb = withC ? KB : 0;
+        const double kc = withC ? (double)keff : 0.0;
+        const double abytes = (sT + 4.0) * (double)Am->nnz + 4.0 * (double)(n + 1);
         for (int j = 1; j <= m; ++j) {
+            cur_step = j;
             std::vector<const void*> Q;
             for (int b = 0; b < ncb; ++b) Q.push_back(cblk(cur, b));
             for (int i = 0; i < j - 1; ++i) Q.push_back(vblk(i));
             const int nq = (int)Q.size();
-            HIPCHK(L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
-                               vblk(j - 1), Wb, bp(Q), nq, 1, part, nwg, ctl));
+            const BlockPtrs Q1 = bp(Q);
+            // model-M bytes: sweep 1 reads A, gathers V_j, writes W and V_j, reads [C V_1..V_{j-1}]
+            const int na = use_mx ? nwg_mx : nwg;
+            run(BGCR_K_SPMM_DOT, abytes + 3.0 * blkb + sT * n * (kc + (double)(j - 1) * P), [&] {
+                if constexpr (!std::is_same<T, zd>::value) {
+                    if (use_mx)
+                        return mfma_spmm_dot<T>(st, P, n, Am->row_ptr, Am->col_idx, avT, W2,
+                                                RinvAll + (size_t)(j - 1) * P2, vblk(j - 1), Wb, Q1, nq, part, ctl, na);
+                }
+                return L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
+                                   vblk(j - 1), Wb, Q1, nq, 1, part, na, ctl);
+            });
             const int nout = (nq + 1) * P2;
-            HIPCHK(reduce_partials<A>(st, part, nwg, nout, nullptr, S1, ctl));
+            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
             Q.push_back(vblk(j - 1));
             const BlockPtrs QB = bp(Q);
-            HIPCHK(L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, nwg, ctl));
-            HIPCHK(reduce_partials<A>(st, part, nwg, nout, S1, Sf, ctl));
-            HIPCHK(L::update_dot(st, P, n, Wb, QB, nq + 1, Sf, nullptr, W2, 0, 1, part, nwg, ctl));
-            HIPCHK(step_small<A>(st, P, part, nwg, P2, 0, Sf, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl,
-                                 thresh));
+            const double qbytes = sT * n * (kc + (double)j * P);
+            run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {
+                if constexpr (!std::is_same<T, zd>::value) {
+                    if (use_mx) return mfma_proj_dot<T>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na);
+                }
+                return L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, na, ctl, 1);
+            });
+            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, S1, Sf, ctl); });
+            run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {
+                if constexpr (!std::is_same<T, zd>::value) {
+                    if (use_mx) return mfma_proj_gram<T>(st, P, n, Wb, QB, nq + 1, Sf, W2, part, ctl, na);
+                }
+                return L::update_dot(st, P, n, Wb, QB, nq + 1, Sf, nullptr, W2, 0, 1, part, na, ctl, 2);
+            });
+            run(BGCR_K_SMALL, 0.0, [&] {
+                HIPCHK(reduce_partials<A>(st, part, na, P2, nullptr, S1, ctl));
+                return step_small<A>(st, P, S1, Sf, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
+            });
         }
+        cur_step = 0;
         Ctl hc;
-        d2h(&hc, ctl, sizeof(Ctl));
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+        if (prof) prof_resolve(hc.meff);
         CycleOut co;
         co.meff = hc.meff;
         co.breakdown = hc.status != 0;
@@ -407,11 +591,11 @@ struct Seq final : bgcr_sequence {
         const int me = co.meff, mp = me * P, ldH = m * P;
         std::vector<A> hH((size_t)(m + 1) * P * ldH), hR((size_t)(m + 1) * P * ldH), hg((size_t)(m + 1) * P * P),
             hRi((size_t)(m + 1) * P2), hF((size_t)std::max(1, KP) * ldH);
-        d2h(hH.data(), H, hH.size() * sizeof(A));
-        d2h(hR.data(), Rh, hR.size() * sizeof(A));
-        d2h(hg.data(), g, hg.size() * sizeof(A));
-        d2h(hRi.data(), RinvAll, hRi.size() * sizeof(A));
-        if (withC && KP > 0) d2h(hF.data(), F, (size_t)KP * ldH * sizeof(A));
+        d2h_many({{hH.data(), H, hH.size() * sizeof(A)},
+                  {hR.data(), Rh, hR.size() * sizeof(A)},
+                  {hg.data(), g, hg.size() * sizeof(A)},
+                  {hRi.data(), RinvAll, hRi.size() * sizeof(A)},
+                  {hF.data(), F, (withC && KP > 0) ? (size_t)KP * ldH * sizeof(A) : 0}});
         co.H = Mat((me + 1) * P, mp);
         for (int i = 0; i < (me + 1) * P; ++i)
             for (int j = 0; j < mp; ++j) co.H(i, j) = to_cd(hH[(size_t)i * ldH + j]);
@@ -437,11 +621,8 @@ struct Seq final : bgcr_sequence {
         }
         if (co.breakdown) breakdown_seen = true;
         // model-M algorithmic bytes of the executed Arnoldi sweeps
-        const double s = (double)sizeof(T), sA = (double)sizeof(T);
-        const double kc = withC ? (double)keff : 0.0;
         for (int j = 1; j <= me; ++j)
-            alg_bytes += (sA + 4.0) * (double)Am->nnz + 4.0 * (double)(n + 1) + 5.0 * s * n * P +
-                         3.0 * s * n * (kc + (double)j * P);
+            alg_bytes += abytes + 5.0 * blkb + 3.0 * sT * n * (kc + (double)j * P);
         n_spmm += me;
         n_steps += me;
         return co;
@@ -506,6 +687,41 @@ struct Seq final : bgcr_sequence {
         }
     }
 
+    // Eigenvalues of K, harmonic Ritz values theta (theta = 1/mu when `inverse`),
+    // selection, and the selected eigenvectors.  `robust` uses the full Schur
+    // form (fallback when inverse iteration gives nearly dependent vectors).
+    void eig_select(const Mat& K, bool inverse, int kt, bool robust, std::vector<cd>& theta, dense::Selection& sel,
+                    std::vector<std::vector<cd>>& vecs) {
+        const int nn = K.r;
+        theta.assign(nn, cd(0.0, 0.0));
+        vecs.clear();
+        auto to_theta = [&](cd mu) { return !inverse ? mu : (std::abs(mu) > 0.0 ? 1.0 / mu : cd(INFINITY, 0.0)); };
+        if (!robust) {
+            dense::EigSolver E;
+            E.compute(K, !cplx);
+            if (E.ok) {
+                for (int i = 0; i < nn; ++i) theta[i] = to_theta(E.lam[i]);
+                sel = dense::select_ritz(theta, kt, prm.select_largest != 0, !cplx);
+                for (int i : sel.idx) vecs.push_back(E.vector_for(E.lam[i], {}));
+                return;
+            }
+        }
+        dense::Schur S = dense::schur(K);
+        if (!S.ok) throw Fail{BGCR_ERR_NUMERICAL};
+        for (int i = 0; i < nn; ++i) theta[i] = to_theta(S.lam[i]);
+        sel = dense::select_ritz(theta, kt, prm.select_largest != 0, !cplx);
+        for (int i : sel.idx) vecs.push_back(dense::schur_eigvec(S, i));
+    }
+
+    static bool well_conditioned_r(const Mat& r) {
+        double mx = 0.0, mn = INFINITY;
+        for (int i = 0; i < std::min(r.r, r.c); ++i) {
+            mx = std::max(mx, std::abs(r(i, i)));
+            mn = std::min(mn, std::abs(r(i, i)));
+        }
+        return mx > 0.0 && mn > 1e-10 * mx;
+    }
+
     // first system, no U (Algorithm 1 else-branch): Proposition block-harm-ritz
     void refresh_first(const CycleOut& co) {
         const int me = co.meff, mp = me * P;
@@ -523,24 +739,24 @@ struct Seq final : bgcr_sequence {
         std::vector<cd> theta;
         std::vector<std::vector<cd>> vecs;
         dense::Selection sel;
-        if (dense::solve_lu(dense::adjoint(Hm), rhs, Xs)) {
+        Mat Pm, Qg, rg;
+        const bool standard = dense::solve_lu(dense::adjoint(Hm), rhs, Xs);
+        if (standard)
             for (int i = 0; i < mp; ++i)
                 for (int b = 0; b < P; ++b) K(i, mp - P + b) += Xs(i, b);
-            dense::Schur S = dense::schur(K);
-            if (!S.ok) throw Fail{BGCR_ERR_NUMERICAL};
-            theta = S.lam;
-            sel = dense::select_ritz(theta, kt, prm.select_largest != 0, !cplx);
-            for (int i : sel.idx) vecs.push_back(dense::schur_eigvec(S, i));
-        } else {
-            // singular H_m: generalized form with no recycled space
-            Mat M(co.H.r, mp);
-            for (int i = 0; i < mp; ++i) M(i, i) = 1.0;
-            gen_harmonic(co.H, M, kt, theta, sel, vecs);
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            if (standard) {
+                eig_select(K, false, kt, attempt == 1, theta, sel, vecs);
+            } else {
+                // singular H_m: generalized form with no recycled space
+                Mat M(co.H.r, mp);
+                for (int i = 0; i < mp; ++i) M(i, i) = 1.0;
+                gen_harmonic(co.H, M, kt, theta, sel, vecs, attempt == 1);
+            }
+            ritz_basis(sel, vecs, Pm);
+            dense::qr_pos(dense::matmul(co.H, Pm), Qg, rg);
+            if (well_conditioned_r(rg)) break;
         }
-        Mat Pm;
-        ritz_basis(sel, vecs, Pm);
-        Mat Qg, rg;
-        dense::qr_pos(dense::matmul(co.H, Pm), Qg, rg);
         const int kn = Pm.c;
         if (kn > KP) throw Fail{BGCR_ERR_NUMERICAL};
         Mat PR = dense::matmul(Pm, dense::tri_inv_upper(rg));
@@ -568,7 +784,7 @@ struct Seq final : bgcr_sequence {
     // G^H G t = theta G^H M t  with G = Qg Rg:  (Qg^H M Rg^{-1}) s = mu s,
     // theta = 1/mu, t = Rg^{-1} s
     void gen_harmonic(const Mat& G, const Mat& M, int kt, std::vector<cd>& theta, dense::Selection& sel,
-                      std::vector<std::vector<cd>>& vecs) {
+                      std::vector<std::vector<cd>>& vecs, bool robust) {
         Mat Qg, Rg;
         dense::qr_pos(G, Qg, Rg);
         const int nn = G.c;
@@ -576,22 +792,13 @@ struct Seq final : bgcr_sequence {
             if (!(std::abs(Rg(i, i)) > 0.0)) throw Fail{BGCR_ERR_NUMERICAL};
         const Mat Rgi = dense::tri_inv_upper(Rg);
         const Mat K = dense::matmul(dense::matmul(dense::adjoint(Qg), M), Rgi);
-        dense::Schur S = dense::schur(K);
-        if (!S.ok) throw Fail{BGCR_ERR_NUMERICAL};
-        theta.assign(nn, cd(0.0, 0.0));
-        for (int i = 0; i < nn; ++i) {
-            const cd mu = S.lam[i];
-            theta[i] = std::abs(mu) > 0.0 ? 1.0 / mu : cd(INFINITY, 0.0);
-        }
-        sel = dense::select_ritz(theta, kt, prm.select_largest != 0, !cplx);
+        std::vector<std::vector<cd>> svecs;
+        eig_select(K, true, kt, robust, theta, sel, svecs);
         vecs.clear();
-        for (int i : sel.idx) {
-            std::vector<cd> s = dense::schur_eigvec(S, i);
-            Mat sv(nn, 1);
-            for (int r = 0; r < nn; ++r) sv(r, 0) = s[r];
-            Mat t = dense::matmul(Rgi, sv);
-            std::vector<cd> tv(nn);
-            for (int r = 0; r < nn; ++r) tv[r] = t(r, 0);
+        for (const auto& sv : svecs) {
+            std::vector<cd> tv(nn, cd(0.0, 0.0));
+            for (int r = 0; r < nn; ++r)
+                for (int c = r; c < nn; ++c) tv[r] += Rgi(r, c) * sv[c];
             vecs.push_back(tv);
         }
     }
@@ -636,13 +843,15 @@ struct Seq final : bgcr_sequence {
         std::vector<cd> theta;
         dense::Selection sel;
         std::vector<std::vector<cd>> vecs;
-        gen_harmonic(G, M, kt, theta, sel, vecs);
-        Mat Pm;
-        ritz_basis(sel, vecs, Pm);
+        Mat Pm, Qg, rg;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            gen_harmonic(G, M, kt, theta, sel, vecs, attempt == 1);
+            ritz_basis(sel, vecs, Pm);
+            dense::qr_pos(dense::matmul(G, Pm), Qg, rg);
+            if (well_conditioned_r(rg)) break;
+        }
         const int kn = Pm.c;
         if (kn > KP) throw Fail{BGCR_ERR_NUMERICAL};
-        Mat Qg, rg;
-        dense::qr_pos(dense::matmul(G, Pm), Qg, rg);
         const Mat PR = dense::matmul(Pm, dense::tri_inv_upper(rg));
         // inputs [U blocks, C blocks, V_1..V_meff, last]; outputs [U' blocks, C' blocks]
         const int nin = 2 * KB + me + 1;
@@ -841,6 +1050,14 @@ struct Seq final : bgcr_sequence {
 
     int recycle_dim() const override { return keff; }
 
+    void get_profile(double* ms, double* bytes, int64_t* launches, int nclass) const override {
+        for (int c = 0; c < nclass && c < BGCR_K_NCLASS; ++c) {
+            if (ms) ms[c] = pms[c];
+            if (bytes) bytes[c] = pby[c];
+            if (launches) launches[c] = pcnt[c];
+        }
+    }
+
     int get_recycle(void* Uo, void* Co, int64_t ld) const override {
         if (ld < std::max(1, keff)) return BGCR_ERR_INVALID;
         auto* self = const_cast<Seq*>(this);
@@ -989,6 +1206,22 @@ int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* 
     else
         return BGCR_ERR_INVALID;
     return e == hipSuccess ? BGCR_OK : BGCR_ERR_HIP;
+}
+
+int bgcr_set_profiling(bgcr_sequence* s, int on) {
+    if (!s) return BGCR_ERR_INVALID;
+    try {
+        s->set_profiling(on);
+    } catch (...) {
+        return BGCR_ERR_HIP;
+    }
+    return BGCR_OK;
+}
+
+int bgcr_get_profile(const bgcr_sequence* s, double* ms, double* bytes, int64_t* launches, int32_t nclass) {
+    if (!s || nclass < 0) return BGCR_ERR_INVALID;
+    s->get_profile(ms, bytes, launches, nclass);
+    return BGCR_OK;
 }
 
 const char* bgcr_strerror(int status) {
