@@ -30,8 +30,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "systems solved/s at rel.res 1e-8; Arnoldi HBM GB/s vs peak; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-ARNOLDI = ("spmm_dot", "proj_dot", "proj_gram")
-KERNEL_SYMBOL = {"spmm_dot": "k_spmm_dot", "proj_dot": "k_proj_dot", "proj_gram": "k_proj_gram"}
+ARNOLDI = ("arn_spmm", "arn_dot", "proj_dot", "proj_gram")
+KERNEL_SYMBOL = {"arn_spmm": "k_spmm_rinv", "arn_dot": "k_proj_dot_mfma (dot only)",
+                 "proj_dot": "k_proj_dot_mfma", "proj_gram": "k_proj_gram_mfma"}
 
 
 def log(*a):

@@ -145,15 +145,16 @@ int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* 
 
 /* Kernel classes of the per-kernel profile. */
 typedef enum {
-    BGCR_K_SPMM_DOT = 0,     /* Arnoldi sweep 1: block SpMM + first block-CGS dots */
-    BGCR_K_PROJ_DOT = 1,     /* Arnoldi sweep 2: second block-CGS pass */
-    BGCR_K_PROJ_GRAM = 2,    /* Arnoldi sweep 3: W'' = W - Q S and its Gram */
-    BGCR_K_SMALL = 3,        /* partial reductions, Cholesky, block-Householder LSQ */
-    BGCR_K_COMBINE = 4,      /* basis updates: solution, residual, recycle refresh */
-    BGCR_K_RESIDUAL = 5,     /* FP64 true residual B - A X */
-    BGCR_K_TSDOT = 6,        /* other tall-skinny products (CholQR of R, recycle dots) */
-    BGCR_K_SPMM = 7,         /* plain block SpMM (recycle import A U) */
-    BGCR_K_NCLASS = 8
+    BGCR_K_ARN_SPMM = 0,     /* Arnoldi sweep 1a: W = A V_j with V_j = W'' R^{-1} */
+    BGCR_K_ARN_DOT = 1,      /* Arnoldi sweep 1b: first block-CGS dots [C V_1..V_j]^H W */
+    BGCR_K_PROJ_DOT = 2,     /* Arnoldi sweep 2: second block-CGS pass */
+    BGCR_K_PROJ_GRAM = 3,    /* Arnoldi sweep 3: W'' = W - Q S and its Gram */
+    BGCR_K_SMALL = 4,        /* partial reductions, Cholesky, block-Householder LSQ */
+    BGCR_K_COMBINE = 5,      /* basis updates: solution, residual, recycle refresh */
+    BGCR_K_RESIDUAL = 6,     /* FP64 true residual B - A X */
+    BGCR_K_TSDOT = 7,        /* other tall-skinny products (CholQR of R, recycle dots) */
+    BGCR_K_SPMM = 8,         /* plain block SpMM (recycle import A U) */
+    BGCR_K_NCLASS = 9
 } bgcr_kernel_class;
 
 /* Turn per-kernel timing on (1) or off (0) and reset the counters.  When on,

@@ -86,6 +86,10 @@ struct Launch {
                                const T* av, const T* Vin, const A* Rinv, T* Vout, T* Wout,
                                const BlockPtrs& Q, int nq, int with_self, A* part, int nwg,
                                const Ctl* ctl);
+    // sweep 1: W = (A Vin) Rinv, Vout = Vin Rinv (Rinv may be NULL = identity)
+    static hipError_t spmm_rinv(hipStream_t st, int P, int64_t n, const int* rp, const int* ci,
+                                const T* av, const T* Vin, const A* Rinv, T* Vout, T* Wout,
+                                const Ctl* ctl);
     // W' = W - Q S (S optional) then W' = W' Rmul (optional); store W' (optional);
     // partials [Q^H W' (dot_q)] [W'^H W' (gram)]
     // kind: 1 = Arnoldi sweep 2 (k_proj_dot), 2 = Arnoldi sweep 3 (k_proj_gram), 0 = other (k_tsdot)

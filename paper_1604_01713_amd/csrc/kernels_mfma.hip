@@ -104,7 +104,7 @@ __device__ inline void load_update_operands(T (&qv)[NQM * (P / 4)], const BlockP
     }
 }
 
-// D (layout of MX<T>) = W^T + (-S)^T Q^T for 16 rows; Ss holds -S as [c][16]
+// D (layout of MX<T>) = W^T + (-S)^T Q^T for 16 rows; Ss holds -S as [c][P]
 template <class T, int P, int NQM>
 __device__ inline typename MX<T>::acc update_mma(typename MX<T>::acc d, const T (&qv)[NQM * (P / 4)], int nq,
                                                  const T* Ss, int lane) {
@@ -114,7 +114,7 @@ __device__ inline typename MX<T>::acc update_mma(typename MX<T>::acc d, const T 
         if (blk < nq) {
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) {
-                const T sv = Ss[(blk * P + 4 * kk + (lane >> 4)) * 16 + (lane & 15)];
+                const T sv = (lane & 15) < P ? Ss[(blk * P + 4 * kk + (lane >> 4)) * P + (lane & 15)] : (T)0;
                 d = MX<T>::mma(sv, qv[blk * KK + kk], d);
             }
         }
@@ -184,16 +184,13 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(int64_t n, const T* __res
     if (ctl && ctl->active == 0) return;
     const int q = nq * P, nc16 = (q + 15) / 16;
     extern __shared__ __align__(16) unsigned char smem[];
-    T* Ss = (T*)smem;                        // [NQM*P][16]
-    T* Qt = Ss + NQM * P * 16;               // [4 waves][16][QLD]
+    T* Ss = (T*)smem;                        // [NQM*P][P]
+    T* Qt = Ss + NQM * P * P;                // [4 waves][16][QLD]
     T* Wt = Qt + 4 * 16 * QLD;               // [4 waves][16][P]
     double* red = (double*)smem;             // reused at the end: 1024 doubles
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int nup = S ? nq : 0;
-    for (int e = t; e < NQM * P * 16; e += 256) {
-        const int c = e >> 4, b = e & 15;
-        Ss[e] = (S && c < q && b < P) ? (T)(-S[c * P + b]) : (T)0;
-    }
+    for (int e = t; e < NQM * P * P; e += 256) Ss[e] = (S && e < q * P) ? (T)(-S[e]) : (T)0;
     typename M::acc acc[NCM];
 #pragma unroll
     for (int ch = 0; ch < NCM; ++ch) acc[ch] = typename M::acc{0, 0, 0, 0};
@@ -203,15 +200,22 @@ __global__ __launch_bounds__(256) void k_proj_dot_mfma(int64_t n, const T* __res
     T* myQ = Qt + wave * 16 * QLD;
     T* myW = Wt + wave * 16 * P;
     T qn[NQV];
-    if (t0 < t1) load_update_operands<T, P, NQM>(qn, Q, nq, t0 * MROWS + wave * 16, n, lane);
+    typename M::acc wn = typename M::acc{0, 0, 0, 0};
+    if (t0 < t1) {
+        load_update_operands<T, P, NQM>(qn, Q, nq, t0 * MROWS + wave * 16, n, lane);
+        wn = load_wt<T, P>(Win, t0 * MROWS + wave * 16, n, lane);
+    }
     __syncthreads();
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t rbase = tile * MROWS + wave * 16;
         T qc[NQV];
 #pragma unroll
         for (int e = 0; e < NQV; ++e) qc[e] = qn[e];
-        typename M::acc d = load_wt<T, P>(Win, rbase, n, lane);
-        if (tile + 1 < t1) load_update_operands<T, P, NQM>(qn, Q, nq, rbase + MROWS, n, lane);
+        typename M::acc d = wn;
+        if (tile + 1 < t1) {
+            load_update_operands<T, P, NQM>(qn, Q, nq, rbase + MROWS, n, lane);
+            wn = load_wt<T, P>(Win, rbase + MROWS, n, lane);
+        }
         d = update_mma<T, P, NQM>(d, qc, nup, Ss, lane);
         d_to_lds<T, P>(d, myW, lane);
 #pragma unroll
@@ -250,14 +254,11 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
     if (ctl && ctl->active == 0) return;
     const int q = nq * P;
     extern __shared__ __align__(16) unsigned char smem[];
-    T* Ss = (T*)smem;                  // [NQM*P][16]
-    T* tr = Ss + NQM * P * 16;         // [4 waves][16][P]
+    T* Ss = (T*)smem;                  // [NQM*P][P]
+    T* tr = Ss + NQM * P * P;          // [4 waves][16][P]
     double* red = (double*)smem;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    for (int e = t; e < NQM * P * 16; e += 256) {
-        const int c = e >> 4, b = e & 15;
-        Ss[e] = (c < q && b < P) ? (T)(-S[c * P + b]) : (T)0;
-    }
+    for (int e = t; e < NQM * P * P; e += 256) Ss[e] = (e < q * P) ? (T)(-S[e]) : (T)0;
     d4v gacc = {0, 0, 0, 0};
     const int lw = mx_logical_wg();
     const int64_t ntiles = (n + MROWS - 1) / MROWS;
@@ -265,13 +266,15 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
     T* mytr = tr + wave * 16 * P;
     constexpr int NQA = NQV > 0 ? NQM : 1;  // register array size (one dummy block when there is no update)
     T qn[NQA * KK];
-    if constexpr (NQV > 0) {
-        if (t0 < t1) load_update_operands<T, P, NQA>(qn, Q, nq, t0 * MROWS + wave * 16, n, lane);
+    typename M::acc wn = typename M::acc{0, 0, 0, 0};
+    if (t0 < t1) {
+        if constexpr (NQV > 0) load_update_operands<T, P, NQA>(qn, Q, nq, t0 * MROWS + wave * 16, n, lane);
+        wn = load_wt<T, P>(Win, t0 * MROWS + wave * 16, n, lane);
     }
     __syncthreads();
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t rbase = tile * MROWS + wave * 16;
-        typename M::acc d = load_wt<T, P>(Win, rbase, n, lane);
+        typename M::acc d = wn;
         if constexpr (NQV > 0) {
             T qc[NQA * KK];
 #pragma unroll
@@ -279,6 +282,7 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
             if (tile + 1 < t1) load_update_operands<T, P, NQA>(qn, Q, nq, rbase + MROWS, n, lane);
             d = update_mma<T, P, NQA>(d, qc, nq, Ss, lane);
         }
+        if (tile + 1 < t1) wn = load_wt<T, P>(Win, rbase + MROWS, n, lane);
         const int64_t row = rbase + (lane & 15);
         if (Wout && row < n) {
 #pragma unroll
@@ -473,7 +477,7 @@ static hipError_t launch_proj_dot(hipStream_t st, int64_t n, const T* Win, const
     const int q = nq * P, nc16 = (q + 15) / 16;
 #define L(NC)                                                                                                \
     {                                                                                                        \
-        const size_t lds = std::max((size_t)((NC * 16 / P) * P * 16 + 4 * 16 * (NC * 16 + 1) + 4 * 16 * P) * \
+        const size_t lds = std::max((size_t)((NC * 16 / P) * P * P + 4 * 16 * (NC * 16 + 1) + 4 * 16 * P) *  \
                                         sizeof(T),                                                           \
                                     (size_t)1024 * sizeof(double));                                          \
         static std::once_flag fl;                                                                            \
@@ -498,7 +502,7 @@ static hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, cons
     }
 #define L(NC)                                                                                                \
     {                                                                                                        \
-        const size_t lds = std::max((size_t)((NC * 16 / P) * P * 16 + 4 * 16 * P) * sizeof(T),             \
+        const size_t lds = std::max((size_t)((NC * 16 / P) * P * P + 4 * 16 * P) * sizeof(T),              \
                                     (size_t)1024 * sizeof(double));                                          \
         hipLaunchKernelGGL((k_proj_gram_mfma<T, P, NC * 16 / P>), dim3(nwg), dim3(256), lds, st, n, Win, Q,  \
                            nq, S, Wout, part, ctl);                                                          \

@@ -545,22 +545,24 @@ struct Seq final : bgcr_sequence {
             for (int i = 0; i < j - 1; ++i) Q.push_back(vblk(i));
             const int nq = (int)Q.size();
             const BlockPtrs Q1 = bp(Q);
-            // model-M bytes: sweep 1 reads A, gathers V_j, writes W and V_j, reads [C V_1..V_{j-1}]
             const int na = use_mx ? nwg_mx : nwg;
-            run(BGCR_K_SPMM_DOT, abytes + 3.0 * blkb + sT * n * (kc + (double)(j - 1) * P), [&] {
-                if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx)
-                        return mfma_spmm_dot<T>(st, P, n, Am->row_ptr, Am->col_idx, avT, W2,
-                                                RinvAll + (size_t)(j - 1) * P2, vblk(j - 1), Wb, Q1, nq, part, ctl, na);
-                }
-                return L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
-                                   vblk(j - 1), Wb, Q1, nq, 1, part, na, ctl);
+            // sweep 1a: W = A V_j with V_j = W2 R^{-1} (reads A, gathers W2, writes W and V_j)
+            run(BGCR_K_ARN_SPMM, abytes + 3.0 * blkb, [&] {
+                return L::spmm_rinv(st, P, n, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
+                                    vblk(j - 1), Wb, ctl);
             });
-            const int nout = (nq + 1) * P2;
-            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
             Q.push_back(vblk(j - 1));
             const BlockPtrs QB = bp(Q);
             const double qbytes = sT * n * (kc + (double)j * P);
+            // sweep 1b: first block-CGS dots [C V_1..V_j]^H W (reads W and Q)
+            run(BGCR_K_ARN_DOT, blkb + qbytes, [&] {
+                if constexpr (!std::is_same<T, zd>::value) {
+                    if (use_mx) return mfma_proj_dot<T>(st, P, n, Wb, QB, nq + 1, nullptr, part, ctl, na);
+                }
+                return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
+            });
+            const int nout = (nq + 1) * P2;
+            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
             run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (use_mx) return mfma_proj_dot<T>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na);
@@ -622,7 +624,7 @@ struct Seq final : bgcr_sequence {
         if (co.breakdown) breakdown_seen = true;
         // model-M algorithmic bytes of the executed Arnoldi sweeps
         for (int j = 1; j <= me; ++j)
-            alg_bytes += abytes + 5.0 * blkb + 3.0 * sT * n * (kc + (double)j * P);
+            alg_bytes += abytes + 7.0 * blkb + 3.0 * sT * n * (kc + (double)j * P);
         n_spmm += me;
         n_steps += me;
         return co;
