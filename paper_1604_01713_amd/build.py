@@ -26,7 +26,7 @@ HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-fcx-limit
 # complex products without the NaN-recovery path (operands are finite and checked)
 CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-march=x86-64-v3", "-fcx-limited-range", "-I", INCLUDE, "-I", CSRC]
 
-HIP_SOURCES = ["kernels.hip", "kernels_mfma.hip", "solver.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_mfma_f64.hip", "kernels_mfma_f32.hip", "solver.cpp"]
 CXX_SOURCES = ["dense.cpp"]
 
 
@@ -52,7 +52,7 @@ def build(verbose: bool = False) -> str:
         o = os.path.join(BUILD, s + ".o")
         objs.append(o)
         jobs.append(["g++", *CXX_FLAGS, "-c", os.path.join(CSRC, s), "-o", o])
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(jobs))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(6, len(jobs))) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:
         for o in outs:

@@ -1,0 +1,511 @@
+// Matrix-core (MFMA) versions of the three block-Arnoldi sweeps for block
+// sizes P = 8 and 16 with real FP64 or FP32 basis storage (templates; the
+// FP64 and FP32 instantiations live in their own translation units).
+//
+// Every sweep streams n rows of a few tall-skinny n x P blocks; all dense
+// contractions run on v_mfma_*_16x16x4 tiles:
+//   * block dot products S = Q^T W   : S^T = W^T Q, contraction over rows
+//     (K = 4 rows per instruction), accumulated over the row range of a
+//     workgroup;
+//   * block-CGS update  W' = W - Q S : (W')^T = W^T + (-S)^T Q^T, contraction
+//     over the columns of Q (K = 4 columns per instruction);
+//   * Gram matrix W''^T W'' in FP64 (also for FP32 storage).
+// Operand layouts of a 16x16x4 instruction (lane l):
+//   A[i][k] = lane (i = l % 16, k = l / 16), B[k][j] = lane (k = l / 16, j = l % 16)
+//   D[i][j]: FP64 lane l element v holds i = l/16 + 4v, j = l % 16;
+//            FP32 lane l element v holds i = 4(l/16) + v, j = l % 16.
+// The kernels are templated on the exact number NC of 16-column chunks of Q,
+// so that every load and MFMA of a tile is straight-line code.  Loads are
+// never conditional and their values never go through a select (the compiler
+// would turn such a select into a branch around the load and wait for it
+// there): addresses are clamped into the buffers, operand lanes past P or
+// past the last column only feed outputs that are never written, and rows
+// past n are zeroed after the loads (on the update result, or on the W
+// operand of the last, partial tile).
+#pragma once
+
+#include <algorithm>
+#include <mutex>
+
+#include "bgcr_internal.h"
+
+namespace bgcr {
+namespace mx {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <class T> struct MX;
+template <> struct MX<double> {
+    using acc = d4v;
+    __device__ static acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int drow(int l, int v) { return (l >> 4) + 4 * v; }
+    // elements v < VN of a D tile can hold a row below P (for every lane)
+    template <int P> static constexpr int vn() { return P / 4 < 4 ? P / 4 : 4; }
+};
+template <> struct MX<float> {
+    using acc = f4v;
+    __device__ static acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int drow(int l, int v) { return 4 * (l >> 4) + v; }
+    template <int P> static constexpr int vn() { return 4; }
+};
+
+constexpr int MROWS = 64;  // rows per workgroup tile of the update sweeps (4 waves x 16 rows)
+
+// XCD-aware renumbering: consecutive logical workgroups (adjacent row ranges)
+// run on the same XCD, which shares one L2.
+__device__ inline int logical_wg() {
+    const int w = blockIdx.x, G = gridDim.x;
+    if (G % 8 != 0) return w;
+    return (w % 8) * (G / 8) + (w / 8);
+}
+
+__device__ inline void tile_span(int64_t ntiles, int lw, int64_t& t0, int64_t& t1) {
+    t0 = (int64_t)lw * ntiles / gridDim.x;
+    t1 = (int64_t)(lw + 1) * ntiles / gridDim.x;
+}
+
+// Cross-wave reduction of the dot accumulators and write of the workgroup
+// partial: chunk ch holds S^T[b][c] with b = drow(l, v), c = 16 ch + l % 16.
+// Output part[lw][c P + b].
+template <class T, int P, int NC>
+__device__ inline void write_dot_partials(const typename MX<T>::acc (&acc)[NC], int q, double* red, double* part,
+                                          int lw, int nout) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) {
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) red[(wave * 4 + v) * 64 + lane] = (double)acc[ch][v];
+        __syncthreads();
+        // thread t -> (v, lane) = (t / 64, t % 64): sum the 4 waves in order
+        const int v = t >> 6, l = t & 63;
+        const double s = red[(0 * 4 + v) * 64 + l] + red[(1 * 4 + v) * 64 + l] + red[(2 * 4 + v) * 64 + l] +
+                         red[(3 * 4 + v) * 64 + l];
+        const int b = MX<T>::drow(l, v);
+        const int c = ch * 16 + (l & 15);
+        if (b < P && c < q) part[(int64_t)lw * nout + (int64_t)c * P + b] = s;
+    }
+}
+
+// Gram accumulator (FP64 MFMA, D[i][j] = G[i][j]) -> part[lw][i P + j]
+template <int P>
+__device__ inline void write_gram_partials(d4v g, double* red, double* part, int lw, int nout) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) red[(wave * 4 + v) * 64 + lane] = g[v];
+    __syncthreads();
+    const int v = t >> 6, l = t & 63;
+    const double s = red[(0 * 4 + v) * 64 + l] + red[(1 * 4 + v) * 64 + l] + red[(2 * 4 + v) * 64 + l] +
+                     red[(3 * 4 + v) * 64 + l];
+    const int i = MX<double>::drow(l, v), j = l & 15;
+    if (i < P && j < P) part[(int64_t)lw * nout + i * P + j] = s;
+}
+
+// Per-lane source of the row-major ("RC") operand: lane l reads column
+// c = 16 ch + l % 16 of [Q_0 .. Q_{nq-1}].  Columns past the last block read
+// block 0 (their dot products are never written).  Block pointers are
+// selected with compile-time indices only (wave-uniform scalar loads).
+template <class T, int P, int NC>
+__device__ inline void rc_pointers(const T* (&qp)[NC], const BlockPtrs& Q, int nq, int lane) {
+    const int cl = lane & 15;
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) {
+        if constexpr (P == 16) {
+            qp[ch] = (const T*)(ch < nq ? Q.p[ch] : Q.p[0]) + cl;
+        } else {
+            const T* p0 = (const T*)(2 * ch < nq ? Q.p[2 * ch] : Q.p[0]);
+            const T* p1 = (const T*)(2 * ch + 1 < nq ? Q.p[2 * ch + 1] : Q.p[0]);
+            qp[ch] = ((cl >> 3) ? p1 : p0) + (cl & 7);
+        }
+    }
+}
+
+__device__ inline int64_t clamp_row(int64_t row, int64_t n) { return row < n ? row : n - 1; }
+
+// RC operands of KS groups of 4 rows from rbase: [ks][ch] holds
+// Q[rbase + 4 ks + l / 16][16 ch + l % 16] (rows clamped to n - 1)
+template <class T, int P, int NC, int KS>
+__device__ inline void load_rc(T (&qv)[KS][NC], const T* const (&qp)[NC], int64_t rbase, int64_t n, int lane) {
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int64_t off = clamp_row(rbase + 4 * ks + (lane >> 4), n) * P;
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) qv[ks][ch] = qp[ch][off];
+    }
+}
+
+// A operand of the dot for KS groups of 4 rows: W[rbase + 4 ks + l / 16][l % 16]
+// (rows clamped; lanes l % 16 >= P repeat column l % P)
+template <class T, int P, int KS>
+__device__ inline void load_wa(T (&w)[KS], const T* __restrict__ W, int64_t rbase, int64_t n, int lane) {
+    const int bc = lane & (P - 1);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) w[ks] = W[clamp_row(rbase + 4 * ks + (lane >> 4), n) * P + bc];
+}
+
+// W^T tile in the D layout for rows rbase .. rbase + 15 (rows clamped; D rows
+// past P repeat row b % P)
+template <class T, int P>
+__device__ inline typename MX<T>::acc load_wt(const T* __restrict__ W, int64_t rbase, int64_t n, int lane) {
+    typename MX<T>::acc d = typename MX<T>::acc{0, 0, 0, 0};
+    const int64_t off = clamp_row(rbase + (lane & 15), n) * P;
+#pragma unroll
+    for (int v = 0; v < MX<T>::template vn<P>(); ++v) d[v] = W[off + (MX<T>::drow(lane, v) & (P - 1))];
+    return d;
+}
+
+// zero a D-layout tile in the rows (j = l % 16) at or past n
+template <class T>
+__device__ inline void zero_tail(typename MX<T>::acc& d, int64_t rbase, int64_t n, int lane) {
+    const bool rok = rbase + (lane & 15) < n;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) d[v] = rok ? d[v] : (T)0;
+}
+
+// D-layout tile -> row-major 16 x P in LDS
+template <class T, int P>
+__device__ inline void d_to_lds(const typename MX<T>::acc& d, T* tr, int lane) {
+#pragma unroll
+    for (int v = 0; v < MX<T>::template vn<P>(); ++v) {
+        const int b = MX<T>::drow(lane, v);
+        if (b < P) tr[(lane & 15) * P + b] = d[v];
+    }
+}
+
+// Wave-private LDS tile of 16 rows x QLD columns (QLD a multiple of 32),
+// XOR-swizzled on column bits 2..4 so that both the row-major (4 rows x 16
+// columns) and the column-major (16 rows x 4 columns) accesses of a wave
+// spread evenly over the banks.
+template <int QLD>
+__device__ inline int qsw(int r, int c) {
+    const int s = ((r & 1) << 2) | ((r >> 1) & 3);
+    return r * QLD + (c ^ (s << 2));
+}
+
+// ---------------------------------------------------------------------------
+// dot sweep: partial S^T = W^T [Q_0 .. Q_{nq-1}] (no update).  Both MFMA
+// operands are loaded from global memory directly in their register layout
+// (A = W[row][b], B = Q[row][c], 4 rows per instruction), so the sweep needs
+// no LDS besides the final cross-wave reduction; the next wave tile is loaded
+// while the current one is multiplied.
+// ---------------------------------------------------------------------------
+template <class T, int P, int NC, int KS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && NC >= 16 ? 1 : 2))) void k_dot_mfma(
+    int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq, double* __restrict__ part, const Ctl* ctl) {
+    using M = MX<T>;
+    constexpr int WROWS = 4 * KS, TROWS = 4 * WROWS;
+    if (ctl && ctl->active == 0) return;
+    const int q = nq * P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* red = (double*)smem;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const T* qp[NC];
+    rc_pointers<T, P, NC>(qp, Q, nq, lane);
+    typename M::acc acc[NC];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) acc[ch] = typename M::acc{0, 0, 0, 0};
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_span((n + TROWS - 1) / TROWS, lw, t0, t1);
+    T qn[KS][NC], wn[KS];
+    if (t0 < t1) {
+        load_rc<T, P, NC, KS>(qn, qp, t0 * TROWS + wave * WROWS, n, lane);
+        load_wa<T, P, KS>(wn, Win, t0 * TROWS + wave * WROWS, n, lane);
+    }
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t rbase = tile * TROWS + wave * WROWS;
+        T qc[KS][NC], wc[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            wc[ks] = wn[ks];
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) qc[ks][ch] = qn[ks][ch];
+        }
+        if (rbase + WROWS > n) {  // last, partial tile: rows past n contribute nothing
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) wc[ks] = rbase + 4 * ks + (lane >> 4) < n ? wc[ks] : (T)0;
+        }
+        if (tile + 1 < t1) {
+            load_rc<T, P, NC, KS>(qn, qp, rbase + TROWS, n, lane);
+            load_wa<T, P, KS>(wn, Win, rbase + TROWS, n, lane);
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) acc[ch] = M::mma(wc[ks], qc[ks][ch], acc[ch]);
+    }
+    write_dot_partials<T, P, NC>(acc, q, red, part, lw, q * P);
+}
+
+// ---------------------------------------------------------------------------
+// update-and-dot sweep: W' = W - Q S (not stored); partial S' = Q^T W'.
+// Q is loaded row-major, staged in a wave-private LDS tile and read back
+// column-major for the update and row-major for the dot; the next tile's
+// loads are in flight while the current one is computed.  No workgroup
+// barrier inside the loop (each wave only reads what it wrote).
+// ---------------------------------------------------------------------------
+template <class T, int P, int NC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 ? NC <= 7 : NC <= 10) ? 2 : 1))) void k_proj_dot_mfma(
+    int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq, const double* __restrict__ S, double* __restrict__ part,
+    const Ctl* ctl) {
+    using M = MX<T>;
+    constexpr int NQ = NC * 16 / P, KK = P / 4, QLD = 32 * ((NC + 1) / 2);
+    if (ctl && ctl->active == 0) return;
+    const int q = nq * P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* Ss = (T*)smem;                        // [NQ*P][P]: -S, zero past q
+    T* Qt = Ss + NQ * P * P;                 // [4 waves][16][QLD]
+    T* Wt = Qt + 4 * 16 * QLD;               // [4 waves][16][P]
+    double* red = (double*)smem;             // reused at the end: 1024 doubles
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int bl = lane & 15, rq = lane >> 4, bc = bl & (P - 1);
+    for (int e = t; e < NQ * P * P; e += 256) Ss[e] = (e < q * P) ? (T)(-S[e]) : (T)0;
+    const T* qp[NC];
+    rc_pointers<T, P, NC>(qp, Q, nq, lane);
+    typename M::acc acc[NC];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) acc[ch] = typename M::acc{0, 0, 0, 0};
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_span((n + MROWS - 1) / MROWS, lw, t0, t1);
+    T* myQ = Qt + wave * 16 * QLD;
+    T* myW = Wt + wave * 16 * P;
+    T qn[4][NC];
+    typename M::acc wn = typename M::acc{0, 0, 0, 0};
+    if (t0 < t1) {
+        load_rc<T, P, NC, 4>(qn, qp, t0 * MROWS + wave * 16, n, lane);
+        wn = load_wt<T, P>(Win, t0 * MROWS + wave * 16, n, lane);
+    }
+    __syncthreads();
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t rbase = tile * MROWS + wave * 16;
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) myQ[qsw<QLD>(4 * ks + rq, 16 * ch + bl)] = qn[ks][ch];
+        typename M::acc d = wn;
+        if (tile + 1 < t1) {
+            load_rc<T, P, NC, 4>(qn, qp, rbase + MROWS, n, lane);
+            wn = load_wt<T, P>(Win, rbase + MROWS, n, lane);
+        }
+        // D = W^T + (-S)^T Q^T over the columns of Q, 4 per instruction
+        // (A rows past P repeat row b % P; those D rows are never stored)
+#pragma unroll
+        for (int blk = 0; blk < NQ; ++blk) {
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                const int c = blk * P + 4 * kk + rq;
+                d = M::mma(Ss[c * P + bc], myQ[qsw<QLD>(bl, c)], d);
+            }
+        }
+        zero_tail<T>(d, rbase, n, lane);
+        d_to_lds<T, P>(d, myW, lane);
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int rl = 4 * ks + rq;
+            const T wv = myW[rl * P + bc];
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) acc[ch] = M::mma(wv, myQ[qsw<QLD>(rl, 16 * ch + bl)], acc[ch]);
+        }
+    }
+    write_dot_partials<T, P, NC>(acc, q, red, part, lw, q * P);
+}
+
+// ---------------------------------------------------------------------------
+// update-and-Gram sweep: W'' = W - Q S, stored (optional); partial Gram
+// W''^T W'' in FP64.  NC = 0: no update (Gram of W only).  The update
+// operands are loaded column-major straight into registers, double-buffered.
+// ---------------------------------------------------------------------------
+template <class T, int P, int NC>
+__global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq,
+                                                        const double* __restrict__ S, T* __restrict__ Wout,
+                                                        double* __restrict__ part, const Ctl* ctl) {
+    using M = MX<T>;
+    constexpr int NQ = NC * 16 / P, KK = P / 4, NQV = NQ * KK, NQA = NQ > 0 ? NQ : 1;
+    if (ctl && ctl->active == 0) return;
+    const int q = nq * P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    T* Ss = (T*)smem;                  // [NQA*P][P]: -S, zero past q
+    T* tr = Ss + NQA * P * P;          // [4 waves][16][P]
+    double* red = (double*)smem;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int bl = lane & 15, rq = lane >> 4, bc = bl & (P - 1);
+    for (int e = t; e < NQA * P * P; e += 256) Ss[e] = (e < q * P) ? (T)(-S[e]) : (T)0;
+    const T* qb[NQA];
+#pragma unroll
+    for (int blk = 0; blk < NQA; ++blk) qb[blk] = (const T*)(blk < nq ? Q.p[blk] : Q.p[0]);
+    d4v gacc = {0, 0, 0, 0};
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_span((n + MROWS - 1) / MROWS, lw, t0, t1);
+    T* mytr = tr + wave * 16 * P;
+    // column-major operands: [blk*KK + kk] holds Q_blk[rbase + l % 16][4 kk + l / 16]
+    auto load_cr = [&](T(&qv)[NQA * KK], int64_t rbase) {
+        const int64_t off = clamp_row(rbase + bl, n) * P + rq;
+#pragma unroll
+        for (int blk = 0; blk < NQ; ++blk)
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) qv[blk * KK + kk] = qb[blk][off + 4 * kk];
+    };
+    T qn[NQA * KK];
+    typename M::acc wn = typename M::acc{0, 0, 0, 0};
+    if (t0 < t1) {
+        if constexpr (NQV > 0) load_cr(qn, t0 * MROWS + wave * 16);
+        wn = load_wt<T, P>(Win, t0 * MROWS + wave * 16, n, lane);
+    }
+    __syncthreads();
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t rbase = tile * MROWS + wave * 16;
+        typename M::acc d = wn;
+        if constexpr (NQV > 0) {
+            T qc[NQA * KK];
+#pragma unroll
+            for (int e = 0; e < NQV; ++e) qc[e] = qn[e];
+            if (tile + 1 < t1) load_cr(qn, rbase + MROWS);
+#pragma unroll
+            for (int blk = 0; blk < NQ; ++blk) {
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) d = M::mma(Ss[(blk * P + 4 * kk + rq) * P + bc], qc[blk * KK + kk], d);
+            }
+        }
+        if (tile + 1 < t1) wn = load_wt<T, P>(Win, rbase + MROWS, n, lane);
+        const int64_t row = rbase + bl;
+        zero_tail<T>(d, rbase, n, lane);
+        if (Wout && row < n) {
+#pragma unroll
+            for (int v = 0; v < M::template vn<P>(); ++v) {
+                const int b = M::drow(lane, v);
+                if (b < P) Wout[row * P + b] = d[v];
+            }
+        }
+        d_to_lds<T, P>(d, mytr, lane);
+        // Gram rows and columns past P repeat column b % P and are never written
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const double wv = (double)mytr[(4 * ks + rq) * P + bc];
+            gacc = MX<double>::mma(wv, wv, gacc);
+        }
+    }
+    write_gram_partials<P>(gacc, red, part, lw, P * P);
+}
+
+// ---------------------------------------------------------------------------
+// launchers: hipErrorNotSupported when the shape has no MFMA variant
+// ---------------------------------------------------------------------------
+template <class F>
+inline void allow_lds(F* f) {
+    (void)hipFuncSetAttribute((const void*)f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+// dispatch on the exact chunk count nc (1..16)
+#define BGCR_MX_NC_DISPATCH(nc, MACRO) \
+    switch (nc) {                      \
+        case 1: MACRO(1); break;       \
+        case 2: MACRO(2); break;       \
+        case 3: MACRO(3); break;       \
+        case 4: MACRO(4); break;       \
+        case 5: MACRO(5); break;       \
+        case 6: MACRO(6); break;       \
+        case 7: MACRO(7); break;       \
+        case 8: MACRO(8); break;       \
+        case 9: MACRO(9); break;       \
+        case 10: MACRO(10); break;     \
+        case 11: MACRO(11); break;     \
+        case 12: MACRO(12); break;     \
+        case 13: MACRO(13); break;     \
+        case 14: MACRO(14); break;     \
+        case 15: MACRO(15); break;     \
+        case 16: MACRO(16); break;     \
+        default: return hipErrorNotSupported; \
+    }
+
+// rows per wave tile of the dot sweep (4 KS) so that the double-buffered
+// operands keep two waves per SIMD
+template <int NC>
+constexpr int dot_ks() {
+    return NC <= 8 ? 4 : (NC <= 12 ? 2 : 1);
+}
+
+template <class T, int P>
+hipError_t launch_dot(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, double* part, int nwg,
+                      const Ctl* ctl) {
+    const int nc = (nq * P + 15) / 16;
+    const size_t lds = (size_t)1024 * sizeof(double);
+#define L(NC)                                                                                                    \
+    hipLaunchKernelGGL((k_dot_mfma<T, P, NC, dot_ks<NC>()>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, part, \
+                       ctl)
+    BGCR_MX_NC_DISPATCH(nc, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <class T, int P>
+hipError_t launch_proj_dot(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
+                           double* part, int nwg, const Ctl* ctl) {
+    const int nc = (nq * P + 15) / 16;
+#define L(NC)                                                                                                   \
+    {                                                                                                           \
+        constexpr int NQ = NC * 16 / P, QLD = 32 * ((NC + 1) / 2);                                              \
+        const size_t lds = std::max((size_t)(NQ * P * P + 4 * 16 * QLD + 4 * 16 * P) * sizeof(T),                \
+                                    (size_t)1024 * sizeof(double));                                             \
+        if (lds > (size_t)160 * 1024) return hipErrorNotSupported;                                              \
+        static std::once_flag fl;                                                                               \
+        std::call_once(fl, [] { allow_lds(k_proj_dot_mfma<T, P, NC>); });                                       \
+        hipLaunchKernelGGL((k_proj_dot_mfma<T, P, NC>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, part, \
+                           ctl);                                                                                \
+    }
+    BGCR_MX_NC_DISPATCH(nc, L)
+#undef L
+    return hipGetLastError();
+}
+
+template <class T, int P>
+hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
+                            T* Wout, double* part, int nwg, const Ctl* ctl) {
+    const int nc = (nq * P + 15) / 16;
+#define L(NC)                                                                                                    \
+    {                                                                                                            \
+        constexpr int NQA = NC * 16 / P > 0 ? NC * 16 / P : 1;                                                   \
+        const size_t lds = std::max((size_t)(NQA * P * P + 4 * 16 * P) * sizeof(T), (size_t)1024 * sizeof(double)); \
+        hipLaunchKernelGGL((k_proj_gram_mfma<T, P, NC>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, Wout,  \
+                           part, ctl);                                                                           \
+    }
+    if (nq == 0) {
+        L(0);
+        return hipGetLastError();
+    }
+    BGCR_MX_NC_DISPATCH(nc, L)
+#undef L
+    return hipGetLastError();
+}
+
+}  // namespace mx
+
+// public entry points (declared in bgcr_internal.h), instantiated per type
+template <class T>
+hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, double* part,
+                    const Ctl* ctl, int nwg) {
+    if (P == 8) return mx::launch_dot<T, 8>(st, n, Win, Q, nq, part, nwg, ctl);
+    if (P == 16) return mx::launch_dot<T, 16>(st, n, Win, Q, nq, part, nwg, ctl);
+    return hipErrorNotSupported;
+}
+
+template <class T>
+hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
+                         double* part, const Ctl* ctl, int nwg) {
+    if (P == 8) return mx::launch_proj_dot<T, 8>(st, n, Win, Q, nq, S, part, nwg, ctl);
+    if (P == 16) return mx::launch_proj_dot<T, 16>(st, n, Win, Q, nq, S, part, nwg, ctl);
+    return hipErrorNotSupported;
+}
+
+template <class T>
+hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
+                          const double* S, T* Wout, double* part, const Ctl* ctl, int nwg) {
+    if (P == 8) return mx::launch_proj_gram<T, 8>(st, n, Win, Q, nq, S, Wout, part, nwg, ctl);
+    if (P == 16) return mx::launch_proj_gram<T, 16>(st, n, Win, Q, nq, S, Wout, part, nwg, ctl);
+    return hipErrorNotSupported;
+}
+
+}  // namespace bgcr

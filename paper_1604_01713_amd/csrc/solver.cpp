@@ -210,7 +210,8 @@ struct Seq final : bgcr_sequence {
         nwg_mx = mfma_nwg(n);
         const char* e = std::getenv("BGCR_NO_MFMA");
         const bool off = e && e[0] == '1';
-        use_mx = !off && !std::is_same<T, zd>::value && (P == 8 || P == 16) && (KB + m) * P <= 256;
+        use_mx = !off && !std::is_same<T, zd>::value && (P == 8 || P == 16) &&
+                 (KB + m) * P <= (P == 16 && sizeof(T) == 8 ? 224 : 256);
     }
 
     ~Seq() override {
@@ -386,7 +387,7 @@ struct Seq final : bgcr_sequence {
                 std::vector<const void*> sub(Q.begin() + q0, Q.begin() + q0 + qn);
                 run(BGCR_K_TSDOT, (double)sizeof(T) * n * P * (1 + qn), [&] {
                     if constexpr (!std::is_same<T, zd>::value) {
-                        if (use_mx) return mfma_proj_dot<T>(st, P, n, W[w], bp(sub), qn, nullptr, part, nullptr, nr);
+                        if (use_mx) return mfma_dot<T>(st, P, n, W[w], bp(sub), qn, part, nullptr, nr);
                     }
                     return L::update_dot(st, P, n, W[w], bp(sub), qn, nullptr, nullptr, nullptr, 1, 0, part, nr, nullptr);
                 });
@@ -557,7 +558,7 @@ struct Seq final : bgcr_sequence {
             // sweep 1b: first block-CGS dots [C V_1..V_j]^H W (reads W and Q)
             run(BGCR_K_ARN_DOT, blkb + qbytes, [&] {
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx) return mfma_proj_dot<T>(st, P, n, Wb, QB, nq + 1, nullptr, part, ctl, na);
+                    if (use_mx) return mfma_dot<T>(st, P, n, Wb, QB, nq + 1, part, ctl, na);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
             });

@@ -101,7 +101,9 @@ def test_reduced_3d_convdiff_parity():
     _compare("cfg2-21^3", systems, w.p, w.m, w.k, w.tol)
 
 
-@pytest.mark.parametrize("p,m,k", [(1, 12, 6), (4, 6, 5), (16, 4, 8), (2, 5, 0)])
+@pytest.mark.parametrize("p,m,k", [(1, 12, 6), (4, 6, 5), (16, 4, 8), (2, 5, 0),
+                                   # wide bases: every chunk count of the matrix-core sweeps up to 15
+                                   (8, 16, 24), (8, 26, 20), (16, 12, 20)])
 def test_block_sizes_and_k0(p, m, k):
     A = problems.convdiff(17, 2, conv=(8.0, -3.0, 0.0))  # n = 289
     rng = np.random.default_rng(10 + p)
