@@ -138,6 +138,12 @@ template <class T>
 hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
                           const double* S, T* Wout, double* part, const Ctl* ctl, int nwg);
 
+// Y (+)= [in..] C on matrix cores (real FP64/FP32 inputs, FP64 coefficients
+// row-major (nin P) x (nout P)); hipErrorNotSupported for other shapes
+template <class TI, class TO>
+hipError_t mfma_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
+                        const double* coef, int accumulate, int nwg);
+
 hipError_t cast_values(hipStream_t st, const double* in, float* out, int64_t nnz);
 template <class TI, class TO>
 hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ldi, TO* out,

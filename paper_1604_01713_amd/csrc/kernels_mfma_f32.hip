@@ -11,4 +11,9 @@ template hipError_t mfma_proj_dot<float>(hipStream_t, int, int64_t, const float*
 template hipError_t mfma_proj_gram<float>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int,
                                           const double*, float*, double*, const Ctl*, int);
 
+template hipError_t mfma_combine<float, float>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&,
+                                                  int, const double*, int, int);
+template hipError_t mfma_combine<float, double>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&,
+                                                  int, const double*, int, int);
+
 }  // namespace bgcr

@@ -32,4 +32,7 @@ template hipError_t mfma_proj_dot<double>(hipStream_t, int, int64_t, const doubl
 template hipError_t mfma_proj_gram<double>(hipStream_t, int, int64_t, const double*, const BlockPtrs&, int,
                                            const double*, double*, double*, const Ctl*, int);
 
+template hipError_t mfma_combine<double, double>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&,
+                                                  int, const double*, int, int);
+
 }  // namespace bgcr

@@ -481,6 +481,126 @@ hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const Block
     return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// block combination Y (+)= X C with X = [in_0 .. in_{nin-1}] (n x K, K = nin P)
+// and Y = [out_0 .. out_{nout-1}] (n x N, N = nout P), C (K x N) row-major in
+// FP64: a tall-skinny product on FP64 matrix cores (FP32 inputs are widened).
+// A = X[row][k] (column-major operand loads straight into registers, G input
+// blocks per pipeline step, the next step's loads in flight while the current
+// one is multiplied; the step sequence runs across row tiles), B = C[k][j]
+// from LDS, padded to NCO chunks of 16 output columns.
+// ---------------------------------------------------------------------------
+template <class TI, class TO, int P, int NCO>
+__global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, int nin, BlockPtrs out, int nout,
+                                                      const double* __restrict__ coef, int accumulate) {
+    using M = MX<double>;
+    constexpr int KK = P / 4, G = 64 / P, NV = G * KK, NPAD = 16 * NCO;
+    const int N = nout * P, K = nin * P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* Cs = (double*)smem;  // [K][NPAD]
+    for (int e = threadIdx.x; e < K * NPAD; e += 256) {
+        const int k = e / NPAD, j = e % NPAD;
+        Cs[e] = j < N ? coef[(int64_t)k * N + j] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, bl = lane & 15, rq = lane >> 4;
+    const int nch = (nin + G - 1) / G;
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_span((n + MROWS - 1) / MROWS, lw, t0, t1);
+    const int64_t nsteps = (t1 - t0) * nch;
+    auto load = [&](double(&v)[NV], int64_t s) {
+        const int64_t tile = t0 + s / nch;
+        const int c = (int)(s % nch);
+        const int64_t off = clamp_row(tile * MROWS + wave * 16 + bl, n) * P + rq;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int blk = c * G + g;
+            const TI* p = (const TI*)in.p[blk < nin ? blk : 0];
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) v[g * KK + kk] = (double)p[off + 4 * kk];
+        }
+    };
+    typename M::acc acc[NCO];
+#pragma unroll
+    for (int oc = 0; oc < NCO; ++oc) acc[oc] = typename M::acc{0, 0, 0, 0};
+    double an[NV];
+    if (nsteps > 0) load(an, 0);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        double ac[NV];
+#pragma unroll
+        for (int e = 0; e < NV; ++e) ac[e] = an[e];
+        if (s + 1 < nsteps) load(an, s + 1);
+        const int c = (int)(s % nch);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int blk = c * G + g;
+            if (blk < nin) {
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) {
+                    const double* cr = Cs + (blk * P + 4 * kk + rq) * NPAD + bl;
+#pragma unroll
+                    for (int oc = 0; oc < NCO; ++oc) acc[oc] = M::mma(ac[g * KK + kk], cr[16 * oc], acc[oc]);
+                }
+            }
+        }
+        if (c == nch - 1) {
+            // D[row][col]: lane l element v holds row rbase + l/16 + 4v, column 16 oc + l%16
+            const int64_t rbase = (t0 + s / nch) * MROWS + wave * 16;
+#pragma unroll
+            for (int oc = 0; oc < NCO; ++oc) {
+                const int col = 16 * oc + bl;
+                const int ob = col / P, b = col % P;
+                TO* ybase;
+                if constexpr (P == 16) {
+                    ybase = (TO*)out.p[oc];
+                } else {
+                    TO* y0 = (TO*)out.p[2 * oc];
+                    TO* y1 = (TO*)out.p[2 * oc + 1 < nout ? 2 * oc + 1 : 2 * oc];
+                    ybase = (ob & 1) ? y1 : y0;
+                }
+                double old[4] = {0, 0, 0, 0};
+                if (accumulate) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        old[v] = (double)ybase[clamp_row(rbase + rq + 4 * v, n) * P + (col < N ? b : 0)];
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = rbase + rq + 4 * v;
+                    if (row < n && col < N) ybase[row * P + b] = (TO)(acc[oc][v] + old[v]);
+                }
+                acc[oc] = typename M::acc{0, 0, 0, 0};
+            }
+        }
+    }
+}
+
+template <class TI, class TO, int P>
+hipError_t launch_combine(hipStream_t st, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
+                          const double* coef, int accumulate, int nwg) {
+    const int nco = (nout * P + 15) / 16;
+    const size_t lds = (size_t)nin * P * 16 * nco * sizeof(double);
+    if (nin < 1 || nout < 1 || lds > (size_t)160 * 1024) return hipErrorNotSupported;
+#define L(NCO)                                                                                             \
+    {                                                                                                      \
+        static std::once_flag fl;                                                                          \
+        std::call_once(fl, [] { allow_lds(k_combine_mfma<TI, TO, P, NCO>); });                             \
+        hipLaunchKernelGGL((k_combine_mfma<TI, TO, P, NCO>), dim3(nwg), dim3(256), lds, st, n, in, nin, out, \
+                           nout, coef, accumulate);                                                         \
+    }
+    switch (nco) {
+        case 1: L(1); break;
+        case 2: L(2); break;
+        case 3: L(3); break;
+        case 4: L(4); break;
+        default: return hipErrorNotSupported;
+    }
+#undef L
+    return hipGetLastError();
+}
+
 }  // namespace mx
 
 // public entry points (declared in bgcr_internal.h), instantiated per type
@@ -505,6 +625,14 @@ hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const 
                           const double* S, T* Wout, double* part, const Ctl* ctl, int nwg) {
     if (P == 8) return mx::launch_proj_gram<T, 8>(st, n, Win, Q, nq, S, Wout, part, nwg, ctl);
     if (P == 16) return mx::launch_proj_gram<T, 16>(st, n, Win, Q, nq, S, Wout, part, nwg, ctl);
+    return hipErrorNotSupported;
+}
+
+template <class TI, class TO>
+hipError_t mfma_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
+                        const double* coef, int accumulate, int nwg) {
+    if (P == 8) return mx::launch_combine<TI, TO, 8>(st, n, in, nin, out, nout, coef, accumulate, nwg);
+    if (P == 16) return mx::launch_combine<TI, TO, 16>(st, n, in, nin, out, nout, coef, accumulate, nwg);
     return hipErrorNotSupported;
 }
 

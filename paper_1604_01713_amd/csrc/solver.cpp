@@ -368,7 +368,16 @@ struct Seq final : bgcr_sequence {
         std::vector<const void*> outc(out.begin(), out.end());
         const A* cf = upload_coef(K, nin, nout, coef);
         const double by = (double)n * P * ((double)sizeof(T) * nin + (double)sizeof(TO) * nout * (accumulate ? 2 : 1));
-        run(BGCR_K_COMBINE, by, [&] { return L::template combine<TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate); });
+        run(BGCR_K_COMBINE, by, [&] {
+            if constexpr (!std::is_same<T, zd>::value) {
+                if (use_mx) {
+                    const hipError_t e =
+                        mfma_combine<T, TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate, nwg_mx);
+                    if (e != hipErrorNotSupported) return e;
+                }
+            }
+            return L::template combine<TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate);
+        });
     }
 
     // Q^H W for a list of W blocks: returns Mat (nq P) x (nw P).  Every piece
