@@ -87,7 +87,7 @@ struct Launch {
                                const BlockPtrs& Q, int nq, int with_self, A* part, int nwg,
                                const Ctl* ctl);
     // sweep 1: W = (A Vin) Rinv, Vout = Vin Rinv (Rinv may be NULL = identity)
-    static hipError_t spmm_rinv(hipStream_t st, int P, int64_t n, const int* rp, const int* ci,
+    static hipError_t spmm_rinv(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci,
                                 const T* av, const T* Vin, const A* Rinv, T* Vout, T* Wout,
                                 const Ctl* ctl);
     // W' = W - Q S (S optional) then W' = W' Rmul (optional); store W' (optional);

@@ -10,8 +10,10 @@
 // Reductions over rows are two-stage and deterministic: a workgroup writes
 // its partial sums to part[wg][*]; a second kernel sums them in fixed order.
 #include <mutex>
+#include <type_traits>
 
 #include "bgcr_internal.h"
+#include "spmm_sweep.h"
 
 namespace bgcr {
 
@@ -200,83 +202,6 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int* __restrict__ 
                                              const T* __restrict__ av, const T* __restrict__ Vin, T* Wout) {
     BlockPtrs none;
     spmm_dot_body<T, P>(n, rp, ci, av, Vin, nullptr, nullptr, Wout, none, 0, 0, nullptr, nullptr);
-}
-
-// ---------------------------------------------------------------------------
-// sweep 1 of a block Arnoldi step: W = (A Vin) Rinv and V_j = Vin Rinv.
-// P lanes per row (lane = column b); 8 nonzeros per batch so that all index
-// loads and then all gathers of a batch are in flight together.  The P
-// values of a row are exchanged through LDS for the P x P product.
-// ---------------------------------------------------------------------------
-template <class T, int P>
-__global__ __launch_bounds__(NT) void k_spmm_rinv(int64_t n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                  const T* __restrict__ av, const T* __restrict__ Vin,
-                                                  const acc_t<T>* __restrict__ Rinv, T* __restrict__ Vout,
-                                                  T* __restrict__ Wout, const Ctl* ctl) {
-    using A = acc_t<T>;
-    if (ctl && ctl->active == 0) return;
-    constexpr int ROWS = NT / P;
-    __shared__ A xr[NT], xv[NT];
-    const int t = threadIdx.x, r = t / P, b = t % P;
-    A rc[P];
-#pragma unroll
-    for (int a = 0; a < P; ++a) rc[a] = Rinv ? Rinv[a * P + b] : from_real_h<A>(a == b ? 1.0 : 0.0);
-    // Each XCD owns a contiguous slice of tiles; inside it the workgroups take
-    // tiles round-robin, so the resident workgroups of an XCD sweep one compact
-    // window and the stencil neighbours of that window stay in its L2.
-    const int64_t ntiles = (n + ROWS - 1) / ROWS;
-    const int G = gridDim.x;
-    int64_t first, step, end;
-    if (G % 8 == 0) {
-        const int x = blockIdx.x % 8, i = blockIdx.x / 8;
-        const int64_t a = (int64_t)x * ntiles / 8, z = (int64_t)(x + 1) * ntiles / 8;
-        first = a + i;
-        step = G / 8;
-        end = z;
-    } else {
-        first = blockIdx.x;
-        step = G;
-        end = ntiles;
-    }
-    for (int64_t tile = first; tile < end; tile += step) {
-        const int64_t row = tile * ROWS + r;
-        const bool ok = row < n;
-        T raw = tz<T>();
-        T vb = tz<T>();
-        if (ok) {
-            vb = Vin[row * P + b];
-            const int e = rp[row + 1];
-            for (int kb = rp[row]; kb < e; kb += 8) {
-                int cols[8];
-                T vals[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int kk = kb + u < e ? kb + u : kb;
-                    cols[u] = ci[kk];
-                    vals[u] = kb + u < e ? av[kk] : tz<T>();
-                }
-                T g[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) g[u] = Vin[(int64_t)cols[u] * P + b];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) raw += vals[u] * g[u];
-            }
-        }
-        xr[t] = widen(raw);
-        xv[t] = widen(vb);
-        __syncthreads();
-        A w = zero<A>(), v = zero<A>();
-#pragma unroll
-        for (int a = 0; a < P; ++a) {
-            w += xr[r * P + a] * rc[a];
-            v += xv[r * P + a] * rc[a];
-        }
-        if (ok) {
-            Wout[row * P + b] = narrow<T>(w);
-            Vout[row * P + b] = narrow<T>(v);
-        }
-        __syncthreads();
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -793,17 +718,12 @@ hipError_t Launch<T>::spmm_dot(hipStream_t st, int P, int64_t n, const int* rp, 
 }
 
 template <class T>
-hipError_t Launch<T>::spmm_rinv(hipStream_t st, int P, int64_t n, const int* rp, const int* ci, const T* av,
-                                const T* Vin, const A* Rinv, T* Vout, T* Wout, const Ctl* ctl) {
-    const int64_t rows = NT / P;
-    const int64_t tiles = (n + rows - 1) / rows;
-    int64_t g = tiles < 4 * NWG_MAX ? tiles : 4 * NWG_MAX;
-    if (g >= 8) g -= g % 8;
-    const int nwg = (int)(g < 1 ? 1 : g);
-#define L(PP) hipLaunchKernelGGL((k_spmm_rinv<T, PP>), dim3(nwg), dim3(NT), 0, st, n, rp, ci, av, Vin, Rinv, Vout, Wout, ctl);
+hipError_t Launch<T>::spmm_rinv(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci,
+                                const T* av, const T* Vin, const A* Rinv, T* Vout, T* Wout, const Ctl* ctl) {
+#define L(PP) return sp::launch_spmm_rinv<T, PP, sp::spmm_cols<T, PP>(), false>(st, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl, 2048);
     BGCR_DISPATCH_P(P, L)
 #undef L
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 template <class T>

@@ -558,7 +558,7 @@ struct Seq final : bgcr_sequence {
             const int na = use_mx ? nwg_mx : nwg;
             // sweep 1a: W = A V_j with V_j = W2 R^{-1} (reads A, gathers W2, writes W and V_j)
             run(BGCR_K_ARN_SPMM, abytes + 3.0 * blkb, [&] {
-                return L::spmm_rinv(st, P, n, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
+                return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
                                     vblk(j - 1), Wb, ctl);
             });
             Q.push_back(vblk(j - 1));
