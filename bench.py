@@ -40,10 +40,15 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of every device source; a committed PMC traffic figure is used
+    only while it matches."""
     h = hashlib.sha256()
-    for f in ("kernels.hip", "bgcr_internal.h"):
-        with open(os.path.join(ROOT, "paper_1604_01713_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    cs = os.path.join(ROOT, "paper_1604_01713_amd", "csrc")
+    for f in sorted(os.listdir(cs)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(cs, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -95,6 +100,8 @@ def main():
     ap.add_argument("--nsys", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB 5 times (scale factor of the PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -108,6 +115,16 @@ def main():
     bg.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        x = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"bytes_read": nb, "bytes_written": nb, "launches": 5}}), flush=True)
+        return
 
     t0 = time.time()
     w = problems.cfg2(N=args.grid, nsys=args.nsys)
@@ -186,11 +203,14 @@ def main():
                 "alg_bytes_per_launch": round(d["bytes"] / max(1, d["launches"]))}
         tb = sum(prof_sum[c]["bytes"] for c in ARNOLDI)
         tm = sum(prof_sum[c]["ms"] for c in ARNOLDI)
-        allms = sum(v["ms"] for v in prof_sum.values())
+        gpu = {c: v for c, v in prof_sum.items() if not c.startswith("host")}
+        allms = sum(v["ms"] for v in gpu.values())
         arnoldi = {"alg_GBs": round(tb / (tm * 1e-3) / 1e9, 1) if tm > 0 else 0.0,
                    "frac": round(tb / (tm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tm > 0 else 0.0,
                    "share_of_kernel_time": round(tm / allms, 3) if allms > 0 else 0.0,
-                   "kernel_ms": {c: round(v["ms"], 1) for c, v in prof_sum.items()}}
+                   "kernel_ms": {c: round(v["ms"], 1) for c, v in gpu.items()},
+                   "host_ms": {c: round(v["ms"], 1) for c, v in prof_sum.items() if c.startswith("host")},
+                   "wall_ms": round(1e3 * elapsed, 1)}
 
     lat_sorted = np.sort(np.array(all_lat))
     cps = float(np.mean(all_cyc))

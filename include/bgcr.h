@@ -154,7 +154,9 @@ typedef enum {
     BGCR_K_RESIDUAL = 6,     /* FP64 true residual B - A X */
     BGCR_K_TSDOT = 7,        /* other tall-skinny products (CholQR of R, recycle dots) */
     BGCR_K_SPMM = 8,         /* plain block SpMM (recycle import A U) */
-    BGCR_K_NCLASS = 9
+    BGCR_K_HOST = 9,         /* host: small dense algebra of a cycle (wall clock, includes BGCR_K_HOST_EIG) */
+    BGCR_K_HOST_EIG = 10,    /* host: harmonic-Ritz eigenproblem (wall clock) */
+    BGCR_K_NCLASS = 11
 } bgcr_kernel_class;
 
 /* Turn per-kernel timing on (1) or off (0) and reset the counters.  When on,

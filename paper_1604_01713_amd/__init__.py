@@ -42,7 +42,8 @@ EXPORTED_SYMBOLS = [
 ]
 
 # kernel classes of the per-kernel profile (bgcr_kernel_class)
-KERNEL_CLASSES = ["arn_spmm", "arn_dot", "proj_dot", "proj_gram", "small", "combine", "residual", "tsdot", "spmm"]
+KERNEL_CLASSES = ["arn_spmm", "arn_dot", "proj_dot", "proj_gram", "small", "combine", "residual", "tsdot", "spmm",
+                  "host", "host_eig"]
 
 
 class bgcr_params(ctypes.Structure):

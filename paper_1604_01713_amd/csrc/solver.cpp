@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <memory>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -188,6 +189,18 @@ struct Seq final : bgcr_sequence {
         }
         pend.clear();
     }
+    // wall-clock time of a host-side phase, recorded while profiling
+    struct HostPhase {
+        Seq* s;
+        int cls;
+        std::chrono::steady_clock::time_point t0;
+        HostPhase(Seq* s_, int c) : s(s_), cls(c), t0(std::chrono::steady_clock::now()) {}
+        ~HostPhase() {
+            if (!s->prof) return;
+            s->pms[cls] += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            s->pcnt[cls] += 1;
+        }
+    };
     void set_profiling(int on) override {
         prof_resolve(1 << 30);
         prof = on != 0;
@@ -608,6 +621,7 @@ struct Seq final : bgcr_sequence {
                   {hg.data(), g, hg.size() * sizeof(A)},
                   {hRi.data(), RinvAll, hRi.size() * sizeof(A)},
                   {hF.data(), F, (withC && KP > 0) ? (size_t)KP * ldH * sizeof(A) : 0}});
+        HostPhase hp(this, BGCR_K_HOST);
         co.H = Mat((me + 1) * P, mp);
         for (int i = 0; i < (me + 1) * P; ++i)
             for (int j = 0; j < mp; ++j) co.H(i, j) = to_cd(hH[(size_t)i * ldH + j]);
@@ -704,6 +718,7 @@ struct Seq final : bgcr_sequence {
     // form (fallback when inverse iteration gives nearly dependent vectors).
     void eig_select(const Mat& K, bool inverse, int kt, bool robust, std::vector<cd>& theta, dense::Selection& sel,
                     std::vector<std::vector<cd>>& vecs) {
+        HostPhase hp(this, BGCR_K_HOST_EIG);
         const int nn = K.r;
         theta.assign(nn, cd(0.0, 0.0));
         vecs.clear();
@@ -742,6 +757,7 @@ struct Seq final : bgcr_sequence {
             keff = 0;
             return;
         }
+        std::unique_ptr<HostPhase> hp(new HostPhase(this, BGCR_K_HOST));
         Mat Hm = co.H.block(0, 0, mp, mp);
         Mat Hs = co.H.block(mp, mp - P, P, P);
         Mat rhs(mp, P);
@@ -788,6 +804,7 @@ struct Seq final : bgcr_sequence {
         std::vector<void*> out;
         for (int b = 0; b < KB; ++b) out.push_back(ublk(cur, b));
         for (int b = 0; b < KB; ++b) out.push_back(cblk(cur, b));
+        hp.reset();
         combine<T>(in, out, K2, 0);
         keff = kn;
     }
@@ -828,6 +845,7 @@ struct Seq final : bgcr_sequence {
         Q.push_back(co.last);
         for (int b = 0; b < KB; ++b) W.push_back(ublk(cur, b));
         const Mat Dm = multi_dot(Q, W);
+        std::unique_ptr<HostPhase> hp(new HostPhase(this, BGCR_K_HOST));
         const int ke = keff;
         std::vector<double> d(ke);
         for (int i = 0; i < ke; ++i) {
@@ -885,6 +903,7 @@ struct Seq final : bgcr_sequence {
         const int o = 1 - cur;
         for (int b = 0; b < KB; ++b) out.push_back(ublk(o, b));
         for (int b = 0; b < KB; ++b) out.push_back(cblk(o, b));
+        hp.reset();
         combine<T>(Q, out, K2, 0);
         cur = o;
         keff = kn;
