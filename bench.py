@@ -91,6 +91,138 @@ def cpu_baseline(systems, m, k, tol, cycles_per_system):
             "seconds_per_cycle": per_cycle}
 
 
+def _host_check(A, B, X):
+    return float(np.linalg.norm(B - A @ X) / np.linalg.norm(B))
+
+
+def bench_precision(args, torch, problems, bg, dev):
+    """Plain FP64 vs the precision form (FP32 SpMM, basis and BCGS2 inside FP64
+    refinement) on the same anisotropic 3D sequence, same tolerance."""
+    grid = args.grid if args.grid != 128 else 192
+    nsys = args.nsys if args.nsys != 10 else 6
+    w = problems.cfg4(N=grid, nsys=nsys)
+    systems = [(s_.A, s_.B) for s_ in w.systems]
+    n, nnz = systems[0][0].shape[0], systems[0][0].nnz
+    log(f"[bench] precision: {nsys} systems n={n} nnz={nnz} p={w.p} m={w.m} k={w.k} tol={w.tol}")
+    dA = [bg.DeviceCSR.from_scipy(A, dev) for (A, _) in systems]
+    dB = [torch.from_numpy(B).to(dev) for (_, B) in systems]
+    out = {}
+    sols = {}
+    for name, prec in (("plain_fp64", bg.BGCR_PLAIN_FP64), ("mixed_fp32_in_fp64", bg.BGCR_MIXED_FP32)):
+        seq = bg.Sequence(n, w.p, w.m, w.k, precision=prec, max_cycles=5000)
+        dX = [torch.zeros_like(b) for b in dB]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat, cyc, ref = [], [], []
+        for i in range(nsys):
+            ts = time.perf_counter()
+            st = seq.solve(dA[i], dB[i], dX[i], w.tol)
+            lat.append(time.perf_counter() - ts)
+            if st.status != 0:
+                raise RuntimeError(f"{name} system {i}: {st.as_dict()}")
+            cyc.append(st.cycles)
+            ref.append(st.refine_steps)
+            log(f"[bench] {name} system {i}: {lat[-1]:.2f}s cycles={st.cycles} refine={st.refine_steps}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        seq.release()
+        sols[name] = [x.cpu().numpy() for x in dX]
+        worst = max(_host_check(A, B, X) for (A, B), X in zip(systems, sols[name]))
+        out[name] = {"systems_per_s": round(nsys / el, 4), "seconds": round(el, 2),
+                     "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
+                     "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
+                     "cycles_per_system": cyc, "refine_steps": ref, "max_rel_res_fp64_check": worst}
+    diff = max(float(np.linalg.norm(a - b) / np.linalg.norm(b))
+               for a, b in zip(sols["mixed_fp32_in_fp64"], sols["plain_fp64"]))
+    res = {"metric": "systems/s, precision form vs plain FP64, same matrices and tolerance", "unit": "systems/s",
+           "config": {"workload": f"convdiff3d_aniso_{grid}^3_seq{nsys}_p{w.p}_m{w.m}_k{w.k}", "n": n, "nnz": nnz,
+                      "tol": w.tol},
+           "plain_fp64": out["plain_fp64"], "mixed_fp32_in_fp64": out["mixed_fp32_in_fp64"],
+           "speedup_mixed_over_plain": round(out["mixed_fp32_in_fp64"]["systems_per_s"] /
+                                             out["plain_fp64"]["systems_per_s"], 3),
+           "max_rel_diff_mixed_vs_plain_fp64": diff, "data": "synthetic", "n_gpus": 1}
+    print(json.dumps(res), flush=True)
+
+
+def bench_serving(args, torch, problems, bg, dev):
+    """A seeded request stream: serial plain FP64 (one request after the other)
+    vs the served form (continuous batching, HBM-budget admission)."""
+    from paper_1604_01713_amd import serving as sv
+    descs = problems.serving_requests(seed=5, nreq=args.requests, sides=(32, 48, 64, 80), ps=(1, 4, 8, 16),
+                                      nsys_range=(2, 5))
+    cache = {}
+    t0 = time.perf_counter()
+    for d in descs:
+        for i in range(d["nsys"]):
+            s_ = problems.request_system(d, i)
+            cache[(d["id"], i)] = (s_.A, s_.B)
+    log(f"[bench] serving: generated {len(cache)} systems for {len(descs)} requests in {time.perf_counter() - t0:.1f}s")
+
+    def make(prec, arrivals=None):
+        reqs = []
+        for d in descs:
+            A0, _ = cache[(d["id"], 0)]
+            reqs.append(sv.Request(rid=d["id"], arrival=0.0 if arrivals is None else arrivals[d["id"]],
+                                   n=A0.shape[0], p=d["p"], nnz=A0.nnz, nsys=d["nsys"],
+                                   system=(lambda dd: (lambda i: cache[(dd["id"], i)]))(d),
+                                   m=10, k=20, tol=1e-8, precision=prec))
+        return reqs
+
+    budget = 4 << 30
+    nb = lambda r: sv.device_bytes(r, sv.library_footprint)
+    run = sv.gpu_runner(device=dev, keep_solutions=True)
+
+    def go(reqs, slots, realtime):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        res = sv.serve(reqs, run, budget_bytes=budget, slots=slots, bytes_of=nb, realtime=realtime)
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - ts
+
+    def accuracy(res, ref=None):
+        worst, dmax = 0.0, 0.0
+        for r in res:
+            if r.error:
+                raise RuntimeError(f"request {r.rid}: {r.error}")
+            for i, X in enumerate(r.solutions):
+                A, B = cache[(r.rid, i)]
+                worst = max(worst, _host_check(A, B, X))
+                if ref is not None:
+                    Xr = ref[r.rid].solutions[i]
+                    dmax = max(dmax, float(np.linalg.norm(X - Xr) / np.linalg.norm(Xr)))
+        return worst, dmax
+
+    serial, t_serial = go(make(bg.BGCR_PLAIN_FP64), 1, False)
+    sref = {r.rid: r for r in serial}
+    out = {"serial_plain_fp64": sv.summarize(serial, t_serial)}
+    out["serial_plain_fp64"]["max_rel_res_fp64_check"] = accuracy(serial)[0]
+    log(f"[bench] serial plain FP64: {out['serial_plain_fp64']}")
+    for name, prec in (("served_plain_fp64", bg.BGCR_PLAIN_FP64), ("served_mixed", bg.BGCR_MIXED_FP32)):
+        res, t = go(make(prec), 8, False)
+        out[name] = sv.summarize(res, t)
+        out[name]["max_rel_res_fp64_check"], out[name]["max_rel_diff_vs_serial_fp64"] = accuracy(res, sref)
+        log(f"[bench] {name} (all requests at t=0): {out[name]}")
+    # Poisson arrivals at 0.8 of the serial request throughput, for latency
+    rate = 0.8 * len(descs) / t_serial
+    rng = np.random.default_rng(55)
+    arr = np.cumsum(rng.exponential(1.0 / rate, size=len(descs)))
+    res, t = go(make(bg.BGCR_MIXED_FP32, {d["id"]: float(arr[d["id"]]) for d in descs}), 8, True)
+    out["served_mixed_poisson"] = sv.summarize(res, t)
+    out["served_mixed_poisson"]["arrival_rate_per_s"] = round(rate, 4)
+    out["served_mixed_poisson"]["max_rel_res_fp64_check"], _ = accuracy(res)
+    log(f"[bench] served mixed, Poisson arrivals: {out['served_mixed_poisson']}")
+    nsys = sum(d["nsys"] for d in descs)
+    resj = {"metric": "served stream: systems/s and p50/p99 request latency vs serial plain FP64", "unit": "systems/s",
+            "config": {"workload": f"served_convdiff3d_{len(descs)}req", "requests": len(descs), "systems": nsys,
+                       "sides": [32, 48, 64, 80], "p": [1, 4, 8, 16], "systems_per_request": [2, 5],
+                       "m": 10, "k": 20, "tol": 1e-8, "slots": 8, "hbm_budget_bytes": budget},
+            **out,
+            "speedup_served_mixed_over_serial_fp64": round(out["served_mixed"]["systems_per_s"] /
+                                                          out["serial_plain_fp64"]["systems_per_s"], 3),
+            "data": "synthetic", "n_gpus": 1}
+    print(json.dumps(resj), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +232,10 @@ def main():
     ap.add_argument("--nsys", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    ap.add_argument("--workload", choices=["cfg2", "precision", "serving"], default="cfg2",
+                    help="cfg2: the headline sequence (default); precision: plain FP64 vs the FP32-in-FP64 form on "
+                         "the anisotropic 192^3 sequence; serving: a request stream, served vs serial")
+    ap.add_argument("--requests", type=int, default=24, help="serving: number of requests")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (scale factor of the PMC byte counters)")
     args = ap.parse_args()
@@ -115,6 +251,11 @@ def main():
     bg.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+
+    if args.workload == "precision":
+        return bench_precision(args, torch, problems, bg, dev)
+    if args.workload == "serving":
+        return bench_serving(args, torch, problems, bg, dev)
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20

@@ -1,0 +1,58 @@
+"""Serving form on the GPU: requests served concurrently give the same results
+as each request solved alone, and every result meets its tolerance."""
+import numpy as np
+import pytest
+
+import problems
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(precision):
+    from paper_1604_01713_amd import serving as sv
+    descs = [{"id": 0, "side": 20, "p": 8, "nsys": 3, "conv": (6.0, -3.0, 2.0), "seed": 11, "arrival": 0.0},
+             {"id": 1, "side": 16, "p": 4, "nsys": 2, "conv": (-2.0, 8.0, 1.0), "seed": 12, "arrival": 0.0},
+             {"id": 2, "side": 24, "p": 16, "nsys": 2, "conv": (3.0, 3.0, -9.0), "seed": 13, "arrival": 0.0},
+             {"id": 3, "side": 18, "p": 1, "nsys": 3, "conv": (1.0, 2.0, 3.0), "seed": 14, "arrival": 0.0}]
+    cache = {}
+
+    def system_of(d):
+        def f(i):
+            if (d["id"], i) not in cache:
+                s = problems.request_system(d, i)
+                cache[(d["id"], i)] = (s.A, s.B)
+            return cache[(d["id"], i)]
+        return f
+
+    reqs = []
+    for d in descs:
+        A0, _ = system_of(d)(0)
+        reqs.append(sv.Request(rid=d["id"], arrival=0.0, n=A0.shape[0], p=d["p"], nnz=A0.nnz, nsys=d["nsys"],
+                               system=system_of(d), m=6, k=8, tol=1e-8, precision=precision))
+    return reqs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_results_are_the_same_alone_and_in_the_mix(precision):
+    from paper_1604_01713_amd import serving as sv
+    reqs = _requests(precision)
+    run = sv.gpu_runner(keep_solutions=True)
+    nb = lambda r: sv.device_bytes(r, sv.library_footprint)
+    mixed = {r.rid: r for r in sv.serve(reqs, run, budget_bytes=1 << 34, slots=4, bytes_of=nb, realtime=False)}
+    alone = {}
+    for q in reqs:
+        alone[q.rid] = sv.serve([q], run, budget_bytes=1 << 34, slots=1, bytes_of=nb, realtime=False)[0]
+    for q in reqs:
+        a, b = mixed[q.rid], alone[q.rid]
+        assert a.error is None and b.error is None, (a.error, b.error)
+        for i in range(q.nsys):
+            A, B = q.system(i)
+            Xm, Xa = a.solutions[i], b.solutions[i]
+            rel = np.linalg.norm(B - A @ Xm) / np.linalg.norm(B)
+            diff = np.linalg.norm(Xm - Xa) / max(np.linalg.norm(Xa), 1e-300)
+            print(f"req {q.rid} sys {i} p={q.p} n={q.n} prec={precision}: rel.res {rel:.2e}, "
+                  f"mix vs alone {diff:.1e}, cycles {a.stats[i]['cycles']}/{b.stats[i]['cycles']}", flush=True)
+            assert a.stats[i]["status"] == 0
+            assert rel <= q.tol * 1.0001
+            # same kernels, same launch shapes, fixed reduction order: identical
+            assert diff == 0.0
