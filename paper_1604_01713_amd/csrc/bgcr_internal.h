@@ -127,10 +127,12 @@ hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, int KP, 
 // 64-row tiles (mfma_nwg gives the default).
 int mfma_nwg(int64_t n);
 hipError_t i_minus(hipStream_t st, const double* M, double* out, int P);
-// partial dots [Q_0 .. Q_{nq-1}]^T W (no update)
+// partial dots [Q_0 .. Q_{nq-1}]^T [W_0 .. W_{nw-1}] (no update), partial
+// layout part[wg][w][c P + b]; at most 32 W columns, and then at most 9
+// chunks of 16 Q columns, per launch (hipErrorNotSupported otherwise)
 template <class T>
-hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, double* part,
-                    const Ctl* ctl, int nwg);
+hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq,
+                    double* part, const Ctl* ctl, int nwg);
 template <class T>
 hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
                          double* part, const Ctl* ctl, int nwg);

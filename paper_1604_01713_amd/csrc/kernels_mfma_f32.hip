@@ -4,7 +4,7 @@
 
 namespace bgcr {
 
-template hipError_t mfma_dot<float>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int, double*,
+template hipError_t mfma_dot<float>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int, double*,
                                     const Ctl*, int);
 template hipError_t mfma_proj_dot<float>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int,
                                          const double*, double*, const Ctl*, int);

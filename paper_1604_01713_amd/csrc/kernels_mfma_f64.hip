@@ -25,7 +25,7 @@ int mfma_nwg(int64_t n) {
     return (int)(g < 1 ? 1 : g);
 }
 
-template hipError_t mfma_dot<double>(hipStream_t, int, int64_t, const double*, const BlockPtrs&, int, double*,
+template hipError_t mfma_dot<double>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int, double*,
                                      const Ctl*, int);
 template hipError_t mfma_proj_dot<double>(hipStream_t, int, int64_t, const double*, const BlockPtrs&, int,
                                           const double*, double*, const Ctl*, int);

@@ -66,25 +66,31 @@ __device__ inline void tile_span(int64_t ntiles, int lw, int64_t& t0, int64_t& t
 }
 
 // Cross-wave reduction of the dot accumulators and write of the workgroup
-// partial: chunk ch holds S^T[b][c] with b = drow(l, v), c = 16 ch + l % 16.
-// Output part[lw][c P + b].
-template <class T, int P, int NC>
-__device__ inline void write_dot_partials(const typename MX<T>::acc (&acc)[NC], int q, double* red, double* part,
-                                          int lw, int nout) {
+// partial: accumulator [g][ch] holds S^T[w][c] for W column w = 16 g +
+// drow(l, v) and Q column c = 16 ch + l % 16.  Output part[lw][(w / P) q P +
+// c P + w % P] (one q x P slice per W block), nout = nw q P.
+template <class T, int P, int NG, int NC>
+__device__ inline void write_dot_partials(const typename MX<T>::acc (&acc)[NG][NC], int q, int nw, double* red,
+                                          double* part, int lw) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int64_t nout = (int64_t)nw * q * P;
 #pragma unroll
-    for (int ch = 0; ch < NC; ++ch) {
-        __syncthreads();
+    for (int g = 0; g < NG; ++g) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) red[(wave * 4 + v) * 64 + lane] = (double)acc[ch][v];
-        __syncthreads();
-        // thread t -> (v, lane) = (t / 64, t % 64): sum the 4 waves in order
-        const int v = t >> 6, l = t & 63;
-        const double s = red[(0 * 4 + v) * 64 + l] + red[(1 * 4 + v) * 64 + l] + red[(2 * 4 + v) * 64 + l] +
-                         red[(3 * 4 + v) * 64 + l];
-        const int b = MX<T>::drow(l, v);
-        const int c = ch * 16 + (l & 15);
-        if (b < P && c < q) part[(int64_t)lw * nout + (int64_t)c * P + b] = s;
+        for (int ch = 0; ch < NC; ++ch) {
+            __syncthreads();
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[(wave * 4 + v) * 64 + lane] = (double)acc[g][ch][v];
+            __syncthreads();
+            // thread t -> (v, lane) = (t / 64, t % 64): sum the 4 waves in order
+            const int v = t >> 6, l = t & 63;
+            const double s = red[(0 * 4 + v) * 64 + l] + red[(1 * 4 + v) * 64 + l] + red[(2 * 4 + v) * 64 + l] +
+                             red[(3 * 4 + v) * 64 + l];
+            const int w = 16 * g + MX<T>::drow(l, v);
+            const int c = ch * 16 + (l & 15);
+            if (w < nw * P && c < q)
+                part[(int64_t)lw * nout + (int64_t)(w / P) * q * P + (int64_t)c * P + w % P] = s;
+        }
     }
 }
 
@@ -136,15 +142,6 @@ __device__ inline void load_rc(T (&qv)[KS][NC], const T* const (&qp)[NC], int64_
     }
 }
 
-// A operand of the dot for KS groups of 4 rows: W[rbase + 4 ks + l / 16][l % 16]
-// (rows clamped; lanes l % 16 >= P repeat column l % P)
-template <class T, int P, int KS>
-__device__ inline void load_wa(T (&w)[KS], const T* __restrict__ W, int64_t rbase, int64_t n, int lane) {
-    const int bc = lane & (P - 1);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) w[ks] = W[clamp_row(rbase + 4 * ks + (lane >> 4), n) * P + bc];
-}
-
 // W^T tile in the D layout for rows rbase .. rbase + 15 (rows clamped; D rows
 // past P repeat row b % P)
 template <class T, int P>
@@ -185,15 +182,16 @@ __device__ inline int qsw(int r, int c) {
 }
 
 // ---------------------------------------------------------------------------
-// dot sweep: partial S^T = W^T [Q_0 .. Q_{nq-1}] (no update).  Both MFMA
+// dot sweep: partial S^T = [W_0 .. W_{nw-1}]^T [Q_0 .. Q_{nq-1}] (no update),
+// NG groups of 16 W columns (two W blocks per group for P = 8).  Both MFMA
 // operands are loaded from global memory directly in their register layout
-// (A = W[row][b], B = Q[row][c], 4 rows per instruction), so the sweep needs
+// (A = W[row][w], B = Q[row][c], 4 rows per instruction), so the sweep needs
 // no LDS besides the final cross-wave reduction; the next wave tile is loaded
 // while the current one is multiplied.
 // ---------------------------------------------------------------------------
-template <class T, int P, int NC, int KS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && NC >= 16 ? 1 : 2))) void k_dot_mfma(
-    int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq, double* __restrict__ part, const Ctl* ctl) {
+template <class T, int P, int NC, int KS, int NG>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && NC * NG > 18 ? 1 : 2))) void
+k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restrict__ part, const Ctl* ctl) {
     using M = MX<T>;
     constexpr int WROWS = 4 * KS, TROWS = 4 * WROWS;
     if (ctl && ctl->active == 0) return;
@@ -203,40 +201,49 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const T* qp[NC];
     rc_pointers<T, P, NC>(qp, Q, nq, lane);
-    typename M::acc acc[NC];
+    const T* wp[NG];
+    rc_pointers<T, P, NG>(wp, W, nw, lane);
+    typename M::acc acc[NG][NC];
 #pragma unroll
-    for (int ch = 0; ch < NC; ++ch) acc[ch] = typename M::acc{0, 0, 0, 0};
+    for (int g = 0; g < NG; ++g)
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) acc[g][ch] = typename M::acc{0, 0, 0, 0};
     const int lw = logical_wg();
     int64_t t0, t1;
     tile_span((n + TROWS - 1) / TROWS, lw, t0, t1);
-    T qn[KS][NC], wn[KS];
+    T qn[KS][NC], wn[KS][NG];
     if (t0 < t1) {
         load_rc<T, P, NC, KS>(qn, qp, t0 * TROWS + wave * WROWS, n, lane);
-        load_wa<T, P, KS>(wn, Win, t0 * TROWS + wave * WROWS, n, lane);
+        load_rc<T, P, NG, KS>(wn, wp, t0 * TROWS + wave * WROWS, n, lane);
     }
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t rbase = tile * TROWS + wave * WROWS;
-        T qc[KS][NC], wc[KS];
+        T qc[KS][NC], wc[KS][NG];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            wc[ks] = wn[ks];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) wc[ks][g] = wn[ks][g];
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch) qc[ks][ch] = qn[ks][ch];
         }
         if (rbase + WROWS > n) {  // last, partial tile: rows past n contribute nothing
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) wc[ks] = rbase + 4 * ks + (lane >> 4) < n ? wc[ks] : (T)0;
+            for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                for (int g = 0; g < NG; ++g) wc[ks][g] = rbase + 4 * ks + (lane >> 4) < n ? wc[ks][g] : (T)0;
         }
         if (tile + 1 < t1) {
             load_rc<T, P, NC, KS>(qn, qp, rbase + TROWS, n, lane);
-            load_wa<T, P, KS>(wn, Win, rbase + TROWS, n, lane);
+            load_rc<T, P, NG, KS>(wn, wp, rbase + TROWS, n, lane);
         }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int ch = 0; ch < NC; ++ch) acc[ch] = M::mma(wc[ks], qc[ks][ch], acc[ch]);
+            for (int g = 0; g < NG; ++g)
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch) acc[g][ch] = M::mma(wc[ks][g], qc[ks][ch], acc[g][ch]);
     }
-    write_dot_partials<T, P, NC>(acc, q, red, part, lw, q * P);
+    write_dot_partials<T, P, NG, NC>(acc, q, nw, red, part, lw);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,7 +317,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
             for (int ch = 0; ch < NC; ++ch) acc[ch] = M::mma(wv, myQ[qsw<QLD>(rl, 16 * ch + bl)], acc[ch]);
         }
     }
-    write_dot_partials<T, P, NC>(acc, q, red, part, lw, q * P);
+    typename M::acc acc1[1][NC];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) acc1[0][ch] = acc[ch];
+    write_dot_partials<T, P, 1, NC>(acc1, q, 1, red, part, lw);
 }
 
 // ---------------------------------------------------------------------------
@@ -429,15 +439,36 @@ constexpr int dot_ks() {
 }
 
 template <class T, int P>
-hipError_t launch_dot(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, double* part, int nwg,
-                      const Ctl* ctl) {
-    const int nc = (nq * P + 15) / 16;
+hipError_t launch_dot(hipStream_t st, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq, double* part,
+                      int nwg, const Ctl* ctl) {
+    const int nc = (nq * P + 15) / 16, ng = (nw * P + 15) / 16;
     const size_t lds = (size_t)1024 * sizeof(double);
-#define L(NC)                                                                                                    \
-    hipLaunchKernelGGL((k_dot_mfma<T, P, NC, dot_ks<NC>()>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, part, \
+    if (ng == 1) {
+#define L(NC)                                                                                                      \
+    hipLaunchKernelGGL((k_dot_mfma<T, P, NC, dot_ks<NC>(), 1>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, part, \
                        ctl)
-    BGCR_MX_NC_DISPATCH(nc, L)
+        BGCR_MX_NC_DISPATCH(nc, L)
 #undef L
+    } else if (ng == 2 && nc <= 9) {
+#define L(NC)                                                                                                      \
+    hipLaunchKernelGGL((k_dot_mfma<T, P, NC, dot_ks<2 * NC>(), 2>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, \
+                       part, ctl)
+        switch (nc) {
+            case 1: L(1); break;
+            case 2: L(2); break;
+            case 3: L(3); break;
+            case 4: L(4); break;
+            case 5: L(5); break;
+            case 6: L(6); break;
+            case 7: L(7); break;
+            case 8: L(8); break;
+            case 9: L(9); break;
+            default: return hipErrorNotSupported;
+        }
+#undef L
+    } else {
+        return hipErrorNotSupported;
+    }
     return hipGetLastError();
 }
 
@@ -605,10 +636,10 @@ hipError_t launch_combine(hipStream_t st, int64_t n, const BlockPtrs& in, int ni
 
 // public entry points (declared in bgcr_internal.h), instantiated per type
 template <class T>
-hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, double* part,
-                    const Ctl* ctl, int nwg) {
-    if (P == 8) return mx::launch_dot<T, 8>(st, n, Win, Q, nq, part, nwg, ctl);
-    if (P == 16) return mx::launch_dot<T, 16>(st, n, Win, Q, nq, part, nwg, ctl);
+hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq,
+                    double* part, const Ctl* ctl, int nwg) {
+    if (P == 8) return mx::launch_dot<T, 8>(st, n, W, nw, Q, nq, part, nwg, ctl);
+    if (P == 16) return mx::launch_dot<T, 16>(st, n, W, nw, Q, nq, part, nwg, ctl);
     return hipErrorNotSupported;
 }
 

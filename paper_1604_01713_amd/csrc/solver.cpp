@@ -69,7 +69,15 @@ struct Sizes {
     int P, m, k, KB, KP;
     size_t s, sa;  // bytes of a basis scalar, of an FP64 scalar
     size_t basis, blk, recyc, small_, part, total_fixed;
+    size_t nout;   // outputs per workgroup of the reduction partials
 };
+
+// outputs per workgroup of the largest reduction: an Arnoldi sweep (q x P)
+// or a recycle dot launch (up to 32 W columns, at most KB blocks, against q)
+size_t part_outputs(int P, int KB, int qmax) {
+    const size_t wg = (size_t)std::max(1, std::min(KB, std::max(1, 32 / P)));
+    return std::max({(size_t)qmax * P, (size_t)KB * P * P, wg * qmax * P});
+}
 
 Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     Sizes z;
@@ -85,8 +93,8 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     z.basis = (size_t)z.m * z.blk;
     z.recyc = 4 * (size_t)z.KB * z.blk;
     const int qmax = (2 * z.KB + z.m + 1) * z.P;
-    const size_t nout = std::max((size_t)qmax * z.P, (size_t)z.KP * z.P);
-    z.part = (size_t)NWG_MAX * nout * z.sa;
+    z.nout = part_outputs(z.P, z.KB, qmax);
+    z.part = (size_t)NWG_MAX * z.nout * z.sa;
     const size_t mp = (size_t)z.m * z.P, m1p = (size_t)(z.m + 1) * z.P;
     z.small_ = z.sa * (2 * (size_t)qmax * z.P + 2 * m1p * mp + (size_t)z.KP * mp + (size_t)z.m * 4 * z.P * z.P +
                        m1p * z.P + (size_t)(z.m + 1) * z.P * z.P + 2 * (size_t)z.P * z.P +
@@ -120,6 +128,7 @@ struct Seq final : bgcr_sequence {
     size_t av32_cap = 0;
     A* dots = nullptr;
     size_t dots_cap = 0;
+    size_t part_cap = 0;  // elements of `part`
     A *part = nullptr, *S1 = nullptr, *Sf = nullptr, *H = nullptr, *F = nullptr, *Rh = nullptr, *QH = nullptr,
       *g = nullptr, *RinvAll = nullptr, *Z1 = nullptr, *Z1i = nullptr, *coef = nullptr;
     size_t coef_cap = 0;
@@ -261,8 +270,8 @@ struct Seq final : bgcr_sequence {
             Cb[i] = dalloc<T>((size_t)KB * blk);
         }
         const int qmax = (2 * KB + m + 1) * P;
-        const size_t nout = std::max((size_t)qmax * P, (size_t)KP * P);
-        part = dalloc<A>((size_t)NWG_MAX * nout);
+        part_cap = (size_t)NWG_MAX * sz.nout;
+        part = dalloc<A>(part_cap);
         S1 = dalloc<A>((size_t)qmax * P);
         dots_cap = (size_t)qmax * P * std::max(KB, 1);
         dots = dalloc<A>(dots_cap);
@@ -399,36 +408,47 @@ struct Seq final : bgcr_sequence {
         const int nq = (int)Q.size();
         const int nw = (int)W.size();
         Mat D(nq * P, nw * P);
-        const int chunk = use_mx ? std::max(1, 256 / P) : std::max(1, (MAXI * NT) / (P * P));
+        // per launch: wg W blocks (32 columns on matrix cores, so that one pass
+        // over a Q chunk serves them all) against a chunk of qc Q blocks
+        const int wg = use_mx ? std::max(1, 32 / P) : 1;
         const int nr = use_mx ? nwg_mx : nwg;
         if ((size_t)nq * P * P * nw > dots_cap) throw Fail{BGCR_ERR_INVALID};
+        struct Piece {
+            int w0, wn, q0, qn;
+            size_t off;
+        };
+        std::vector<Piece> pieces;
         size_t off = 0;
-        for (int w = 0; w < nw; ++w) {
+        for (int w0 = 0; w0 < nw; w0 += wg) {
+            const int wn = std::min(wg, nw - w0);
+            const int ng = (wn * P + 15) / 16;
+            const int chunk = use_mx ? std::max(1, (ng == 2 ? 9 : 16) * 16 / P) : std::max(1, (MAXI * NT) / (P * P));
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = std::min(chunk, nq - q0);
+                const int nout = wn * qn * P * P;
+                if ((size_t)nr * nout > part_cap) throw Fail{BGCR_ERR_INVALID};
                 std::vector<const void*> sub(Q.begin() + q0, Q.begin() + q0 + qn);
-                run(BGCR_K_TSDOT, (double)sizeof(T) * n * P * (1 + qn), [&] {
+                std::vector<const void*> ws(W.begin() + w0, W.begin() + w0 + wn);
+                run(BGCR_K_TSDOT, (double)sizeof(T) * n * P * (wn + qn), [&] {
                     if constexpr (!std::is_same<T, zd>::value) {
-                        if (use_mx) return mfma_dot<T>(st, P, n, W[w], bp(sub), qn, part, nullptr, nr);
+                        if (use_mx) return mfma_dot<T>(st, P, n, bp(ws), wn, bp(sub), qn, part, nullptr, nr);
                     }
-                    return L::update_dot(st, P, n, W[w], bp(sub), qn, nullptr, nullptr, nullptr, 1, 0, part, nr, nullptr);
+                    return L::update_dot(st, P, n, W[w0], bp(sub), qn, nullptr, nullptr, nullptr, 1, 0, part, nr,
+                                         nullptr);
                 });
-                const int nout = qn * P * P;
                 run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nr, nout, nullptr, dots + off, nullptr); });
+                pieces.push_back({w0, wn, q0, qn, off});
                 off += nout;
             }
         }
         std::vector<A> h(off);
         d2h(h.data(), dots, off * sizeof(A));
-        off = 0;
-        for (int w = 0; w < nw; ++w) {
-            for (int q0 = 0; q0 < nq; q0 += chunk) {
-                const int qn = std::min(chunk, nq - q0);
-                for (int c = 0; c < qn * P; ++c)
-                    for (int b = 0; b < P; ++b) D(q0 * P + c, w * P + b) = to_cd(h[off + (size_t)c * P + b]);
-                off += (size_t)qn * P * P;
-            }
-        }
+        for (const Piece& pc : pieces)
+            for (int wl = 0; wl < pc.wn; ++wl)
+                for (int c = 0; c < pc.qn * P; ++c)
+                    for (int b = 0; b < P; ++b)
+                        D(pc.q0 * P + c, (pc.w0 + wl) * P + b) =
+                            to_cd(h[pc.off + (size_t)wl * pc.qn * P * P + (size_t)c * P + b]);
         return D;
     }
 
@@ -580,7 +600,7 @@ struct Seq final : bgcr_sequence {
             // sweep 1b: first block-CGS dots [C V_1..V_j]^H W (reads W and Q)
             run(BGCR_K_ARN_DOT, blkb + qbytes, [&] {
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx) return mfma_dot<T>(st, P, n, Wb, QB, nq + 1, part, ctl, na);
+                    if (use_mx) return mfma_dot<T>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
             });
