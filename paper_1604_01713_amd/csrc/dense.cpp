@@ -23,7 +23,39 @@ void Mat::set_block(int i0, int j0, const Mat& B) {
         for (int i = 0; i < B.r; ++i) (*this)(i0 + i, j0 + j) = B(i, j);
 }
 
+// Real-arithmetic fast paths: the refresh problems of real systems are real
+// (only eigenvectors of complex-conjugate pairs are complex), and real
+// arithmetic does a quarter of the work of complex arithmetic.
+static bool all_real(const Mat& A) {
+    for (const cd& v : A.a)
+        if (v.imag() != 0.0) return false;
+    return true;
+}
+static std::vector<double> real_part(const Mat& A) {
+    std::vector<double> r(A.a.size());
+    for (size_t e = 0; e < r.size(); ++e) r[e] = A.a[e].real();
+    return r;
+}
+static Mat from_real(int r, int c, const std::vector<double>& a) {
+    Mat M(r, c);
+    for (size_t e = 0; e < a.size(); ++e) M.a[e] = cd(a[e], 0.0);
+    return M;
+}
+
 Mat matmul(const Mat& A, const Mat& B) {
+    if (all_real(A) && all_real(B)) {
+        const std::vector<double> a = real_part(A), b = real_part(B);
+        std::vector<double> c((size_t)A.r * B.c, 0.0);
+        for (int j = 0; j < B.c; ++j)
+            for (int l = 0; l < A.c; ++l) {
+                const double bl = b[(size_t)j * A.c + l];
+                if (bl == 0.0) continue;
+                const double* al = &a[(size_t)l * A.r];
+                double* cj = &c[(size_t)j * A.r];
+                for (int i = 0; i < A.r; ++i) cj[i] += al[i] * bl;
+            }
+        return from_real(A.r, B.c, c);
+    }
     Mat C(A.r, B.c);
     for (int j = 0; j < B.c; ++j)
         for (int l = 0; l < A.c; ++l) {
@@ -72,6 +104,21 @@ bool chol_upper(const Mat& G, Mat& R) {
 
 Mat tri_inv_upper(const Mat& R) {
     const int n = R.r;
+    if (all_real(R)) {
+        const std::vector<double> r = real_part(R);
+        std::vector<double> x((size_t)n * n, 0.0);
+        auto Rr = [&](int i, int j) { return r[(size_t)i + (size_t)j * R.r]; };
+        for (int j = 0; j < n; ++j) {
+            double* xj = &x[(size_t)j * n];
+            xj[j] = 1.0 / Rr(j, j);
+            for (int i = j - 1; i >= 0; --i) {
+                double s = 0.0;
+                for (int l = i + 1; l <= j; ++l) s += Rr(i, l) * xj[l];
+                xj[i] = -s / Rr(i, i);
+            }
+        }
+        return from_real(n, n, x);
+    }
     Mat X(n, n);
     for (int j = 0; j < n; ++j) {
         X(j, j) = 1.0 / R(j, j);
@@ -143,7 +190,67 @@ static double house(const cd* x, int len, std::vector<cd>& v) {
     return s;
 }
 
+// real Householder QR with positive diagonal (column-major, m x n)
+static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R) {
+    const int m = A0.r, n = A0.c;
+    std::vector<double> a = real_part(A0);
+    auto col = [&](int j) { return &a[(size_t)j * m]; };
+    const int kk = std::min(m, n);
+    std::vector<std::vector<double>> vs(kk);
+    std::vector<double> vvs(kk, 0.0);
+    for (int k = 0; k < kk; ++k) {
+        double* ck = col(k);
+        double al = 0.0;
+        for (int i = k; i < m; ++i) al += ck[i] * ck[i];
+        al = std::sqrt(al);
+        if (al == 0.0) continue;
+        const double beta = ck[k] >= 0.0 ? -al : al;
+        std::vector<double>& v = vs[k];
+        v.assign(ck + k, ck + m);
+        v[0] = ck[k] - beta;
+        double vv = 0.0;
+        for (double x : v) vv += x * x;
+        vvs[k] = vv;
+        if (vv == 0.0) continue;
+        const double f = 2.0 / vv;
+        for (int j = k; j < n; ++j) {
+            double* cj = col(j) + k;
+            double w = 0.0;
+            for (int i = 0; i < m - k; ++i) w += v[i] * cj[i];
+            w *= f;
+            for (int i = 0; i < m - k; ++i) cj[i] -= w * v[i];
+        }
+    }
+    std::vector<double> r((size_t)kk * n, 0.0), q((size_t)m * kk, 0.0);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i <= std::min(j, kk - 1); ++i) r[(size_t)i + (size_t)j * kk] = col(j)[i];
+    for (int i = 0; i < kk; ++i) q[(size_t)i + (size_t)i * m] = 1.0;
+    for (int k = kk - 1; k >= 0; --k) {
+        if (vvs[k] == 0.0) continue;
+        const std::vector<double>& v = vs[k];
+        const double f = 2.0 / vvs[k];
+        for (int j = 0; j < kk; ++j) {
+            double* qj = &q[(size_t)j * m + k];
+            double w = 0.0;
+            for (int i = 0; i < m - k; ++i) w += v[i] * qj[i];
+            w *= f;
+            for (int i = 0; i < m - k; ++i) qj[i] -= w * v[i];
+        }
+    }
+    for (int i = 0; i < kk; ++i)
+        if (r[(size_t)i + (size_t)i * kk] < 0.0) {
+            for (int j = 0; j < n; ++j) r[(size_t)i + (size_t)j * kk] = -r[(size_t)i + (size_t)j * kk];
+            for (int rr = 0; rr < m; ++rr) q[(size_t)rr + (size_t)i * m] = -q[(size_t)rr + (size_t)i * m];
+        }
+    R = from_real(kk, n, r);
+    Q = from_real(m, kk, q);
+}
+
 void qr_pos(const Mat& A0, Mat& Q, Mat& R) {
+    if (all_real(A0)) {
+        qr_pos_real(A0, Q, R);
+        return;
+    }
     const int m = A0.r, n = A0.c;
     Mat A = A0;
     std::vector<std::vector<cd>> vs(n);
@@ -550,11 +657,75 @@ static bool eig_complex_window(std::vector<cd>& T, int n, std::vector<cd>& lam) 
     return true;
 }
 
+// Hessenberg reduction of a real row-major matrix by Householder reflectors
+// (reflector k acts on rows/columns k+1 .. n-1)
+static void hessenberg_real(std::vector<double>& H, int n, std::vector<std::vector<double>>& refl,
+                            std::vector<double>& vvs) {
+    refl.assign(n, {});
+    vvs.assign(n, 0.0);
+    std::vector<double> w(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        const int len = n - k - 1;
+        std::vector<double>& v = refl[k];
+        v.resize(len);
+        double al = 0.0;
+        for (int i = 0; i < len; ++i) {
+            v[i] = H[(size_t)(k + 1 + i) * n + k];
+            al += v[i] * v[i];
+        }
+        al = std::sqrt(al);
+        if (al == 0.0) continue;
+        const double beta = v[0] >= 0.0 ? -al : al;
+        v[0] -= beta;
+        double vv = 0.0;
+        for (double x : v) vv += x * x;
+        vvs[k] = vv;
+        if (vv == 0.0) continue;
+        const double f = 2.0 / vv;
+        // left: rows k+1.. of columns k..
+        std::fill(w.begin(), w.end(), 0.0);
+        for (int i = 0; i < len; ++i) {
+            const double vi = v[i];
+            const double* row = &H[(size_t)(k + 1 + i) * n];
+            for (int j = k; j < n; ++j) w[j] += vi * row[j];
+        }
+        for (int i = 0; i < len; ++i) {
+            const double fv = f * v[i];
+            double* row = &H[(size_t)(k + 1 + i) * n];
+            for (int j = k; j < n; ++j) row[j] -= fv * w[j];
+        }
+        // right: columns k+1.. of every row
+        for (int i = 0; i < n; ++i) {
+            double* row = &H[(size_t)i * n + k + 1];
+            double dot = 0.0;
+            for (int l = 0; l < len; ++l) dot += row[l] * v[l];
+            dot *= f;
+            for (int l = 0; l < len; ++l) row[l] -= dot * v[l];
+        }
+        for (int i = k + 2; i < n; ++i) H[(size_t)i * n + k] = 0.0;
+    }
+}
+
 void EigSolver::compute(const Mat& A, bool real_input) {
     n = A.r;
     real = real_input;
     ok = false;
     lam.assign(n, cd(0.0, 0.0));
+    if (real) {
+        Hd.assign((size_t)n * n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double v = A(i, j).real();
+                if (!std::isfinite(v)) return;
+                Hd[(size_t)i * n + j] = v;
+            }
+        hessenberg_real(Hd, n, reflr, reflvv);
+        hnorm = 0.0;
+        for (double v : Hd) hnorm = std::max(hnorm, std::abs(v));
+        std::vector<double> H = Hd;
+        ok = eig_real_francis(H, n, lam);
+        return;
+    }
     Hh.assign((size_t)n * n, cd(0.0, 0.0));
     refl.assign(n, {});
     reflvv.assign(n, 0.0);
@@ -597,13 +768,51 @@ void EigSolver::compute(const Mat& A, bool real_input) {
     }
     hnorm = 0.0;
     for (const cd& v : Hh) hnorm = std::max(hnorm, std::abs(v));
-    if (real) {
-        std::vector<double> H((size_t)n * n);
-        for (size_t e = 0; e < H.size(); ++e) H[e] = Hh[e].real();
-        ok = eig_real_francis(H, n, lam);
-    } else {
-        std::vector<cd> T = Hh;
-        ok = eig_complex_window(T, n, lam);
+    std::vector<cd> T = Hh;
+    ok = eig_complex_window(T, n, lam);
+}
+
+// inverse iteration with a real shift on the real Hessenberg matrix
+static void inverse_iteration_real(const std::vector<double>& Hd, int n, double sh, double pert,
+                                   std::vector<double>& x) {
+    std::vector<double> U = Hd;
+    for (int i = 0; i < n; ++i) U[(size_t)i * n + i] -= sh;
+    std::vector<int> swp(n, 0);
+    std::vector<double> mult(n, 0.0);
+    for (int k = 0; k + 1 < n; ++k) {
+        double* rk = &U[(size_t)k * n];
+        double* rk1 = &U[(size_t)(k + 1) * n];
+        if (std::abs(rk1[k]) > std::abs(rk[k])) {
+            for (int j = k; j < n; ++j) std::swap(rk[j], rk1[j]);
+            swp[k] = 1;
+        }
+        if (rk[k] == 0.0) rk[k] = pert;
+        const double l = rk1[k] / rk[k];
+        mult[k] = l;
+        if (l != 0.0)
+            for (int j = k; j < n; ++j) rk1[j] -= l * rk[j];
+    }
+    if (U[(size_t)(n - 1) * n + n - 1] == 0.0) U[(size_t)(n - 1) * n + n - 1] = pert;
+    auto nrm = [&](std::vector<double>& v) {
+        double s = 0.0;
+        for (double a : v) s += a * a;
+        s = std::sqrt(s);
+        if (s > 0.0)
+            for (double& a : v) a /= s;
+    };
+    nrm(x);
+    for (int it = 0; it < 3; ++it) {
+        for (int k = 0; k + 1 < n; ++k) {
+            if (swp[k]) std::swap(x[k], x[k + 1]);
+            x[k + 1] -= mult[k] * x[k];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            const double* row = &U[(size_t)i * n];
+            double s = x[i];
+            for (int j = i + 1; j < n; ++j) s -= row[j] * x[j];
+            x[i] = s / row[i];
+        }
+        nrm(x);
     }
 }
 
@@ -611,8 +820,46 @@ std::vector<cd> EigSolver::vector_for(cd lambda, const std::vector<std::vector<c
     // inverse iteration on the Hessenberg matrix with a slightly perturbed shift
     const double pert = std::max(hnorm, 1e-300) * 1e-13;
     const cd sh = lambda + cd(pert, 0.0);
+    // back to the basis of A: x <- H_0 H_1 ... H_{n-3} x
+    auto back = [&](std::vector<cd>& x) {
+        for (int k = n - 3; k >= 0; --k) {
+            if (reflvv[k] == 0.0) continue;
+            const double f = 2.0 / reflvv[k];
+            const int len = n - k - 1;
+            cd d = 0.0;
+            if (real) {
+                const std::vector<double>& v = reflr[k];
+                for (int l = 0; l < len; ++l) d += v[l] * x[k + 1 + l];
+                d *= f;
+                for (int l = 0; l < len; ++l) x[k + 1 + l] -= d * v[l];
+            } else {
+                const std::vector<cd>& v = refl[k];
+                for (int l = 0; l < len; ++l) d += std::conj(v[l]) * x[k + 1 + l];
+                d *= f;
+                for (int l = 0; l < len; ++l) x[k + 1 + l] -= d * v[l];
+            }
+        }
+    };
+    std::vector<cd> x(n);
+    uint64_t st = 0x9E3779B97F4A7C15ull;
+    std::vector<double> x0(n);
+    for (int i = 0; i < n; ++i) {
+        st ^= st << 13;
+        st ^= st >> 7;
+        st ^= st << 17;
+        x0[i] = 0.5 + (double)(st % 1000003) / 1000003.0;
+    }
+    if (real && lambda.imag() == 0.0 && against.empty()) {
+        inverse_iteration_real(Hd, n, sh.real(), pert, x0);
+        for (int i = 0; i < n; ++i) x[i] = cd(x0[i], 0.0);
+        back(x);
+        return x;
+    }
     std::vector<cd> U((size_t)n * n);
-    for (size_t e = 0; e < U.size(); ++e) U[e] = Hh[e];
+    if (real)
+        for (size_t e = 0; e < U.size(); ++e) U[e] = cd(Hd[e], 0.0);
+    else
+        for (size_t e = 0; e < U.size(); ++e) U[e] = Hh[e];
     for (int i = 0; i < n; ++i) U[(size_t)i * n + i] -= sh;
     // Hessenberg LU with partial pivoting (only rows k, k+1 compete); record ops
     std::vector<int> swp(n, 0);
@@ -655,30 +902,14 @@ std::vector<cd> EigSolver::vector_for(cd lambda, const std::vector<std::vector<c
         if (nr > 0.0)
             for (cd& v : x) v /= nr;
     };
-    std::vector<cd> x(n);
-    uint64_t st = 0x9E3779B97F4A7C15ull;
-    for (int i = 0; i < n; ++i) {
-        st ^= st << 13;
-        st ^= st >> 7;
-        st ^= st << 17;
-        x[i] = cd(0.5 + (double)(st % 1000003) / 1000003.0, 0.0);
-    }
+    for (int i = 0; i < n; ++i) x[i] = cd(x0[i], 0.0);
     // vectors of nearby eigenvalues are carried in the Hessenberg basis
     orth_normalize(x);
     for (int it = 0; it < 3; ++it) {
         solve(x);
         orth_normalize(x);
     }
-    // back to the basis of A: x <- H_0 H_1 ... H_{n-3} x
-    for (int k = n - 3; k >= 0; --k) {
-        if (reflvv[k] == 0.0) continue;
-        const std::vector<cd>& v = refl[k];
-        const int len = n - k - 1;
-        cd d = 0.0;
-        for (int l = 0; l < len; ++l) d += std::conj(v[l]) * x[k + 1 + l];
-        d *= 2.0 / reflvv[k];
-        for (int l = 0; l < len; ++l) x[k + 1 + l] -= d * v[l];
-    }
+    back(x);
     return x;
 }
 

@@ -65,6 +65,8 @@ struct EigSolver {
     std::vector<cd> Hh;                 // Hessenberg form, row-major
     std::vector<std::vector<cd>> refl;  // Householder vectors of the reduction
     std::vector<double> reflvv;
+    std::vector<double> Hd;                  // real input: Hessenberg form, row-major
+    std::vector<std::vector<double>> reflr;  // real input: Householder vectors
     std::vector<cd> lam;
     double hnorm = 0.0;
     bool ok = false;
