@@ -141,7 +141,8 @@ hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const 
                           const double* S, T* Wout, double* part, const Ctl* ctl, int nwg);
 
 // Y (+)= [in..] C on matrix cores (real FP64/FP32 inputs, FP64 coefficients
-// row-major (nin P) x (nout P)); hipErrorNotSupported for other shapes
+// row-major (nin P) x (nout P)); the first `accumulate` output blocks are
+// accumulated, the rest overwritten; hipErrorNotSupported for other shapes
 template <class TI, class TO>
 hipError_t mfma_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
                         const double* coef, int accumulate, int nwg);

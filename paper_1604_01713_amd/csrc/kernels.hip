@@ -293,7 +293,8 @@ BGCR_UPDATE_KERNEL(k_tsdot)
 // outputs of its row in registers.  The coefficients are the same for every
 // row, so their loads are wave-uniform (scalar loads).  Layout of coef:
 // [nin][P][nout][P], i.e. for input i and its column a the nout*P
-// coefficients are contiguous.  Outputs are done in chunks of OC blocks.
+// coefficients are contiguous.  Outputs are done in chunks of OC blocks; the
+// first `accumulate` output blocks are accumulated, the others overwritten.
 template <class TI, class TO, int P, int OC>
 __global__ __launch_bounds__(NT) void k_combine(int64_t n, BlockPtrs in, int nin, BlockPtrs out, int nout,
                                                 const acc_t<TI>* __restrict__ coef, int accumulate) {
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(NT) void k_combine(int64_t n, BlockPtrs in, int nin
 #pragma unroll
                     for (int b = 0; b < P; ++b) {
                         A v = acc[oo * P + b];
-                        if (accumulate) v += widen(y[b]);
+                        if (o0 + oo < accumulate) v += widen(y[b]);
                         y[b] = narrow<TO>(v);
                     }
                 }

@@ -517,6 +517,8 @@ hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const Block
 // block combination Y (+)= X C with X = [in_0 .. in_{nin-1}] (n x K, K = nin P)
 // and Y = [out_0 .. out_{nout-1}] (n x N, N = nout P), C (K x N) row-major in
 // FP64: a tall-skinny product on FP64 matrix cores (FP32 inputs are widened).
+// The first `accumulate` output blocks are accumulated (Y += X C), the others
+// overwritten.
 // A = X[row][k] (column-major operand loads straight into registers, G input
 // blocks per pipeline step, the next step's loads in flight while the current
 // one is multiplied; the step sequence runs across row tiles), B = C[k][j]
@@ -592,10 +594,11 @@ __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, i
                     ybase = (ob & 1) ? y1 : y0;
                 }
                 double old[4] = {0, 0, 0, 0};
-                if (accumulate) {
+                if (16 * oc < accumulate * P) {  // some output block of this chunk is accumulated
+                    const double keep = ob < accumulate ? 1.0 : 0.0;
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        old[v] = (double)ybase[clamp_row(rbase + rq + 4 * v, n) * P + (col < N ? b : 0)];
+                        old[v] = keep * (double)ybase[clamp_row(rbase + rq + 4 * v, n) * P + (col < N ? b : 0)];
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {

@@ -98,7 +98,7 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     const size_t mp = (size_t)z.m * z.P, m1p = (size_t)(z.m + 1) * z.P;
     z.small_ = z.sa * (2 * (size_t)qmax * z.P + 2 * m1p * mp + (size_t)z.KP * mp + (size_t)z.m * 4 * z.P * z.P +
                        m1p * z.P + (size_t)(z.m + 1) * z.P * z.P + 2 * (size_t)z.P * z.P +
-                       (size_t)(2 * z.KB + z.m + 1) * z.P * 2 * z.KP) +
+                       (size_t)(2 * z.KB + z.m + 1) * z.P * (2 * std::max(z.KP, z.P) + 2 * z.P)) +
                sizeof(double) * ((size_t)z.m + (size_t)NWG_MAX * 2 * z.P) + sizeof(Ctl);
     z.total_fixed = z.basis + 3 * z.blk /* W2, Wb, R */ + (size_t)n * z.P * z.sa /* X */ + z.recyc + z.part + z.small_;
     return z;
@@ -285,7 +285,7 @@ struct Seq final : bgcr_sequence {
         RinvAll = dalloc<A>((size_t)(m + 1) * P * P);
         Z1 = dalloc<A>((size_t)P * P);
         Z1i = dalloc<A>((size_t)P * P);
-        coef_cap = (size_t)(2 * KB + m + 1) * P * 2 * std::max(KP, P);
+        coef_cap = (size_t)(2 * KB + m + 1) * P * (2 * std::max(KP, P) + 2 * P);
         coef = dalloc<A>(coef_cap);
         rho = dalloc<double>(m);
         dpart = dalloc<double>((size_t)NWG_MAX * 2 * P);
@@ -389,7 +389,7 @@ struct Seq final : bgcr_sequence {
         if ((size_t)nin * nout * P * P > coef_cap) throw Fail{BGCR_ERR_INVALID};
         std::vector<const void*> outc(out.begin(), out.end());
         const A* cf = upload_coef(K, nin, nout, coef);
-        const double by = (double)n * P * ((double)sizeof(T) * nin + (double)sizeof(TO) * nout * (accumulate ? 2 : 1));
+        const double by = (double)n * P * ((double)sizeof(T) * nin + (double)sizeof(TO) * (nout + accumulate));
         run(BGCR_K_COMBINE, by, [&] {
             if constexpr (!std::is_same<T, zd>::value) {
                 if (use_mx) {
@@ -769,8 +769,24 @@ struct Seq final : bgcr_sequence {
         return mx > 0.0 && mn > 1e-10 * mx;
     }
 
+    // The refresh of (U, C) as one block combination: outputs = inputs K
+    struct RefreshPlan {
+        bool active = false;
+        std::vector<const void*> in;
+        std::vector<void*> out;
+        Mat K;
+        int kn = 0;
+        int next_cur = 0;
+    };
+
+    void apply_refresh(const RefreshPlan& rp) {
+        combine<T>(rp.in, rp.out, rp.K, 0);
+        cur = rp.next_cur;
+        keff = rp.kn;
+    }
+
     // first system, no U (Algorithm 1 else-branch): Proposition block-harm-ritz
-    void refresh_first(const CycleOut& co) {
+    void refresh_first(const CycleOut& co, RefreshPlan& rp) {
         const int me = co.meff, mp = me * P;
         const int kt = std::min(k, mp);
         if (kt == 0) {
@@ -824,9 +840,12 @@ struct Seq final : bgcr_sequence {
         std::vector<void*> out;
         for (int b = 0; b < KB; ++b) out.push_back(ublk(cur, b));
         for (int b = 0; b < KB; ++b) out.push_back(cblk(cur, b));
-        hp.reset();
-        combine<T>(in, out, K2, 0);
-        keff = kn;
+        rp.active = true;
+        rp.in = in;
+        rp.out = out;
+        rp.K = K2;
+        rp.kn = kn;
+        rp.next_cur = cur;
     }
 
     // harmonic Ritz on the augmented space, eq. harm-ritz-gen-eig:
@@ -854,7 +873,7 @@ struct Seq final : bgcr_sequence {
 
     // Algorithm 1, end of a cycle with recycling: D, G_m, harmonic Ritz on
     // U + K_m, then C <- [C W_{m+1}] Q, U <- [U D  W_m] P rho^{-1}
-    void refresh_aug(const CycleOut& co) {
+    void refresh_aug(const CycleOut& co, RefreshPlan& rp) {
         const int me = co.meff, mp = me * P;
         // dots [U, C, V_1..V_meff, last]^H U
         std::vector<const void*> Q;
@@ -923,18 +942,64 @@ struct Seq final : bgcr_sequence {
         const int o = 1 - cur;
         for (int b = 0; b < KB; ++b) out.push_back(ublk(o, b));
         for (int b = 0; b < KB; ++b) out.push_back(cblk(o, b));
-        hp.reset();
-        combine<T>(Q, out, K2, 0);
-        cur = o;
-        keff = kn;
+        rp.active = true;
+        rp.in = Q;
+        rp.out = out;
+        rp.K = K2;
+        rp.kn = kn;
+        rp.next_cur = o;
     }
 
-    void refresh(const CycleOut& co, bool withC) {
-        if (k == 0) return;
-        if (withC)
-            refresh_aug(co);
-        else
-            refresh_first(co);
+    // End of a cycle (Algorithm 1): X += [V_m U] [Y; -F Y], R -= V_{m+1} H Y
+    // (the recurrence; skipped in the precision form, whose outer loop takes
+    // the FP64 true residual) and the refresh of (U, C).  On matrix cores in
+    // plain FP64 all of it is one pass over [U, C, V_1..V_m, V_{m+1}] writing
+    // [X, R, U', C'] (the refresh reads a superset of the update's inputs).
+    void finish_cycle(const CycleOut& co, bool withC, bool update_R) {
+        RefreshPlan rp;
+        if (k > 0) {
+            if (withC)
+                refresh_aug(co, rp);
+            else
+                refresh_first(co, rp);
+        }
+        const int nx = update_R ? 2 : 1;
+        const bool fuse = rp.active && use_mx && !mixed && !std::is_same<T, zd>::value &&
+                          (int)(nx + rp.out.size()) * P <= 64;
+        if (!fuse) {
+            update_solution(co, withC, update_R);
+            if (rp.active) apply_refresh(rp);
+            return;
+        }
+        std::unique_ptr<HostPhase> hp(new HostPhase(this, BGCR_K_HOST));
+        const int me = co.meff, mp = me * P;
+        const int voff = withC ? 2 * KP : 0;  // row of V_1 in the refresh inputs
+        Mat Kall((int)rp.in.size() * P, (nx + (int)rp.out.size()) * P);
+        for (int i = 0; i < mp; ++i)
+            for (int b = 0; b < P; ++b) Kall(voff + i, b) = co.Y(i, b);
+        if (withC) {
+            const Mat FY = dense::matmul(co.F, co.Y);
+            for (int i = 0; i < keff; ++i)
+                for (int b = 0; b < P; ++b) Kall(i, b) = -FY(i, b);
+        }
+        if (update_R) {
+            const Mat HY = dense::matmul(co.H, co.Y);
+            for (int i = 0; i < mp; ++i)
+                for (int b = 0; b < P; ++b) Kall(voff + i, P + b) = -HY(i, b);
+            const Mat last = dense::matmul(co.RinvLast, HY.block(mp, 0, P, P));
+            for (int i = 0; i < P; ++i)
+                for (int b = 0; b < P; ++b) Kall(voff + mp + i, P + b) = -last(i, b);
+        }
+        for (int c = 0; c < rp.K.c; ++c)
+            for (int r = 0; r < rp.K.r; ++r) Kall(r, nx * P + c) = rp.K(r, c);
+        std::vector<void*> outs;
+        outs.push_back(X);
+        if (update_R) outs.push_back(R);
+        for (void* o : rp.out) outs.push_back(o);
+        hp.reset();
+        combine<T>(rp.in, outs, Kall, nx);
+        cur = rp.next_cur;
+        keff = rp.kn;
     }
 
     int solve(const bgcr_csr* Am, const void* Bv, int64_t ldb, void* Xv, int64_t ldx, double tol,
@@ -1033,8 +1098,7 @@ struct Seq final : bgcr_sequence {
             project();
         } else {
             CycleOut co = cycle(Am, avT, false, thresh);
-            update_solution(co, false, true);
-            refresh(co, false);
+            finish_cycle(co, false, true);
             ++n_cycles;
             log_steps.push_back(co.meff);
             log_res.push_back(0.0);
@@ -1052,8 +1116,7 @@ struct Seq final : bgcr_sequence {
             if (n_cycles >= prm.max_cycles) return BGCR_NOT_CONVERGED;
             const bool withC = keff > 0;
             CycleOut co = cycle(Am, avT, withC, thresh);
-            update_solution(co, withC, true);
-            refresh(co, withC);
+            finish_cycle(co, withC, true);
             ++n_cycles;
             log_steps.push_back(co.meff);
             log_res.push_back(0.0);
@@ -1090,8 +1153,7 @@ struct Seq final : bgcr_sequence {
             const bool withC = keff > 0;
             if (withC) project();
             CycleOut co = cycle(Am, avT, withC, thresh);
-            update_solution(co, withC, false);
-            refresh(co, withC);
+            finish_cycle(co, withC, false);
             ++n_cycles;
             ++n_refine;
             log_steps.push_back(co.meff);
