@@ -24,7 +24,7 @@ HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-fcx-limit
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-I", INCLUDE, "-I", CSRC]
 # complex products without the NaN-recovery path (operands are finite and checked)
-CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-march=x86-64-v3", "-fcx-limited-range", "-I", INCLUDE, "-I", CSRC]
+CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-march=x86-64-v3", "-fcx-limited-range", "-fopenmp", "-I", INCLUDE, "-I", CSRC]
 
 HIP_SOURCES = ["kernels.hip", "kernels_mfma_f64.hip", "kernels_mfma_f32.hip", "solver.cpp"]
 CXX_SOURCES = ["dense.cpp"]
@@ -59,7 +59,7 @@ def build(verbose: bool = False) -> str:
             if o.strip():
                 print(o)
     tmp = LIB + ".tmp"
-    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run(["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-lgomp"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -1,6 +1,8 @@
 // Small dense FP64 linear algebra on the host (see dense.h).
 #include "dense.h"
 
+#include <omp.h>
+
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -10,6 +12,14 @@ namespace bgcr {
 namespace dense {
 
 static const double EPS = std::numeric_limits<double>::epsilon();
+
+// Host threads for the independent loops of one small problem (output
+// columns of a product, columns of Q, eigenvectors); a team only pays off
+// above ~1e5 flops of work.
+static int team(double work) {
+    if (work < 2e5) return 1;
+    return std::max(1, std::min(4, omp_get_max_threads()));
+}
 
 Mat Mat::block(int i0, int j0, int nr, int nc) const {
     Mat B(nr, nc);
@@ -46,6 +56,7 @@ Mat matmul(const Mat& A, const Mat& B) {
     if (all_real(A) && all_real(B)) {
         const std::vector<double> a = real_part(A), b = real_part(B);
         std::vector<double> c((size_t)A.r * B.c, 0.0);
+#pragma omp parallel for schedule(static) num_threads(team(2.0 * A.r * A.c * B.c))
         for (int j = 0; j < B.c; ++j)
             for (int l = 0; l < A.c; ++l) {
                 const double bl = b[(size_t)j * A.c + l];
@@ -57,6 +68,7 @@ Mat matmul(const Mat& A, const Mat& B) {
         return from_real(A.r, B.c, c);
     }
     Mat C(A.r, B.c);
+#pragma omp parallel for schedule(static) num_threads(team(8.0 * A.r * A.c * B.c))
     for (int j = 0; j < B.c; ++j)
         for (int l = 0; l < A.c; ++l) {
             const cd b = B(l, j);
@@ -225,15 +237,15 @@ static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R) {
     for (int j = 0; j < n; ++j)
         for (int i = 0; i <= std::min(j, kk - 1); ++i) r[(size_t)i + (size_t)j * kk] = col(j)[i];
     for (int i = 0; i < kk; ++i) q[(size_t)i + (size_t)i * m] = 1.0;
-    for (int k = kk - 1; k >= 0; --k) {
-        if (vvs[k] == 0.0) continue;
-        const std::vector<double>& v = vs[k];
-        const double f = 2.0 / vvs[k];
-        for (int j = 0; j < kk; ++j) {
+#pragma omp parallel for schedule(static) num_threads(team(4.0 * m * kk * kk))
+    for (int j = 0; j < kk; ++j) {
+        for (int k = std::min(j, kk - 1); k >= 0; --k) {  // reflectors k > j leave column j unchanged
+            if (vvs[k] == 0.0) continue;
+            const std::vector<double>& v = vs[k];
             double* qj = &q[(size_t)j * m + k];
             double w = 0.0;
             for (int i = 0; i < m - k; ++i) w += v[i] * qj[i];
-            w *= f;
+            w *= 2.0 / vvs[k];
             for (int i = 0; i < m - k; ++i) qj[i] -= w * v[i];
         }
     }
@@ -911,6 +923,13 @@ std::vector<cd> EigSolver::vector_for(cd lambda, const std::vector<std::vector<c
     }
     back(x);
     return x;
+}
+
+std::vector<std::vector<cd>> EigSolver::vectors_for(const std::vector<int>& idx) const {
+    std::vector<std::vector<cd>> out(idx.size());
+#pragma omp parallel for schedule(dynamic, 1) num_threads(team(20.0 * n * n * idx.size()))
+    for (int i = 0; i < (int)idx.size(); ++i) out[i] = vector_for(lam[idx[i]], {});
+    return out;
 }
 
 Selection select_ritz(const std::vector<cd>& theta, int k, bool largest, bool real) {

@@ -75,6 +75,8 @@ struct EigSolver {
     // eigenvector for eigenvalue lambda (unit 2-norm, in the basis of A);
     // `against`: vectors already chosen for nearby eigenvalues (kept apart)
     std::vector<cd> vector_for(cd lambda, const std::vector<std::vector<cd>>& against) const;
+    // vector_for(lam[i], {}) for each i in idx, computed concurrently
+    std::vector<std::vector<cd>> vectors_for(const std::vector<int>& idx) const;
 };
 
 // harmonic Ritz selection rules (Section 4.1): k values of smallest modulus

@@ -749,7 +749,7 @@ struct Seq final : bgcr_sequence {
             if (E.ok) {
                 for (int i = 0; i < nn; ++i) theta[i] = to_theta(E.lam[i]);
                 sel = dense::select_ritz(theta, kt, prm.select_largest != 0, !cplx);
-                for (int i : sel.idx) vecs.push_back(E.vector_for(E.lam[i], {}));
+                vecs = E.vectors_for(sel.idx);
                 return;
             }
         }
