@@ -128,6 +128,8 @@ struct Seq final : bgcr_sequence {
     size_t av32_cap = 0;
     A* dots = nullptr;
     size_t dots_cap = 0;
+    unsigned char* hr = nullptr;  // host-read region (see the constructor)
+    size_t off_H = 0, off_Rh = 0, off_g = 0, off_Ri = 0, off_F = 0, off_dots = 0, hr_bytes = 0;
     size_t part_cap = 0;  // elements of `part`
     A *part = nullptr, *S1 = nullptr, *Sf = nullptr, *H = nullptr, *F = nullptr, *Rh = nullptr, *QH = nullptr,
       *g = nullptr, *RinvAll = nullptr, *Z1 = nullptr, *Z1i = nullptr, *coef = nullptr;
@@ -274,23 +276,37 @@ struct Seq final : bgcr_sequence {
         part = dalloc<A>(part_cap);
         S1 = dalloc<A>((size_t)qmax * P);
         dots_cap = (size_t)qmax * P * std::max(KB, 1);
-        dots = dalloc<A>(dots_cap);
         Sf = dalloc<A>((size_t)qmax * P);
         const size_t mp = (size_t)m * P, m1p = (size_t)(m + 1) * P;
-        H = dalloc<A>(m1p * mp);
-        Rh = dalloc<A>(m1p * mp);
-        F = dalloc<A>(std::max<size_t>(1, (size_t)KP * mp));
+        // everything the host reads at the end of a cycle, contiguous so that
+        // one copy brings it over: control block, H and its triangular factor,
+        // g, R^{-1} of every step, F and the refresh dot products
+        {
+            auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+            off_H = al(sizeof(Ctl));
+            off_Rh = off_H + al(m1p * mp * sizeof(A));
+            off_g = off_Rh + al(m1p * mp * sizeof(A));
+            off_Ri = off_g + al(m1p * P * sizeof(A));
+            off_F = off_Ri + al((size_t)(m + 1) * P * P * sizeof(A));
+            off_dots = off_F + al(std::max<size_t>(1, (size_t)KP * mp) * sizeof(A));
+            hr_bytes = off_dots + al(dots_cap * sizeof(A));
+            hr = dalloc<unsigned char>(hr_bytes);
+            ctl = (Ctl*)hr;
+            H = (A*)(hr + off_H);
+            Rh = (A*)(hr + off_Rh);
+            g = (A*)(hr + off_g);
+            RinvAll = (A*)(hr + off_Ri);
+            F = (A*)(hr + off_F);
+            dots = (A*)(hr + off_dots);
+        }
         QH = dalloc<A>((size_t)m * 4 * P * P);
-        g = dalloc<A>(m1p * P);
-        RinvAll = dalloc<A>((size_t)(m + 1) * P * P);
         Z1 = dalloc<A>((size_t)P * P);
         Z1i = dalloc<A>((size_t)P * P);
         coef_cap = (size_t)(2 * KB + m + 1) * P * (2 * std::max(KP, P) + 2 * P);
         coef = dalloc<A>(coef_cap);
         rho = dalloc<double>(m);
         dpart = dalloc<double>((size_t)NWG_MAX * 2 * P);
-        ctl = dalloc<Ctl>(1);
-        hcap = std::max<size_t>((size_t)4 << 20, 2 * coef_cap * sizeof(A) + (64 << 10));
+        hcap = std::max({(size_t)4 << 20, 2 * coef_cap * sizeof(A) + (64 << 10), hr_bytes + (64 << 10)});
         if (hipHostMalloc((void**)&hbuf, hcap, hipHostMallocDefault) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
         HIPCHK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
         HIPCHK(hipMemsetAsync(Ub[0], 0, (size_t)KB * blk * sizeof(T), st));
@@ -404,20 +420,29 @@ struct Seq final : bgcr_sequence {
 
     // Q^H W for a list of W blocks: returns Mat (nq P) x (nw P).  Every piece
     // is reduced into its own slice of `dots`; one copy to the host at the end.
-    Mat multi_dot(const std::vector<const void*>& Q, const std::vector<const T*>& W) {
-        const int nq = (int)Q.size();
-        const int nw = (int)W.size();
-        Mat D(nq * P, nw * P);
-        // per launch: wg W blocks (32 columns on matrix cores, so that one pass
-        // over a Q chunk serves them all) against a chunk of qc Q blocks
-        const int wg = use_mx ? std::max(1, 32 / P) : 1;
-        const int nr = use_mx ? nwg_mx : nwg;
-        if ((size_t)nq * P * P * nw > dots_cap) throw Fail{BGCR_ERR_INVALID};
+    // Q^H W for a list of W blocks, as (nq P) x (nw P): enqueued pieces reduced
+    // into consecutive slices of `dots`, assembled on the host by dot_collect
+    struct DotJob {
         struct Piece {
             int w0, wn, q0, qn;
             size_t off;
         };
         std::vector<Piece> pieces;
+        size_t total = 0;  // elements of `dots` written
+        int nq = 0, nw = 0;
+        bool valid = false;
+    };
+
+    DotJob dot_enqueue(const std::vector<const void*>& Q, const std::vector<const T*>& W) {
+        DotJob job;
+        job.nq = (int)Q.size();
+        job.nw = (int)W.size();
+        const int nq = job.nq, nw = job.nw;
+        // per launch: wg W blocks (32 columns on matrix cores, so that one pass
+        // over a Q chunk serves them all) against a chunk of Q blocks
+        const int wg = use_mx ? std::max(1, 32 / P) : 1;
+        const int nr = use_mx ? nwg_mx : nwg;
+        if ((size_t)nq * P * P * nw > dots_cap) throw Fail{BGCR_ERR_INVALID};
         size_t off = 0;
         for (int w0 = 0; w0 < nw; w0 += wg) {
             const int wn = std::min(wg, nw - w0);
@@ -437,19 +462,32 @@ struct Seq final : bgcr_sequence {
                                          nullptr);
                 });
                 run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nr, nout, nullptr, dots + off, nullptr); });
-                pieces.push_back({w0, wn, q0, qn, off});
+                job.pieces.push_back({w0, wn, q0, qn, off});
                 off += nout;
             }
         }
-        std::vector<A> h(off);
-        d2h(h.data(), dots, off * sizeof(A));
-        for (const Piece& pc : pieces)
+        job.total = off;
+        job.valid = true;
+        return job;
+    }
+
+    // assemble a job's result from a host copy of `dots`
+    Mat dot_collect(const DotJob& job, const A* h) const {
+        Mat D(job.nq * P, job.nw * P);
+        for (const auto& pc : job.pieces)
             for (int wl = 0; wl < pc.wn; ++wl)
                 for (int c = 0; c < pc.qn * P; ++c)
                     for (int b = 0; b < P; ++b)
                         D(pc.q0 * P + c, (pc.w0 + wl) * P + b) =
                             to_cd(h[pc.off + (size_t)wl * pc.qn * P * P + (size_t)c * P + b]);
         return D;
+    }
+
+    Mat multi_dot(const std::vector<const void*>& Q, const std::vector<const T*>& W) {
+        const DotJob job = dot_enqueue(Q, W);
+        std::vector<A> h(job.total);
+        d2h(h.data(), dots, job.total * sizeof(A));
+        return dot_collect(job, h.data());
     }
 
     // per-column ||B - A X||^2 and ||B||^2 (FP64); stores R (narrowed) if Rout
@@ -538,6 +576,8 @@ struct Seq final : bgcr_sequence {
     struct CycleOut {
         int meff = 0;
         bool breakdown = false;
+        bool has_dots = false;  // refresh dots [U, C, V_1..V_m, V_{m+1}]^H U taken with the cycle
+        Mat Dm;
         Mat H, F, Y, RinvLast;
         const T* last = nullptr;  // block holding V_{meff+1} up to RinvLast
     };
@@ -625,23 +665,44 @@ struct Seq final : bgcr_sequence {
             });
         }
         cur_step = 0;
-        Ctl hc;
+        // The refresh after this cycle needs [U, C, V_1..V_meff, V_{meff+1}]^H U;
+        // every cycle but a system's last runs all m steps without breakdown,
+        // so the dots are taken now, with V_{m+1} = W'' R^{-1}, and arrive with
+        // the cycle's small results in one copy (redone by the refresh when the
+        // guess was wrong).
+        DotJob spec;
+        if (withC && k > 0) {
+            std::vector<const void*> Qs;
+            std::vector<const T*> Ws;
+            for (int b = 0; b < KB; ++b) Qs.push_back(ublk(cur, b));
+            for (int b = 0; b < KB; ++b) Qs.push_back(cblk(cur, b));
+            for (int i = 0; i < m; ++i) Qs.push_back(vblk(i));
+            Qs.push_back(W2);
+            for (int b = 0; b < KB; ++b) Ws.push_back(ublk(cur, b));
+            spec = dot_enqueue(Qs, Ws);
+        }
+        // (stream order puts the copy after every staged upload that reads hbuf)
+        const size_t nread = off_dots + (spec.valid ? spec.total * sizeof(A) : 0);
+        HIPCHK(hipMemcpyAsync(hbuf, hr, nread, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipMemcpy(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
-        if (prof) prof_resolve(hc.meff);
+        hoff = 0;
+        Ctl hc;
+        std::memcpy(&hc, hbuf, sizeof(Ctl));
+        const A* hH = (const A*)(hbuf + off_H);
+        const A* hR = (const A*)(hbuf + off_Rh);
+        const A* hg = (const A*)(hbuf + off_g);
+        const A* hRi = (const A*)(hbuf + off_Ri);
+        const A* hF = (const A*)(hbuf + off_F);
         CycleOut co;
         co.meff = hc.meff;
         co.breakdown = hc.status != 0;
         if (co.meff == 0) throw Fail{BGCR_ERR_NUMERICAL};
         const int me = co.meff, mp = me * P, ldH = m * P;
-        std::vector<A> hH((size_t)(m + 1) * P * ldH), hR((size_t)(m + 1) * P * ldH), hg((size_t)(m + 1) * P * P),
-            hRi((size_t)(m + 1) * P2), hF((size_t)std::max(1, KP) * ldH);
-        d2h_many({{hH.data(), H, hH.size() * sizeof(A)},
-                  {hR.data(), Rh, hR.size() * sizeof(A)},
-                  {hg.data(), g, hg.size() * sizeof(A)},
-                  {hRi.data(), RinvAll, hRi.size() * sizeof(A)},
-                  {hF.data(), F, (withC && KP > 0) ? (size_t)KP * ldH * sizeof(A) : 0}});
         HostPhase hp(this, BGCR_K_HOST);
+        if (spec.valid && me == m && !co.breakdown) {
+            co.Dm = dot_collect(spec, (const A*)(hbuf + off_dots));
+            co.has_dots = true;
+        }
         co.H = Mat((me + 1) * P, mp);
         for (int i = 0; i < (me + 1) * P; ++i)
             for (int j = 0; j < mp; ++j) co.H(i, j) = to_cd(hH[(size_t)i * ldH + j]);
@@ -666,6 +727,7 @@ struct Seq final : bgcr_sequence {
                 for (int b = 0; b < P; ++b) co.RinvLast(a, b) = to_cd(hRi[(size_t)me * P2 + a * P + b]);
         }
         if (co.breakdown) breakdown_seen = true;
+        if (prof) prof_resolve(hc.meff);
         // model-M algorithmic bytes of the executed Arnoldi sweeps
         for (int j = 1; j <= me; ++j)
             alg_bytes += abytes + 7.0 * blkb + 3.0 * sT * n * (kc + (double)j * P);
@@ -883,7 +945,7 @@ struct Seq final : bgcr_sequence {
         for (int i = 0; i < me; ++i) Q.push_back(vblk(i));
         Q.push_back(co.last);
         for (int b = 0; b < KB; ++b) W.push_back(ublk(cur, b));
-        const Mat Dm = multi_dot(Q, W);
+        const Mat Dm = co.has_dots ? co.Dm : multi_dot(Q, W);
         std::unique_ptr<HostPhase> hp(new HostPhase(this, BGCR_K_HOST));
         const int ke = keff;
         std::vector<double> d(ke);
