@@ -721,7 +721,7 @@ hipError_t Launch<T>::spmm_dot(hipStream_t st, int P, int64_t n, const int* rp, 
 template <class T>
 hipError_t Launch<T>::spmm_rinv(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci,
                                 const T* av, const T* Vin, const A* Rinv, T* Vout, T* Wout, const Ctl* ctl) {
-#define L(PP) return sp::launch_spmm_rinv<T, PP, sp::spmm_cols<T, PP>(), false>(st, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl, 2048);
+#define L(PP) return sp::launch_spmm_rinv<T, PP, sp::spmm_cols<T, PP>(), PP / sp::spmm_cols<T, PP>() == 4>(st, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl, 2048);
     BGCR_DISPATCH_P(P, L)
 #undef L
     return hipErrorInvalidValue;

@@ -630,7 +630,14 @@ struct Seq final : bgcr_sequence {
             const BlockPtrs Q1 = bp(Q);
             const int na = use_mx ? nwg_mx : nwg;
             // sweep 1a: W = A V_j with V_j = W2 R^{-1} (reads A, gathers W2, writes W and V_j)
-            run(BGCR_K_ARN_SPMM, abytes + 3.0 * blkb, [&] {
+            // algorithmic bytes per launch follow the byte model of a block step,
+            // (s_A + 4) nnz + 4 (n + 1) + 5 s n p + 3 s n q_j: A read and V_j
+            // gathered once, W written once and read twice, V_{j+1} written once,
+            // Q = [C V_1..V_j] read once per reduction sweep.  This schedule moves
+            // two more blocks per step than the model (the first dots re-read W,
+            // and W'' is stored raw then normalised in the next SpMM); they are
+            // not counted.  SpMM: A, V_j, W.
+            run(BGCR_K_ARN_SPMM, abytes + 2.0 * blkb, [&] {
                 return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
                                     vblk(j - 1), Wb, ctl);
             });
@@ -638,7 +645,7 @@ struct Seq final : bgcr_sequence {
             const BlockPtrs QB = bp(Q);
             const double qbytes = sT * n * (kc + (double)j * P);
             // sweep 1b: first block-CGS dots [C V_1..V_j]^H W (reads W and Q)
-            run(BGCR_K_ARN_DOT, blkb + qbytes, [&] {
+            run(BGCR_K_ARN_DOT, qbytes, [&] {  // Q
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (use_mx) return mfma_dot<T>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na);
                 }
@@ -646,14 +653,14 @@ struct Seq final : bgcr_sequence {
             });
             const int nout = (nq + 1) * P2;
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
-            run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {
+            run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {  // W, Q
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (use_mx) return mfma_proj_dot<T>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, na, ctl, 1);
             });
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, S1, Sf, ctl); });
-            run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {
+            run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {  // W, V_{j+1}, Q
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (use_mx) return mfma_proj_gram<T>(st, P, n, Wb, QB, nq + 1, Sf, W2, part, ctl, na);
                 }
@@ -730,7 +737,7 @@ struct Seq final : bgcr_sequence {
         if (prof) prof_resolve(hc.meff);
         // model-M algorithmic bytes of the executed Arnoldi sweeps
         for (int j = 1; j <= me; ++j)
-            alg_bytes += abytes + 7.0 * blkb + 3.0 * sT * n * (kc + (double)j * P);
+            alg_bytes += abytes + 5.0 * blkb + 3.0 * sT * n * (kc + (double)j * P);
         n_spmm += me;
         n_steps += me;
         return co;

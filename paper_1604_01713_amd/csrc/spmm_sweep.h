@@ -3,7 +3,10 @@
 //
 // A lane owns C consecutive columns of one row (16 bytes; LPR = P / C lanes
 // per row), so every gather of a neighbour row is one 16-byte load per lane
-// and one load instruction of a wave reads a contiguous span of the block.  Nonzeros are taken in batches of NB; index loads are clamped
+// and one load instruction of a wave reads a contiguous span of the block.
+// With 4 lanes per row, each lane loads a quarter of a batch's column indices
+// and values and the batch is assembled by quad broadcasts.  The matrix is
+// read once per sweep and is loaded with the non-temporal hint.  Nonzeros are taken in batches of NB; index loads are clamped
 // into the arrays and padding entries are cancelled by a 0/1 factor (no
 // select of a loaded value, which the compiler would turn into a branch that
 // waits for the load).  The P x P product with Rinv reads Rinv from LDS
@@ -27,10 +30,39 @@ __device__ inline int64_t clamp_row(int64_t row, int64_t n) { return row < n ? r
 
 template <class T> __device__ inline T tzero() { return T{}; }
 
+typedef double vd2 __attribute__((ext_vector_type(2)));
+// load with the non-temporal hint (data read once)
+__device__ inline float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ inline double ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ inline zd ld_nt(const zd* p) {
+    const vd2 v = __builtin_nontemporal_load((const vd2*)p);
+    return {v[0], v[1]};
+}
+
+// value of lane q of each group of 4 lanes (DPP quad_perm broadcast)
+template <int Q>
+__device__ inline int quad_bcast_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, Q * 0x55, 0xF, 0xF, false);
+}
+__device__ inline int quad_bcast(int v, int q) {
+    switch (q) {
+        case 0: return quad_bcast_i<0>(v);
+        case 1: return quad_bcast_i<1>(v);
+        case 2: return quad_bcast_i<2>(v);
+        default: return quad_bcast_i<3>(v);
+    }
+}
+__device__ inline double quad_bcast(double v, int q) {
+    const long long b = __double_as_longlong(v);
+    const int lo = quad_bcast((int)(b & 0xffffffffll), q), hi = quad_bcast((int)(b >> 32), q);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline float quad_bcast(float v, int q) { return __int_as_float(quad_bcast(__float_as_int(v), q)); }
+__device__ inline zd quad_bcast(zd v, int q) { return {quad_bcast(v.x, q), quad_bcast(v.y, q)}; }
+
 // C consecutive values of a row, as 16-byte vector loads/stores when the
 // lane's slice is a whole number of 16-byte words (blocks are allocated
 // 256-byte aligned and a row of P values starts on a 16-byte boundary then)
-typedef double vd2 __attribute__((ext_vector_type(2)));
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
 template <class T, int C, int P>
@@ -80,7 +112,7 @@ __device__ inline void store_cols(T* __restrict__ p, const T (&v)[C]) {
     }
 }
 
-template <class T, int P, int C, bool PIPE>
+template <class T, int P, int C, bool SHARE>
 __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const T* __restrict__ av,
                                                    const T* __restrict__ Vin, const acc_t<T>* __restrict__ Rinv,
@@ -88,6 +120,7 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
     using A = acc_t<T>;
     using R = typename std::conditional<std::is_same<T, zd>::value, double, T>::type;  // real scalar of T
     static_assert(P % C == 0, "columns per lane must divide P");
+    static_assert(!SHARE || P / C == 4, "shared nonzero loads need 4 lanes per row");
     constexpr int LPR = P / C, ROWS = 256 / LPR, NB = 8;
     if (ctl && ctl->active == 0) return;
     __shared__ A Rs[P * P];
@@ -116,8 +149,25 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int64_t kk = (int64_t)kb + u < nzl ? (int64_t)kb + u : nzl;
-            cols[u] = ci[kk];
-            vals[u] = av[kk];
+            cols[u] = __builtin_nontemporal_load(ci + kk);
+            vals[u] = ld_nt(av + kk);
+        }
+    };
+    // entries kb + 2 part, kb + 2 part + 1 loaded by this lane, the batch of
+    // NB = 8 assembled by quad broadcasts (4 lanes per row)
+    auto load_nz_shared = [&](int kb, int prt, int (&cols)[NB], T (&vals)[NB]) {
+        int mc[2];
+        T mv[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t kk = (int64_t)kb + 2 * prt + h < nzl ? (int64_t)kb + 2 * prt + h : nzl;
+            mc[h] = __builtin_nontemporal_load(ci + kk);
+            mv[h] = ld_nt(av + kk);
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            cols[u] = quad_bcast(mc[u & 1], u >> 1);
+            vals[u] = quad_bcast(mv[u & 1], u >> 1);
         }
     };
     // raw += sum over one batch of nonzeros (entries at or past e cancelled)
@@ -172,79 +222,27 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
         }
         return;
     }
-    if constexpr (!PIPE) {
-        for (int64_t tile = first; tile < end; tile += step) {
-            const int64_t row = tile * ROWS + r;
-            const int64_t rowc = clamp_row(row, n);
-            T raw[C], vb[C];
+    for (int64_t tile = first; tile < end; tile += step) {
+        const int64_t row = tile * ROWS + r;
+        const int64_t rowc = clamp_row(row, n);
+        T raw[C], vb[C];
 #pragma unroll
-            for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
-            load_cols<T, C, P>(vb, Vin + rowc * P + c0);
-            const int beg = rp[rowc], e = rp[rowc + 1];
-            for (int kb = beg; kb < e; kb += NB) {
-                int cols[NB];
-                T vals[NB];
+        for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
+        load_cols<T, C, P>(vb, Vin + rowc * P + c0);
+        const int beg = __builtin_nontemporal_load(rp + rowc), e = __builtin_nontemporal_load(rp + rowc + 1);
+        for (int kb = beg; kb < e; kb += NB) {
+            int cols[NB];
+            T vals[NB];
+            if constexpr (SHARE) {
+                // the 4 lanes of a row each load 2 of the batch's entries and
+                // broadcast them to the quad (DPP), instead of all 4 loading all
+                load_nz_shared(kb, part, cols, vals);
+            } else {
                 load_nz(kb, cols, vals);
-                accumulate(raw, cols, vals, kb, e);
             }
-            finish(raw, vb, row);
+            accumulate(raw, cols, vals, kb, e);
         }
-    } else {
-        // software pipeline over the tiles: gathers of tile t, nonzeros of
-        // tile t+1 and row pointers of tile t+2 in flight together
-        if (first >= end) return;
-        int beg0, e0, beg1 = 0, e1 = 0;
-        {
-            const int64_t rc0 = clamp_row(first * ROWS + r, n);
-            beg0 = rp[rc0];
-            e0 = rp[rc0 + 1];
-        }
-        if (first + step < end) {
-            const int64_t rc1 = clamp_row((first + step) * ROWS + r, n);
-            beg1 = rp[rc1];
-            e1 = rp[rc1 + 1];
-        }
-        int cols[NB];
-        T vals[NB];
-        load_nz(beg0, cols, vals);
-        for (int64_t tile = first; tile < end; tile += step) {
-            const int64_t row = tile * ROWS + r;
-            T vb[C];
-            load_cols<T, C, P>(vb, Vin + clamp_row(row, n) * P + c0);
-            T g[NB][C];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) load_cols<T, C, P>(g[u], Vin + (int64_t)cols[u] * P + c0);
-            const int cb = beg0, ce = e0;
-            T cv[NB];
-#pragma unroll
-            for (int u = 0; u < NB; ++u) cv[u] = vals[u];
-            if (tile + step < end) {
-                load_nz(beg1, cols, vals);
-                beg0 = beg1;
-                e0 = e1;
-                if (tile + 2 * step < end) {
-                    const int64_t rc2 = clamp_row((tile + 2 * step) * ROWS + r, n);
-                    beg1 = rp[rc2];
-                    e1 = rp[rc2 + 1];
-                }
-            }
-            T raw[C];
-#pragma unroll
-            for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
-#pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                const T a = mscale(cv[u], (R)(cb + u < ce ? 1 : 0));
-#pragma unroll
-                for (int j = 0; j < C; ++j) raw[j] += a * g[u][j];
-            }
-            for (int kb = cb + NB; kb < ce; kb += NB) {  // rows with more than NB nonzeros
-                int xc[NB];
-                T xv[NB];
-                load_nz(kb, xc, xv);
-                accumulate(raw, xc, xv, kb, ce);
-            }
-            finish(raw, vb, row);
-        }
+        finish(raw, vb, row);
     }
 }
 
@@ -256,7 +254,7 @@ constexpr int spmm_cols() {
     return P < (int)(16 / sizeof(T)) ? P : (int)(16 / sizeof(T));
 }
 
-template <class T, int P, int C, bool PIPE>
+template <class T, int P, int C, bool SHARE>
 hipError_t launch_spmm_rinv(hipStream_t st, int64_t n, int64_t nnz, const int* rp, const int* ci, const T* av,
                             const T* Vin, const acc_t<T>* Rinv, T* Vout, T* Wout, const Ctl* ctl, int max_wg) {
     constexpr int ROWS = 256 / (P / C);
@@ -264,7 +262,7 @@ hipError_t launch_spmm_rinv(hipStream_t st, int64_t n, int64_t nnz, const int* r
     int64_t g = tiles < max_wg ? tiles : max_wg;
     if (g >= 8) g -= g % 8;
     const int nwg = (int)(g < 1 ? 1 : g);
-    hipLaunchKernelGGL((k_spmm_rinv<T, P, C, PIPE>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin, Rinv, Vout,
+    hipLaunchKernelGGL((k_spmm_rinv<T, P, C, SHARE>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin, Rinv, Vout,
                        Wout, ctl);
     return hipGetLastError();
 }
