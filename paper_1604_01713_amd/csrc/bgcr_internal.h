@@ -102,10 +102,11 @@ struct Launch {
                               const BlockPtrs& out, int nout, const A* coef, int accumulate);
 };
 
-// reduce partials: out[o] = (add ? add[o] : 0) + sum_w part[w*nout + o]
+// reduce partials: out[o] = (add && o < nadd ? add[o] : 0) + sum_w part[w*nout + o]
+// (nadd < 0: all outputs)
 template <class A>
 hipError_t reduce_partials(hipStream_t st, const A* part, int nwg, int nout, const A* add, A* out,
-                           const Ctl* ctl);
+                           const Ctl* ctl, int nadd = -1);
 
 // R = B - A X in FP64 (complex128); optional store of R narrowed to TR; per-WG
 // partial sums [|r_b|^2 (P)] [|b_b|^2 (P)] into part (double)
@@ -118,8 +119,10 @@ template <class A>
 hipError_t cholqr_first(hipStream_t st, int P, const A* gram, A* Z1, A* Z1inv, Ctl* ctl);
 template <class A>
 hipError_t cholqr_second(hipStream_t st, int P, const A* gram, const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl);
+// S1 non-null: `gram` is W'^H W' of the second pass and W''^H W'' = gram - S2^H S2
+// with S2 = S - S1 (Pythagorean Gram of the stored block)
 template <class A>
-hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, int KP, int j, int m, A* H, A* F,
+hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, const A* S1, int KP, int j, int m, A* H, A* F,
                       A* Rh, A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl, double thresh);
 
 // matrix-core versions of the three Arnoldi sweeps (real FP64/FP32 storage,
@@ -133,12 +136,17 @@ hipError_t i_minus(hipStream_t st, const double* M, double* out, int P);
 template <class T>
 hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq,
                     double* part, const Ctl* ctl, int nwg);
+// sweep 2: partial Q^T (W - Q S) and, with gram, (W - Q S)^T (W - Q S) after it
 template <class T>
 hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                         double* part, const Ctl* ctl, int nwg);
+                         double* part, const Ctl* ctl, int nwg, bool gram = false);
+// sweep 3: W'' = W - Q S stored with its Gram partials, or with Rinv given,
+// V = W'' Rinv stored (no Gram); with a control block it runs while the cycle
+// is active and also for block step `step` if the cycle just stopped there
 template <class T>
 hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
-                          const double* S, T* Wout, double* part, const Ctl* ctl, int nwg);
+                          const double* S, T* Wout, double* part, const Ctl* ctl, int nwg, const double* Rinv = nullptr,
+                          int step = -1);
 
 // Y (+)= [in..] C on matrix cores (real FP64/FP32 inputs, FP64 coefficients
 // row-major (nin P) x (nout P)); the first `accumulate` output blocks are

@@ -346,7 +346,7 @@ __global__ __launch_bounds__(NT) void k_combine(int64_t n, BlockPtrs in, int nin
 // sums are added in order (deterministic).
 template <class A>
 __global__ __launch_bounds__(256) void k_reduce(const A* __restrict__ part, int nwg, int nout,
-                                                const A* __restrict__ add, A* out, const Ctl* ctl) {
+                                                const A* __restrict__ add, int nadd, A* out, const Ctl* ctl) {
     if (ctl && ctl->active == 0) return;
     __shared__ A red[256];
     const int t = threadIdx.x;
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(256) void k_reduce(const A* __restrict__ part, int 
     red[t] = s0 + s1;
     __syncthreads();
     if (t < 16 && o < nout) {
-        A s = add ? add[o] : zero<A>();
+        A s = (add && o < nadd) ? add[o] : zero<A>();
         for (int q = 0; q < 16; ++q) s += red[q * 16 + t];
         out[o] = s;
     }
@@ -537,9 +537,9 @@ __global__ void k_cholqr_second(const A* gram, const A* Z1, A* Rinv0, A* g, int 
 // of block column j are accumulated into one 2P x 2P unitary QH_j that later
 // columns apply as a single matrix product.
 template <class A, int P>
-__global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, int KP, int j, int m, A* H, A* F,
-                                                   A* Rh, A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl,
-                                                   double thresh) {
+__global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, const A* S1, int KP, int j, int m,
+                                                   A* H, A* F, A* Rh, A* QH, A* g, A* RinvAll, double* rho,
+                                                   Ctl* ctl, double thresh) {
     if (ctl->active == 0) return;
     constexpr int P2 = 2 * P;
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
@@ -549,7 +549,19 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, in
     const int t = threadIdx.x;
     const int jc = j - 1;
     const int ldH = m * P;
-    for (int e = t; e < P * P; e += NT) Gs[e] = gram[e];
+    if (S1) {
+        // Gram of W'' = W' - Q S2 from the second pass's data (Pythagoras,
+        // Q^H W'' = 0): W''^H W'' = W'^H W' - S2^H S2 with S2 = S - S1
+        const int q = KP + j * P;
+        for (int e = t; e < P * P; e += NT) {
+            const int a = e / P, b = e % P;
+            A acc = gram[e];
+            for (int c = 0; c < q; ++c) acc -= cj(S[c * P + a] - S1[c * P + a]) * (S[c * P + b] - S1[c * P + b]);
+            Gs[e] = acc;
+        }
+    } else {
+        for (int e = t; e < P * P; e += NT) Gs[e] = gram[e];
+    }
     __syncthreads();
     if (t == 0) {
         okf = chol_upper(Gs, Rs, P);
@@ -773,9 +785,11 @@ hipError_t Launch<T>::combine(hipStream_t st, int P, int64_t n, const BlockPtrs&
 }
 
 template <class A>
-hipError_t reduce_partials(hipStream_t st, const A* part, int nwg, int nout, const A* add, A* out, const Ctl* ctl) {
+hipError_t reduce_partials(hipStream_t st, const A* part, int nwg, int nout, const A* add, A* out, const Ctl* ctl,
+                           int nadd) {
     if (nout <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_reduce<A>), dim3((nout + 15) / 16), dim3(256), 0, st, part, nwg, nout, add, out, ctl);
+    hipLaunchKernelGGL((k_reduce<A>), dim3((nout + 15) / 16), dim3(256), 0, st, part, nwg, nout, add,
+                       nadd < 0 ? nout : nadd, out, ctl);
     return hipGetLastError();
 }
 
@@ -805,9 +819,9 @@ hipError_t cholqr_second(hipStream_t st, int P, const A* gram, const A* Z1, A* R
 }
 
 template <class A>
-hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, int KP, int j, int m, A* H, A* F, A* Rh,
-                      A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl, double thresh) {
-#define L(PP) hipLaunchKernelGGL((k_step_small<A, PP>), dim3(1), dim3(NT), 0, st, gram, S, KP, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
+hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, const A* S1, int KP, int j, int m, A* H, A* F,
+                      A* Rh, A* QH, A* g, A* RinvAll, double* rho, Ctl* ctl, double thresh) {
+#define L(PP) hipLaunchKernelGGL((k_step_small<A, PP>), dim3(1), dim3(NT), 0, st, gram, S, S1, KP, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
     BGCR_DISPATCH_P(P, L)
 #undef L
     return hipGetLastError();
@@ -840,8 +854,9 @@ template hipError_t Launch<float>::combine<double>(hipStream_t, int, int64_t, co
                                                    const BlockPtrs&, int, const double*, int);
 template hipError_t Launch<zd>::combine<zd>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int,
                                             const zd*, int);
-template hipError_t reduce_partials<double>(hipStream_t, const double*, int, int, const double*, double*, const Ctl*);
-template hipError_t reduce_partials<zd>(hipStream_t, const zd*, int, int, const zd*, zd*, const Ctl*);
+template hipError_t reduce_partials<double>(hipStream_t, const double*, int, int, const double*, double*, const Ctl*,
+                                            int);
+template hipError_t reduce_partials<zd>(hipStream_t, const zd*, int, int, const zd*, zd*, const Ctl*, int);
 template hipError_t residual<double, double>(hipStream_t, int, int64_t, const int*, const int*, const double*,
                                              const double*, int64_t, const double*, double*, double*, int);
 template hipError_t residual<double, float>(hipStream_t, int, int64_t, const int*, const int*, const double*,
@@ -852,10 +867,10 @@ template hipError_t cholqr_first<double>(hipStream_t, int, const double*, double
 template hipError_t cholqr_first<zd>(hipStream_t, int, const zd*, zd*, zd*, Ctl*);
 template hipError_t cholqr_second<double>(hipStream_t, int, const double*, const double*, double*, double*, int, Ctl*);
 template hipError_t cholqr_second<zd>(hipStream_t, int, const zd*, const zd*, zd*, zd*, int, Ctl*);
-template hipError_t step_small<double>(hipStream_t, int, const double*, const double*, int, int, int, double*, double*,
-                                       double*, double*, double*, double*, double*, Ctl*, double);
-template hipError_t step_small<zd>(hipStream_t, int, const zd*, const zd*, int, int, int, zd*, zd*, zd*, zd*, zd*, zd*,
-                                   double*, Ctl*, double);
+template hipError_t step_small<double>(hipStream_t, int, const double*, const double*, const double*, int, int, int,
+                                       double*, double*, double*, double*, double*, double*, double*, Ctl*, double);
+template hipError_t step_small<zd>(hipStream_t, int, const zd*, const zd*, const zd*, int, int, int, zd*, zd*, zd*,
+                                   zd*, zd*, zd*, double*, Ctl*, double);
 template hipError_t copy_block<double, double>(hipStream_t, int64_t, int, const double*, int64_t, double*, int64_t,
                                                int);
 template hipError_t copy_block<zd, zd>(hipStream_t, int64_t, int, const zd*, int64_t, zd*, int64_t, int);

@@ -71,9 +71,9 @@ __device__ inline void tile_span(int64_t ntiles, int lw, int64_t& t0, int64_t& t
 // c P + w % P] (one q x P slice per W block), nout = nw q P.
 template <class T, int P, int NG, int NC>
 __device__ inline void write_dot_partials(const typename MX<T>::acc (&acc)[NG][NC], int q, int nw, double* red,
-                                          double* part, int lw) {
+                                          double* part, int lw, int64_t stride = -1) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int64_t nout = (int64_t)nw * q * P;
+    const int64_t nout = stride < 0 ? (int64_t)nw * q * P : stride;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
 #pragma unroll
@@ -94,9 +94,9 @@ __device__ inline void write_dot_partials(const typename MX<T>::acc (&acc)[NG][N
     }
 }
 
-// Gram accumulator (FP64 MFMA, D[i][j] = G[i][j]) -> part[lw][i P + j]
+// Gram accumulator (FP64 MFMA, D[i][j] = G[i][j]) -> part[lw][off + i P + j]
 template <int P>
-__device__ inline void write_gram_partials(d4v g, double* red, double* part, int lw, int nout) {
+__device__ inline void write_gram_partials(d4v g, double* red, double* part, int lw, int nout, int off = 0) {
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     __syncthreads();
 #pragma unroll
@@ -106,7 +106,7 @@ __device__ inline void write_gram_partials(d4v g, double* red, double* part, int
     const double s = red[(0 * 4 + v) * 64 + l] + red[(1 * 4 + v) * 64 + l] + red[(2 * 4 + v) * 64 + l] +
                      red[(3 * 4 + v) * 64 + l];
     const int i = MX<double>::drow(l, v), j = l & 15;
-    if (i < P && j < P) part[(int64_t)lw * nout + i * P + j] = s;
+    if (i < P && j < P) part[(int64_t)lw * nout + off + i * P + j] = s;
 }
 
 // Per-lane source of the row-major ("RC") operand: lane l reads column
@@ -247,13 +247,14 @@ k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restri
 }
 
 // ---------------------------------------------------------------------------
-// update-and-dot sweep: W' = W - Q S (not stored); partial S' = Q^T W'.
+// update-and-dot sweep: W' = W - Q S (not stored); partial S' = Q^T W' and,
+// with GRAM, partial W'^T W' (FP64) after it (partial layout [q P dots][P P]).
 // Q is loaded row-major, staged in a wave-private LDS tile and read back
 // column-major for the update and row-major for the dot; the next tile's
 // loads are in flight while the current one is computed.  No workgroup
 // barrier inside the loop (each wave only reads what it wrote).
 // ---------------------------------------------------------------------------
-template <class T, int P, int NC>
+template <class T, int P, int NC, bool GRAM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 ? NC <= 7 : NC <= 10) ? 2 : 1))) void k_proj_dot_mfma(
     int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq, const double* __restrict__ S, double* __restrict__ part,
     const Ctl* ctl) {
@@ -274,6 +275,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
     typename M::acc acc[NC];
 #pragma unroll
     for (int ch = 0; ch < NC; ++ch) acc[ch] = typename M::acc{0, 0, 0, 0};
+    d4v gacc = {0, 0, 0, 0};
     const int lw = logical_wg();
     int64_t t0, t1;
     tile_span((n + MROWS - 1) / MROWS, lw, t0, t1);
@@ -315,26 +317,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
             const T wv = myW[rl * P + bc];
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch) acc[ch] = M::mma(wv, myQ[qsw<QLD>(rl, 16 * ch + bl)], acc[ch]);
+            if constexpr (GRAM) gacc = MX<double>::mma((double)wv, (double)wv, gacc);
         }
     }
     typename M::acc acc1[1][NC];
 #pragma unroll
     for (int ch = 0; ch < NC; ++ch) acc1[0][ch] = acc[ch];
-    write_dot_partials<T, P, 1, NC>(acc1, q, 1, red, part, lw);
+    const int64_t stride = (int64_t)q * P + (GRAM ? P * P : 0);
+    write_dot_partials<T, P, 1, NC>(acc1, q, 1, red, part, lw, stride);
+    if constexpr (GRAM) write_gram_partials<P>(gacc, red, part, lw, (int)stride, q * P);
 }
 
 // ---------------------------------------------------------------------------
 // update-and-Gram sweep: W'' = W - Q S, stored (optional); partial Gram
-// W''^T W'' in FP64.  NC = 0: no update (Gram of W only).  The update
-// operands are loaded column-major straight into registers, double-buffered.
+// W''^T W'' in FP64.  NC = 0: no update (Gram of W only).  With NORM the
+// sweep stores V = W'' R^{-1} instead (R^{-1} given, P x P FP64) and computes
+// no Gram.  The update operands are loaded column-major straight into
+// registers, double-buffered.
 // ---------------------------------------------------------------------------
-template <class T, int P, int NC>
+template <class T, int P, int NC, bool NORM>
 __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq,
                                                         const double* __restrict__ S, T* __restrict__ Wout,
-                                                        double* __restrict__ part, const Ctl* ctl) {
+                                                        double* __restrict__ part, const double* __restrict__ Rinv,
+                                                        const Ctl* ctl, int step) {
     using M = MX<T>;
     constexpr int NQ = NC * 16 / P, KK = P / 4, NQV = NQ * KK, NQA = NQ > 0 ? NQ : 1;
-    if (ctl && ctl->active == 0) return;
+    // runs while the cycle is active, and also for the step at which it just
+    // stopped without breakdown (its block V_{step+1} is still needed)
+    if (ctl && ctl->active == 0 && !(ctl->meff == step && ctl->status == 0)) return;
     const int q = nq * P;
     extern __shared__ __align__(16) unsigned char smem[];
     T* Ss = (T*)smem;                  // [NQA*P][P]: -S, zero past q
@@ -351,6 +361,12 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
     int64_t t0, t1;
     tile_span((n + MROWS - 1) / MROWS, lw, t0, t1);
     T* mytr = tr + wave * 16 * P;
+    // NORM: A operands (R^{-1})^T[b'][b] for b = 4 kk + l/16, b' = l % 16
+    T ra[KK];
+    if constexpr (NORM) {
+#pragma unroll
+        for (int kk = 0; kk < KK; ++kk) ra[kk] = (T)Rinv[(4 * kk + rq) * P + bc];
+    }
     // column-major operands: [blk*KK + kk] holds Q_blk[rbase + l % 16][4 kk + l / 16]
     auto load_cr = [&](T(&qv)[NQA * KK], int64_t rbase) {
         const int64_t off = clamp_row(rbase + bl, n) * P + rq;
@@ -383,22 +399,37 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
         if (tile + 1 < t1) wn = load_wt<T, P>(Win, rbase + MROWS, n, lane);
         const int64_t row = rbase + bl;
         zero_tail<T>(d, rbase, n, lane);
-        if (Wout && row < n) {
+        if constexpr (NORM) {
+            // V^T = (R^{-1})^T W''^T: B operand W''^T[4 kk + l/16][row l % 16] from the tile in LDS
+            d_to_lds<T, P>(d, mytr, lane);
+            typename M::acc dv = typename M::acc{0, 0, 0, 0};
 #pragma unroll
-            for (int v = 0; v < M::template vn<P>(); ++v) {
-                const int b = M::drow(lane, v);
-                if (b < P) Wout[row * P + b] = d[v];
+            for (int kk = 0; kk < KK; ++kk) dv = M::mma(ra[kk], mytr[bl * P + 4 * kk + rq], dv);
+            if (row < n) {
+#pragma unroll
+                for (int v = 0; v < M::template vn<P>(); ++v) {
+                    const int b = M::drow(lane, v);
+                    if (b < P) Wout[row * P + b] = dv[v];
+                }
+            }
+        } else {
+            if (Wout && row < n) {
+#pragma unroll
+                for (int v = 0; v < M::template vn<P>(); ++v) {
+                    const int b = M::drow(lane, v);
+                    if (b < P) Wout[row * P + b] = d[v];
+                }
+            }
+            d_to_lds<T, P>(d, mytr, lane);
+            // Gram rows and columns past P repeat column b % P and are never written
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const double wv = (double)mytr[(4 * ks + rq) * P + bc];
+                gacc = MX<double>::mma(wv, wv, gacc);
             }
         }
-        d_to_lds<T, P>(d, mytr, lane);
-        // Gram rows and columns past P repeat column b % P and are never written
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const double wv = (double)mytr[(4 * ks + rq) * P + bc];
-            gacc = MX<double>::mma(wv, wv, gacc);
-        }
     }
-    write_gram_partials<P>(gacc, red, part, lw, P * P);
+    if constexpr (!NORM) write_gram_partials<P>(gacc, red, part, lw, P * P);
 }
 
 // ---------------------------------------------------------------------------
@@ -472,9 +503,9 @@ hipError_t launch_dot(hipStream_t st, int64_t n, const BlockPtrs& W, int nw, con
     return hipGetLastError();
 }
 
-template <class T, int P>
-hipError_t launch_proj_dot(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                           double* part, int nwg, const Ctl* ctl) {
+template <class T, int P, bool GRAM>
+hipError_t launch_proj_dot_t(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
+                             double* part, int nwg, const Ctl* ctl) {
     const int nc = (nq * P + 15) / 16;
 #define L(NC)                                                                                                   \
     {                                                                                                           \
@@ -483,9 +514,9 @@ hipError_t launch_proj_dot(hipStream_t st, int64_t n, const T* Win, const BlockP
                                     (size_t)1024 * sizeof(double));                                             \
         if (lds > (size_t)160 * 1024) return hipErrorNotSupported;                                              \
         static std::once_flag fl;                                                                               \
-        std::call_once(fl, [] { allow_lds(k_proj_dot_mfma<T, P, NC>); });                                       \
-        hipLaunchKernelGGL((k_proj_dot_mfma<T, P, NC>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, part, \
-                           ctl);                                                                                \
+        std::call_once(fl, [] { allow_lds(k_proj_dot_mfma<T, P, NC, GRAM>); });                                 \
+        hipLaunchKernelGGL((k_proj_dot_mfma<T, P, NC, GRAM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S,  \
+                           part, ctl);                                                                          \
     }
     BGCR_MX_NC_DISPATCH(nc, L)
 #undef L
@@ -493,15 +524,22 @@ hipError_t launch_proj_dot(hipStream_t st, int64_t n, const T* Win, const BlockP
 }
 
 template <class T, int P>
-hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                            T* Wout, double* part, int nwg, const Ctl* ctl) {
+hipError_t launch_proj_dot(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
+                           double* part, int nwg, const Ctl* ctl, bool gram) {
+    return gram ? launch_proj_dot_t<T, P, true>(st, n, Win, Q, nq, S, part, nwg, ctl)
+                : launch_proj_dot_t<T, P, false>(st, n, Win, Q, nq, S, part, nwg, ctl);
+}
+
+template <class T, int P, bool NORM>
+hipError_t launch_proj_gram_t(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
+                              T* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step) {
     const int nc = (nq * P + 15) / 16;
 #define L(NC)                                                                                                    \
     {                                                                                                            \
         constexpr int NQA = NC * 16 / P > 0 ? NC * 16 / P : 1;                                                   \
         const size_t lds = std::max((size_t)(NQA * P * P + 4 * 16 * P) * sizeof(T), (size_t)1024 * sizeof(double)); \
-        hipLaunchKernelGGL((k_proj_gram_mfma<T, P, NC>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, Wout,  \
-                           part, ctl);                                                                           \
+        hipLaunchKernelGGL((k_proj_gram_mfma<T, P, NC, NORM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, \
+                           Wout, part, Rinv, ctl, step);                                                         \
     }
     if (nq == 0) {
         L(0);
@@ -510,6 +548,13 @@ hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const Block
     BGCR_MX_NC_DISPATCH(nc, L)
 #undef L
     return hipGetLastError();
+}
+
+template <class T, int P>
+hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
+                            T* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step) {
+    return Rinv ? launch_proj_gram_t<T, P, true>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step)
+                : launch_proj_gram_t<T, P, false>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
 }
 
 
@@ -648,17 +693,18 @@ hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw
 
 template <class T>
 hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                         double* part, const Ctl* ctl, int nwg) {
-    if (P == 8) return mx::launch_proj_dot<T, 8>(st, n, Win, Q, nq, S, part, nwg, ctl);
-    if (P == 16) return mx::launch_proj_dot<T, 16>(st, n, Win, Q, nq, S, part, nwg, ctl);
+                         double* part, const Ctl* ctl, int nwg, bool gram) {
+    if (P == 8) return mx::launch_proj_dot<T, 8>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
+    if (P == 16) return mx::launch_proj_dot<T, 16>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
     return hipErrorNotSupported;
 }
 
 template <class T>
 hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
-                          const double* S, T* Wout, double* part, const Ctl* ctl, int nwg) {
-    if (P == 8) return mx::launch_proj_gram<T, 8>(st, n, Win, Q, nq, S, Wout, part, nwg, ctl);
-    if (P == 16) return mx::launch_proj_gram<T, 16>(st, n, Win, Q, nq, S, Wout, part, nwg, ctl);
+                          const double* S, T* Wout, double* part, const Ctl* ctl, int nwg, const double* Rinv,
+                          int step) {
+    if (P == 8) return mx::launch_proj_gram<T, 8>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+    if (P == 16) return mx::launch_proj_gram<T, 16>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
     return hipErrorNotSupported;
 }
 

@@ -76,7 +76,8 @@ struct Sizes {
 // or a recycle dot launch (up to 32 W columns, at most KB blocks, against q)
 size_t part_outputs(int P, int KB, int qmax) {
     const size_t wg = (size_t)std::max(1, std::min(KB, std::max(1, 32 / P)));
-    return std::max({(size_t)qmax * P, (size_t)KB * P * P, wg * qmax * P});
+    // the second pass of a block step writes its dots and the new block's Gram
+    return std::max({(size_t)qmax * P + (size_t)P * P, (size_t)KB * P * P, wg * qmax * P});
 }
 
 Sizes sizes_of(const bgcr_params* prm, int64_t n) {
@@ -90,13 +91,13 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     z.sa = cplx ? 16 : 8;
     z.s = cplx ? 16 : (prm->precision == BGCR_MIXED_FP32 ? 4 : 8);
     z.blk = (size_t)n * z.P * z.s;
-    z.basis = (size_t)z.m * z.blk;
+    z.basis = (size_t)(z.m + 1) * z.blk;  // V_1 .. V_{m+1}
     z.recyc = 4 * (size_t)z.KB * z.blk;
     const int qmax = (2 * z.KB + z.m + 1) * z.P;
     z.nout = part_outputs(z.P, z.KB, qmax);
     z.part = (size_t)NWG_MAX * z.nout * z.sa;
     const size_t mp = (size_t)z.m * z.P, m1p = (size_t)(z.m + 1) * z.P;
-    z.small_ = z.sa * (2 * (size_t)qmax * z.P + 2 * m1p * mp + (size_t)z.KP * mp + (size_t)z.m * 4 * z.P * z.P +
+    z.small_ = z.sa * (2 * (size_t)qmax * z.P + (size_t)z.P * z.P + 2 * m1p * mp + (size_t)z.KP * mp + (size_t)z.m * 4 * z.P * z.P +
                        m1p * z.P + (size_t)(z.m + 1) * z.P * z.P + 2 * (size_t)z.P * z.P +
                        (size_t)(2 * z.KB + z.m + 1) * z.P * (2 * std::max(z.KP, z.P) + 2 * z.P)) +
                sizeof(double) * ((size_t)z.m + (size_t)NWG_MAX * 2 * z.P) + sizeof(Ctl);
@@ -262,7 +263,7 @@ struct Seq final : bgcr_sequence {
 
     void allocate() {
         const size_t blk = (size_t)n * P;
-        Vb = dalloc<T>((size_t)m * blk);
+        Vb = dalloc<T>((size_t)(m + 1) * blk);
         W2 = dalloc<T>(blk);
         Wb = dalloc<T>(blk);
         R = dalloc<T>(blk);
@@ -276,7 +277,7 @@ struct Seq final : bgcr_sequence {
         part = dalloc<A>(part_cap);
         S1 = dalloc<A>((size_t)qmax * P);
         dots_cap = (size_t)qmax * P * std::max(KB, 1);
-        Sf = dalloc<A>((size_t)qmax * P);
+        Sf = dalloc<A>((size_t)qmax * P + (size_t)P * P);  // [S1 + S2 | W'^H W']
         const size_t mp = (size_t)m * P, m1p = (size_t)(m + 1) * P;
         // everything the host reads at the end of a cycle, contiguous so that
         // one copy brings it over: control block, H and its triangular factor,
@@ -621,6 +622,11 @@ struct Seq final : bgcr_sequence {
         const int ncb = withC ? KB : 0;
         const double kc = withC ? (double)keff : 0.0;
         const double abytes = (sT + 4.0) * (double)Am->nnz + 4.0 * (double)(n + 1);
+        // On matrix cores the new block's Gram comes from the second pass
+        // (W''^H W'' = W'^H W' - S2^H S2), so its Cholesky factor is known
+        // before sweep 3, which then stores V_{j+1} = W'' R_j^{-1} directly;
+        // the SpMM of the next step gathers V_{j+1} without normalising.
+        const bool pip = use_mx;
         for (int j = 1; j <= m; ++j) {
             cur_step = j;
             std::vector<const void*> Q;
@@ -638,6 +644,9 @@ struct Seq final : bgcr_sequence {
             // and W'' is stored raw then normalised in the next SpMM); they are
             // not counted.  SpMM: A, V_j, W.
             run(BGCR_K_ARN_SPMM, abytes + 2.0 * blkb, [&] {
+                if (pip && j > 1)
+                    return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, vblk(j - 1), nullptr,
+                                        nullptr, Wb, ctl);
                 return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
                                     vblk(j - 1), Wb, ctl);
             });
@@ -655,10 +664,25 @@ struct Seq final : bgcr_sequence {
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
             run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {  // W, Q
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx) return mfma_proj_dot<T>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na);
+                    if (use_mx) return mfma_proj_dot<T>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, na, ctl, 1);
             });
+            if (pip) {
+                run(BGCR_K_SMALL, 0.0, [&] {
+                    HIPCHK(reduce_partials<A>(st, part, na, nout + P2, S1, Sf, ctl, nout));
+                    return step_small<A>(st, P, Sf + nout, Sf, S1, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl,
+                                         thresh);
+                });
+                run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {  // W, V_{j+1}, Q
+                    if constexpr (!std::is_same<T, zd>::value) {
+                        return mfma_proj_gram<T>(st, P, n, Wb, QB, nq + 1, Sf, vblk(j), part, ctl, na,
+                                                 (const double*)(RinvAll + (size_t)j * P2), j);
+                    }
+                    return hipErrorNotSupported;
+                });
+                continue;
+            }
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, S1, Sf, ctl); });
             run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {  // W, V_{j+1}, Q
                 if constexpr (!std::is_same<T, zd>::value) {
@@ -668,7 +692,7 @@ struct Seq final : bgcr_sequence {
             });
             run(BGCR_K_SMALL, 0.0, [&] {
                 HIPCHK(reduce_partials<A>(st, part, na, P2, nullptr, S1, ctl));
-                return step_small<A>(st, P, S1, Sf, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
+                return step_small<A>(st, P, S1, Sf, nullptr, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
             });
         }
         cur_step = 0;
@@ -684,7 +708,7 @@ struct Seq final : bgcr_sequence {
             for (int b = 0; b < KB; ++b) Qs.push_back(ublk(cur, b));
             for (int b = 0; b < KB; ++b) Qs.push_back(cblk(cur, b));
             for (int i = 0; i < m; ++i) Qs.push_back(vblk(i));
-            Qs.push_back(W2);
+            Qs.push_back(use_mx ? (const void*)vblk(m) : (const void*)W2);
             for (int b = 0; b < KB; ++b) Ws.push_back(ublk(cur, b));
             spec = dot_enqueue(Qs, Ws);
         }
@@ -724,7 +748,11 @@ struct Seq final : bgcr_sequence {
             for (int i = 0; i < KP; ++i)
                 for (int j = 0; j < mp; ++j) co.F(i, j) = to_cd(hF[(size_t)i * ldH + j]);
         co.RinvLast = Mat(P, P);
-        if (co.breakdown) {
+        if (use_mx) {
+            // V_{meff+1} was stored normalised by sweep 3 of step meff (or of the last good step)
+            co.last = vblk(me);
+            co.RinvLast = Mat::eye(P);
+        } else if (co.breakdown) {
             // step meff+1 failed its Cholesky: V_{meff+1} is the normalised block in slot meff
             co.last = vblk(me);
             co.RinvLast = Mat::eye(P);

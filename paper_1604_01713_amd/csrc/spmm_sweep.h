@@ -1,15 +1,16 @@
 // Sweep 1 of a block Arnoldi step on the GPU: W = (A Vin) Rinv and
-// V_j = Vin Rinv for a CSR matrix A and row-major n x P blocks.
+// V_j = Vin Rinv for a CSR matrix A and row-major n x P blocks, or W = A Vin
+// alone when Vin is already normalised (no Rinv and no V_j output).
 //
 // A lane owns C consecutive columns of one row (16 bytes; LPR = P / C lanes
 // per row), so every gather of a neighbour row is one 16-byte load per lane
 // and one load instruction of a wave reads a contiguous span of the block.
 // With 4 lanes per row, each lane loads a quarter of a batch's column indices
 // and values and the batch is assembled by quad broadcasts.  The matrix is
-// read once per sweep and is loaded with the non-temporal hint.  Nonzeros are taken in batches of NB; index loads are clamped
-// into the arrays and padding entries are cancelled by a 0/1 factor (no
-// select of a loaded value, which the compiler would turn into a branch that
-// waits for the load).  The P x P product with Rinv reads Rinv from LDS
+// read once per sweep and is loaded with the non-temporal hint.  Nonzeros
+// are taken in batches of NB; index loads are clamped into the arrays and
+// padding entries are cancelled by a 0/1 factor (no select of a loaded value,
+// which the compiler would turn into a branch that waits for the load).  The P x P product with Rinv reads Rinv from LDS
 // (broadcast) and takes the other lanes' columns of the row by wave shuffles.
 #pragma once
 
@@ -112,7 +113,8 @@ __device__ inline void store_cols(T* __restrict__ p, const T (&v)[C]) {
     }
 }
 
-template <class T, int P, int C, bool SHARE>
+// SCALE false: W = A Vin only (Vin already normalised; no Rinv, no V_j store)
+template <class T, int P, int C, bool SHARE, bool SCALE>
 __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const T* __restrict__ av,
                                                    const T* __restrict__ Vin, const acc_t<T>* __restrict__ Rinv,
@@ -123,11 +125,13 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
     static_assert(!SHARE || P / C == 4, "shared nonzero loads need 4 lanes per row");
     constexpr int LPR = P / C, ROWS = 256 / LPR, NB = 8;
     if (ctl && ctl->active == 0) return;
-    __shared__ A Rs[P * P];
+    __shared__ A Rs[SCALE ? P * P : 1];
     const int t = threadIdx.x, r = t / LPR, part = t % LPR, c0 = part * C;
     const int lead = (t & 63) - part;  // lane holding columns 0..C-1 of this row
-    for (int e = t; e < P * P; e += 256) Rs[e] = Rinv ? Rinv[e] : (e / P == e % P ? A{1.0} : A{});
-    __syncthreads();
+    if constexpr (SCALE) {
+        for (int e = t; e < P * P; e += 256) Rs[e] = Rinv ? Rinv[e] : (e / P == e % P ? A{1.0} : A{});
+        __syncthreads();
+    }
     // Each XCD owns a contiguous slice of tiles; inside it the workgroups take
     // tiles round-robin, so the resident workgroups of an XCD sweep one compact
     // window and the stencil neighbours of that window stay in its L2.
@@ -183,6 +187,10 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
     };
     // W = raw Rinv, V = vb Rinv for this lane's columns c0 .. c0 + C - 1
     auto finish = [&](const T (&raw)[C], const T (&vb)[C], int64_t row) {
+        if constexpr (!SCALE) {
+            if (row < n) store_cols<T, C, P>(Wout + row * P + c0, raw);
+            return;
+        }
         A w[C], v[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) w[j] = v[j] = A{};
@@ -217,7 +225,7 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
             T raw[C], vb[C];
 #pragma unroll
             for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
-            load_cols<T, C, P>(vb, Vin + clamp_row(row, n) * P + c0);
+            if constexpr (SCALE) load_cols<T, C, P>(vb, Vin + clamp_row(row, n) * P + c0);
             finish(raw, vb, row);
         }
         return;
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
         T raw[C], vb[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
-        load_cols<T, C, P>(vb, Vin + rowc * P + c0);
+        if constexpr (SCALE) load_cols<T, C, P>(vb, Vin + rowc * P + c0);
         const int beg = __builtin_nontemporal_load(rp + rowc), e = __builtin_nontemporal_load(rp + rowc + 1);
         for (int kb = beg; kb < e; kb += NB) {
             int cols[NB];
@@ -262,8 +270,14 @@ hipError_t launch_spmm_rinv(hipStream_t st, int64_t n, int64_t nnz, const int* r
     int64_t g = tiles < max_wg ? tiles : max_wg;
     if (g >= 8) g -= g % 8;
     const int nwg = (int)(g < 1 ? 1 : g);
-    hipLaunchKernelGGL((k_spmm_rinv<T, P, C, SHARE>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin, Rinv, Vout,
-                       Wout, ctl);
+    if (Vout)
+        hipLaunchKernelGGL((k_spmm_rinv<T, P, C, SHARE, true>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin,
+                           Rinv, Vout, Wout, ctl);
+    else if (Rinv)
+        return hipErrorInvalidValue;  // a scaled product needs its V_j output
+    else
+        hipLaunchKernelGGL((k_spmm_rinv<T, P, C, SHARE, false>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin,
+                           Rinv, Vout, Wout, ctl);
     return hipGetLastError();
 }
 
