@@ -97,7 +97,8 @@ def _host_check(A, B, X):
 
 def bench_precision(args, torch, problems, bg, dev):
     """Plain FP64 vs the precision form (FP32 SpMM, basis and BCGS2 inside FP64
-    refinement) on the same anisotropic 3D sequence, same tolerance."""
+    refinement), with FP32 or BF16 basis storage, on the same anisotropic 3D
+    sequence, same tolerance."""
     grid = args.grid if args.grid != 128 else 192
     nsys = args.nsys if args.nsys != 10 else 6
     w = problems.cfg4(N=grid, nsys=nsys)
@@ -108,7 +109,9 @@ def bench_precision(args, torch, problems, bg, dev):
     dB = [torch.from_numpy(B).to(dev) for (_, B) in systems]
     out = {}
     sols = {}
-    for name, prec in (("plain_fp64", bg.BGCR_PLAIN_FP64), ("mixed_fp32_in_fp64", bg.BGCR_MIXED_FP32)):
+    variants = (("plain_fp64", bg.BGCR_PLAIN_FP64), ("mixed_fp32_in_fp64", bg.BGCR_MIXED_FP32),
+                ("mixed_fp32_bf16_basis_in_fp64", bg.BGCR_MIXED_FP32_BF16))
+    for name, prec in variants:
         seq = bg.Sequence(n, w.p, w.m, w.k, precision=prec, max_cycles=5000)
         dX = [torch.zeros_like(b) for b in dB]
         torch.cuda.synchronize()
@@ -132,15 +135,17 @@ def bench_precision(args, torch, problems, bg, dev):
                      "p50_latency_s": round(float(np.percentile(lat, 50)), 3),
                      "p99_latency_s": round(float(np.percentile(lat, 99)), 3),
                      "cycles_per_system": cyc, "refine_steps": ref, "max_rel_res_fp64_check": worst}
-    diff = max(float(np.linalg.norm(a - b) / np.linalg.norm(b))
-               for a, b in zip(sols["mixed_fp32_in_fp64"], sols["plain_fp64"]))
     res = {"metric": "systems/s, precision form vs plain FP64, same matrices and tolerance", "unit": "systems/s",
            "config": {"workload": f"convdiff3d_aniso_{grid}^3_seq{nsys}_p{w.p}_m{w.m}_k{w.k}", "n": n, "nnz": nnz,
                       "tol": w.tol},
-           "plain_fp64": out["plain_fp64"], "mixed_fp32_in_fp64": out["mixed_fp32_in_fp64"],
-           "speedup_mixed_over_plain": round(out["mixed_fp32_in_fp64"]["systems_per_s"] /
-                                             out["plain_fp64"]["systems_per_s"], 3),
-           "max_rel_diff_mixed_vs_plain_fp64": diff, "data": "synthetic", "n_gpus": 1}
+           "data": "synthetic", "n_gpus": 1}
+    for name, _ in variants:
+        res[name] = out[name]
+        if name == "plain_fp64":
+            continue
+        res[name]["speedup_over_plain_fp64"] = round(out[name]["systems_per_s"] / out["plain_fp64"]["systems_per_s"], 3)
+        res[name]["max_rel_diff_vs_plain_fp64"] = max(float(np.linalg.norm(a - b) / np.linalg.norm(b))
+                                                      for a, b in zip(sols[name], sols["plain_fp64"]))
     print(json.dumps(res), flush=True)
 
 

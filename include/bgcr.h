@@ -47,8 +47,14 @@ typedef enum { BGCR_F64 = 0, BGCR_C128 = 1 } bgcr_dtype;
 
 typedef enum {
     BGCR_PLAIN_FP64 = 0,           /* every step in FP64 (complex128 for BGCR_C128) */
-    BGCR_MIXED_FP32 = 1            /* FP32 SpMM/basis/BCGS2 cycles inside an FP64
+    BGCR_MIXED_FP32 = 1,           /* FP32 SpMM/basis/BCGS2 cycles inside an FP64
                                       iterative-refinement loop (real data only) */
+    BGCR_MIXED_FP32_BF16 = 2       /* as BGCR_MIXED_FP32 with the basis blocks (V, U, C)
+                                      stored in BF16 (round to nearest even) and widened
+                                      to FP32 on every load; W, R, Gram, LSQ, eigenproblem
+                                      and the solution as in BGCR_MIXED_FP32.  Real data,
+                                      p = 8 or 16, 2 * ceil((k+1)/p) * p <= 64; otherwise
+                                      bgcr_create_sequence returns BGCR_ERR_INVALID */
 } bgcr_precision;
 
 typedef struct bgcr_sequence bgcr_sequence;   /* opaque; owns U, C and workspaces */

@@ -14,7 +14,7 @@ import os
 __all__ = [
     "BGCR_OK", "BGCR_NOT_CONVERGED", "BGCR_ERR_INVALID", "BGCR_ERR_NOMEM", "BGCR_ERR_HIP",
     "BGCR_ERR_NONFINITE", "BGCR_ERR_NUMERICAL", "BGCR_F64", "BGCR_C128", "BGCR_PLAIN_FP64",
-    "BGCR_MIXED_FP32", "BgcrError", "bgcr_params", "bgcr_csr", "bgcr_stats", "lib", "LIB_PATH",
+    "BGCR_MIXED_FP32", "BGCR_MIXED_FP32_BF16", "BgcrError", "bgcr_params", "bgcr_csr", "bgcr_stats", "lib", "LIB_PATH",
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_strerror",
     "bgcr_set_profiling", "bgcr_get_profile", "KERNEL_CLASSES",
@@ -34,6 +34,7 @@ BGCR_F64 = 0
 BGCR_C128 = 1
 BGCR_PLAIN_FP64 = 0
 BGCR_MIXED_FP32 = 1
+BGCR_MIXED_FP32_BF16 = 2
 
 EXPORTED_SYMBOLS = [
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",

@@ -48,6 +48,36 @@ template <> __host__ __device__ inline float narrow<float>(double v) { return (f
 template <> __host__ __device__ inline double narrow<double>(double v) { return v; }
 template <> __host__ __device__ inline zd narrow<zd>(zd v) { return v; }
 
+// BF16 storage scalar: the upper 16 bits of an IEEE binary32.  Used only to
+// store basis blocks; every load widens it to FP32 (exact) before arithmetic.
+struct bf16 {
+    unsigned short u;
+};
+__host__ __device__ inline float bf16_to_float(bf16 h) { return __builtin_bit_cast(float, (unsigned)h.u << 16); }
+// round to nearest, ties to even; NaN stays a (quiet) NaN
+__host__ __device__ inline bf16 float_to_bf16(float f) {
+    unsigned b = __builtin_bit_cast(unsigned, f);
+    if ((b & 0x7fffffffu) > 0x7f800000u) return bf16{(unsigned short)((b >> 16) | 0x40u)};
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return bf16{(unsigned short)(b >> 16)};
+}
+__host__ __device__ inline double widen(bf16 v) { return (double)bf16_to_float(v); }
+// FP64 -> BF16 rounds through FP32 (the values come from FP32 arithmetic)
+template <> __host__ __device__ inline bf16 narrow<bf16>(double v) { return float_to_bf16((float)v); }
+
+// value of a stored scalar in the arithmetic type T (FP32 or FP64)
+template <class T> __host__ __device__ inline T as(float v) { return (T)v; }
+template <class T> __host__ __device__ inline T as(double v) { return (T)v; }
+template <class T> __host__ __device__ inline T as(bf16 v) { return (T)bf16_to_float(v); }
+// an FP32/FP64 value in the storage type TO
+template <class TO> struct store_of {
+    template <class V> __host__ __device__ static TO get(V v) { return (TO)v; }
+};
+template <> struct store_of<bf16> {
+    template <class V> __host__ __device__ static bf16 get(V v) { return float_to_bf16((float)v); }
+};
+template <class TO, class V> __host__ __device__ inline TO to_store(V v) { return store_of<TO>::get(v); }
+
 // Pointers to column blocks (each n x P, row-major, leading dimension P).
 constexpr int MAXB = 64;
 struct BlockPtrs {
@@ -130,27 +160,38 @@ hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, const A*
 // 64-row tiles (mfma_nwg gives the default).
 int mfma_nwg(int64_t n);
 hipError_t i_minus(hipStream_t st, const double* M, double* out, int P);
+// T is the arithmetic type (FP64 or FP32); TW, TQ and TO the storage types of
+// the W blocks, the Q blocks and the output (T itself, or BF16 for basis
+// blocks of the FP32 form).
 // partial dots [Q_0 .. Q_{nq-1}]^T [W_0 .. W_{nw-1}] (no update), partial
 // layout part[wg][w][c P + b]; at most 32 W columns, and then at most 9
 // chunks of 16 Q columns, per launch (hipErrorNotSupported otherwise)
-template <class T>
+template <class T, class TW = T, class TQ = T>
 hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq,
                     double* part, const Ctl* ctl, int nwg);
 // sweep 2: partial Q^T (W - Q S) and, with gram, (W - Q S)^T (W - Q S) after it
-template <class T>
+template <class T, class TQ = T>
 hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
                          double* part, const Ctl* ctl, int nwg, bool gram = false);
 // sweep 3: W'' = W - Q S stored with its Gram partials, or with Rinv given,
 // V = W'' Rinv stored (no Gram); with a control block it runs while the cycle
 // is active and also for block step `step` if the cycle just stopped there
-template <class T>
+template <class T, class TQ = T, class TO = T>
 hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
-                          const double* S, T* Wout, double* part, const Ctl* ctl, int nwg, const double* Rinv = nullptr,
-                          int step = -1);
+                          const double* S, TO* Wout, double* part, const Ctl* ctl, int nwg,
+                          const double* Rinv = nullptr, int step = -1);
 
-// Y (+)= [in..] C on matrix cores (real FP64/FP32 inputs, FP64 coefficients
-// row-major (nin P) x (nout P)); the first `accumulate` output blocks are
-// accumulated, the rest overwritten; hipErrorNotSupported for other shapes
+// Sweep 1 of a block step with separate storage types: W = (A Vin) Rinv and
+// Vout = Vin Rinv, or W = A Vin alone (Rinv and Vout NULL).  T is the type of
+// the matrix values and of the arithmetic; TI, TV, TW those of Vin, Vout, W.
+template <class T, class TI, class TV, class TW>
+hipError_t spmm_block(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci, const T* av,
+                      const TI* Vin, const acc_t<T>* Rinv, TV* Vout, TW* Wout, const Ctl* ctl);
+
+// Y (+)= [in..] C on matrix cores (real FP64/FP32/BF16 inputs, FP64
+// coefficients row-major (nin P) x (nout P)); the first `accumulate` output
+// blocks are accumulated, the rest overwritten; hipErrorNotSupported for other
+// shapes
 template <class TI, class TO>
 hipError_t mfma_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
                         const double* coef, int accumulate, int nwg);

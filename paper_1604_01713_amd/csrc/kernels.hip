@@ -28,6 +28,7 @@ template <class T> __host__ __device__ inline T tz();
 template <> __host__ __device__ inline float tz<float>() { return 0.f; }
 template <> __host__ __device__ inline double tz<double>() { return 0.0; }
 template <> __host__ __device__ inline zd tz<zd>() { return {0.0, 0.0}; }
+template <> __host__ __device__ inline bf16 tz<bf16>() { return bf16{0}; }
 
 __device__ inline double inv_real(double a) { return 1.0 / a; }
 __device__ inline double scale_by(double s, double a) { return s * a; }
@@ -42,6 +43,8 @@ template <> __host__ __device__ inline float conv<float, double>(double v) { ret
 template <> __host__ __device__ inline double conv<double, float>(float v) { return (double)v; }
 template <> __host__ __device__ inline float conv<float, float>(float v) { return v; }
 template <> __host__ __device__ inline zd conv<zd, zd>(zd v) { return v; }
+template <> __host__ __device__ inline double conv<double, bf16>(bf16 v) { return widen(v); }
+template <> __host__ __device__ inline bf16 conv<bf16, double>(double v) { return narrow<bf16>(v); }
 
 // Workgroup renumbering: hardware dispatches workgroup w to XCD w % 8; the
 // logical index gives XCD x the contiguous logical range [x G/8, (x+1) G/8).
@@ -733,10 +736,7 @@ hipError_t Launch<T>::spmm_dot(hipStream_t st, int P, int64_t n, const int* rp, 
 template <class T>
 hipError_t Launch<T>::spmm_rinv(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci,
                                 const T* av, const T* Vin, const A* Rinv, T* Vout, T* Wout, const Ctl* ctl) {
-#define L(PP) return sp::launch_spmm_rinv<T, PP, sp::spmm_cols<T, PP>(), PP / sp::spmm_cols<T, PP>() == 4>(st, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl, 2048);
-    BGCR_DISPATCH_P(P, L)
-#undef L
-    return hipErrorInvalidValue;
+    return spmm_block<T, T, T, T>(st, P, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl);
 }
 
 template <class T>
@@ -876,5 +876,7 @@ template hipError_t copy_block<double, double>(hipStream_t, int64_t, int, const 
 template hipError_t copy_block<zd, zd>(hipStream_t, int64_t, int, const zd*, int64_t, zd*, int64_t, int);
 template hipError_t copy_block<float, double>(hipStream_t, int64_t, int, const float*, int64_t, double*, int64_t, int);
 template hipError_t copy_block<double, float>(hipStream_t, int64_t, int, const double*, int64_t, float*, int64_t, int);
+template hipError_t copy_block<bf16, double>(hipStream_t, int64_t, int, const bf16*, int64_t, double*, int64_t, int);
+template hipError_t copy_block<double, bf16>(hipStream_t, int64_t, int, const double*, int64_t, bf16*, int64_t, int);
 
 }  // namespace bgcr

@@ -1,6 +1,7 @@
 // Matrix-core (MFMA) versions of the three block-Arnoldi sweeps for block
-// sizes P = 8 and 16 with real FP64 or FP32 basis storage (templates; the
-// FP64 and FP32 instantiations live in their own translation units).
+// sizes P = 8 and 16 with real FP64, FP32 or BF16 basis storage (templates;
+// the instantiations live in their own translation units).  BF16 blocks are
+// widened to FP32 as they are loaded; all arithmetic is FP32 or FP64.
 //
 // Every sweep streams n rows of a few tall-skinny n x P blocks; all dense
 // contractions run on v_mfma_*_16x16x4 tiles:
@@ -131,14 +132,15 @@ __device__ inline void rc_pointers(const T* (&qp)[NC], const BlockPtrs& Q, int n
 __device__ inline int64_t clamp_row(int64_t row, int64_t n) { return row < n ? row : n - 1; }
 
 // RC operands of KS groups of 4 rows from rbase: [ks][ch] holds
-// Q[rbase + 4 ks + l / 16][16 ch + l % 16] (rows clamped to n - 1)
-template <class T, int P, int NC, int KS>
-__device__ inline void load_rc(T (&qv)[KS][NC], const T* const (&qp)[NC], int64_t rbase, int64_t n, int lane) {
+// Q[rbase + 4 ks + l / 16][16 ch + l % 16] (rows clamped to n - 1), stored as
+// TS, in the arithmetic type T
+template <class T, class TS, int P, int NC, int KS>
+__device__ inline void load_rc(T (&qv)[KS][NC], const TS* const (&qp)[NC], int64_t rbase, int64_t n, int lane) {
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int64_t off = clamp_row(rbase + 4 * ks + (lane >> 4), n) * P;
 #pragma unroll
-        for (int ch = 0; ch < NC; ++ch) qv[ks][ch] = qp[ch][off];
+        for (int ch = 0; ch < NC; ++ch) qv[ks][ch] = as<T>(qp[ch][off]);
     }
 }
 
@@ -189,7 +191,7 @@ __device__ inline int qsw(int r, int c) {
 // no LDS besides the final cross-wave reduction; the next wave tile is loaded
 // while the current one is multiplied.
 // ---------------------------------------------------------------------------
-template <class T, int P, int NC, int KS, int NG>
+template <class T, class TW, class TQ, int P, int NC, int KS, int NG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && NC * NG > 18 ? 1 : 2))) void
 k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restrict__ part, const Ctl* ctl) {
     using M = MX<T>;
@@ -199,10 +201,10 @@ k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restri
     extern __shared__ __align__(16) unsigned char smem[];
     double* red = (double*)smem;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const T* qp[NC];
-    rc_pointers<T, P, NC>(qp, Q, nq, lane);
-    const T* wp[NG];
-    rc_pointers<T, P, NG>(wp, W, nw, lane);
+    const TQ* qp[NC];
+    rc_pointers<TQ, P, NC>(qp, Q, nq, lane);
+    const TW* wp[NG];
+    rc_pointers<TW, P, NG>(wp, W, nw, lane);
     typename M::acc acc[NG][NC];
 #pragma unroll
     for (int g = 0; g < NG; ++g)
@@ -213,8 +215,8 @@ k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restri
     tile_span((n + TROWS - 1) / TROWS, lw, t0, t1);
     T qn[KS][NC], wn[KS][NG];
     if (t0 < t1) {
-        load_rc<T, P, NC, KS>(qn, qp, t0 * TROWS + wave * WROWS, n, lane);
-        load_rc<T, P, NG, KS>(wn, wp, t0 * TROWS + wave * WROWS, n, lane);
+        load_rc<T, TQ, P, NC, KS>(qn, qp, t0 * TROWS + wave * WROWS, n, lane);
+        load_rc<T, TW, P, NG, KS>(wn, wp, t0 * TROWS + wave * WROWS, n, lane);
     }
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t rbase = tile * TROWS + wave * WROWS;
@@ -233,8 +235,8 @@ k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restri
                 for (int g = 0; g < NG; ++g) wc[ks][g] = rbase + 4 * ks + (lane >> 4) < n ? wc[ks][g] : (T)0;
         }
         if (tile + 1 < t1) {
-            load_rc<T, P, NC, KS>(qn, qp, rbase + TROWS, n, lane);
-            load_rc<T, P, NG, KS>(wn, wp, rbase + TROWS, n, lane);
+            load_rc<T, TQ, P, NC, KS>(qn, qp, rbase + TROWS, n, lane);
+            load_rc<T, TW, P, NG, KS>(wn, wp, rbase + TROWS, n, lane);
         }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
@@ -254,7 +256,7 @@ k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restri
 // loads are in flight while the current one is computed.  No workgroup
 // barrier inside the loop (each wave only reads what it wrote).
 // ---------------------------------------------------------------------------
-template <class T, int P, int NC, bool GRAM>
+template <class T, class TQ, int P, int NC, bool GRAM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 ? NC <= 7 : NC <= 10) ? 2 : 1))) void k_proj_dot_mfma(
     int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq, const double* __restrict__ S, double* __restrict__ part,
     const Ctl* ctl) {
@@ -270,8 +272,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int bl = lane & 15, rq = lane >> 4, bc = bl & (P - 1);
     for (int e = t; e < NQ * P * P; e += 256) Ss[e] = (e < q * P) ? (T)(-S[e]) : (T)0;
-    const T* qp[NC];
-    rc_pointers<T, P, NC>(qp, Q, nq, lane);
+    const TQ* qp[NC];
+    rc_pointers<TQ, P, NC>(qp, Q, nq, lane);
     typename M::acc acc[NC];
 #pragma unroll
     for (int ch = 0; ch < NC; ++ch) acc[ch] = typename M::acc{0, 0, 0, 0};
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
     T qn[4][NC];
     typename M::acc wn = typename M::acc{0, 0, 0, 0};
     if (t0 < t1) {
-        load_rc<T, P, NC, 4>(qn, qp, t0 * MROWS + wave * 16, n, lane);
+        load_rc<T, TQ, P, NC, 4>(qn, qp, t0 * MROWS + wave * 16, n, lane);
         wn = load_wt<T, P>(Win, t0 * MROWS + wave * 16, n, lane);
     }
     __syncthreads();
@@ -296,7 +298,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
             for (int ch = 0; ch < NC; ++ch) myQ[qsw<QLD>(4 * ks + rq, 16 * ch + bl)] = qn[ks][ch];
         typename M::acc d = wn;
         if (tile + 1 < t1) {
-            load_rc<T, P, NC, 4>(qn, qp, rbase + MROWS, n, lane);
+            load_rc<T, TQ, P, NC, 4>(qn, qp, rbase + MROWS, n, lane);
             wn = load_wt<T, P>(Win, rbase + MROWS, n, lane);
         }
         // D = W^T + (-S)^T Q^T over the columns of Q, 4 per instruction
@@ -335,9 +337,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
 // no Gram.  The update operands are loaded column-major straight into
 // registers, double-buffered.
 // ---------------------------------------------------------------------------
-template <class T, int P, int NC, bool NORM>
+template <class T, class TQ, class TO, int P, int NC, bool NORM>
 __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq,
-                                                        const double* __restrict__ S, T* __restrict__ Wout,
+                                                        const double* __restrict__ S, TO* __restrict__ Wout,
                                                         double* __restrict__ part, const double* __restrict__ Rinv,
                                                         const Ctl* ctl, int step) {
     using M = MX<T>;
@@ -353,9 +355,9 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int bl = lane & 15, rq = lane >> 4, bc = bl & (P - 1);
     for (int e = t; e < NQA * P * P; e += 256) Ss[e] = (e < q * P) ? (T)(-S[e]) : (T)0;
-    const T* qb[NQA];
+    const TQ* qb[NQA];
 #pragma unroll
-    for (int blk = 0; blk < NQA; ++blk) qb[blk] = (const T*)(blk < nq ? Q.p[blk] : Q.p[0]);
+    for (int blk = 0; blk < NQA; ++blk) qb[blk] = (const TQ*)(blk < nq ? Q.p[blk] : Q.p[0]);
     d4v gacc = {0, 0, 0, 0};
     const int lw = logical_wg();
     int64_t t0, t1;
@@ -373,7 +375,7 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
 #pragma unroll
         for (int blk = 0; blk < NQ; ++blk)
 #pragma unroll
-            for (int kk = 0; kk < KK; ++kk) qv[blk * KK + kk] = qb[blk][off + 4 * kk];
+            for (int kk = 0; kk < KK; ++kk) qv[blk * KK + kk] = as<T>(qb[blk][off + 4 * kk]);
     };
     T qn[NQA * KK];
     typename M::acc wn = typename M::acc{0, 0, 0, 0};
@@ -409,7 +411,7 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
 #pragma unroll
                 for (int v = 0; v < M::template vn<P>(); ++v) {
                     const int b = M::drow(lane, v);
-                    if (b < P) Wout[row * P + b] = dv[v];
+                    if (b < P) Wout[row * P + b] = to_store<TO>(dv[v]);
                 }
             }
         } else {
@@ -417,7 +419,7 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
 #pragma unroll
                 for (int v = 0; v < M::template vn<P>(); ++v) {
                     const int b = M::drow(lane, v);
-                    if (b < P) Wout[row * P + b] = d[v];
+                    if (b < P) Wout[row * P + b] = to_store<TO>(d[v]);
                 }
             }
             d_to_lds<T, P>(d, mytr, lane);
@@ -469,20 +471,20 @@ constexpr int dot_ks() {
     return NC <= 8 ? 4 : (NC <= 12 ? 2 : 1);
 }
 
-template <class T, int P>
+template <class T, class TW, class TQ, int P>
 hipError_t launch_dot(hipStream_t st, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq, double* part,
                       int nwg, const Ctl* ctl) {
     const int nc = (nq * P + 15) / 16, ng = (nw * P + 15) / 16;
     const size_t lds = (size_t)1024 * sizeof(double);
     if (ng == 1) {
 #define L(NC)                                                                                                      \
-    hipLaunchKernelGGL((k_dot_mfma<T, P, NC, dot_ks<NC>(), 1>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, part, \
+    hipLaunchKernelGGL((k_dot_mfma<T, TW, TQ, P, NC, dot_ks<NC>(), 1>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, part, \
                        ctl)
         BGCR_MX_NC_DISPATCH(nc, L)
 #undef L
     } else if (ng == 2 && nc <= 9) {
 #define L(NC)                                                                                                      \
-    hipLaunchKernelGGL((k_dot_mfma<T, P, NC, dot_ks<2 * NC>(), 2>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, \
+    hipLaunchKernelGGL((k_dot_mfma<T, TW, TQ, P, NC, dot_ks<2 * NC>(), 2>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, \
                        part, ctl)
         switch (nc) {
             case 1: L(1); break;
@@ -503,7 +505,7 @@ hipError_t launch_dot(hipStream_t st, int64_t n, const BlockPtrs& W, int nw, con
     return hipGetLastError();
 }
 
-template <class T, int P, bool GRAM>
+template <class T, class TQ, int P, bool GRAM>
 hipError_t launch_proj_dot_t(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
                              double* part, int nwg, const Ctl* ctl) {
     const int nc = (nq * P + 15) / 16;
@@ -514,8 +516,8 @@ hipError_t launch_proj_dot_t(hipStream_t st, int64_t n, const T* Win, const Bloc
                                     (size_t)1024 * sizeof(double));                                             \
         if (lds > (size_t)160 * 1024) return hipErrorNotSupported;                                              \
         static std::once_flag fl;                                                                               \
-        std::call_once(fl, [] { allow_lds(k_proj_dot_mfma<T, P, NC, GRAM>); });                                 \
-        hipLaunchKernelGGL((k_proj_dot_mfma<T, P, NC, GRAM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S,  \
+        std::call_once(fl, [] { allow_lds(k_proj_dot_mfma<T, TQ, P, NC, GRAM>); });                             \
+        hipLaunchKernelGGL((k_proj_dot_mfma<T, TQ, P, NC, GRAM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, \
                            part, ctl);                                                                          \
     }
     BGCR_MX_NC_DISPATCH(nc, L)
@@ -523,22 +525,22 @@ hipError_t launch_proj_dot_t(hipStream_t st, int64_t n, const T* Win, const Bloc
     return hipGetLastError();
 }
 
-template <class T, int P>
+template <class T, class TQ, int P>
 hipError_t launch_proj_dot(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
                            double* part, int nwg, const Ctl* ctl, bool gram) {
-    return gram ? launch_proj_dot_t<T, P, true>(st, n, Win, Q, nq, S, part, nwg, ctl)
-                : launch_proj_dot_t<T, P, false>(st, n, Win, Q, nq, S, part, nwg, ctl);
+    return gram ? launch_proj_dot_t<T, TQ, P, true>(st, n, Win, Q, nq, S, part, nwg, ctl)
+                : launch_proj_dot_t<T, TQ, P, false>(st, n, Win, Q, nq, S, part, nwg, ctl);
 }
 
-template <class T, int P, bool NORM>
+template <class T, class TQ, class TO, int P, bool NORM>
 hipError_t launch_proj_gram_t(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                              T* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step) {
+                              TO* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step) {
     const int nc = (nq * P + 15) / 16;
 #define L(NC)                                                                                                    \
     {                                                                                                            \
         constexpr int NQA = NC * 16 / P > 0 ? NC * 16 / P : 1;                                                   \
         const size_t lds = std::max((size_t)(NQA * P * P + 4 * 16 * P) * sizeof(T), (size_t)1024 * sizeof(double)); \
-        hipLaunchKernelGGL((k_proj_gram_mfma<T, P, NC, NORM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, \
+        hipLaunchKernelGGL((k_proj_gram_mfma<T, TQ, TO, P, NC, NORM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, \
                            Wout, part, Rinv, ctl, step);                                                         \
     }
     if (nq == 0) {
@@ -550,11 +552,11 @@ hipError_t launch_proj_gram_t(hipStream_t st, int64_t n, const T* Win, const Blo
     return hipGetLastError();
 }
 
-template <class T, int P>
+template <class T, class TQ, class TO, int P>
 hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                            T* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step) {
-    return Rinv ? launch_proj_gram_t<T, P, true>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step)
-                : launch_proj_gram_t<T, P, false>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+                            TO* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step) {
+    return Rinv ? launch_proj_gram_t<T, TQ, TO, P, true>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step)
+                : launch_proj_gram_t<T, TQ, TO, P, false>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
 }
 
 
@@ -597,7 +599,7 @@ __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, i
             const int blk = c * G + g;
             const TI* p = (const TI*)in.p[blk < nin ? blk : 0];
 #pragma unroll
-            for (int kk = 0; kk < KK; ++kk) v[g * KK + kk] = (double)p[off + 4 * kk];
+            for (int kk = 0; kk < KK; ++kk) v[g * KK + kk] = as<double>(p[off + 4 * kk]);
         }
     };
     typename M::acc acc[NCO];
@@ -643,12 +645,12 @@ __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, i
                     const double keep = ob < accumulate ? 1.0 : 0.0;
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        old[v] = keep * (double)ybase[clamp_row(rbase + rq + 4 * v, n) * P + (col < N ? b : 0)];
+                        old[v] = keep * as<double>(ybase[clamp_row(rbase + rq + 4 * v, n) * P + (col < N ? b : 0)]);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int64_t row = rbase + rq + 4 * v;
-                    if (row < n && col < N) ybase[row * P + b] = (TO)(acc[oc][v] + old[v]);
+                    if (row < n && col < N) ybase[row * P + b] = to_store<TO>(acc[oc][v] + old[v]);
                 }
                 acc[oc] = typename M::acc{0, 0, 0, 0};
             }
@@ -683,28 +685,28 @@ hipError_t launch_combine(hipStream_t st, int64_t n, const BlockPtrs& in, int ni
 }  // namespace mx
 
 // public entry points (declared in bgcr_internal.h), instantiated per type
-template <class T>
+template <class T, class TW, class TQ>
 hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq,
                     double* part, const Ctl* ctl, int nwg) {
-    if (P == 8) return mx::launch_dot<T, 8>(st, n, W, nw, Q, nq, part, nwg, ctl);
-    if (P == 16) return mx::launch_dot<T, 16>(st, n, W, nw, Q, nq, part, nwg, ctl);
+    if (P == 8) return mx::launch_dot<T, TW, TQ, 8>(st, n, W, nw, Q, nq, part, nwg, ctl);
+    if (P == 16) return mx::launch_dot<T, TW, TQ, 16>(st, n, W, nw, Q, nq, part, nwg, ctl);
     return hipErrorNotSupported;
 }
 
-template <class T>
+template <class T, class TQ>
 hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
                          double* part, const Ctl* ctl, int nwg, bool gram) {
-    if (P == 8) return mx::launch_proj_dot<T, 8>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
-    if (P == 16) return mx::launch_proj_dot<T, 16>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
+    if (P == 8) return mx::launch_proj_dot<T, TQ, 8>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
+    if (P == 16) return mx::launch_proj_dot<T, TQ, 16>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
     return hipErrorNotSupported;
 }
 
-template <class T>
+template <class T, class TQ, class TO>
 hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
-                          const double* S, T* Wout, double* part, const Ctl* ctl, int nwg, const double* Rinv,
+                          const double* S, TO* Wout, double* part, const Ctl* ctl, int nwg, const double* Rinv,
                           int step) {
-    if (P == 8) return mx::launch_proj_gram<T, 8>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
-    if (P == 16) return mx::launch_proj_gram<T, 16>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+    if (P == 8) return mx::launch_proj_gram<T, TQ, TO, 8>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+    if (P == 16) return mx::launch_proj_gram<T, TQ, TO, 16>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
     return hipErrorNotSupported;
 }
 

@@ -56,8 +56,12 @@ bool valid_params(const bgcr_params* prm, int64_t n) {
     if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16)) return false;
     if (prm->m < 1 || prm->m > 64 || prm->k < 0 || prm->k > 128) return false;
     if (prm->dtype != BGCR_F64 && prm->dtype != BGCR_C128) return false;
-    if (prm->precision != BGCR_PLAIN_FP64 && prm->precision != BGCR_MIXED_FP32) return false;
+    if (prm->precision != BGCR_PLAIN_FP64 && prm->precision != BGCR_MIXED_FP32 &&
+        prm->precision != BGCR_MIXED_FP32_BF16)
+        return false;
     if (prm->dtype == BGCR_C128 && prm->precision != BGCR_PLAIN_FP64) return false;
+    // BF16 basis storage runs on the matrix-core sweeps only (P = 8 or 16)
+    if (prm->precision == BGCR_MIXED_FP32_BF16 && !(p == 8 || p == 16)) return false;
     if (prm->max_cycles < 1 || prm->reserved != 0) return false;
     const int KB = (prm->k + (prm->dtype == BGCR_F64 ? 1 : 0) + p - 1) / p;
     if (KB + prm->m + 1 > MAXB) return false;
@@ -67,7 +71,7 @@ bool valid_params(const bgcr_params* prm, int64_t n) {
 
 struct Sizes {
     int P, m, k, KB, KP;
-    size_t s, sa;  // bytes of a basis scalar, of an FP64 scalar
+    size_t s, sw, sa;  // bytes of a basis scalar, of a work-block scalar (W, R), of an FP64 scalar
     size_t basis, blk, recyc, small_, part, total_fixed;
     size_t nout;   // outputs per workgroup of the reduction partials
 };
@@ -89,7 +93,8 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     z.KB = z.k > 0 ? (z.k + (cplx ? 0 : 1) + z.P - 1) / z.P : 0;
     z.KP = z.KB * z.P;
     z.sa = cplx ? 16 : 8;
-    z.s = cplx ? 16 : (prm->precision == BGCR_MIXED_FP32 ? 4 : 8);
+    z.sw = cplx ? 16 : (prm->precision == BGCR_PLAIN_FP64 ? 8 : 4);
+    z.s = prm->precision == BGCR_MIXED_FP32_BF16 ? 2 : z.sw;
     z.blk = (size_t)n * z.P * z.s;
     z.basis = (size_t)(z.m + 1) * z.blk;  // V_1 .. V_{m+1}
     z.recyc = 4 * (size_t)z.KB * z.blk;
@@ -101,16 +106,21 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
                        m1p * z.P + (size_t)(z.m + 1) * z.P * z.P + 2 * (size_t)z.P * z.P +
                        (size_t)(2 * z.KB + z.m + 1) * z.P * (2 * std::max(z.KP, z.P) + 2 * z.P)) +
                sizeof(double) * ((size_t)z.m + (size_t)NWG_MAX * 2 * z.P) + sizeof(Ctl);
-    z.total_fixed = z.basis + 3 * z.blk /* W2, Wb, R */ + (size_t)n * z.P * z.sa /* X */ + z.recyc + z.part + z.small_;
+    z.total_fixed = z.basis + 3 * (size_t)n * z.P * z.sw /* W2, Wb, R */ + (size_t)n * z.P * z.sa /* X */ + z.recyc +
+                    z.part + z.small_;
     return z;
 }
 
 }  // namespace
 
-template <class T>
+// T: storage and arithmetic type of the work blocks (W, R, the start block)
+// and of the matrix copy of the cycles; TB: storage type of the basis blocks
+// (V, U, C), T itself or BF16 (FP32 form with BF16 basis storage).
+template <class T, class TB = T>
 struct Seq final : bgcr_sequence {
     using A = acc_t<T>;  // FP64 real or complex128: coefficients, solution, matrix for the residual
     using L = Launch<T>;
+    static constexpr bool half = !std::is_same<T, TB>::value;  // basis stored in BF16
 
     bgcr_params prm;
     int64_t n;
@@ -121,9 +131,10 @@ struct Seq final : bgcr_sequence {
     hipStream_t st;
     Sizes sz;
 
-    T *Vb = nullptr, *W2 = nullptr, *Wb = nullptr, *R = nullptr;
-    T* Ub[2] = {nullptr, nullptr};
-    T* Cb[2] = {nullptr, nullptr};
+    TB* Vb = nullptr;
+    T *W2 = nullptr, *Wb = nullptr, *R = nullptr;
+    TB* Ub[2] = {nullptr, nullptr};
+    TB* Cb[2] = {nullptr, nullptr};
     A* X = nullptr;
     float* av32 = nullptr;
     size_t av32_cap = 0;
@@ -227,7 +238,7 @@ struct Seq final : bgcr_sequence {
         m = prm.m;
         k = prm.k;
         cplx = prm.dtype == BGCR_C128;
-        mixed = prm.precision == BGCR_MIXED_FP32;
+        mixed = prm.precision != BGCR_PLAIN_FP64;
         sz = sizes_of(&prm, n);
         KB = sz.KB;
         KP = sz.KP;
@@ -237,6 +248,11 @@ struct Seq final : bgcr_sequence {
         const bool off = e && e[0] == '1';
         use_mx = !off && !std::is_same<T, zd>::value && (P == 8 || P == 16) &&
                  (KB + m) * P <= (P == 16 && sizeof(T) == 8 ? 224 : 256);
+        // BF16 basis blocks have matrix-core kernels only; every basis
+        // combination has to fit one launch (at most 64 output columns)
+        if (half && (!use_mx || 2 * KP > 64 ||
+                     (size_t)(2 * KB + m + 1) * P * 16 * ((2 * KP + 15) / 16) * sizeof(double) > (size_t)160 * 1024))
+            throw Fail{BGCR_ERR_INVALID};
     }
 
     ~Seq() override {
@@ -263,14 +279,14 @@ struct Seq final : bgcr_sequence {
 
     void allocate() {
         const size_t blk = (size_t)n * P;
-        Vb = dalloc<T>((size_t)(m + 1) * blk);
+        Vb = dalloc<TB>((size_t)(m + 1) * blk);
         W2 = dalloc<T>(blk);
         Wb = dalloc<T>(blk);
         R = dalloc<T>(blk);
         X = dalloc<A>(blk);
         for (int i = 0; i < 2; ++i) {
-            Ub[i] = dalloc<T>((size_t)KB * blk);
-            Cb[i] = dalloc<T>((size_t)KB * blk);
+            Ub[i] = dalloc<TB>((size_t)KB * blk);
+            Cb[i] = dalloc<TB>((size_t)KB * blk);
         }
         const int qmax = (2 * KB + m + 1) * P;
         part_cap = (size_t)NWG_MAX * sz.nout;
@@ -310,16 +326,16 @@ struct Seq final : bgcr_sequence {
         hcap = std::max({(size_t)4 << 20, 2 * coef_cap * sizeof(A) + (64 << 10), hr_bytes + (64 << 10)});
         if (hipHostMalloc((void**)&hbuf, hcap, hipHostMallocDefault) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
         HIPCHK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
-        HIPCHK(hipMemsetAsync(Ub[0], 0, (size_t)KB * blk * sizeof(T), st));
-        HIPCHK(hipMemsetAsync(Ub[1], 0, (size_t)KB * blk * sizeof(T), st));
-        HIPCHK(hipMemsetAsync(Cb[0], 0, (size_t)KB * blk * sizeof(T), st));
-        HIPCHK(hipMemsetAsync(Cb[1], 0, (size_t)KB * blk * sizeof(T), st));
+        HIPCHK(hipMemsetAsync(Ub[0], 0, (size_t)KB * blk * sizeof(TB), st));
+        HIPCHK(hipMemsetAsync(Ub[1], 0, (size_t)KB * blk * sizeof(TB), st));
+        HIPCHK(hipMemsetAsync(Cb[0], 0, (size_t)KB * blk * sizeof(TB), st));
+        HIPCHK(hipMemsetAsync(Cb[1], 0, (size_t)KB * blk * sizeof(TB), st));
         HIPCHK(hipStreamSynchronize(st));
     }
 
-    T* vblk(int j) { return Vb + (size_t)j * n * P; }
-    T* ublk(int buf, int b) { return Ub[buf] + (size_t)b * n * P; }
-    T* cblk(int buf, int b) { return Cb[buf] + (size_t)b * n * P; }
+    TB* vblk(int j) { return Vb + (size_t)j * n * P; }
+    TB* ublk(int buf, int b) { return Ub[buf] + (size_t)b * n * P; }
+    TB* cblk(int buf, int b) { return Cb[buf] + (size_t)b * n * P; }
 
     // ---- host <-> device staging through pinned memory --------------------
     void sync() {
@@ -400,22 +416,27 @@ struct Seq final : bgcr_sequence {
         return dst;
     }
 
+    // inputs are basis blocks (TB), or work blocks when TB is T
     template <class TO>
     void combine(const std::vector<const void*>& in, const std::vector<void*>& out, const Mat& K, int accumulate) {
         const int nin = (int)in.size(), nout = (int)out.size();
         if ((size_t)nin * nout * P * P > coef_cap) throw Fail{BGCR_ERR_INVALID};
         std::vector<const void*> outc(out.begin(), out.end());
         const A* cf = upload_coef(K, nin, nout, coef);
-        const double by = (double)n * P * ((double)sizeof(T) * nin + (double)sizeof(TO) * (nout + accumulate));
+        const double by = (double)n * P * ((double)sizeof(TB) * nin + (double)sizeof(TO) * (nout + accumulate));
         run(BGCR_K_COMBINE, by, [&] {
             if constexpr (!std::is_same<T, zd>::value) {
                 if (use_mx) {
                     const hipError_t e =
-                        mfma_combine<T, TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate, nwg_mx);
+                        mfma_combine<TB, TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate, nwg_mx);
                     if (e != hipErrorNotSupported) return e;
                 }
             }
-            return L::template combine<TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate);
+            if constexpr (half) {
+                return hipErrorNotSupported;
+            } else {
+                return L::template combine<TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate);
+            }
         });
     }
 
@@ -434,7 +455,9 @@ struct Seq final : bgcr_sequence {
         bool valid = false;
     };
 
-    DotJob dot_enqueue(const std::vector<const void*>& Q, const std::vector<const T*>& W) {
+    // Q: basis blocks (TB); W: blocks of type TW (TB or T)
+    template <class TW>
+    DotJob dot_enqueue(const std::vector<const void*>& Q, const std::vector<const TW*>& W) {
         DotJob job;
         job.nq = (int)Q.size();
         job.nw = (int)W.size();
@@ -455,12 +478,16 @@ struct Seq final : bgcr_sequence {
                 if ((size_t)nr * nout > part_cap) throw Fail{BGCR_ERR_INVALID};
                 std::vector<const void*> sub(Q.begin() + q0, Q.begin() + q0 + qn);
                 std::vector<const void*> ws(W.begin() + w0, W.begin() + w0 + wn);
-                run(BGCR_K_TSDOT, (double)sizeof(T) * n * P * (wn + qn), [&] {
+                run(BGCR_K_TSDOT, (double)n * P * ((double)sizeof(TW) * wn + (double)sizeof(TB) * qn), [&] {
                     if constexpr (!std::is_same<T, zd>::value) {
-                        if (use_mx) return mfma_dot<T>(st, P, n, bp(ws), wn, bp(sub), qn, part, nullptr, nr);
+                        if (use_mx) return mfma_dot<T, TW, TB>(st, P, n, bp(ws), wn, bp(sub), qn, part, nullptr, nr);
                     }
-                    return L::update_dot(st, P, n, W[w0], bp(sub), qn, nullptr, nullptr, nullptr, 1, 0, part, nr,
-                                         nullptr);
+                    if constexpr (half) {
+                        return hipErrorNotSupported;
+                    } else {
+                        return L::update_dot(st, P, n, (const T*)W[w0], bp(sub), qn, nullptr, nullptr, nullptr, 1, 0,
+                                             part, nr, nullptr);
+                    }
                 });
                 run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nr, nout, nullptr, dots + off, nullptr); });
                 job.pieces.push_back({w0, wn, q0, qn, off});
@@ -484,7 +511,8 @@ struct Seq final : bgcr_sequence {
         return D;
     }
 
-    Mat multi_dot(const std::vector<const void*>& Q, const std::vector<const T*>& W) {
+    template <class TW>
+    Mat multi_dot(const std::vector<const void*>& Q, const std::vector<const TW*>& W) {
         const DotJob job = dot_enqueue(Q, W);
         std::vector<A> h(job.total);
         d2h(h.data(), dots, job.total * sizeof(A));
@@ -515,15 +543,20 @@ struct Seq final : bgcr_sequence {
     void import_basis(const bgcr_csr* Am, const T* avT) {
         const int o = 1 - cur;
         for (int b = 0; b < KB; ++b) {
-            run(BGCR_K_SPMM, (double)(sizeof(T) + 4) * Am->nnz + 4.0 * (n + 1) + 2.0 * sizeof(T) * n * P, [&] {
-                return L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, ublk(cur, b), nullptr, nullptr, cblk(o, b),
-                                   bp({}), 0, 0, part, nwg, nullptr);
+            run(BGCR_K_SPMM, (double)(sizeof(T) + 4) * Am->nnz + 4.0 * (n + 1) + 2.0 * sizeof(TB) * n * P, [&] {
+                if constexpr (half) {
+                    return spmm_block<T, TB, TB, TB>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, ublk(cur, b),
+                                                     nullptr, nullptr, cblk(o, b), nullptr);
+                } else {
+                    return L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, ublk(cur, b), nullptr, nullptr,
+                                       cblk(o, b), bp({}), 0, 0, part, nwg, nullptr);
+                }
             });
             ++n_spmm;
         }
         auto gram_of = [&](int buf) {
             std::vector<const void*> Q;
-            std::vector<const T*> W;
+            std::vector<const TB*> W;
             for (int b = 0; b < KB; ++b) {
                 Q.push_back(cblk(buf, b));
                 W.push_back(cblk(buf, b));
@@ -539,7 +572,7 @@ struct Seq final : bgcr_sequence {
             inC.push_back(cblk(o, b));
             outCcur.push_back(cblk(cur, b));
         }
-        combine<T>(inC, outCcur, S1i, 0);
+        combine<TB>(inC, outCcur, S1i, 0);
         if (!dense::chol_upper(gram_of(cur), S2)) throw Fail{BGCR_ERR_NUMERICAL};
         const Mat S2i = dense::tri_inv_upper(S2);
         inC.clear();
@@ -549,9 +582,9 @@ struct Seq final : bgcr_sequence {
             outCo.push_back(cblk(o, b));
             outUo.push_back(ublk(o, b));
         }
-        combine<T>(inC, outCo, S2i, 0);
+        combine<TB>(inC, outCo, S2i, 0);
         const Mat Si = dense::matmul(S1i, S2i);  // S = S2 S1 -> S^{-1} = S1^{-1} S2^{-1}
-        combine<T>(inU, outUo, Si, 0);
+        combine<TB>(inU, outUo, Si, 0);
         cur = o;
     }
 
@@ -560,7 +593,7 @@ struct Seq final : bgcr_sequence {
     void project() {
         std::vector<const void*> Q;
         for (int b = 0; b < KB; ++b) Q.push_back(cblk(cur, b));
-        Mat Tm = multi_dot(Q, {R});
+        Mat Tm = multi_dot(Q, std::vector<const T*>{R});
         for (int i = keff; i < KP; ++i)
             for (int b = 0; b < P; ++b) Tm(i, b) = 0.0;
         std::vector<const void*> inU, inC;
@@ -580,7 +613,7 @@ struct Seq final : bgcr_sequence {
         bool has_dots = false;  // refresh dots [U, C, V_1..V_m, V_{m+1}]^H U taken with the cycle
         Mat Dm;
         Mat H, F, Y, RinvLast;
-        const T* last = nullptr;  // block holding V_{meff+1} up to RinvLast
+        const void* last = nullptr;  // block holding V_{meff+1} up to RinvLast
     };
 
     // One restart cycle: CholQR2 of R, m block Arnoldi steps on (I - C C^H) A
@@ -593,11 +626,12 @@ struct Seq final : bgcr_sequence {
         HIPCHK(hipMemsetAsync(H, 0, hb, st));
         HIPCHK(hipMemsetAsync(Rh, 0, hb, st));
         const double sT = (double)sizeof(T), blkb = sT * (double)n * P;
+        const double sB = (double)sizeof(TB), vblkb = sB * (double)n * P;  // basis scalar, basis block
         // CholQR2 of the cycle's starting block R = V_1 Z (Algorithm 1)
         const int nr = use_mx ? nwg_mx : nwg;
         run(BGCR_K_TSDOT, blkb, [&] {
             if constexpr (!std::is_same<T, zd>::value) {
-                if (use_mx) return mfma_proj_gram<T>(st, P, n, R, bp({}), 0, nullptr, nullptr, part, nullptr, nr);
+                if (use_mx) return mfma_proj_gram<T, T, T>(st, P, n, R, bp({}), 0, nullptr, nullptr, part, nullptr, nr);
             }
             return L::update_dot(st, P, n, R, bp({}), 0, nullptr, nullptr, nullptr, 0, 1, part, nr, nullptr);
         });
@@ -643,20 +677,28 @@ struct Seq final : bgcr_sequence {
             // two more blocks per step than the model (the first dots re-read W,
             // and W'' is stored raw then normalised in the next SpMM); they are
             // not counted.  SpMM: A, V_j, W.
-            run(BGCR_K_ARN_SPMM, abytes + 2.0 * blkb, [&] {
-                if (pip && j > 1)
-                    return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, vblk(j - 1), nullptr,
-                                        nullptr, Wb, ctl);
-                return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, W2, RinvAll + (size_t)(j - 1) * P2,
-                                    vblk(j - 1), Wb, ctl);
+            run(BGCR_K_ARN_SPMM, abytes + vblkb + blkb, [&] {
+                if constexpr (half) {
+                    if (j > 1)
+                        return spmm_block<T, TB, TB, T>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, vblk(j - 1),
+                                                        nullptr, nullptr, Wb, ctl);
+                    return spmm_block<T, T, TB, T>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, W2, RinvAll,
+                                                   vblk(0), Wb, ctl);
+                } else {
+                    if (pip && j > 1)
+                        return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, vblk(j - 1), nullptr,
+                                            nullptr, Wb, ctl);
+                    return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, W2,
+                                        RinvAll + (size_t)(j - 1) * P2, vblk(j - 1), Wb, ctl);
+                }
             });
             Q.push_back(vblk(j - 1));
             const BlockPtrs QB = bp(Q);
-            const double qbytes = sT * n * (kc + (double)j * P);
+            const double qbytes = sB * n * (kc + (double)j * P);
             // sweep 1b: first block-CGS dots [C V_1..V_j]^H W (reads W and Q)
             run(BGCR_K_ARN_DOT, qbytes, [&] {  // Q
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx) return mfma_dot<T>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na);
+                    if (use_mx) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
             });
@@ -664,7 +706,7 @@ struct Seq final : bgcr_sequence {
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
             run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {  // W, Q
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx) return mfma_proj_dot<T>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip);
+                    if (use_mx) return mfma_proj_dot<T, TB>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, na, ctl, 1);
             });
@@ -674,10 +716,10 @@ struct Seq final : bgcr_sequence {
                     return step_small<A>(st, P, Sf + nout, Sf, S1, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl,
                                          thresh);
                 });
-                run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {  // W, V_{j+1}, Q
+                run(BGCR_K_PROJ_GRAM, blkb + vblkb + qbytes, [&] {  // W, V_{j+1}, Q
                     if constexpr (!std::is_same<T, zd>::value) {
-                        return mfma_proj_gram<T>(st, P, n, Wb, QB, nq + 1, Sf, vblk(j), part, ctl, na,
-                                                 (const double*)(RinvAll + (size_t)j * P2), j);
+                        return mfma_proj_gram<T, TB, TB>(st, P, n, Wb, QB, nq + 1, Sf, vblk(j), part, ctl, na,
+                                                         (const double*)(RinvAll + (size_t)j * P2), j);
                     }
                     return hipErrorNotSupported;
                 });
@@ -704,7 +746,7 @@ struct Seq final : bgcr_sequence {
         DotJob spec;
         if (withC && k > 0) {
             std::vector<const void*> Qs;
-            std::vector<const T*> Ws;
+            std::vector<const TB*> Ws;
             for (int b = 0; b < KB; ++b) Qs.push_back(ublk(cur, b));
             for (int b = 0; b < KB; ++b) Qs.push_back(cblk(cur, b));
             for (int i = 0; i < m; ++i) Qs.push_back(vblk(i));
@@ -763,9 +805,11 @@ struct Seq final : bgcr_sequence {
         }
         if (co.breakdown) breakdown_seen = true;
         if (prof) prof_resolve(hc.meff);
-        // model-M algorithmic bytes of the executed Arnoldi sweeps
+        // model-M algorithmic bytes of the executed Arnoldi sweeps: V_j
+        // gathered and V_{j+1} written in the basis type, W written once and
+        // read twice in the work type, Q read once per reduction sweep
         for (int j = 1; j <= me; ++j)
-            alg_bytes += abytes + 5.0 * blkb + 3.0 * sT * n * (kc + (double)j * P);
+            alg_bytes += abytes + 2.0 * vblkb + 3.0 * blkb + 3.0 * sB * n * (kc + (double)j * P);
         n_spmm += me;
         n_steps += me;
         return co;
@@ -877,7 +921,7 @@ struct Seq final : bgcr_sequence {
     };
 
     void apply_refresh(const RefreshPlan& rp) {
-        combine<T>(rp.in, rp.out, rp.K, 0);
+        combine<TB>(rp.in, rp.out, rp.K, 0);
         cur = rp.next_cur;
         keff = rp.kn;
     }
@@ -974,7 +1018,7 @@ struct Seq final : bgcr_sequence {
         const int me = co.meff, mp = me * P;
         // dots [U, C, V_1..V_meff, last]^H U
         std::vector<const void*> Q;
-        std::vector<const T*> W;
+        std::vector<const TB*> W;
         for (int b = 0; b < KB; ++b) Q.push_back(ublk(cur, b));
         for (int b = 0; b < KB; ++b) Q.push_back(cblk(cur, b));
         for (int i = 0; i < me; ++i) Q.push_back(vblk(i));
@@ -1276,11 +1320,11 @@ struct Seq final : bgcr_sequence {
                 const int cols = std::min(P, keff - b * P);
                 if (cols <= 0) break;
                 if (Uo)
-                    HIPCHK(copy_block<T, A>(self->st, n, cols, self->ublk(cur, b), P, (A*)Uo + (size_t)b * P, ld,
-                                            cols));
+                    HIPCHK(copy_block<TB, A>(self->st, n, cols, self->ublk(cur, b), P, (A*)Uo + (size_t)b * P, ld,
+                                             cols));
                 if (Co)
-                    HIPCHK(copy_block<T, A>(self->st, n, cols, self->cblk(cur, b), P, (A*)Co + (size_t)b * P, ld,
-                                            cols));
+                    HIPCHK(copy_block<TB, A>(self->st, n, cols, self->cblk(cur, b), P, (A*)Co + (size_t)b * P, ld,
+                                             cols));
             }
             self->sync();
         } catch (const Fail& f) {
@@ -1295,9 +1339,9 @@ struct Seq final : bgcr_sequence {
             for (int b = 0; b < KB; ++b) {
                 const int cols = std::max(0, std::min(P, k_in - b * P));
                 if (cols > 0)
-                    HIPCHK(copy_block<A, T>(st, n, cols, (const A*)Ui + (size_t)b * P, ld, ublk(cur, b), P, P));
+                    HIPCHK(copy_block<A, TB>(st, n, cols, (const A*)Ui + (size_t)b * P, ld, ublk(cur, b), P, P));
                 else
-                    HIPCHK(hipMemsetAsync(ublk(cur, b), 0, (size_t)n * P * sizeof(T), st));
+                    HIPCHK(hipMemsetAsync(ublk(cur, b), 0, (size_t)n * P * sizeof(TB), st));
             }
             sync();
             keff = k_in;
@@ -1328,6 +1372,10 @@ int bgcr_create_sequence(const bgcr_params* prm, int64_t n, void* hip_stream, bg
             q->allocate();
         } else if (prm->precision == BGCR_MIXED_FP32) {
             auto* q = new Seq<float>(prm, n, st);
+            s = q;
+            q->allocate();
+        } else if (prm->precision == BGCR_MIXED_FP32_BF16) {
+            auto* q = new Seq<float, bf16>(prm, n, st);
             s = q;
             q->allocate();
         } else {
@@ -1365,7 +1413,7 @@ size_t bgcr_footprint_bytes(const bgcr_params* prm, int64_t n, int64_t nnz) {
     if (!valid_params(prm, n) || nnz < 0) return 0;
     const Sizes z = sizes_of(prm, n);
     size_t b = z.total_fixed;
-    if (prm->precision == BGCR_MIXED_FP32) b += (size_t)nnz * sizeof(float);
+    if (prm->precision != BGCR_PLAIN_FP64) b += (size_t)nnz * sizeof(float);
     return b;
 }
 

@@ -114,11 +114,59 @@ __device__ inline void store_cols(T* __restrict__ p, const T (&v)[C]) {
 }
 
 // SCALE false: W = A Vin only (Vin already normalised; no Rinv, no V_j store)
-template <class T, int P, int C, bool SHARE, bool SCALE>
+// C consecutive BF16 values of a row (C = 2 or 4: one 4- or 8-byte load or
+// store) converted from / to the arithmetic type T
+typedef unsigned int vu2 __attribute__((ext_vector_type(2)));
+template <class T, int C>
+__device__ inline void load_cols_bf16(T (&v)[C], const bf16* __restrict__ p) {
+    static_assert(C == 2 || C == 4, "BF16 rows are gathered 2 or 4 columns per lane");
+    unsigned w[C / 2];
+    if constexpr (C == 4) {
+        const vu2 x = *(const vu2*)p;
+        w[0] = x[0];
+        w[1] = x[1];
+    } else {
+        w[0] = *(const unsigned*)p;
+    }
+#pragma unroll
+    for (int k = 0; k < C / 2; ++k) {
+        v[2 * k] = (T)__uint_as_float(w[k] << 16);
+        v[2 * k + 1] = (T)__uint_as_float(w[k] & 0xffff0000u);
+    }
+}
+template <class T, int C>
+__device__ inline void store_cols_bf16(bf16* __restrict__ p, const T (&v)[C]) {
+    static_assert(C == 2 || C == 4, "BF16 rows are stored 2 or 4 columns per lane");
+    unsigned w[C / 2];
+#pragma unroll
+    for (int k = 0; k < C / 2; ++k)
+        w[k] = (unsigned)float_to_bf16((float)v[2 * k]).u | ((unsigned)float_to_bf16((float)v[2 * k + 1]).u << 16);
+    if constexpr (C == 4)
+        *(vu2*)p = vu2{w[0], w[1]};
+    else
+        *(unsigned*)p = w[0];
+}
+// load / store C columns held as TS (T itself or BF16)
+template <class T, class TS, int C, int P>
+__device__ inline void load_as(T (&v)[C], const TS* __restrict__ p) {
+    if constexpr (std::is_same<TS, bf16>::value)
+        load_cols_bf16<T, C>(v, p);
+    else
+        load_cols<T, C, P>(v, p);
+}
+template <class T, class TS, int C, int P>
+__device__ inline void store_as(TS* __restrict__ p, const T (&v)[C]) {
+    if constexpr (std::is_same<TS, bf16>::value)
+        store_cols_bf16<T, C>(p, v);
+    else
+        store_cols<T, C, P>(p, v);
+}
+
+template <class T, class TI, class TV, class TW, int P, int C, bool SHARE, bool SCALE>
 __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const int* __restrict__ rp,
                                                    const int* __restrict__ ci, const T* __restrict__ av,
-                                                   const T* __restrict__ Vin, const acc_t<T>* __restrict__ Rinv,
-                                                   T* __restrict__ Vout, T* __restrict__ Wout, const Ctl* ctl) {
+                                                   const TI* __restrict__ Vin, const acc_t<T>* __restrict__ Rinv,
+                                                   TV* __restrict__ Vout, TW* __restrict__ Wout, const Ctl* ctl) {
     using A = acc_t<T>;
     using R = typename std::conditional<std::is_same<T, zd>::value, double, T>::type;  // real scalar of T
     static_assert(P % C == 0, "columns per lane must divide P");
@@ -179,7 +227,7 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             T g[C];
-            load_cols<T, C, P>(g, Vin + (int64_t)cols[u] * P + c0);
+            load_as<T, TI, C, P>(g, Vin + (int64_t)cols[u] * P + c0);
             const T a = mscale(vals[u], (R)(kb + u < e ? 1 : 0));
 #pragma unroll
             for (int j = 0; j < C; ++j) raw[j] += a * g[j];
@@ -188,7 +236,7 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
     // W = raw Rinv, V = vb Rinv for this lane's columns c0 .. c0 + C - 1
     auto finish = [&](const T (&raw)[C], const T (&vb)[C], int64_t row) {
         if constexpr (!SCALE) {
-            if (row < n) store_cols<T, C, P>(Wout + row * P + c0, raw);
+            if (row < n) store_as<T, TW, C, P>(Wout + row * P + c0, raw);
             return;
         }
         A w[C], v[C];
@@ -215,8 +263,8 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
                 wo[j] = narrow<T>(w[j]);
                 vo[j] = narrow<T>(v[j]);
             }
-            store_cols<T, C, P>(Wout + row * P + c0, wo);
-            store_cols<T, C, P>(Vout + row * P + c0, vo);
+            store_as<T, TW, C, P>(Wout + row * P + c0, wo);
+            store_as<T, TV, C, P>(Vout + row * P + c0, vo);
         }
     };
     if (nnz <= 0) {  // A = 0: W = 0, V_j = Vin Rinv
@@ -225,7 +273,7 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
             T raw[C], vb[C];
 #pragma unroll
             for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
-            if constexpr (SCALE) load_cols<T, C, P>(vb, Vin + clamp_row(row, n) * P + c0);
+            if constexpr (SCALE) load_as<T, TI, C, P>(vb, Vin + clamp_row(row, n) * P + c0);
             finish(raw, vb, row);
         }
         return;
@@ -236,7 +284,7 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
         T raw[C], vb[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
-        if constexpr (SCALE) load_cols<T, C, P>(vb, Vin + rowc * P + c0);
+        if constexpr (SCALE) load_as<T, TI, C, P>(vb, Vin + rowc * P + c0);
         const int beg = __builtin_nontemporal_load(rp + rowc), e = __builtin_nontemporal_load(rp + rowc + 1);
         for (int kb = beg; kb < e; kb += NB) {
             int cols[NB];
@@ -262,24 +310,45 @@ constexpr int spmm_cols() {
     return P < (int)(16 / sizeof(T)) ? P : (int)(16 / sizeof(T));
 }
 
-template <class T, int P, int C, bool SHARE>
+template <class T, class TI, class TV, class TW, int P, int C, bool SHARE>
 hipError_t launch_spmm_rinv(hipStream_t st, int64_t n, int64_t nnz, const int* rp, const int* ci, const T* av,
-                            const T* Vin, const acc_t<T>* Rinv, T* Vout, T* Wout, const Ctl* ctl, int max_wg) {
+                            const TI* Vin, const acc_t<T>* Rinv, TV* Vout, TW* Wout, const Ctl* ctl, int max_wg) {
     constexpr int ROWS = 256 / (P / C);
     const int64_t tiles = (n + ROWS - 1) / ROWS;
     int64_t g = tiles < max_wg ? tiles : max_wg;
     if (g >= 8) g -= g % 8;
     const int nwg = (int)(g < 1 ? 1 : g);
     if (Vout)
-        hipLaunchKernelGGL((k_spmm_rinv<T, P, C, SHARE, true>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin,
+        hipLaunchKernelGGL((k_spmm_rinv<T, TI, TV, TW, P, C, SHARE, true>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin,
                            Rinv, Vout, Wout, ctl);
     else if (Rinv)
         return hipErrorInvalidValue;  // a scaled product needs its V_j output
     else
-        hipLaunchKernelGGL((k_spmm_rinv<T, P, C, SHARE, false>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin,
+        hipLaunchKernelGGL((k_spmm_rinv<T, TI, TV, TW, P, C, SHARE, false>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci, av, Vin,
                            Rinv, Vout, Wout, ctl);
     return hipGetLastError();
 }
 
 }  // namespace sp
+
+template <class T, class TI, class TV, class TW>
+hipError_t spmm_block(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci, const T* av,
+                      const TI* Vin, const acc_t<T>* Rinv, TV* Vout, TW* Wout, const Ctl* ctl) {
+    // BF16 blocks are gathered 2 or 4 columns per lane: P = 8 and 16 only
+    constexpr bool half =
+        std::is_same<TI, bf16>::value || std::is_same<TV, bf16>::value || std::is_same<TW, bf16>::value;
+#define BGCR_SP_L(PP)                                                                                              \
+    return sp::launch_spmm_rinv<T, TI, TV, TW, PP, sp::spmm_cols<T, PP>(), PP / sp::spmm_cols<T, PP>() == 4>(      \
+        st, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl, 2048);
+    if (P == 8) BGCR_SP_L(8)
+    if (P == 16) BGCR_SP_L(16)
+    if constexpr (!half) {
+        if (P == 1) BGCR_SP_L(1)
+        if (P == 2) BGCR_SP_L(2)
+        if (P == 4) BGCR_SP_L(4)
+    }
+#undef BGCR_SP_L
+    return hipErrorInvalidValue;
+}
+
 }  // namespace bgcr

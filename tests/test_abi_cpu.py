@@ -53,6 +53,22 @@ def test_strerror_and_footprint_without_gpu(lib):
     assert fm < fb
 
 
+def test_bf16_basis_footprint_and_limits_without_gpu(lib):
+    n = 64**3
+    fm = bg.bgcr_footprint_bytes(bg.bgcr_params(8, 10, 20, bg.BGCR_F64, bg.BGCR_MIXED_FP32, 100, 0, 0), n, 7 * n)
+    fh = bg.bgcr_footprint_bytes(bg.bgcr_params(8, 10, 20, bg.BGCR_F64, bg.BGCR_MIXED_FP32_BF16, 100, 0, 0), n,
+                                 7 * n)
+    # only the basis blocks shrink: V_1..V_{m+1} and two copies each of U and C
+    # (k + 1 = 21 columns -> 3 blocks of 8), 4 -> 2 bytes per value
+    assert fm - fh == (11 + 4 * 3) * n * 8 * 2
+    for bad in (bg.bgcr_params(4, 10, 20, bg.BGCR_F64, bg.BGCR_MIXED_FP32_BF16, 100, 0, 0),
+                bg.bgcr_params(16, 10, 20, bg.BGCR_C128, bg.BGCR_MIXED_FP32_BF16, 100, 0, 0),
+                bg.bgcr_params(8, 10, 20, bg.BGCR_F64, 3, 100, 0, 0)):
+        assert bg.bgcr_footprint_bytes(bad, n, 7 * n) == 0
+        h = ctypes.c_void_p()
+        assert lib.bgcr_create_sequence(ctypes.byref(bad), n, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID
+
+
 def test_invalid_arguments_are_rejected_without_a_gpu(lib):
     h = ctypes.c_void_p()
     assert lib.bgcr_create_sequence(None, 10, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID

@@ -138,6 +138,45 @@ def test_mixed_precision_matches_fp64_oracle():
     seq.release()
 
 
+@pytest.mark.parametrize("p", [16, 8])
+def test_bf16_basis_matches_fp64_oracle(p):
+    """FP32 cycles with the basis (V, U, C) stored in BF16, inside the FP64
+    refinement: same residual target and the same parity bar as the FP64 path."""
+    w = problems.cfg4(N=14, nsys=2, p=p, m=10, k=24)   # n = 2744, target 1e-10
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    bg = _bg()
+    seq, gpu = _run_sequence(systems, w.p, w.m, w.k, w.tol, precision=bg.BGCR_MIXED_FP32_BF16)
+    orc, _ = oracle.solve_sequence(systems, w.tol, w.m, w.k)
+    for i, ((Xg, st, log), (Xo, so)) in enumerate(zip(gpu, orc)):
+        A, B, _ = systems[i]
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+        print(f"bf16 p={p} sys{i}: gpu cycles={st['cycles']} refine={st['refine_steps']} relres={rg:.2e} | "
+              f"oracle cycles={so['cycles']} | rel diff vs FP64 oracle={rel:.2e}", flush=True)
+        assert st["status"] == 0
+        assert rg <= w.tol * 1.0001
+        assert rel <= PARITY
+    # the recycle pair is stored in BF16: A U = C and C^T C = I hold to BF16
+    # rounding (unit roundoff 2^-8 per stored value)
+    ke = seq.recycle_dim()
+    n = systems[0][0].shape[0]
+    dev = _dev()
+    U = torch.zeros((n, ke), dtype=torch.float64, device=dev)
+    C = torch.zeros_like(U)
+    seq.get_recycle(U, C)
+    torch.cuda.synchronize()
+    U, C = U.cpu().numpy(), C.cpu().numpy()
+    # every stored value is a BF16 number: 8 significant bits
+    m, _ = np.frexp(C[C != 0])
+    assert np.all(np.abs(m * 2**8 - np.round(m * 2**8)) == 0)
+    assert np.linalg.norm(C.T @ C - np.eye(ke)) <= 0.05
+    # rounding U to BF16 alone moves A U by up to 2^-8 |A| |U| (entrywise)
+    A = systems[-1][0]
+    scale = np.linalg.norm(abs(A) @ abs(U)) + np.linalg.norm(C)
+    assert np.linalg.norm(A @ U - C) <= 0.05 * scale
+    seq.release()
+
+
 def test_recycle_pair_satisfies_AU_equals_C():
     bg = _bg()
     dev = _dev()
