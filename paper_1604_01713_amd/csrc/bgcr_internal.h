@@ -141,7 +141,7 @@ hipError_t reduce_partials(hipStream_t st, const A* part, int nwg, int nout, con
 // R = B - A X in FP64 (complex128); optional store of R narrowed to TR; per-WG
 // partial sums [|r_b|^2 (P)] [|b_b|^2 (P)] into part (double)
 template <class TA, class TR>
-hipError_t residual(hipStream_t st, int P, int64_t n, const int* rp, const int* ci, const TA* av,
+hipError_t residual(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci, const TA* av,
                     const TA* B, int64_t ldb, const TA* X, TR* Rout, double* part, int nwg);
 
 // small kernels read a reduced P x P Gram matrix

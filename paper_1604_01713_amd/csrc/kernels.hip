@@ -374,47 +374,6 @@ __global__ __launch_bounds__(256) void k_reduce(const A* __restrict__ part, int 
 }
 
 // ---------------------------------------------------------------------------
-// true residual R = B - A X (FP64 / complex128) with per-column norms
-// ---------------------------------------------------------------------------
-template <class TA, class TR, int P>
-__global__ __launch_bounds__(NT) void k_residual(int64_t n, const int* __restrict__ rp, const int* __restrict__ ci,
-                                                 const TA* __restrict__ av, const TA* __restrict__ B,
-                                                 int64_t ldb, const TA* __restrict__ X, TR* Rout,
-                                                 double* __restrict__ part) {
-    constexpr int ROWS = NT / P;
-    __shared__ double red[2 * NT];
-    const int t = threadIdx.x, r = t / P, b = t % P;
-    const int lw = logical_wg();
-    int64_t t0, t1;
-    tile_range((n + ROWS - 1) / ROWS, lw, t0, t1);
-    double rs = 0.0, bs = 0.0;
-    for (int64_t tile = t0; tile < t1; ++tile) {
-        const int64_t row = tile * ROWS + r;
-        if (row >= n) continue;
-        TA s = tz<TA>();
-        const int e = rp[row + 1];
-        for (int kk = rp[row]; kk < e; ++kk) s += av[kk] * X[(int64_t)ci[kk] * P + b];
-        const TA bv = B[row * ldb + b];
-        const TA rv = bv - s;
-        if (Rout) Rout[row * P + b] = narrow<TR>(rv);
-        rs += absq(rv);
-        bs += absq(bv);
-    }
-    red[t] = rs;
-    red[NT + t] = bs;
-    __syncthreads();
-    if (t < P) {
-        double a = 0.0, c = 0.0;
-        for (int q = 0; q < ROWS; ++q) {
-            a += red[q * P + t];
-            c += red[NT + q * P + t];
-        }
-        part[(int64_t)lw * 2 * P + t] = a;
-        part[(int64_t)lw * 2 * P + P + t] = c;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // small FP64 problems on the device (one workgroup)
 // ---------------------------------------------------------------------------
 __device__ inline double dabs(double a) { return fabs(a); }
@@ -794,12 +753,9 @@ hipError_t reduce_partials(hipStream_t st, const A* part, int nwg, int nout, con
 }
 
 template <class TA, class TR>
-hipError_t residual(hipStream_t st, int P, int64_t n, const int* rp, const int* ci, const TA* av, const TA* B,
-                    int64_t ldb, const TA* X, TR* Rout, double* part, int nwg) {
-#define L(PP) hipLaunchKernelGGL((k_residual<TA, TR, PP>), dim3(nwg), dim3(NT), 0, st, n, rp, ci, av, B, ldb, X, Rout, part);
-    BGCR_DISPATCH_P(P, L)
-#undef L
-    return hipGetLastError();
+hipError_t residual(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci, const TA* av,
+                    const TA* B, int64_t ldb, const TA* X, TR* Rout, double* part, int nwg) {
+    return residual_rows<TA, TR>(st, P, n, nnz, rp, ci, av, B, ldb, X, Rout, part, nwg);
 }
 
 template <class A>
@@ -857,11 +813,11 @@ template hipError_t Launch<zd>::combine<zd>(hipStream_t, int, int64_t, const Blo
 template hipError_t reduce_partials<double>(hipStream_t, const double*, int, int, const double*, double*, const Ctl*,
                                             int);
 template hipError_t reduce_partials<zd>(hipStream_t, const zd*, int, int, const zd*, zd*, const Ctl*, int);
-template hipError_t residual<double, double>(hipStream_t, int, int64_t, const int*, const int*, const double*,
+template hipError_t residual<double, double>(hipStream_t, int, int64_t, int64_t, const int*, const int*, const double*,
                                              const double*, int64_t, const double*, double*, double*, int);
-template hipError_t residual<double, float>(hipStream_t, int, int64_t, const int*, const int*, const double*,
+template hipError_t residual<double, float>(hipStream_t, int, int64_t, int64_t, const int*, const int*, const double*,
                                             const double*, int64_t, const double*, float*, double*, int);
-template hipError_t residual<zd, zd>(hipStream_t, int, int64_t, const int*, const int*, const zd*, const zd*, int64_t,
+template hipError_t residual<zd, zd>(hipStream_t, int, int64_t, int64_t, const int*, const int*, const zd*, const zd*, int64_t,
                                      const zd*, zd*, double*, int);
 template hipError_t cholqr_first<double>(hipStream_t, int, const double*, double*, double*, Ctl*);
 template hipError_t cholqr_first<zd>(hipStream_t, int, const zd*, zd*, zd*, Ctl*);

@@ -525,7 +525,8 @@ struct Seq final : bgcr_sequence {
         const double by = (double)(sizeof(A) + 4) * Am->nnz + 4.0 * (n + 1) + 2.0 * sizeof(A) * n * P +
                           (Rout ? (double)sizeof(T) * n * P : 0.0);
         run(BGCR_K_RESIDUAL, by, [&] {
-            return residual<A, T>(st, P, n, Am->row_ptr, Am->col_idx, (const A*)Am->values, B, ldb, X, Rout, dpart, nwg);
+            return residual<A, T>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, (const A*)Am->values, B, ldb, X, Rout,
+                                  dpart, nwg);
         });
         std::vector<double> h((size_t)nwg * 2 * P);
         d2h(h.data(), dpart, h.size() * sizeof(double));

@@ -162,30 +162,12 @@ __device__ inline void store_as(TS* __restrict__ p, const T (&v)[C]) {
         store_cols<T, C, P>(p, v);
 }
 
-template <class T, class TI, class TV, class TW, int P, int C, bool SHARE, bool SCALE>
-__global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const int* __restrict__ rp,
-                                                   const int* __restrict__ ci, const T* __restrict__ av,
-                                                   const TI* __restrict__ Vin, const acc_t<T>* __restrict__ Rinv,
-                                                   TV* __restrict__ Vout, TW* __restrict__ Wout, const Ctl* ctl) {
-    using A = acc_t<T>;
-    using R = typename std::conditional<std::is_same<T, zd>::value, double, T>::type;  // real scalar of T
-    static_assert(P % C == 0, "columns per lane must divide P");
-    static_assert(!SHARE || P / C == 4, "shared nonzero loads need 4 lanes per row");
-    constexpr int LPR = P / C, ROWS = 256 / LPR, NB = 8;
-    if (ctl && ctl->active == 0) return;
-    __shared__ A Rs[SCALE ? P * P : 1];
-    const int t = threadIdx.x, r = t / LPR, part = t % LPR, c0 = part * C;
-    const int lead = (t & 63) - part;  // lane holding columns 0..C-1 of this row
-    if constexpr (SCALE) {
-        for (int e = t; e < P * P; e += 256) Rs[e] = Rinv ? Rinv[e] : (e / P == e % P ? A{1.0} : A{});
-        __syncthreads();
-    }
-    // Each XCD owns a contiguous slice of tiles; inside it the workgroups take
-    // tiles round-robin, so the resident workgroups of an XCD sweep one compact
-    // window and the stencil neighbours of that window stay in its L2.
-    const int64_t ntiles = (n + ROWS - 1) / ROWS;
+// Tiles of ROWS rows taken by this workgroup: each XCD owns a contiguous
+// slice of tiles and inside it the workgroups take tiles round-robin, so the
+// resident workgroups of an XCD sweep one compact window and the stencil
+// neighbours of that window stay in its L2.
+__device__ inline void xcd_tiles(int64_t ntiles, int64_t& first, int64_t& step, int64_t& end) {
     const int G = gridDim.x;
-    int64_t first, step, end;
     if (G % 8 == 0) {
         const int x = blockIdx.x % 8, i = blockIdx.x / 8;
         first = (int64_t)x * ntiles / 8 + i;
@@ -196,34 +178,47 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
         step = G;
         end = ntiles;
     }
-    const int64_t nzl = nnz - 1;
-    auto load_nz = [&](int kb, int (&cols)[NB], T (&vals)[NB]) {
+}
+
+// raw[0..C-1] = sum over row `rowc` of A of a_rk Vin[k][c0 .. c0 + C - 1].
+// Nonzeros are taken in batches of NB = 8 with indices clamped to nzl =
+// nnz - 1 and padding entries cancelled by a 0/1 factor; with SHARE (4 lanes
+// per row, `prt` the lane's position) each lane loads 2 entries of a batch
+// and the batch is assembled by quad broadcasts.
+template <class T, class TI, int P, int C, bool SHARE>
+__device__ inline void row_product(T (&raw)[C], const int* __restrict__ rp, const int* __restrict__ ci,
+                                   const T* __restrict__ av, const TI* __restrict__ Vin, int64_t rowc, int prt, int c0,
+                                   int64_t nzl) {
+    using R = typename std::conditional<std::is_same<T, zd>::value, double, T>::type;  // real scalar of T
+    constexpr int NB = 8;
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const int64_t kk = (int64_t)kb + u < nzl ? (int64_t)kb + u : nzl;
-            cols[u] = __builtin_nontemporal_load(ci + kk);
-            vals[u] = ld_nt(av + kk);
-        }
-    };
-    // entries kb + 2 part, kb + 2 part + 1 loaded by this lane, the batch of
-    // NB = 8 assembled by quad broadcasts (4 lanes per row)
-    auto load_nz_shared = [&](int kb, int prt, int (&cols)[NB], T (&vals)[NB]) {
-        int mc[2];
-        T mv[2];
+    for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
+    const int beg = __builtin_nontemporal_load(rp + rowc), e = __builtin_nontemporal_load(rp + rowc + 1);
+    for (int kb = beg; kb < e; kb += NB) {
+        int cols[NB];
+        T vals[NB];
+        if constexpr (SHARE) {
+            int mc[2];
+            T mv[2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int64_t kk = (int64_t)kb + 2 * prt + h < nzl ? (int64_t)kb + 2 * prt + h : nzl;
-            mc[h] = __builtin_nontemporal_load(ci + kk);
-            mv[h] = ld_nt(av + kk);
-        }
+            for (int h = 0; h < 2; ++h) {
+                const int64_t kk = (int64_t)kb + 2 * prt + h < nzl ? (int64_t)kb + 2 * prt + h : nzl;
+                mc[h] = __builtin_nontemporal_load(ci + kk);
+                mv[h] = ld_nt(av + kk);
+            }
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            cols[u] = quad_bcast(mc[u & 1], u >> 1);
-            vals[u] = quad_bcast(mv[u & 1], u >> 1);
+            for (int u = 0; u < NB; ++u) {
+                cols[u] = quad_bcast(mc[u & 1], u >> 1);
+                vals[u] = quad_bcast(mv[u & 1], u >> 1);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int64_t kk = (int64_t)kb + u < nzl ? (int64_t)kb + u : nzl;
+                cols[u] = __builtin_nontemporal_load(ci + kk);
+                vals[u] = ld_nt(av + kk);
+            }
         }
-    };
-    // raw += sum over one batch of nonzeros (entries at or past e cancelled)
-    auto accumulate = [&](T (&raw)[C], const int (&cols)[NB], const T (&vals)[NB], int kb, int e) {
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             T g[C];
@@ -232,7 +227,30 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
 #pragma unroll
             for (int j = 0; j < C; ++j) raw[j] += a * g[j];
         }
-    };
+    }
+}
+
+template <class T, class TI, class TV, class TW, int P, int C, bool SHARE, bool SCALE>
+__global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const int* __restrict__ rp,
+                                                   const int* __restrict__ ci, const T* __restrict__ av,
+                                                   const TI* __restrict__ Vin, const acc_t<T>* __restrict__ Rinv,
+                                                   TV* __restrict__ Vout, TW* __restrict__ Wout, const Ctl* ctl) {
+    using A = acc_t<T>;
+    static_assert(P % C == 0, "columns per lane must divide P");
+    static_assert(!SHARE || P / C == 4, "shared nonzero loads need 4 lanes per row");
+    constexpr int LPR = P / C, ROWS = 256 / LPR;
+    if (ctl && ctl->active == 0) return;
+    __shared__ A Rs[SCALE ? P * P : 1];
+    const int t = threadIdx.x, r = t / LPR, part = t % LPR, c0 = part * C;
+    const int lead = (t & 63) - part;  // lane holding columns 0..C-1 of this row
+    if constexpr (SCALE) {
+        for (int e = t; e < P * P; e += 256) Rs[e] = Rinv ? Rinv[e] : (e / P == e % P ? A{1.0} : A{});
+        __syncthreads();
+    }
+    const int64_t ntiles = (n + ROWS - 1) / ROWS;
+    int64_t first, step, end;
+    xcd_tiles(ntiles, first, step, end);
+    const int64_t nzl = nnz - 1;
     // W = raw Rinv, V = vb Rinv for this lane's columns c0 .. c0 + C - 1
     auto finish = [&](const T (&raw)[C], const T (&vb)[C], int64_t row) {
         if constexpr (!SCALE) {
@@ -267,38 +285,64 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
             store_as<T, TV, C, P>(Vout + row * P + c0, vo);
         }
     };
-    if (nnz <= 0) {  // A = 0: W = 0, V_j = Vin Rinv
-        for (int64_t tile = first; tile < end; tile += step) {
-            const int64_t row = tile * ROWS + r;
-            T raw[C], vb[C];
-#pragma unroll
-            for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
-            if constexpr (SCALE) load_as<T, TI, C, P>(vb, Vin + clamp_row(row, n) * P + c0);
-            finish(raw, vb, row);
-        }
-        return;
-    }
+    // (with nnz = 0 every row is empty and no index is loaded)
     for (int64_t tile = first; tile < end; tile += step) {
         const int64_t row = tile * ROWS + r;
         const int64_t rowc = clamp_row(row, n);
         T raw[C], vb[C];
-#pragma unroll
-        for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
         if constexpr (SCALE) load_as<T, TI, C, P>(vb, Vin + rowc * P + c0);
-        const int beg = __builtin_nontemporal_load(rp + rowc), e = __builtin_nontemporal_load(rp + rowc + 1);
-        for (int kb = beg; kb < e; kb += NB) {
-            int cols[NB];
-            T vals[NB];
-            if constexpr (SHARE) {
-                // the 4 lanes of a row each load 2 of the batch's entries and
-                // broadcast them to the quad (DPP), instead of all 4 loading all
-                load_nz_shared(kb, part, cols, vals);
-            } else {
-                load_nz(kb, cols, vals);
-            }
-            accumulate(raw, cols, vals, kb, e);
-        }
+        row_product<T, TI, P, C, SHARE>(raw, rp, ci, av, Vin, rowc, part, c0, nzl);
         finish(raw, vb, row);
+    }
+}
+
+// R = B - A X in the matrix type (FP64 or complex128) for row-major n x P
+// blocks (B with leading dimension ldb), with the lane layout of the block
+// SpMM; optional store of R as TR; per-workgroup partial column sums of |r|^2
+// and |b|^2 into part[wg][2P] ([P of r][P of b]) in a fixed order.
+template <class TA, class TR, int P, int C, bool SHARE>
+__global__ __launch_bounds__(256) void k_residual_rows(int64_t n, int64_t nnz, const int* __restrict__ rp,
+                                                       const int* __restrict__ ci, const TA* __restrict__ av,
+                                                       const TA* __restrict__ B, int64_t ldb, const TA* __restrict__ X,
+                                                       TR* __restrict__ Rout, double* __restrict__ part) {
+    constexpr int LPR = P / C, ROWS = 256 / LPR;
+    __shared__ double red[2 * 256 * C];
+    const int t = threadIdx.x, r = t / LPR, prt = t % LPR, c0 = prt * C;
+    int64_t first, step, end;
+    xcd_tiles((n + ROWS - 1) / ROWS, first, step, end);
+    const int64_t nzl = nnz - 1;
+    double rs[C], bs[C];
+#pragma unroll
+    for (int j = 0; j < C; ++j) rs[j] = bs[j] = 0.0;
+    for (int64_t tile = first; tile < end; tile += step) {
+        const int64_t row = tile * ROWS + r;
+        const int64_t rowc = clamp_row(row, n);
+        TA ax[C], bv[C];
+        row_product<TA, TA, P, C, SHARE>(ax, rp, ci, av, X, rowc, prt, c0, nzl);
+#pragma unroll
+        for (int j = 0; j < C; ++j) bv[j] = B[rowc * ldb + c0 + j];
+        const double f = row < n ? 1.0 : 0.0;  // rows past n count nothing
+        TR ro[C];
+#pragma unroll
+        for (int j = 0; j < C; ++j) {
+            const TA rv = bv[j] - ax[j];
+            rs[j] += f * absq(rv);
+            bs[j] += f * absq(bv[j]);
+            ro[j] = narrow<TR>(rv);
+        }
+        if (Rout && row < n) store_cols<TR, C, P>(Rout + row * P + c0, ro);
+    }
+#pragma unroll
+    for (int j = 0; j < C; ++j) {
+        red[t * C + j] = rs[j];
+        red[(256 + t) * C + j] = bs[j];
+    }
+    __syncthreads();
+    if (t < 2 * P) {
+        const int which = t / P, b = t % P, pr = b / C, j = b % C;
+        double a = 0.0;
+        for (int rr = 0; rr < ROWS; ++rr) a += red[(which * 256 + rr * LPR + pr) * C + j];
+        part[(int64_t)blockIdx.x * 2 * P + t] = a;
     }
 }
 
@@ -330,6 +374,27 @@ hipError_t launch_spmm_rinv(hipStream_t st, int64_t n, int64_t nnz, const int* r
 }
 
 }  // namespace sp
+
+template <class TA, class TR>
+hipError_t residual_rows(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci, const TA* av,
+                         const TA* B, int64_t ldb, const TA* X, TR* Rout, double* part, int nwg) {
+#define BGCR_RES_L(PP)                                                                                            \
+    {                                                                                                             \
+        constexpr int C = sp::spmm_cols<TA, PP>();                                                                \
+        hipLaunchKernelGGL((sp::k_residual_rows<TA, TR, PP, C, PP / C == 4>), dim3(nwg), dim3(256), 0, st, n, nnz, \
+                           rp, ci, av, B, ldb, X, Rout, part);                                                    \
+        return hipGetLastError();                                                                                 \
+    }
+    switch (P) {
+        case 1: BGCR_RES_L(1)
+        case 2: BGCR_RES_L(2)
+        case 4: BGCR_RES_L(4)
+        case 8: BGCR_RES_L(8)
+        case 16: BGCR_RES_L(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef BGCR_RES_L
+}
 
 template <class T, class TI, class TV, class TW>
 hipError_t spmm_block(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci, const T* av,
