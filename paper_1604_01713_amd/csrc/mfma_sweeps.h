@@ -494,31 +494,29 @@ __device__ inline void wide_load(u4v* buf, const TS* const* qb, int64_t rbase, i
     }
 }
 
+// write the loaded tile to the wave-private LDS tile [16][QLD] in type T
+// (T at least as wide as TS), 16 bytes per LDS write; 16-byte groups of
+// columns stay contiguous under the swizzle (it changes bits 2..4 only)
 template <class T, class TS, int P, int NQ, int QLD>
 __device__ inline void wide_to_lds(T* myQ, const u4v* buf, int lane) {
     using Wd = Wide<TS, P, NQ>;
+    constexpr int V = Wd::V, VT = 16 / (int)sizeof(T);
+    static_assert(sizeof(TS) <= sizeof(T), "tiles are widened, never narrowed");
 #pragma unroll
     for (int i = 0; i < Wd::NI; ++i) {
         int blk, r, c0;
         wide_slot<TS, P, NQ>(i, lane, blk, r, c0);
         if ((NQ * Wd::LPB) % 64 != 0 && blk >= NQ) continue;
-        const u4v x = buf[i];
-        if constexpr (std::is_same<TS, T>::value) {
-            // 16 bytes of T stay contiguous under the swizzle (bits 2..4 of the column)
-            *(u4v*)(myQ + qsw<QLD>(r, c0)) = x;
-        } else {
-            static_assert(std::is_same<TS, bf16>::value && std::is_same<T, float>::value, "BF16 -> FP32 tiles only");
-            f4v lo, hi;
-            lo[0] = __uint_as_float(x[0] << 16);
-            lo[1] = __uint_as_float(x[0] & 0xffff0000u);
-            lo[2] = __uint_as_float(x[1] << 16);
-            lo[3] = __uint_as_float(x[1] & 0xffff0000u);
-            hi[0] = __uint_as_float(x[2] << 16);
-            hi[1] = __uint_as_float(x[2] & 0xffff0000u);
-            hi[2] = __uint_as_float(x[3] << 16);
-            hi[3] = __uint_as_float(x[3] & 0xffff0000u);
-            *(f4v*)(myQ + qsw<QLD>(r, c0)) = lo;
-            *(f4v*)(myQ + qsw<QLD>(r, c0 + 4)) = hi;
+        TS e[V];
+        __builtin_memcpy(e, &buf[i], 16);
+#pragma unroll
+        for (int h = 0; h < V; h += VT) {
+            T o[VT];
+#pragma unroll
+            for (int u = 0; u < VT; ++u) o[u] = as<T>(e[h + u]);
+            u4v w;
+            __builtin_memcpy(&w, o, 16);
+            *(u4v*)(myQ + qsw<QLD>(r, c0 + h)) = w;
         }
     }
 }
@@ -789,55 +787,57 @@ hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const Block
 // ---------------------------------------------------------------------------
 // block combination Y (+)= X C with X = [in_0 .. in_{nin-1}] (n x K, K = nin P)
 // and Y = [out_0 .. out_{nout-1}] (n x N, N = nout P), C (K x N) row-major in
-// FP64: a tall-skinny product on FP64 matrix cores (FP32 inputs are widened).
-// The first `accumulate` output blocks are accumulated (Y += X C), the others
-// overwritten.
-// A = X[row][k] (column-major operand loads straight into registers, G input
-// blocks per pipeline step, the next step's loads in flight while the current
-// one is multiplied; the step sequence runs across row tiles), B = C[k][j]
-// from LDS, padded to NCO chunks of 16 output columns.
+// FP64: a tall-skinny product on matrix cores in the arithmetic type TC (FP64,
+// or FP32 when inputs and outputs are FP32/BF16 blocks; then the
+// coefficients are rounded to FP32).  At N = 64 the product is bound by the
+// matrix-core rate, not by memory.  The first `accumulate` output blocks are
+// accumulated (Y += X C), the others overwritten.
+// The pipeline steps over (16-row wave tile, group of G = 64 / P input
+// blocks): the group is read with wide loads (the next step's in flight while
+// the current one is multiplied), widened into a wave-private LDS tile of type
+// TC and read back as the A operand X[row][k]; B = C[k][j] from LDS, padded
+// to NCO chunks of 16 output columns.
 // ---------------------------------------------------------------------------
-template <class TI, class TO, int P, int NCO>
+template <class TI, class TO, class TC, int P, int NCO>
 __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, int nin, BlockPtrs out, int nout,
                                                       const double* __restrict__ coef, int accumulate) {
-    using M = MX<double>;
-    constexpr int KK = P / 4, G = 64 / P, NV = G * KK, NPAD = 16 * NCO;
+    using M = MX<TC>;
+    constexpr int KK = P / 4, G = 64 / P, NPAD = 16 * NCO, XLD = 64;
+    using Wd = Wide<TI, P, G>;
     const int N = nout * P, K = nin * P;
     extern __shared__ __align__(16) unsigned char smem[];
-    double* Cs = (double*)smem;  // [K][NPAD]
+    TC* Cs = (TC*)smem;                              // [K][NPAD]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, bl = lane & 15, rq = lane >> 4;
+    TC* myX = Cs + (size_t)K * NPAD + wave * 16 * XLD;  // [16][XLD] per wave
     for (int e = threadIdx.x; e < K * NPAD; e += 256) {
         const int k = e / NPAD, j = e % NPAD;
-        Cs[e] = j < N ? coef[(int64_t)k * N + j] : 0.0;
+        Cs[e] = j < N ? (TC)coef[(int64_t)k * N + j] : (TC)0;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, bl = lane & 15, rq = lane >> 4;
     const int nch = (nin + G - 1) / G;
     const int lw = logical_wg();
     int64_t t0, t1;
     tile_span((n + MROWS - 1) / MROWS, lw, t0, t1);
     const int64_t nsteps = (t1 - t0) * nch;
-    auto load = [&](double(&v)[NV], int64_t s) {
+    auto load = [&](u4v* buf, int64_t s) {
         const int64_t tile = t0 + s / nch;
         const int c = (int)(s % nch);
-        const int64_t off = clamp_row(tile * MROWS + wave * 16 + bl, n) * P + rq;
+        const TI* qb[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int blk = c * G + g;
-            const TI* p = (const TI*)in.p[blk < nin ? blk : 0];
-#pragma unroll
-            for (int kk = 0; kk < KK; ++kk) v[g * KK + kk] = as<double>(p[off + 4 * kk]);
+            qb[g] = (const TI*)in.p[blk < nin ? blk : 0];
         }
+        wide_load<TI, P, G>(buf, qb, tile * MROWS + wave * 16, n, lane);
     };
     typename M::acc acc[NCO];
 #pragma unroll
     for (int oc = 0; oc < NCO; ++oc) acc[oc] = typename M::acc{0, 0, 0, 0};
-    double an[NV];
-    if (nsteps > 0) load(an, 0);
+    u4v xn[Wd::NIA];
+    if (nsteps > 0) load(xn, 0);
     for (int64_t s = 0; s < nsteps; ++s) {
-        double ac[NV];
-#pragma unroll
-        for (int e = 0; e < NV; ++e) ac[e] = an[e];
-        if (s + 1 < nsteps) load(an, s + 1);
+        wide_to_lds<TC, TI, P, G, XLD>(myX, xn, lane);
+        if (s + 1 < nsteps) load(xn, s + 1);
         const int c = (int)(s % nch);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -845,14 +845,15 @@ __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, i
             if (blk < nin) {
 #pragma unroll
                 for (int kk = 0; kk < KK; ++kk) {
-                    const double* cr = Cs + (blk * P + 4 * kk + rq) * NPAD + bl;
+                    const TC a = myX[qsw<XLD>(bl, g * P + 4 * kk + rq)];
+                    const TC* cr = Cs + (blk * P + 4 * kk + rq) * NPAD + bl;
 #pragma unroll
-                    for (int oc = 0; oc < NCO; ++oc) acc[oc] = M::mma(ac[g * KK + kk], cr[16 * oc], acc[oc]);
+                    for (int oc = 0; oc < NCO; ++oc) acc[oc] = M::mma(a, cr[16 * oc], acc[oc]);
                 }
             }
         }
         if (c == nch - 1) {
-            // D[row][col]: lane l element v holds row rbase + l/16 + 4v, column 16 oc + l%16
+            // D[row][col]: lane l element v holds row rbase + drow(l, v), column 16 oc + l % 16
             const int64_t rbase = (t0 + s / nch) * MROWS + wave * 16;
 #pragma unroll
             for (int oc = 0; oc < NCO; ++oc) {
@@ -871,12 +872,12 @@ __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, i
                     const double keep = ob < accumulate ? 1.0 : 0.0;
 #pragma unroll
                     for (int v = 0; v < 4; ++v)
-                        old[v] = keep * as<double>(ybase[clamp_row(rbase + rq + 4 * v, n) * P + (col < N ? b : 0)]);
+                        old[v] = keep * as<double>(ybase[clamp_row(rbase + M::drow(lane, v), n) * P + (col < N ? b : 0)]);
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int64_t row = rbase + rq + 4 * v;
-                    if (row < n && col < N) ybase[row * P + b] = to_store<TO>(acc[oc][v] + old[v]);
+                    const int64_t row = rbase + M::drow(lane, v);
+                    if (row < n && col < N) ybase[row * P + b] = to_store<TO>((double)acc[oc][v] + old[v]);
                 }
                 acc[oc] = typename M::acc{0, 0, 0, 0};
             }
@@ -887,15 +888,19 @@ __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, i
 template <class TI, class TO, int P>
 hipError_t launch_combine(hipStream_t st, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
                           const double* coef, int accumulate, int nwg) {
+    // FP32 arithmetic when neither side is FP64 (basis combinations of the
+    // FP32 forms); FP64 otherwise (solution updates, FP64 bases)
+    using TC = typename std::conditional<!std::is_same<TI, double>::value && !std::is_same<TO, double>::value, float,
+                                         double>::type;
     const int nco = (nout * P + 15) / 16;
-    const size_t lds = (size_t)nin * P * 16 * nco * sizeof(double);
+    const size_t lds = ((size_t)nin * P * 16 * nco + 4 * 16 * 64) * sizeof(TC);
     if (nin < 1 || nout < 1 || lds > (size_t)160 * 1024) return hipErrorNotSupported;
-#define L(NCO)                                                                                             \
-    {                                                                                                      \
-        static std::once_flag fl;                                                                          \
-        std::call_once(fl, [] { allow_lds(k_combine_mfma<TI, TO, P, NCO>); });                             \
-        hipLaunchKernelGGL((k_combine_mfma<TI, TO, P, NCO>), dim3(nwg), dim3(256), lds, st, n, in, nin, out, \
-                           nout, coef, accumulate);                                                         \
+#define L(NCO)                                                                                                 \
+    {                                                                                                          \
+        static std::once_flag fl;                                                                              \
+        std::call_once(fl, [] { allow_lds(k_combine_mfma<TI, TO, TC, P, NCO>); });                             \
+        hipLaunchKernelGGL((k_combine_mfma<TI, TO, TC, P, NCO>), dim3(nwg), dim3(256), lds, st, n, in, nin, out, \
+                           nout, coef, accumulate);                                                             \
     }
     switch (nco) {
         case 1: L(1); break;

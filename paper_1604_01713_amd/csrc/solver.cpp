@@ -251,7 +251,8 @@ struct Seq final : bgcr_sequence {
         // BF16 basis blocks have matrix-core kernels only; every basis
         // combination has to fit one launch (at most 64 output columns)
         if (half && (!use_mx || 2 * KP > 64 ||
-                     (size_t)(2 * KB + m + 1) * P * 16 * ((2 * KP + 15) / 16) * sizeof(double) > (size_t)160 * 1024))
+                     ((size_t)(2 * KB + m + 1) * P * 16 * ((2 * KP + 15) / 16) + 4 * 16 * 64) * sizeof(double) >
+                         (size_t)160 * 1024))
             throw Fail{BGCR_ERR_INVALID};
     }
 
