@@ -36,6 +36,7 @@ namespace mx {
 
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 template <class T> struct MX;
 template <> struct MX<double> {
@@ -171,6 +172,32 @@ __device__ inline void d_to_lds(const typename MX<T>::acc& d, T* tr, int lane) {
     for (int v = 0; v < MX<T>::template vn<P>(); ++v) {
         const int b = MX<T>::drow(lane, v);
         if (b < P) tr[(lane & 15) * P + b] = d[v];
+    }
+}
+
+// Row-major 16 x P tile in LDS -> rows rbase .. rbase + 15 of Y (type TO),
+// 16 bytes of T per lane and row piece, so that a wave store instruction
+// writes whole rows
+template <class T, class TO, int P>
+__device__ inline void store_tile(const T* tr, TO* __restrict__ Y, int64_t rbase, int64_t n, int lane) {
+    constexpr int VT = 16 / (int)sizeof(T), LPRW = P / VT, RPI = 64 / LPRW;  // lanes per row, rows per instruction
+    static_assert(P % VT == 0 && 64 % LPRW == 0, "16-byte pieces of a row");
+#pragma unroll
+    for (int r0 = 0; r0 < 16; r0 += RPI) {
+        const int r = r0 + lane / LPRW, c = (lane % LPRW) * VT;
+        const int64_t row = rbase + r;
+        if (r < 16 && row < n) {
+            T v[VT];
+            __builtin_memcpy(v, tr + r * P + c, 16);
+            if constexpr (std::is_same<TO, T>::value) {
+                __builtin_memcpy(Y + row * P + c, v, 16);
+            } else {
+                TO o[VT];
+#pragma unroll
+                for (int u = 0; u < VT; ++u) o[u] = to_store<TO>(v[u]);
+                __builtin_memcpy(Y + row * P + c, o, sizeof(o));
+            }
+        }
     }
 }
 
@@ -442,7 +469,6 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __re
 // the storage type; the tile is written to the wave-private LDS tile in the
 // arithmetic type T and the MFMA operands are read back from there.
 // ---------------------------------------------------------------------------
-typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 
 template <class TS, int P, int NQ>
 struct Wide {
@@ -538,7 +564,7 @@ template <class T, int P, int NC, class TQ, bool UPD, bool DOT>
 constexpr int sweep_waves() {
     // two waves per SIMD up to the chunk counts at which the FP32 variants
     // still compile without spills at 256 registers; one wave above
-    return NC <= (UPD && DOT ? (sizeof(TQ) == 2 ? 11 : 9) : 14) ? 2 : 1;
+    return NC <= (UPD && DOT ? (sizeof(T) == 8 ? 6 : (sizeof(TQ) == 2 ? 11 : 9)) : 14) ? 2 : 1;
 }
 
 template <class T, class TQ, class TO, int P, int NC, bool UPD, bool DOT, bool GRAM, bool NORM>
@@ -617,13 +643,9 @@ k_sweep_mfma(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq, const do
             typename M::acc dv = typename M::acc{0, 0, 0, 0};
 #pragma unroll
             for (int kk = 0; kk < KK; ++kk) dv = M::mma(ra[kk], myW[bl * P + 4 * kk + rq], dv);
-            if (row < n) {
-#pragma unroll
-                for (int v = 0; v < M::template vn<P>(); ++v) {
-                    const int b = M::drow(lane, v);
-                    if (b < P) Wout[row * P + b] = to_store<TO>(dv[v]);
-                }
-            }
+            // (the wave's LDS operations run in order: the tile is read above before it is overwritten)
+            d_to_lds<T, P>(dv, myW, lane);
+            store_tile<T, TO, P>(myW, Wout, rbase, n, lane);
         } else {
             if (Wout && row < n) {
 #pragma unroll
@@ -785,6 +807,103 @@ hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const Block
 
 
 // ---------------------------------------------------------------------------
+// block combination, FP64 inputs: as k_combine_mfma below (FP64 arithmetic)
+// with the A operands loaded straight into registers instead of through an
+// LDS tile, which keeps the LDS to the coefficients (two workgroups per CU at
+// 64 output columns).
+// A = X[row][k] (column-major operand loads straight into registers, G input
+// blocks per pipeline step, the next step's loads in flight while the current
+// one is multiplied; the step sequence runs across row tiles), B = C[k][j]
+// from LDS, padded to NCO chunks of 16 output columns.
+// ---------------------------------------------------------------------------
+template <class TI, class TO, int P, int NCO>
+__global__ __launch_bounds__(256) void k_combine_scalar(int64_t n, BlockPtrs in, int nin, BlockPtrs out, int nout,
+                                                      const double* __restrict__ coef, int accumulate) {
+    using M = MX<double>;
+    constexpr int KK = P / 4, G = 64 / P, NV = G * KK, NPAD = 16 * NCO;
+    const int N = nout * P, K = nin * P;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* Cs = (double*)smem;  // [K][NPAD]
+    for (int e = threadIdx.x; e < K * NPAD; e += 256) {
+        const int k = e / NPAD, j = e % NPAD;
+        Cs[e] = j < N ? coef[(int64_t)k * N + j] : 0.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, bl = lane & 15, rq = lane >> 4;
+    const int nch = (nin + G - 1) / G;
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_span((n + MROWS - 1) / MROWS, lw, t0, t1);
+    const int64_t nsteps = (t1 - t0) * nch;
+    auto load = [&](double(&v)[NV], int64_t s) {
+        const int64_t tile = t0 + s / nch;
+        const int c = (int)(s % nch);
+        const int64_t off = clamp_row(tile * MROWS + wave * 16 + bl, n) * P + rq;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int blk = c * G + g;
+            const TI* p = (const TI*)in.p[blk < nin ? blk : 0];
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) v[g * KK + kk] = as<double>(p[off + 4 * kk]);
+        }
+    };
+    typename M::acc acc[NCO];
+#pragma unroll
+    for (int oc = 0; oc < NCO; ++oc) acc[oc] = typename M::acc{0, 0, 0, 0};
+    double an[NV];
+    if (nsteps > 0) load(an, 0);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        double ac[NV];
+#pragma unroll
+        for (int e = 0; e < NV; ++e) ac[e] = an[e];
+        if (s + 1 < nsteps) load(an, s + 1);
+        const int c = (int)(s % nch);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int blk = c * G + g;
+            if (blk < nin) {
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) {
+                    const double* cr = Cs + (blk * P + 4 * kk + rq) * NPAD + bl;
+#pragma unroll
+                    for (int oc = 0; oc < NCO; ++oc) acc[oc] = M::mma(ac[g * KK + kk], cr[16 * oc], acc[oc]);
+                }
+            }
+        }
+        if (c == nch - 1) {
+            // D[row][col]: lane l element v holds row rbase + l/16 + 4v, column 16 oc + l%16
+            const int64_t rbase = (t0 + s / nch) * MROWS + wave * 16;
+#pragma unroll
+            for (int oc = 0; oc < NCO; ++oc) {
+                const int col = 16 * oc + bl;
+                const int ob = col / P, b = col % P;
+                TO* ybase;
+                if constexpr (P == 16) {
+                    ybase = (TO*)out.p[oc];
+                } else {
+                    TO* y0 = (TO*)out.p[2 * oc];
+                    TO* y1 = (TO*)out.p[2 * oc + 1 < nout ? 2 * oc + 1 : 2 * oc];
+                    ybase = (ob & 1) ? y1 : y0;
+                }
+                double old[4] = {0, 0, 0, 0};
+                if (16 * oc < accumulate * P) {  // some output block of this chunk is accumulated
+                    const double keep = ob < accumulate ? 1.0 : 0.0;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        old[v] = keep * as<double>(ybase[clamp_row(rbase + rq + 4 * v, n) * P + (col < N ? b : 0)]);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t row = rbase + rq + 4 * v;
+                    if (row < n && col < N) ybase[row * P + b] = to_store<TO>(acc[oc][v] + old[v]);
+                }
+                acc[oc] = typename M::acc{0, 0, 0, 0};
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // block combination Y (+)= X C with X = [in_0 .. in_{nin-1}] (n x K, K = nin P)
 // and Y = [out_0 .. out_{nout-1}] (n x N, N = nout P), C (K x N) row-major in
 // FP64: a tall-skinny product on matrix cores in the arithmetic type TC (FP64,
@@ -892,15 +1011,23 @@ hipError_t launch_combine(hipStream_t st, int64_t n, const BlockPtrs& in, int ni
     // FP32 forms); FP64 otherwise (solution updates, FP64 bases)
     using TC = typename std::conditional<!std::is_same<TI, double>::value && !std::is_same<TO, double>::value, float,
                                          double>::type;
+    constexpr bool wide = !std::is_same<TI, double>::value;  // FP64 inputs: scalar-load kernel
     const int nco = (nout * P + 15) / 16;
-    const size_t lds = ((size_t)nin * P * 16 * nco + 4 * 16 * 64) * sizeof(TC);
+    const size_t lds = ((size_t)nin * P * 16 * nco + (wide ? 4 * 16 * 64 : 0)) * sizeof(TC);
     if (nin < 1 || nout < 1 || lds > (size_t)160 * 1024) return hipErrorNotSupported;
-#define L(NCO)                                                                                                 \
-    {                                                                                                          \
-        static std::once_flag fl;                                                                              \
-        std::call_once(fl, [] { allow_lds(k_combine_mfma<TI, TO, TC, P, NCO>); });                             \
-        hipLaunchKernelGGL((k_combine_mfma<TI, TO, TC, P, NCO>), dim3(nwg), dim3(256), lds, st, n, in, nin, out, \
-                           nout, coef, accumulate);                                                             \
+#define L(NCO)                                                                                                     \
+    {                                                                                                              \
+        if constexpr (wide) {                                                                                      \
+            static std::once_flag fl;                                                                              \
+            std::call_once(fl, [] { allow_lds(k_combine_mfma<TI, TO, TC, P, NCO>); });                             \
+            hipLaunchKernelGGL((k_combine_mfma<TI, TO, TC, P, NCO>), dim3(nwg), dim3(256), lds, st, n, in, nin, out, \
+                               nout, coef, accumulate);                                                             \
+        } else {                                                                                                   \
+            static std::once_flag fl;                                                                              \
+            std::call_once(fl, [] { allow_lds(k_combine_scalar<TI, TO, P, NCO>); });                               \
+            hipLaunchKernelGGL((k_combine_scalar<TI, TO, P, NCO>), dim3(nwg), dim3(256), lds, st, n, in, nin, out,   \
+                               nout, coef, accumulate);                                                             \
+        }                                                                                                          \
     }
     switch (nco) {
         case 1: L(1); break;
@@ -944,10 +1071,9 @@ hipError_t launch_sweep_t(hipStream_t st, int64_t n, const T* Win, const BlockPt
 // public entry points (declared in bgcr_internal.h), instantiated per type
 // Kernel choice per arithmetic type (measured on the sweeps of a block step):
 // with FP32 arithmetic the wide-load sweep (16 bytes per lane and load) is
-// 1.1-2.9x faster than the scalar-load kernels for the dots of one W block,
-// the normalising and Gram sweeps, and the update-and-dot sweep at P = 8; the
-// FP64 kernels and the FP32 update-and-dot sweep at P = 16 (register-bound
-// with the wide prefetch) keep the scalar-load versions.
+// 1.1-2.9x faster than the scalar-load kernels for every sweep; the FP64
+// sweeps keep the scalar-load kernels, which are as fast at P = 8 (where the
+// wide prefetch costs occupancy).
 template <class T, class TW, class TQ>
 hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq,
                     double* part, const Ctl* ctl, int nwg) {
@@ -968,11 +1094,14 @@ template <class T, class TQ>
 hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
                          double* part, const Ctl* ctl, int nwg, bool gram) {
     if constexpr (sizeof(T) == 4) {
-        if (P == 8)
-            return gram ? mx::launch_sweep_t<T, TQ, T, 8, true, true, true, false>(st, n, Win, Q, nq, S, (T*)nullptr,
-                                                                                    part, nullptr, nwg, ctl, -1)
-                        : mx::launch_sweep_t<T, TQ, T, 8, true, true, false, false>(st, n, Win, Q, nq, S, (T*)nullptr,
-                                                                                     part, nullptr, nwg, ctl, -1);
+#define BGCR_SWEEP2(PP)                                                                                             \
+    return gram ? mx::launch_sweep_t<T, TQ, T, PP, true, true, true, false>(st, n, Win, Q, nq, S, (T*)nullptr, part, \
+                                                                            nullptr, nwg, ctl, -1)                   \
+                : mx::launch_sweep_t<T, TQ, T, PP, true, true, false, false>(st, n, Win, Q, nq, S, (T*)nullptr, part, \
+                                                                             nullptr, nwg, ctl, -1);
+        if (P == 8) BGCR_SWEEP2(8)
+        if (P == 16) BGCR_SWEEP2(16)
+#undef BGCR_SWEEP2
     }
     if (P == 8) return mx::launch_proj_dot<T, TQ, 8>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
     if (P == 16) return mx::launch_proj_dot<T, TQ, 16>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);

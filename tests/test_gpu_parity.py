@@ -29,13 +29,14 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=1000):
+def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=1000, select_largest=False):
     bg = _bg()
     dev = _dev()
     n = systems[0][0].shape[0]
     cplx = np.iscomplexobj(systems[0][1]) or np.iscomplexobj(systems[0][0].data)
     dt = bg.BGCR_C128 if cplx else bg.BGCR_F64
-    seq = bg.Sequence(n, p, m, k, dtype=dt, precision=precision, max_cycles=max_cycles)
+    seq = bg.Sequence(n, p, m, k, dtype=dt, precision=precision, max_cycles=max_cycles,
+                      select_largest=select_largest)
     out = []
     for (A, B, X0) in systems:
         Ad = bg.DeviceCSR.from_scipy(A, dev)
@@ -121,8 +122,9 @@ def test_complex_helmholtz_parity():
     _compare("cfg3-41^2", systems, w.p, w.m, w.k, w.tol)
 
 
-def test_mixed_precision_matches_fp64_oracle():
-    w = problems.cfg4(N=14, nsys=2, p=16, m=10, k=24)   # n = 2744, target 1e-10
+@pytest.mark.parametrize("p", [16, 8])
+def test_mixed_precision_matches_fp64_oracle(p):
+    w = problems.cfg4(N=14, nsys=2, p=p, m=10, k=24)   # n = 2744, target 1e-10
     systems = [(s.A, s.B, s.X0) for s in w.systems]
     seq, gpu = _run_sequence(systems, w.p, w.m, w.k, w.tol, precision=1)
     orc, _ = oracle.solve_sequence(systems, w.tol, w.m, w.k)
@@ -130,7 +132,7 @@ def test_mixed_precision_matches_fp64_oracle():
         A, B, _ = systems[i]
         rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
         rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
-        print(f"mixed sys{i}: gpu cycles={st['cycles']} refine={st['refine_steps']} relres={rg:.2e} | "
+        print(f"mixed p={p} sys{i}: gpu cycles={st['cycles']} refine={st['refine_steps']} relres={rg:.2e} | "
               f"oracle cycles={so['cycles']} | rel diff vs FP64 oracle={rel:.2e}", flush=True)
         assert st["status"] == 0
         assert rg <= w.tol * 1.0001
@@ -174,6 +176,27 @@ def test_bf16_basis_matches_fp64_oracle(p):
     A = systems[-1][0]
     scale = np.linalg.norm(abs(A) @ abs(U)) + np.linalg.norm(C)
     assert np.linalg.norm(A @ U - C) <= 0.05 * scale
+    seq.release()
+
+
+def test_select_largest_matches_oracle():
+    """Keeping the harmonic Ritz values of largest modulus (the selection
+    switch of Section 4.1) follows the oracle's selection, cycle for cycle."""
+    w = problems.cfg2(N=13, nsys=2, p=8, m=6, k=10)
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    seq, gpu = _run_sequence(systems, w.p, w.m, w.k, w.tol, select_largest=True)
+    orc, _ = oracle.solve_sequence(systems, w.tol, w.m, w.k, select_largest=True)
+    orc_small, _ = oracle.solve_sequence(systems, w.tol, w.m, w.k)
+    for i, ((Xg, st, log), (Xo, so)) in enumerate(zip(gpu, orc)):
+        A, B, _ = systems[i]
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+        print(f"largest sys{i}: gpu cycles={st['cycles']} | oracle cycles={so['cycles']} "
+              f"(smallest-|theta| oracle: {orc_small[i][1]['cycles']}) | rel diff={rel:.2e}", flush=True)
+        assert st["status"] == 0
+        assert rg <= w.tol * 1.0001
+        assert rel <= PARITY
+        assert abs(st["cycles"] - so["cycles"]) <= 1
     seq.release()
 
 
