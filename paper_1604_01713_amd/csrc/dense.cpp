@@ -21,6 +21,17 @@ static int team(double work) {
     return std::max(1, std::min(4, omp_get_max_threads()));
 }
 
+// sum of x[i] y[i] with eight independent partial sums (two AVX2 vectors),
+// combined in a fixed order: the result depends only on the inputs
+static inline double dotr(const double* __restrict__ x, const double* __restrict__ y, int len) {
+    double s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = 0;
+    for (; i + 8 <= len; i += 8)
+        for (int u = 0; u < 8; ++u) s[u] += x[i + u] * y[i + u];
+    for (int u = 0; i < len; ++i, ++u) s[u] += x[i] * y[i];
+    return ((s[0] + s[4]) + (s[1] + s[5])) + ((s[2] + s[6]) + (s[3] + s[7]));
+}
+
 Mat Mat::block(int i0, int j0, int nr, int nc) const {
     Mat B(nr, nc);
     for (int j = 0; j < nc; ++j)
@@ -117,16 +128,17 @@ bool chol_upper(const Mat& G, Mat& R) {
 Mat tri_inv_upper(const Mat& R) {
     const int n = R.r;
     if (all_real(R)) {
-        const std::vector<double> r = real_part(R);
+        // rows of R contiguous (rt[i][l] = R(i, l)) for the row-times-column sums
+        std::vector<double> rt((size_t)n * n);
+        for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) rt[(size_t)i * n + j] = R.a[(size_t)i + (size_t)j * R.r].real();
         std::vector<double> x((size_t)n * n, 0.0);
-        auto Rr = [&](int i, int j) { return r[(size_t)i + (size_t)j * R.r]; };
         for (int j = 0; j < n; ++j) {
             double* xj = &x[(size_t)j * n];
-            xj[j] = 1.0 / Rr(j, j);
+            xj[j] = 1.0 / rt[(size_t)j * n + j];
             for (int i = j - 1; i >= 0; --i) {
-                double s = 0.0;
-                for (int l = i + 1; l <= j; ++l) s += Rr(i, l) * xj[l];
-                xj[i] = -s / Rr(i, i);
+                const double s = dotr(&rt[(size_t)i * n + i + 1], xj + i + 1, j - i);
+                xj[i] = -s / rt[(size_t)i * n + i];
             }
         }
         return from_real(n, n, x);
@@ -212,24 +224,19 @@ static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R) {
     std::vector<double> vvs(kk, 0.0);
     for (int k = 0; k < kk; ++k) {
         double* ck = col(k);
-        double al = 0.0;
-        for (int i = k; i < m; ++i) al += ck[i] * ck[i];
-        al = std::sqrt(al);
+        const double al = std::sqrt(dotr(ck + k, ck + k, m - k));
         if (al == 0.0) continue;
         const double beta = ck[k] >= 0.0 ? -al : al;
         std::vector<double>& v = vs[k];
         v.assign(ck + k, ck + m);
         v[0] = ck[k] - beta;
-        double vv = 0.0;
-        for (double x : v) vv += x * x;
+        const double vv = dotr(v.data(), v.data(), m - k);
         vvs[k] = vv;
         if (vv == 0.0) continue;
         const double f = 2.0 / vv;
         for (int j = k; j < n; ++j) {
             double* cj = col(j) + k;
-            double w = 0.0;
-            for (int i = 0; i < m - k; ++i) w += v[i] * cj[i];
-            w *= f;
+            const double w = f * dotr(v.data(), cj, m - k);
             for (int i = 0; i < m - k; ++i) cj[i] -= w * v[i];
         }
     }
@@ -243,9 +250,7 @@ static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R) {
             if (vvs[k] == 0.0) continue;
             const std::vector<double>& v = vs[k];
             double* qj = &q[(size_t)j * m + k];
-            double w = 0.0;
-            for (int i = 0; i < m - k; ++i) w += v[i] * qj[i];
-            w *= 2.0 / vvs[k];
+            const double w = 2.0 / vvs[k] * dotr(v.data(), qj, m - k);
             for (int i = 0; i < m - k; ++i) qj[i] -= w * v[i];
         }
     }
@@ -709,9 +714,7 @@ static void hessenberg_real(std::vector<double>& H, int n, std::vector<std::vect
         // right: columns k+1.. of every row
         for (int i = 0; i < n; ++i) {
             double* row = &H[(size_t)i * n + k + 1];
-            double dot = 0.0;
-            for (int l = 0; l < len; ++l) dot += row[l] * v[l];
-            dot *= f;
+            const double dot = f * dotr(row, v.data(), len);
             for (int l = 0; l < len; ++l) row[l] -= dot * v[l];
         }
         for (int i = k + 2; i < n; ++i) H[(size_t)i * n + k] = 0.0;
@@ -820,9 +823,7 @@ static void inverse_iteration_real(const std::vector<double>& Hd, int n, double 
         }
         for (int i = n - 1; i >= 0; --i) {
             const double* row = &U[(size_t)i * n];
-            double s = x[i];
-            for (int j = i + 1; j < n; ++j) s -= row[j] * x[j];
-            x[i] = s / row[i];
+            x[i] = (x[i] - dotr(row + i + 1, x.data() + i + 1, n - i - 1)) / row[i];
         }
         nrm(x);
     }

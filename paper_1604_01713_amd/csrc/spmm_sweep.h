@@ -219,13 +219,16 @@ __device__ inline void row_product(T (&raw)[C], const int* __restrict__ rp, cons
                 vals[u] = ld_nt(av + kk);
             }
         }
+        // all gathers of the batch are issued before the first product, so
+        // that their latencies overlap
+        T g[NB][C];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) load_as<T, TI, C, P>(g[u], Vin + (int64_t)cols[u] * P + c0);
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
-            T g[C];
-            load_as<T, TI, C, P>(g, Vin + (int64_t)cols[u] * P + c0);
             const T a = mscale(vals[u], (R)(kb + u < e ? 1 : 0));
 #pragma unroll
-            for (int j = 0; j < C; ++j) raw[j] += a * g[j];
+            for (int j = 0; j < C; ++j) raw[j] += a * g[u][j];
         }
     }
 }
