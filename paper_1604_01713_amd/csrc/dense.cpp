@@ -214,9 +214,12 @@ static double house(const cd* x, int len, std::vector<cd>& v) {
     return s;
 }
 
-// real Householder QR with positive diagonal (column-major, m x n)
-static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R) {
+// real Householder QR with positive diagonal (column-major, m x n); with
+// lower bandwidth bw >= 0 (A(i, j) = 0 for i > j + bw, a band Householder
+// preserves) the reflector of column k spans rows k .. k + bw only
+static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R, int bw) {
     const int m = A0.r, n = A0.c;
+    auto rows_of = [&](int k) { return bw < 0 ? m - k : std::min(m - k, bw + 1); };
     std::vector<double> a = real_part(A0);
     auto col = [&](int j) { return &a[(size_t)j * m]; };
     const int kk = std::min(m, n);
@@ -224,20 +227,21 @@ static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R) {
     std::vector<double> vvs(kk, 0.0);
     for (int k = 0; k < kk; ++k) {
         double* ck = col(k);
-        const double al = std::sqrt(dotr(ck + k, ck + k, m - k));
+        const int len = rows_of(k);
+        const double al = std::sqrt(dotr(ck + k, ck + k, len));
         if (al == 0.0) continue;
         const double beta = ck[k] >= 0.0 ? -al : al;
         std::vector<double>& v = vs[k];
-        v.assign(ck + k, ck + m);
+        v.assign(ck + k, ck + k + len);
         v[0] = ck[k] - beta;
-        const double vv = dotr(v.data(), v.data(), m - k);
+        const double vv = dotr(v.data(), v.data(), len);
         vvs[k] = vv;
         if (vv == 0.0) continue;
         const double f = 2.0 / vv;
         for (int j = k; j < n; ++j) {
             double* cj = col(j) + k;
-            const double w = f * dotr(v.data(), cj, m - k);
-            for (int i = 0; i < m - k; ++i) cj[i] -= w * v[i];
+            const double w = f * dotr(v.data(), cj, len);
+            for (int i = 0; i < len; ++i) cj[i] -= w * v[i];
         }
     }
     std::vector<double> r((size_t)kk * n, 0.0), q((size_t)m * kk, 0.0);
@@ -249,9 +253,10 @@ static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R) {
         for (int k = std::min(j, kk - 1); k >= 0; --k) {  // reflectors k > j leave column j unchanged
             if (vvs[k] == 0.0) continue;
             const std::vector<double>& v = vs[k];
+            const int len = (int)v.size();
             double* qj = &q[(size_t)j * m + k];
-            const double w = 2.0 / vvs[k] * dotr(v.data(), qj, m - k);
-            for (int i = 0; i < m - k; ++i) qj[i] -= w * v[i];
+            const double w = 2.0 / vvs[k] * dotr(v.data(), qj, len);
+            for (int i = 0; i < len; ++i) qj[i] -= w * v[i];
         }
     }
     for (int i = 0; i < kk; ++i)
@@ -263,24 +268,26 @@ static void qr_pos_real(const Mat& A0, Mat& Q, Mat& R) {
     Q = from_real(m, kk, q);
 }
 
-void qr_pos(const Mat& A0, Mat& Q, Mat& R) {
+void qr_pos(const Mat& A0, Mat& Q, Mat& R, int bw) {
     if (all_real(A0)) {
-        qr_pos_real(A0, Q, R);
+        qr_pos_real(A0, Q, R, bw);
         return;
     }
     const int m = A0.r, n = A0.c;
+    auto end_of = [&](int k) { return bw < 0 ? m : std::min(m, k + bw + 1); };
     Mat A = A0;
     std::vector<std::vector<cd>> vs(n);
     std::vector<double> vvs(n, 0.0);
     for (int k = 0; k < n && k < m; ++k) {
-        vvs[k] = house(&A(k, k), m - k, vs[k]);
+        const int ke = end_of(k);
+        vvs[k] = house(&A(k, k), ke - k, vs[k]);
         if (vvs[k] == 0.0) continue;
         const double f = 2.0 / vvs[k];
         for (int j = k; j < n; ++j) {
             cd w = 0.0;
-            for (int i = k; i < m; ++i) w += std::conj(vs[k][i - k]) * A(i, j);
+            for (int i = k; i < ke; ++i) w += std::conj(vs[k][i - k]) * A(i, j);
             w *= f;
-            for (int i = k; i < m; ++i) A(i, j) -= vs[k][i - k] * w;
+            for (int i = k; i < ke; ++i) A(i, j) -= vs[k][i - k] * w;
         }
     }
     const int kk = std::min(m, n);
@@ -293,11 +300,12 @@ void qr_pos(const Mat& A0, Mat& Q, Mat& R) {
     for (int k = kk - 1; k >= 0; --k) {
         if (vvs[k] == 0.0) continue;
         const double f = 2.0 / vvs[k];
+        const int ke = end_of(k);
         for (int j = 0; j < kk; ++j) {
             cd w = 0.0;
-            for (int i = k; i < m; ++i) w += std::conj(vs[k][i - k]) * Q(i, j);
+            for (int i = k; i < ke; ++i) w += std::conj(vs[k][i - k]) * Q(i, j);
             w *= f;
-            for (int i = k; i < m; ++i) Q(i, j) -= vs[k][i - k] * w;
+            for (int i = k; i < ke; ++i) Q(i, j) -= vs[k][i - k] * w;
         }
     }
     // positive real diagonal

@@ -42,8 +42,10 @@ Mat tri_inv_upper(const Mat& R);
 Mat solve_upper(const Mat& R, const Mat& B);
 // X with A X = B, Gaussian elimination with partial pivoting; false if singular
 bool solve_lu(const Mat& A, const Mat& B, Mat& X);
-// thin Householder QR, A = Q R with diag(R) real and >= 0
-void qr_pos(const Mat& A, Mat& Q, Mat& R);
+// thin Householder QR, A = Q R with diag(R) real and >= 0; lower_bw >= 0
+// declares A(i, j) = 0 for i > j + lower_bw (the reflectors then span
+// lower_bw + 1 rows; a band Householder preserves)
+void qr_pos(const Mat& A, Mat& Q, Mat& R, int lower_bw = -1);
 
 // complex Schur form A = Z T Z^H (T upper triangular)
 struct Schur {

@@ -503,9 +503,12 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
                                                    A* H, A* F, A* Rh, A* QH, A* g, A* RinvAll, double* rho,
                                                    Ctl* ctl, double thresh) {
     if (ctl->active == 0) return;
-    constexpr int P2 = 2 * P;
+    constexpr int P2 = 2 * P, SROWS = 32;
+    static_assert(P * P <= NT, "one Gram entry per thread");
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
     __shared__ A X[P2 * P], M[P2 * P2], tmp[P2 * P], V[P2];
+    __shared__ A Sd[SROWS * P];
+    A* const Qs = M;  // reflector of an earlier column; M is set up after the last use
     __shared__ double vv, red[NT];
     __shared__ int okf;
     const int t = threadIdx.x;
@@ -513,14 +516,21 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
     const int ldH = m * P;
     if (S1) {
         // Gram of W'' = W' - Q S2 from the second pass's data (Pythagoras,
-        // Q^H W'' = 0): W''^H W'' = W'^H W' - S2^H S2 with S2 = S - S1
+        // Q^H W'' = 0): W''^H W'' = W'^H W' - S2^H S2 with S2 = S - S1; the
+        // rows of S2 are staged in LDS, SROWS at a time, by the whole group
         const int q = KP + j * P;
-        for (int e = t; e < P * P; e += NT) {
-            const int a = e / P, b = e % P;
-            A acc = gram[e];
-            for (int c = 0; c < q; ++c) acc -= cj(S[c * P + a] - S1[c * P + a]) * (S[c * P + b] - S1[c * P + b]);
-            Gs[e] = acc;
+        A acc = t < P * P ? gram[t] : zero<A>();
+        for (int c0 = 0; c0 < q; c0 += SROWS) {
+            const int cn = q - c0 < SROWS ? q - c0 : SROWS;
+            __syncthreads();
+            for (int e = t; e < cn * P; e += NT) Sd[e] = S[c0 * P + e] - S1[c0 * P + e];
+            __syncthreads();
+            if (t < P * P) {
+                const int a = t / P, b = t % P;
+                for (int c = 0; c < cn; ++c) acc -= cj(Sd[c * P + a]) * Sd[c * P + b];
+            }
         }
+        if (t < P * P) Gs[t] = acc;
     } else {
         for (int e = t; e < P * P; e += NT) Gs[e] = gram[e];
     }
@@ -539,36 +549,42 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
         return;
     }
     for (int e = t; e < P * P; e += NT) RinvAll[(int64_t)j * P * P + e] = Ri[e];
+    // new block column of H: rows < jP are the dots against V_1..V_j, rows
+    // jP .. (j+1)P - 1 the factor R_j
+    auto hcol = [&](int i, int bb) { return (i < j * P) ? S[(KP + i) * P + bb] : Rs[(i - j * P) * P + bb]; };
     for (int e = t; e < (j + 1) * P * P; e += NT) {
         const int i = e / P, bb = e % P;
-        const A v = (i < j * P) ? S[(KP + i) * P + bb] : Rs[(i - j * P) * P + bb];
-        H[(int64_t)i * ldH + jc * P + bb] = v;
-        Rh[(int64_t)i * ldH + jc * P + bb] = v;
+        H[(int64_t)i * ldH + jc * P + bb] = hcol(i, bb);
     }
     for (int e = t; e < KP * P; e += NT) {
         const int i = e / P, bb = e % P;
         F[(int64_t)i * ldH + jc * P + bb] = S[i * P + bb];
     }
-    __threadfence_block();
-    __syncthreads();
-    // apply the stored block reflectors of earlier block columns
+    // apply the stored block reflectors of earlier block columns: reflector i
+    // acts on row blocks i-1 and i, so a 2P-row window X slides down the
+    // column (its lower block enters unreflected) and the finished upper block
+    // of each window is written to Rh
+    for (int e = t; e < P2 * P; e += NT) X[e] = hcol(e / P, e % P);
     for (int i = 1; i < j; ++i) {
-        const int r0 = (i - 1) * P;
-        for (int e = t; e < P2 * P; e += NT) tmp[e] = Rh[(int64_t)(r0 + e / P) * ldH + jc * P + e % P];
+        for (int e = t; e < P2 * P2; e += NT) Qs[e] = QH[(int64_t)(i - 1) * P2 * P2 + e];
         __syncthreads();
-        const A* Q = QH + (int64_t)(i - 1) * P2 * P2;
         for (int e = t; e < P2 * P; e += NT) {
             const int rr = e / P, bb = e % P;
             A s = zero<A>();
-            for (int l = 0; l < P2; ++l) s += Q[rr * P2 + l] * tmp[l * P + bb];
-            Rh[(int64_t)(r0 + rr) * ldH + jc * P + bb] = s;
+            for (int l = 0; l < P2; ++l) s += Qs[rr * P2 + l] * X[l * P + bb];
+            tmp[e] = s;
         }
-        __threadfence_block();
         __syncthreads();
+        const int r0 = (i - 1) * P;
+        for (int e = t; e < P * P; e += NT) {
+            Rh[(int64_t)(r0 + e / P) * ldH + jc * P + e % P] = tmp[e];
+            X[e] = tmp[P * P + e];
+            X[P * P + e] = hcol((i + 1) * P + e / P, e % P);
+        }
     }
-    // Householder QR of the 2P x P block in rows (j-1)P .. (j+1)P-1
+    __syncthreads();
+    // Householder QR of the 2P x P block in rows (j-1)P .. (j+1)P-1 (now in X)
     const int r0 = (j - 1) * P;
-    for (int e = t; e < P2 * P; e += NT) X[e] = Rh[(int64_t)(r0 + e / P) * ldH + jc * P + e % P];
     for (int e = t; e < P2 * P2; e += NT) M[e] = from_real<A>((e / P2) == (e % P2) ? 1.0 : 0.0);
     __syncthreads();
     for (int c = 0; c < P; ++c) {

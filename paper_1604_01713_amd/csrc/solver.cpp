@@ -993,11 +993,13 @@ struct Seq final : bgcr_sequence {
 
     // harmonic Ritz on the augmented space, eq. harm-ritz-gen-eig:
     // G^H G t = theta G^H M t  with G = Qg Rg:  (Qg^H M Rg^{-1}) s = mu s,
-    // theta = 1/mu, t = Rg^{-1} s
+    // theta = 1/mu, t = Rg^{-1} s.  G = [[D, F], [0, H_m]] (or H_m) has lower
+    // bandwidth P: D is diagonal and the subdiagonal blocks R_j of the block
+    // Hessenberg H_m are upper triangular.
     void gen_harmonic(const Mat& G, const Mat& M, int kt, std::vector<cd>& theta, dense::Selection& sel,
                       std::vector<std::vector<cd>>& vecs, bool robust) {
         Mat Qg, Rg;
-        dense::qr_pos(G, Qg, Rg);
+        dense::qr_pos(G, Qg, Rg, P);
         const int nn = G.c;
         for (int i = 0; i < nn; ++i)
             if (!(std::abs(Rg(i, i)) > 0.0)) throw Fail{BGCR_ERR_NUMERICAL};
