@@ -150,6 +150,7 @@ struct Seq final : bgcr_sequence {
     Ctl* ctl = nullptr;
     unsigned char* hbuf = nullptr;
     size_t hcap = 0, hoff = 0;
+    double* rbuf = nullptr;  // pinned: residual partials copied back while the host works
     int cur = 0, keff = 0;
     // per-solve counters
     int n_spmm = 0, n_steps = 0, n_cycles = 0, n_refine = 0;
@@ -265,6 +266,7 @@ struct Seq final : bgcr_sequence {
         for (hipEvent_t e : evfree) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
         if (hbuf) (void)hipHostFree(hbuf);
+        if (rbuf) (void)hipHostFree(rbuf);
     }
 
     template <class U_>
@@ -326,6 +328,8 @@ struct Seq final : bgcr_sequence {
         dpart = dalloc<double>((size_t)NWG_MAX * 2 * P);
         hcap = std::max({(size_t)4 << 20, 2 * coef_cap * sizeof(A) + (64 << 10), hr_bytes + (64 << 10)});
         if (hipHostMalloc((void**)&hbuf, hcap, hipHostMallocDefault) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
+        if (hipHostMalloc((void**)&rbuf, (size_t)NWG_MAX * 2 * P * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            throw Fail{BGCR_ERR_NOMEM};
         HIPCHK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
         HIPCHK(hipMemsetAsync(Ub[0], 0, (size_t)KB * blk * sizeof(TB), st));
         HIPCHK(hipMemsetAsync(Ub[1], 0, (size_t)KB * blk * sizeof(TB), st));
@@ -520,25 +524,33 @@ struct Seq final : bgcr_sequence {
         return dot_collect(job, h.data());
     }
 
-    // per-column ||B - A X||^2 and ||B||^2 (FP64); stores R (narrowed) if Rout
-    void residual_norms(const bgcr_csr* Am, const A* B, int64_t ldb, T* Rout, std::vector<double>& rn2,
-                        std::vector<double>& bn2) {
+    // per-column ||B - A X||^2 and ||B||^2 (FP64); stores R (narrowed) if
+    // Rout.  residual_enqueue queues the kernel and the copy of its partials
+    // to pinned memory; residual_collect waits for them and sums.
+    void residual_enqueue(const bgcr_csr* Am, const A* B, int64_t ldb, T* Rout) {
         const double by = (double)(sizeof(A) + 4) * Am->nnz + 4.0 * (n + 1) + 2.0 * sizeof(A) * n * P +
                           (Rout ? (double)sizeof(T) * n * P : 0.0);
         run(BGCR_K_RESIDUAL, by, [&] {
             return residual<A, T>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, (const A*)Am->values, B, ldb, X, Rout,
                                   dpart, nwg);
         });
-        std::vector<double> h((size_t)nwg * 2 * P);
-        d2h(h.data(), dpart, h.size() * sizeof(double));
+        HIPCHK(hipMemcpyAsync(rbuf, dpart, (size_t)nwg * 2 * P * sizeof(double), hipMemcpyDeviceToHost, st));
+        ++n_spmm;
+    }
+    void residual_collect(std::vector<double>& rn2, std::vector<double>& bn2) {
+        sync();
         rn2.assign(P, 0.0);
         bn2.assign(P, 0.0);
         for (int w = 0; w < nwg; ++w)
             for (int b = 0; b < P; ++b) {
-                rn2[b] += h[(size_t)w * 2 * P + b];
-                bn2[b] += h[(size_t)w * 2 * P + P + b];
+                rn2[b] += rbuf[(size_t)w * 2 * P + b];
+                bn2[b] += rbuf[(size_t)w * 2 * P + P + b];
             }
-        ++n_spmm;
+    }
+    void residual_norms(const bgcr_csr* Am, const A* B, int64_t ldb, T* Rout, std::vector<double>& rn2,
+                        std::vector<double>& bn2) {
+        residual_enqueue(Am, B, ldb, Rout);
+        residual_collect(rn2, bn2);
     }
 
     // Algorithm 1, U available: A U = C S (CholQR2), U <- U S^{-1}
@@ -1097,10 +1109,14 @@ struct Seq final : bgcr_sequence {
 
     // End of a cycle (Algorithm 1): X += [V_m U] [Y; -F Y], R -= V_{m+1} H Y
     // (the recurrence; skipped in the precision form, whose outer loop takes
-    // the FP64 true residual) and the refresh of (U, C).  On matrix cores in
-    // plain FP64 all of it is one pass over [U, C, V_1..V_m, V_{m+1}] writing
-    // [X, R, U', C'] (the refresh reads a superset of the update's inputs).
-    void finish_cycle(const CycleOut& co, bool withC, bool update_R) {
+    // the FP64 true residual) and the refresh of (U, C).  The update and the
+    // true residual (`residual_enqueue`, given by the caller) are queued
+    // before the host solves the refresh problem, so the GPU computes them
+    // meanwhile; the refresh combination follows.
+    template <class FN>
+    void finish_cycle(const CycleOut& co, bool withC, bool update_R, FN&& residual_enqueue) {
+        update_solution(co, withC, update_R);
+        residual_enqueue();
         RefreshPlan rp;
         if (k > 0) {
             if (withC)
@@ -1108,43 +1124,7 @@ struct Seq final : bgcr_sequence {
             else
                 refresh_first(co, rp);
         }
-        const int nx = update_R ? 2 : 1;
-        const bool fuse = rp.active && use_mx && !mixed && !std::is_same<T, zd>::value &&
-                          (int)(nx + rp.out.size()) * P <= 64;
-        if (!fuse) {
-            update_solution(co, withC, update_R);
-            if (rp.active) apply_refresh(rp);
-            return;
-        }
-        std::unique_ptr<HostPhase> hp(new HostPhase(this, BGCR_K_HOST));
-        const int me = co.meff, mp = me * P;
-        const int voff = withC ? 2 * KP : 0;  // row of V_1 in the refresh inputs
-        Mat Kall((int)rp.in.size() * P, (nx + (int)rp.out.size()) * P);
-        for (int i = 0; i < mp; ++i)
-            for (int b = 0; b < P; ++b) Kall(voff + i, b) = co.Y(i, b);
-        if (withC) {
-            const Mat FY = dense::matmul(co.F, co.Y);
-            for (int i = 0; i < keff; ++i)
-                for (int b = 0; b < P; ++b) Kall(i, b) = -FY(i, b);
-        }
-        if (update_R) {
-            const Mat HY = dense::matmul(co.H, co.Y);
-            for (int i = 0; i < mp; ++i)
-                for (int b = 0; b < P; ++b) Kall(voff + i, P + b) = -HY(i, b);
-            const Mat last = dense::matmul(co.RinvLast, HY.block(mp, 0, P, P));
-            for (int i = 0; i < P; ++i)
-                for (int b = 0; b < P; ++b) Kall(voff + mp + i, P + b) = -last(i, b);
-        }
-        for (int c = 0; c < rp.K.c; ++c)
-            for (int r = 0; r < rp.K.r; ++r) Kall(r, nx * P + c) = rp.K(r, c);
-        std::vector<void*> outs;
-        outs.push_back(X);
-        if (update_R) outs.push_back(R);
-        for (void* o : rp.out) outs.push_back(o);
-        hp.reset();
-        combine<T>(rp.in, outs, Kall, nx);
-        cur = rp.next_cur;
-        keff = rp.kn;
+        if (rp.active) apply_refresh(rp);
     }
 
     int solve(const bgcr_csr* Am, const void* Bv, int64_t ldb, void* Xv, int64_t ldx, double tol,
@@ -1238,19 +1218,28 @@ struct Seq final : bgcr_sequence {
     int run_plain(const bgcr_csr* Am, const T* avT, const A* B, int64_t ldb, double thresh,
                   std::vector<double>& rn2, std::vector<double>& bn2, FN& finish_norms) {
         bool pending = false;  // the last cycle's true residual is still to be logged
+        bool queued = false;   // that residual is already queued (finish_cycle)
+        auto enqueue = [&] {
+            residual_enqueue(Am, B, ldb, nullptr);
+            queued = true;
+        };
         if (keff > 0) {
             import_basis(Am, avT);
             project();
         } else {
             CycleOut co = cycle(Am, avT, false, thresh);
-            finish_cycle(co, false, true);
+            finish_cycle(co, false, true, enqueue);
             ++n_cycles;
             log_steps.push_back(co.meff);
             log_res.push_back(0.0);
             pending = true;
         }
         for (;;) {
-            residual_norms(Am, B, ldb, nullptr, rn2, bn2);
+            if (queued)
+                residual_collect(rn2, bn2);
+            else
+                residual_norms(Am, B, ldb, nullptr, rn2, bn2);
+            queued = false;
             double s = 0.0;
             for (double v : rn2) s += v;
             if (!std::isfinite(s)) throw Fail{BGCR_ERR_NONFINITE};
@@ -1261,7 +1250,7 @@ struct Seq final : bgcr_sequence {
             if (n_cycles >= prm.max_cycles) return BGCR_NOT_CONVERGED;
             const bool withC = keff > 0;
             CycleOut co = cycle(Am, avT, withC, thresh);
-            finish_cycle(co, withC, true);
+            finish_cycle(co, withC, true, enqueue);
             ++n_cycles;
             log_steps.push_back(co.meff);
             log_res.push_back(0.0);
@@ -1283,9 +1272,10 @@ struct Seq final : bgcr_sequence {
                   std::vector<double>& rn2, std::vector<double>& bn2, FN& finish_norms) {
         if (keff > 0) import_basis(Am, avT);
         bool first = true;
+        auto enqueue = [&] { residual_enqueue(Am, B, ldb, R); };
         for (;;) {
             if (!first) {
-                residual_norms(Am, B, ldb, R, rn2, bn2);
+                residual_collect(rn2, bn2);  // queued by finish_cycle
                 finish_norms(rn2, bn2);
                 if (!log_steps.empty()) log_res.back() = rel_now(rn2, bn2);
             }
@@ -1298,7 +1288,7 @@ struct Seq final : bgcr_sequence {
             const bool withC = keff > 0;
             if (withC) project();
             CycleOut co = cycle(Am, avT, withC, thresh);
-            finish_cycle(co, withC, false);
+            finish_cycle(co, withC, false, enqueue);
             ++n_cycles;
             ++n_refine;
             log_steps.push_back(co.meff);
