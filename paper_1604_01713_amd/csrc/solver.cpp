@@ -632,16 +632,17 @@ struct Seq final : bgcr_sequence {
 
     // One restart cycle: CholQR2 of R, m block Arnoldi steps on (I - C C^H) A
     // with BCGS2 + CholQR and the progressive LSQ, then Y (Algorithm 1 loop body).
-    CycleOut cycle(const bgcr_csr* Am, const T* avT, bool withC, double thresh) {
+    // Start of a cycle: cleared H and its triangular factor, and CholQR2 of
+    // the starting block R = V_1 Z (Algorithm 1).  Needs R only, so plain
+    // FP64 queues it before the host solves the previous cycle's refresh.
+    void cycle_prologue() {
         const int P2 = P * P;
         // H and its triangularised copy are read below the block subdiagonal
         // (block upper Hessenberg structure): those entries must be zero
         const size_t hb = (size_t)(m + 1) * P * m * P * sizeof(A);
         HIPCHK(hipMemsetAsync(H, 0, hb, st));
         HIPCHK(hipMemsetAsync(Rh, 0, hb, st));
-        const double sT = (double)sizeof(T), blkb = sT * (double)n * P;
-        const double sB = (double)sizeof(TB), vblkb = sB * (double)n * P;  // basis scalar, basis block
-        // CholQR2 of the cycle's starting block R = V_1 Z (Algorithm 1)
+        const double blkb = (double)sizeof(T) * n * P;
         const int nr = use_mx ? nwg_mx : nwg;
         run(BGCR_K_TSDOT, blkb, [&] {
             if constexpr (!std::is_same<T, zd>::value) {
@@ -667,6 +668,13 @@ struct Seq final : bgcr_sequence {
             HIPCHK(reduce_partials<A>(st, part, nr, P2, nullptr, Sf, nullptr));
             return cholqr_second<A>(st, P, Sf, Z1, RinvAll, g, m, ctl);
         });
+    }
+
+    CycleOut cycle(const bgcr_csr* Am, const T* avT, bool withC, double thresh, bool prologue_done = false) {
+        const int P2 = P * P;
+        if (!prologue_done) cycle_prologue();
+        const double sT = (double)sizeof(T), blkb = sT * (double)n * P;
+        const double sB = (double)sizeof(TB), vblkb = sB * (double)n * P;  // basis scalar, basis block
         const int ncb = withC ? KB : 0;
         const double kc = withC ? (double)keff : 0.0;
         const double abytes = (sT + 4.0) * (double)Am->nnz + 4.0 * (double)(n + 1);
@@ -1218,10 +1226,17 @@ struct Seq final : bgcr_sequence {
     int run_plain(const bgcr_csr* Am, const T* avT, const A* B, int64_t ldb, double thresh,
                   std::vector<double>& rn2, std::vector<double>& bn2, FN& finish_norms) {
         bool pending = false;  // the last cycle's true residual is still to be logged
-        bool queued = false;   // that residual is already queued (finish_cycle)
+        bool queued = false;    // that residual is already queued (finish_cycle)
+        bool prologued = false; // so is the next cycle's prologue
         auto enqueue = [&] {
             residual_enqueue(Am, B, ldb, nullptr);
             queued = true;
+            // the prologue writes the start block into W2, which off matrix
+            // cores still holds V_{m+1} for the refresh: there it waits
+            if (use_mx) {
+                cycle_prologue();  // wasted once per system, on the converged cycle
+                prologued = true;
+            }
         };
         if (keff > 0) {
             import_basis(Am, avT);
@@ -1235,11 +1250,12 @@ struct Seq final : bgcr_sequence {
             pending = true;
         }
         for (;;) {
+            const bool prologue_done = prologued;
             if (queued)
                 residual_collect(rn2, bn2);
             else
                 residual_norms(Am, B, ldb, nullptr, rn2, bn2);
-            queued = false;
+            queued = prologued = false;
             double s = 0.0;
             for (double v : rn2) s += v;
             if (!std::isfinite(s)) throw Fail{BGCR_ERR_NONFINITE};
@@ -1249,7 +1265,7 @@ struct Seq final : bgcr_sequence {
             if (std::sqrt(s) <= thresh) return BGCR_OK;
             if (n_cycles >= prm.max_cycles) return BGCR_NOT_CONVERGED;
             const bool withC = keff > 0;
-            CycleOut co = cycle(Am, avT, withC, thresh);
+            CycleOut co = cycle(Am, avT, withC, thresh, prologue_done);
             finish_cycle(co, withC, true, enqueue);
             ++n_cycles;
             log_steps.push_back(co.meff);
