@@ -38,6 +38,11 @@ Readings of points the paper leaves open (each one is listed in the design doc):
   * The first-cycle selection uses Proposition block-harm-ritz; if the square
     part H_m is numerically singular it falls back to the generalized form with
     no recycled space.
+  * Enlarged block (p = 1, block size L > 1, Section 3.1): every cycle starts
+    from [r, Z] with the same L - 1 vectors Z, drawn once by a counter-based
+    SplitMix64 (entry (i, c) of the n x L block, c = 1 .. L-1), and solves the
+    single-vector problem eq. 1rhs-block-gmres-min (right-hand side
+    E_1 F_0 e_1).
 """
 from __future__ import annotations
 
@@ -64,6 +69,33 @@ def qr_pos(M):
     return Q, R
 
 
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_MIX1 = np.uint64(0xBF58476D1CE4E5B9)
+_MIX2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(counter):
+    """SplitMix64 (Steele, Lea and Flood, OOPSLA 2014; the finaliser of
+    Vigna's splitmix64.c) applied to a uint64 counter array: the output for
+    state x is mix(x + golden gamma).  counter 0 gives 0xE220A8397B1DCDAF, the
+    generator's first output from seed 0."""
+    z = np.asarray(counter, dtype=np.uint64) + _GOLDEN
+    z = (z ^ (z >> np.uint64(30))) * _MIX1
+    z = (z ^ (z >> np.uint64(27))) * _MIX2
+    return z ^ (z >> np.uint64(31))
+
+
+def enlarging_vectors(n, L, seed=0):
+    """The L - 1 extra start vectors of the enlarged block: entry (i, c) for
+    c = 1 .. L-1 is 2 u - 1 with u the top 53 bits of
+    splitmix64(i + 2^40 c + 2^56 seed) scaled to [0, 1)."""
+    i = np.arange(n, dtype=np.uint64)[:, None]
+    c = np.arange(1, L, dtype=np.uint64)[None, :]
+    ctr = i + (c << np.uint64(40)) + (np.uint64(seed) << np.uint64(56))
+    u = (splitmix64(ctr) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+    return 2.0 * u - 1.0
+
+
 def _bj(j, p):
     """Row/column slice of block j (0-based) with block size p."""
     return slice(j * p, (j + 1) * p)
@@ -74,9 +106,11 @@ def _bj(j, p):
 # Algorithm 1 cycle body)
 # ----------------------------------------------------------------------------
 
-def block_arnoldi_cycle(A, R, C, m, thresh):
+def block_arnoldi_cycle(A, R, C, m, thresh, extra=None):
     """Block Arnoldi on (I - C C^H) A started from the block residual R, with the
-    block GMRES least-squares problem solved after every block step.
+    block GMRES least-squares problem solved after every block step.  With
+    `extra` (enlarged block, p = 1) the start block is [R, extra] and only R's
+    column is a right-hand side (eq. 1rhs-block-gmres-min).
 
     Returns a dict with
       V   : list of m_eff+1 orthonormal n x p blocks (W_{m_eff+1} = [V_1 .. V_{m_eff+1}])
@@ -87,15 +121,18 @@ def block_arnoldi_cycle(A, R, C, m, thresh):
       rho : list of the LSQ residual norms after each block step
       m_eff
     """
-    n, p = R.shape
+    nrhs = R.shape[1]
+    if extra is not None:
+        R = np.hstack([R, extra.astype(R.dtype)])
+    n, p = R.shape                                   # p: block size (L when enlarged)
     k = 0 if C is None else C.shape[1]
     dt = np.result_type(R.dtype, A.dtype, np.float64)
     V1, Z = qr_pos(R.astype(dt))
     V = [V1]
     H = np.zeros(((m + 1) * p, m * p), dtype=dt)
     F = np.zeros((k, m * p), dtype=dt)
-    EZ = np.zeros(((m + 1) * p, p), dtype=dt)
-    EZ[:p, :] = Z                                    # E Z with E = I_{(m+1)p}[:, :p]
+    EZ = np.zeros(((m + 1) * p, nrhs), dtype=dt)
+    EZ[:p, :] = Z[:, :nrhs]                          # E Z (E = I_{(m+1)p}[:, :p]), or E_1 F_0 e_1
     rho = []
     Y = None
     m_eff = 0
@@ -269,12 +306,14 @@ def recycle_import(A, U, X, R):
     return U, C, X + U @ T, R - C @ T
 
 
-def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, trace=False):
+def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, trace=False, block_size=None,
+          seed=0):
     """Algorithm 1 (block RGMRES / block GCRO-DR) for one system A X = B.
 
     Returns (X, U, stats).  stats holds per-cycle block-step counts, the LSQ
     residual history, true relative residuals and (with trace=True) the cycle
-    internals used by the pins.
+    internals used by the pins.  block_size L > 1 with one right-hand side
+    enlarges the block with enlarging_vectors(n, L, seed).
     """
     A = A.tocsr() if hasattr(A, "tocsr") else A
     B = np.asarray(B)
@@ -293,6 +332,11 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
         stats["rel_res"] = 0.0
         return X, U, stats
     thresh = tol * bn
+    extra = None
+    if block_size is not None and block_size > p:
+        if p != 1:
+            raise ValueError("an enlarged block needs a single right-hand side")
+        extra = enlarging_vectors(n, block_size, seed).astype(dt)
     R = B - A @ X
     if np.linalg.norm(R) <= thresh:
         stats["rel_res"] = float(np.linalg.norm(R)) / bn
@@ -301,7 +345,7 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
     if U is not None:
         U, C, X, R = recycle_import(A, U.astype(dt), X, R)
     else:
-        cyc = block_arnoldi_cycle(A, R, None, m, thresh)
+        cyc = block_arnoldi_cycle(A, R, None, m, thresh, extra)
         me = cyc["m_eff"]
         Wm = np.hstack(cyc["V"][:me])
         Wm1 = np.hstack(cyc["V"])
@@ -314,7 +358,7 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
         if np.linalg.norm(Rt) <= thresh or stats["cycles"] >= max_cycles:
             break
         Uold, Cold = U, C
-        cyc = block_arnoldi_cycle(A, R, C, m, thresh)
+        cyc = block_arnoldi_cycle(A, R, C, m, thresh, extra)
         me = cyc["m_eff"]
         Wm = np.hstack(cyc["V"][:me])
         Wm1 = np.hstack(cyc["V"])
@@ -347,13 +391,13 @@ def _log(stats, cyc, A, B, X, R, bn, trace, U, C, Uold=None, Cold=None):
                                "X": X.copy(), "R": R.copy()})
 
 
-def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False):
+def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False, block_size=None, seed=0):
     """Solve a sequence A^[i] X = B^[i], carrying U from each system to the next
     (Algorithm 1, last line).  `systems` is a list of (A, B, X0)."""
     U = None
     out = []
     for (A, B, X0) in systems:
         X, U, st = solve(A, B, X0, tol, m, k, U=U, max_cycles=max_cycles,
-                         select_largest=select_largest)
+                         select_largest=select_largest, block_size=block_size, seed=seed)
         out.append((X, st))
     return out, U

@@ -171,6 +171,51 @@ def test_k0_block_is_block_gmres_over_block_krylov_space():
     assert np.linalg.norm(X - Xb) < 1e-9 * np.linalg.norm(Xb)
 
 
+# ---- enlarged block (p = 1, block size L > 1; Section 3.1) ------------------
+
+def test_splitmix64_matches_published_outputs():
+    """The enlarging vectors come from SplitMix64; its first three outputs from
+    seed 0 (states golden, 2 golden, 3 golden) are published test values."""
+    g = int(0x9E3779B97F4A7C15)
+    out = O.splitmix64(np.array([0, g, (2 * g) % 2**64], dtype=np.uint64))
+    assert [int(v) for v in out] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    Z = O.enlarging_vectors(1000, 4, seed=0)
+    assert Z.shape == (1000, 3) and Z.min() >= -1.0 and Z.max() < 1.0
+    assert abs(Z.mean()) < 0.05 and abs(Z.std() - 1 / np.sqrt(3)) < 0.02
+
+
+def test_enlarged_block_cycle_is_min_residual_over_block_krylov_space():
+    """p = 1, L = 3, k = 0, one cycle: the correction minimises the single
+    residual over blspan{[r Z], A [r Z], ..., A^{m-1} [r Z]} (eq.
+    1rhs-block-gmres-min), built here from explicit powers."""
+    A, B = _small(N=9, p=1)
+    m, L = 3, 3
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-300, m, 0, max_cycles=1, block_size=L)
+    Ad = A.toarray()
+    K = [np.hstack([B, O.enlarging_vectors(A.shape[0], L)])]
+    for _ in range(m - 1):
+        K.append(Ad @ K[-1])
+    Qk, _ = np.linalg.qr(np.hstack(K))
+    zb, *_ = np.linalg.lstsq(Ad @ Qk, B, rcond=None)
+    xb = Qk @ zb
+    assert np.linalg.norm(X - xb) < 1e-9 * np.linalg.norm(xb)
+    # the enlarged space is richer: a smaller residual than one GMRES(m) cycle
+    Xg, _, _ = O.solve(A, B, np.zeros_like(B), 1e-300, m, 0, max_cycles=1)
+    assert np.linalg.norm(B - A @ X) < np.linalg.norm(B - A @ Xg)
+
+
+def test_enlarged_block_sequence_with_recycling_matches_dense_lu():
+    A, B = _small(N=10, p=1)
+    systems = [(A, B, np.zeros_like(B)),
+               ((A + 0.05 * sp.identity(A.shape[0])).tocsr(), B[::-1].copy(), np.zeros_like(B))]
+    out, U = O.solve_sequence(systems, 1e-10, 4, 5, block_size=4)
+    for (Ai, Bi, _), (X, st) in zip(systems, out):
+        Xd = np.linalg.solve(Ai.toarray(), Bi)
+        assert np.linalg.norm(X - Xd) <= 1e-8 * np.linalg.norm(Xd)
+        assert st["rel_res"] <= 1e-10
+    assert U.shape[1] in (5, 6)
+
+
 # ---- P10: harmonic Ritz ----------------------------------------------------
 
 def _toeplitz_tridiag(n, a, b, c):
