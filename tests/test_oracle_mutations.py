@@ -56,8 +56,8 @@ def test_dropped_F_block_in_G_is_caught(monkeypatch):
 def test_wrong_sign_of_pi_term_is_caught(monkeypatch):
     orig_cycle = ob.block_arnoldi_cycle
 
-    def bad_cycle(A, R, C, m, thresh):
-        cyc = orig_cycle(A, R, C, m, thresh)
+    def bad_cycle(A, R, C, m, thresh, extra=None):
+        cyc = orig_cycle(A, R, C, m, thresh, extra)
         cyc["F"] = -cyc["F"]                          # X += W Y + U F Y instead of - U F Y
         return cyc
 
