@@ -39,10 +39,11 @@ Readings of points the paper leaves open (each one is listed in the design doc):
     part H_m is numerically singular it falls back to the generalized form with
     no recycled space.
   * Enlarged block (p = 1, block size L > 1, Section 3.1): every cycle starts
-    from [r, Z] with the same L - 1 vectors Z, drawn once by a counter-based
-    SplitMix64 (entry (i, c) of the n x L block, c = 1 .. L-1), and solves the
-    single-vector problem eq. 1rhs-block-gmres-min (right-hand side
-    E_1 F_0 e_1).
+    from (I - C C^H) [r, Z] (the Krylov space of the augmented method is built
+    from (I - Phi) R_0) with the same L - 1 vectors Z, drawn once by a
+    counter-based SplitMix64 (entry (i, c) of the n x L block, c = 1 .. L-1),
+    and solves the single-vector problem eq. 1rhs-block-gmres-min (right-hand
+    side E_1 F_0 e_1).
 """
 from __future__ import annotations
 
@@ -123,7 +124,14 @@ def block_arnoldi_cycle(A, R, C, m, thresh, extra=None):
     """
     nrhs = R.shape[1]
     if extra is not None:
-        R = np.hstack([R, extra.astype(R.dtype)])
+        # the start block of the augmented method is (I - C C^H) [R, Z]; R is
+        # already orthogonal to C, the enlarging vectors are projected here
+        # (twice, as in the block Gram-Schmidt passes)
+        Zx = extra.astype(np.result_type(R.dtype, extra.dtype))
+        if C is not None:
+            for _ in range(2):
+                Zx = Zx - C @ (C.conj().T @ Zx)
+        R = np.hstack([R, Zx])
     n, p = R.shape                                   # p: block size (L when enlarged)
     k = 0 if C is None else C.shape[1]
     dt = np.result_type(R.dtype, A.dtype, np.float64)

@@ -216,6 +216,20 @@ def test_enlarged_block_sequence_with_recycling_matches_dense_lu():
     assert U.shape[1] in (5, 6)
 
 
+def test_enlarged_block_basis_is_orthogonal_to_C():
+    """With a recycled space the enlarged start block is (I - C C^H) [r, Z]:
+    the basis of every cycle is orthogonal to C, as the modified Arnoldi
+    relation (eq. block-modified-arnoldi) needs."""
+    A, B = _small(N=10, p=1)
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-10, 4, 5, block_size=4, trace=True)
+    assert st["cycles"] >= 3
+    for tr in st["trace"][1:]:
+        C = tr["C_in"]
+        Wm1 = np.hstack(tr["cyc"]["V"])
+        assert np.linalg.norm(C.conj().T @ Wm1) < 1e-12
+        assert np.linalg.norm(Wm1.conj().T @ Wm1 - np.eye(Wm1.shape[1])) < 1e-12
+
+
 # ---- P10: harmonic Ritz ----------------------------------------------------
 
 def _toeplitz_tridiag(n, a, b, c):
