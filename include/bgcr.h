@@ -69,7 +69,14 @@ typedef struct {
     int32_t max_cycles;      /* restart cycles per solve before BGCR_NOT_CONVERGED (>= 1) */
     int32_t select_largest;  /* 0: keep harmonic Ritz values of smallest modulus
                                 (Section 4.1 default); 1: largest */
-    int32_t reserved;        /* must be 0 */
+    int32_t block_size;      /* block size L of the Krylov basis: 0 or p for L = p.
+                                With p = 1, L in {2, 4, 8, 16} enlarges the block
+                                (Section 3.1, eq. 1rhs-block-gmres-min): every cycle
+                                starts from [r, Z], Z the same L - 1 vectors drawn by
+                                SplitMix64 (entry (i, c) from the counter
+                                i + 2^40 c, mapped to [-1, 1)), and minimises the
+                                single residual; U, C and the basis are n x L blocks,
+                                B and X stay n x 1.  Other values: BGCR_ERR_INVALID */
 } bgcr_params;
 
 typedef struct {

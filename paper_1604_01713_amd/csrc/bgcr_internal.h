@@ -145,10 +145,22 @@ hipError_t residual(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp
                     const TA* B, int64_t ldb, const TA* X, TR* Rout, double* part, int nwg);
 
 // small kernels read a reduced P x P Gram matrix
+// first CholQR pass of the start block; with nrhs < P (enlarged block) the
+// enlarging columns are scaled to the residual's norm and Z1inv is D Z1^{-1}
 template <class A>
-hipError_t cholqr_first(hipStream_t st, int P, const A* gram, A* Z1, A* Z1inv, Ctl* ctl);
+hipError_t cholqr_first(hipStream_t st, int P, const A* gram, A* Z1, A* Z1inv, int nrhs, Ctl* ctl);
+// second CholQR pass of the start block; g = E Z with only its first nrhs
+// columns kept (nrhs < P: enlarged block, right-hand side E_1 F_0 e_1)
 template <class A>
-hipError_t cholqr_second(hipStream_t st, int P, const A* gram, const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl);
+hipError_t cholqr_second(hipStream_t st, int P, const A* gram, const A* Z1, A* Rinv0, A* g, int m, int nrhs,
+                         Ctl* ctl);
+// columns c0 .. P-1 of the row-major n x P block Y <- SplitMix64 vectors in
+// [-1, 1) (the enlarging vectors of a single right-hand side)
+template <class T>
+hipError_t fill_enlarging(hipStream_t st, T* Y, int64_t n, int P, int c0, uint64_t seed);
+// S[r][c] = 0 for the columns c < ncols of a row-major rows x P matrix
+template <class A>
+hipError_t zero_cols(hipStream_t st, A* S, int rows, int P, int ncols);
 // S1 non-null: `gram` is W'^H W' of the second pass and W''^H W'' = gram - S2^H S2
 // with S2 = S - S1 (Pythagorean Gram of the stored block)
 template <class A>

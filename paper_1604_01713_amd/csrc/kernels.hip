@@ -36,6 +36,7 @@ __device__ inline zd scale_by(double s, zd a) { return {s * a.x, s * a.y}; }
 template <class A> __device__ inline A from_real(double v);
 template <> __device__ inline double from_real<double>(double v) { return v; }
 template <> __device__ inline zd from_real<zd>(double v) { return {v, 0.0}; }
+template <> __device__ inline float from_real<float>(double v) { return (float)v; }
 
 template <class TO, class TI> __host__ __device__ inline TO conv(TI v);
 template <> __host__ __device__ inline double conv<double, double>(double v) { return v; }
@@ -428,12 +429,32 @@ __device__ void reduce_small(const A* part, int nwg, int nout, int off, A* out, 
     }
 }
 
-// first pass of CholQR of the cycle's starting block: Z1 = chol(Gram)
+// first pass of CholQR of the cycle's starting block: Z1 = chol(Gram).
+// With an enlarged block (nrhs < P) the block is [r, Z] and its enlarging
+// columns are scaled by s with s^2 = |r|^2 / mean |z_j|^2 (the span, hence
+// the iterate, is unchanged, while the Gram matrix stays well conditioned
+// when |r| has become small): the Gram of [r, s Z] is D G D with
+// D = diag(1.., s..), and the update matrix returned is D Z1^{-1}, so that
+// [r, Z] (D Z1^{-1}) = [r, s Z] Z1^{-1}.
 template <class A, int P>
-__global__ void k_cholqr_first(const A* gram, A* Z1, A* Z1inv, Ctl* ctl) {
+__global__ void k_cholqr_first(const A* gram, A* Z1, A* Z1inv, int nrhs, Ctl* ctl) {
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
     __shared__ int okf;
-    for (int e = threadIdx.x; e < P * P; e += blockDim.x) Gs[e] = gram[e];
+    __shared__ double dsc[P];
+    if (threadIdx.x == 0) {
+        double s = 1.0;
+        if (nrhs < P) {
+            double r2 = 0.0, z2 = 0.0;
+            for (int i = 0; i < nrhs; ++i) r2 += re(gram[i * P + i]);
+            for (int i = nrhs; i < P; ++i) z2 += re(gram[i * P + i]);
+            r2 /= nrhs;
+            z2 /= (P - nrhs);
+            if (r2 > 0.0 && z2 > 0.0) s = sqrt(r2 / z2);
+        }
+        for (int i = 0; i < P; ++i) dsc[i] = i < nrhs ? 1.0 : s;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P * P; e += blockDim.x) Gs[e] = scale_by(dsc[e / P] * dsc[e % P], gram[e]);
     __syncthreads();
     if (threadIdx.x == 0) {
         okf = chol_upper(Gs, Rs, P);
@@ -450,7 +471,7 @@ __global__ void k_cholqr_first(const A* gram, A* Z1, A* Z1inv, Ctl* ctl) {
     }
     for (int e = threadIdx.x; e < P * P; e += blockDim.x) {
         Z1[e] = Rs[e];
-        Z1inv[e] = Ri[e];
+        Z1inv[e] = scale_by(dsc[e / P], Ri[e]);
     }
     if (threadIdx.x == 0) ctl->status = 0;
 }
@@ -458,7 +479,7 @@ __global__ void k_cholqr_first(const A* gram, A* Z1, A* Z1inv, Ctl* ctl) {
 // second pass: Z2 = chol(Gram of R Z1^{-1}); Z = Z2 Z1; LSQ right-hand side
 // E Z (Algorithm 1) and the cycle control block are initialised here.
 template <class A, int P>
-__global__ void k_cholqr_second(const A* gram, const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl) {
+__global__ void k_cholqr_second(const A* gram, const A* Z1, A* Rinv0, A* g, int m, int nrhs, Ctl* ctl) {
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
     __shared__ int okf;
     if (ctl->status != 0) return;
@@ -480,8 +501,9 @@ __global__ void k_cholqr_second(const A* gram, const A* Z1, A* Rinv0, A* g, int 
     for (int e = threadIdx.x; e < P * P; e += blockDim.x) Rinv0[e] = Ri[e];
     for (int e = threadIdx.x; e < (m + 1) * P * P; e += blockDim.x) {
         const int i = e / P, j = e % P;
+        // E Z, or with an enlarged block its first column only (E_1 F_0 e_1)
         A z = zero<A>();
-        if (i < P)
+        if (i < P && j < nrhs)
             for (int l = 0; l < P; ++l) z += Rs[i * P + l] * Z1[l * P + j];
         g[e] = z;
     }
@@ -651,6 +673,36 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
     }
 }
 
+// Enlarging vectors of a single right-hand side (p = 1, block size P):
+// columns c0 .. P-1 of the row-major n x P block Y get 2 u - 1, u the top 53
+// bits of SplitMix64 (Steele, Lea and Flood 2014; Vigna's finaliser) of the
+// counter i + 2^40 c + 2^56 seed, scaled to [0, 1).
+__device__ inline uint64_t splitmix64(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+template <class T>
+__global__ void k_fill_enlarging(T* __restrict__ Y, int64_t n, int P, int c0, uint64_t seed) {
+    const int w = P - c0;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * w) return;
+    const int64_t i = e / w;
+    const int c = c0 + (int)(e % w);
+    const uint64_t ctr = (uint64_t)i + ((uint64_t)c << 40) + (seed << 56);
+    const double u = (double)(splitmix64(ctr) >> 11) * (1.0 / 9007199254740992.0);
+    Y[i * P + c] = from_real<T>(2.0 * u - 1.0);
+}
+
+// S[r][c] = 0 for columns c < ncols of a row-major rows x P matrix
+template <class A>
+__global__ void k_zero_cols(A* S, int rows, int P, int ncols) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < rows * ncols) S[(e / ncols) * P + e % ncols] = zero<A>();
+}
+
 template <class TI, class TO>
 __global__ void k_copy_block(int64_t n, int p, const TI* __restrict__ in, int64_t ldi, TO* __restrict__ out,
                              int64_t ldo, int padto) {
@@ -775,16 +827,16 @@ hipError_t residual(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp
 }
 
 template <class A>
-hipError_t cholqr_first(hipStream_t st, int P, const A* gram, A* Z1, A* Z1inv, Ctl* ctl) {
-#define L(PP) hipLaunchKernelGGL((k_cholqr_first<A, PP>), dim3(1), dim3(NT), 0, st, gram, Z1, Z1inv, ctl);
+hipError_t cholqr_first(hipStream_t st, int P, const A* gram, A* Z1, A* Z1inv, int nrhs, Ctl* ctl) {
+#define L(PP) hipLaunchKernelGGL((k_cholqr_first<A, PP>), dim3(1), dim3(NT), 0, st, gram, Z1, Z1inv, nrhs, ctl);
     BGCR_DISPATCH_P(P, L)
 #undef L
     return hipGetLastError();
 }
 
 template <class A>
-hipError_t cholqr_second(hipStream_t st, int P, const A* gram, const A* Z1, A* Rinv0, A* g, int m, Ctl* ctl) {
-#define L(PP) hipLaunchKernelGGL((k_cholqr_second<A, PP>), dim3(1), dim3(NT), 0, st, gram, Z1, Rinv0, g, m, ctl);
+hipError_t cholqr_second(hipStream_t st, int P, const A* gram, const A* Z1, A* Rinv0, A* g, int m, int nrhs, Ctl* ctl) {
+#define L(PP) hipLaunchKernelGGL((k_cholqr_second<A, PP>), dim3(1), dim3(NT), 0, st, gram, Z1, Rinv0, g, m, nrhs, ctl);
     BGCR_DISPATCH_P(P, L)
 #undef L
     return hipGetLastError();
@@ -802,6 +854,21 @@ hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, const A*
 hipError_t cast_values(hipStream_t st, const double* in, float* out, int64_t nnz) {
     if (nnz <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_cast, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, in, out, nnz);
+    return hipGetLastError();
+}
+
+template <class A>
+hipError_t zero_cols(hipStream_t st, A* S, int rows, int P, int ncols) {
+    if (rows * ncols <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_zero_cols<A>), dim3((rows * ncols + 255) / 256), dim3(256), 0, st, S, rows, P, ncols);
+    return hipGetLastError();
+}
+
+template <class T>
+hipError_t fill_enlarging(hipStream_t st, T* Y, int64_t n, int P, int c0, uint64_t seed) {
+    const int64_t tot = n * (P - c0);
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_fill_enlarging<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, Y, n, P, c0, seed);
     return hipGetLastError();
 }
 
@@ -835,10 +902,11 @@ template hipError_t residual<double, float>(hipStream_t, int, int64_t, int64_t, 
                                             const double*, int64_t, const double*, float*, double*, int);
 template hipError_t residual<zd, zd>(hipStream_t, int, int64_t, int64_t, const int*, const int*, const zd*, const zd*, int64_t,
                                      const zd*, zd*, double*, int);
-template hipError_t cholqr_first<double>(hipStream_t, int, const double*, double*, double*, Ctl*);
-template hipError_t cholqr_first<zd>(hipStream_t, int, const zd*, zd*, zd*, Ctl*);
-template hipError_t cholqr_second<double>(hipStream_t, int, const double*, const double*, double*, double*, int, Ctl*);
-template hipError_t cholqr_second<zd>(hipStream_t, int, const zd*, const zd*, zd*, zd*, int, Ctl*);
+template hipError_t cholqr_first<double>(hipStream_t, int, const double*, double*, double*, int, Ctl*);
+template hipError_t cholqr_first<zd>(hipStream_t, int, const zd*, zd*, zd*, int, Ctl*);
+template hipError_t cholqr_second<double>(hipStream_t, int, const double*, const double*, double*, double*, int, int,
+                                          Ctl*);
+template hipError_t cholqr_second<zd>(hipStream_t, int, const zd*, const zd*, zd*, zd*, int, int, Ctl*);
 template hipError_t step_small<double>(hipStream_t, int, const double*, const double*, const double*, int, int, int,
                                        double*, double*, double*, double*, double*, double*, double*, Ctl*, double);
 template hipError_t step_small<zd>(hipStream_t, int, const zd*, const zd*, const zd*, int, int, int, zd*, zd*, zd*,
@@ -848,6 +916,11 @@ template hipError_t copy_block<double, double>(hipStream_t, int64_t, int, const 
 template hipError_t copy_block<zd, zd>(hipStream_t, int64_t, int, const zd*, int64_t, zd*, int64_t, int);
 template hipError_t copy_block<float, double>(hipStream_t, int64_t, int, const float*, int64_t, double*, int64_t, int);
 template hipError_t copy_block<double, float>(hipStream_t, int64_t, int, const double*, int64_t, float*, int64_t, int);
+template hipError_t zero_cols<double>(hipStream_t, double*, int, int, int);
+template hipError_t zero_cols<zd>(hipStream_t, zd*, int, int, int);
+template hipError_t fill_enlarging<double>(hipStream_t, double*, int64_t, int, int, uint64_t);
+template hipError_t fill_enlarging<float>(hipStream_t, float*, int64_t, int, int, uint64_t);
+template hipError_t fill_enlarging<zd>(hipStream_t, zd*, int64_t, int, int, uint64_t);
 template hipError_t copy_block<bf16, double>(hipStream_t, int64_t, int, const bf16*, int64_t, double*, int64_t, int);
 template hipError_t copy_block<double, bf16>(hipStream_t, int64_t, int, const double*, int64_t, bf16*, int64_t, int);
 

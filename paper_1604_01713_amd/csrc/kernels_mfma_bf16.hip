@@ -19,6 +19,11 @@ template hipError_t mfma_proj_gram<float, bf16, bf16>(hipStream_t, int, int64_t,
                                                       const double*, bf16*, double*, const Ctl*, int, const double*,
                                                       int);
 
+// R - C T with C in BF16 (enlarged start block projected against C)
+template hipError_t mfma_proj_gram<float, bf16, float>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int,
+                                                       const double*, float*, double*, const Ctl*, int, const double*,
+                                                       int);
+
 template hipError_t mfma_combine<bf16, double>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int,
                                                const double*, int, int);
 template hipError_t mfma_combine<bf16, float>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int,

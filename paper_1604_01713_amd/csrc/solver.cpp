@@ -50,10 +50,16 @@ struct Fail {
         if (e_ != hipSuccess) throw Fail{BGCR_ERR_HIP};  \
     } while (0)
 
+// block size of the Krylov basis: p, or the enlarged size for p = 1
+int block_of(const bgcr_params* prm) { return prm->block_size > 0 ? prm->block_size : prm->p; }
+
 bool valid_params(const bgcr_params* prm, int64_t n) {
     if (!prm || n <= 0) return false;
-    const int p = prm->p;
-    if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16)) return false;
+    const int pu = prm->p;
+    if (!(pu == 1 || pu == 2 || pu == 4 || pu == 8 || pu == 16)) return false;
+    const int bs = prm->block_size;
+    if (bs != 0 && bs != pu && !(pu == 1 && (bs == 2 || bs == 4 || bs == 8 || bs == 16))) return false;
+    const int p = block_of(prm);
     if (prm->m < 1 || prm->m > 64 || prm->k < 0 || prm->k > 128) return false;
     if (prm->dtype != BGCR_F64 && prm->dtype != BGCR_C128) return false;
     if (prm->precision != BGCR_PLAIN_FP64 && prm->precision != BGCR_MIXED_FP32 &&
@@ -62,7 +68,7 @@ bool valid_params(const bgcr_params* prm, int64_t n) {
     if (prm->dtype == BGCR_C128 && prm->precision != BGCR_PLAIN_FP64) return false;
     // BF16 basis storage runs on the matrix-core sweeps only (P = 8 or 16)
     if (prm->precision == BGCR_MIXED_FP32_BF16 && !(p == 8 || p == 16)) return false;
-    if (prm->max_cycles < 1 || prm->reserved != 0) return false;
+    if (prm->max_cycles < 1) return false;
     const int KB = (prm->k + (prm->dtype == BGCR_F64 ? 1 : 0) + p - 1) / p;
     if (KB + prm->m + 1 > MAXB) return false;
     if ((KB + prm->m) * p * p > MAXI * NT) return false;
@@ -86,7 +92,7 @@ size_t part_outputs(int P, int KB, int qmax) {
 
 Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     Sizes z;
-    z.P = prm->p;
+    z.P = block_of(prm);
     z.m = prm->m;
     z.k = prm->k;
     const bool cplx = prm->dtype == BGCR_C128;
@@ -106,8 +112,9 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
                        m1p * z.P + (size_t)(z.m + 1) * z.P * z.P + 2 * (size_t)z.P * z.P +
                        (size_t)(2 * z.KB + z.m + 1) * z.P * (2 * std::max(z.KP, z.P) + 2 * z.P)) +
                sizeof(double) * ((size_t)z.m + (size_t)NWG_MAX * 2 * z.P) + sizeof(Ctl);
-    z.total_fixed = z.basis + 3 * (size_t)n * z.P * z.sw /* W2, Wb, R */ + (size_t)n * z.P * z.sa /* X */ + z.recyc +
-                    z.part + z.small_;
+    const bool enlarged = z.P > prm->p;
+    z.total_fixed = z.basis + 3 * (size_t)n * z.P * z.sw /* W2, Wb, R */ +
+                    (size_t)n * z.P * z.sa * (enlarged ? 2 : 1) /* X (and B padded) */ + z.recyc + z.part + z.small_;
     return z;
 }
 
@@ -125,6 +132,7 @@ struct Seq final : bgcr_sequence {
     bgcr_params prm;
     int64_t n;
     int P, m, k, KB, KP, nwg;
+    int pu = 0;  // right-hand sides of the caller (P > pu: enlarged block, pu = 1)
     int nwg_mx = 0;      // workgroups of the matrix-core sweeps (64-row tiles)
     bool use_mx = false; // Arnoldi sweeps on matrix cores
     bool mixed, cplx;
@@ -136,6 +144,7 @@ struct Seq final : bgcr_sequence {
     TB* Ub[2] = {nullptr, nullptr};
     TB* Cb[2] = {nullptr, nullptr};
     A* X = nullptr;
+    A* Bpad = nullptr;  // B padded to P columns (enlarged block)
     float* av32 = nullptr;
     size_t av32_cap = 0;
     A* dots = nullptr;
@@ -235,7 +244,8 @@ struct Seq final : bgcr_sequence {
     }
 
     Seq(const bgcr_params* p_, int64_t n_, hipStream_t s_) : prm(*p_), n(n_), st(s_) {
-        P = prm.p;
+        P = block_of(&prm);
+        pu = prm.p;
         m = prm.m;
         k = prm.k;
         cplx = prm.dtype == BGCR_C128;
@@ -287,6 +297,7 @@ struct Seq final : bgcr_sequence {
         Wb = dalloc<T>(blk);
         R = dalloc<T>(blk);
         X = dalloc<A>(blk);
+        if (P > pu) Bpad = dalloc<A>(blk);
         for (int i = 0; i < 2; ++i) {
             Ub[i] = dalloc<TB>((size_t)KB * blk);
             Cb[i] = dalloc<TB>((size_t)KB * blk);
@@ -633,9 +644,10 @@ struct Seq final : bgcr_sequence {
     // One restart cycle: CholQR2 of R, m block Arnoldi steps on (I - C C^H) A
     // with BCGS2 + CholQR and the progressive LSQ, then Y (Algorithm 1 loop body).
     // Start of a cycle: cleared H and its triangular factor, and CholQR2 of
-    // the starting block R = V_1 Z (Algorithm 1).  Needs R only, so plain
-    // FP64 queues it before the host solves the previous cycle's refresh.
-    void cycle_prologue() {
+    // the starting block R = V_1 Z (Algorithm 1).  Without an enlarged block
+    // it needs R only, so plain FP64 queues it before the host solves the
+    // previous cycle's refresh.
+    void cycle_prologue(bool withC) {
         const int P2 = P * P;
         // H and its triangularised copy are read below the block subdiagonal
         // (block upper Hessenberg structure): those entries must be zero
@@ -644,15 +656,54 @@ struct Seq final : bgcr_sequence {
         HIPCHK(hipMemsetAsync(Rh, 0, hb, st));
         const double blkb = (double)sizeof(T) * n * P;
         const int nr = use_mx ? nwg_mx : nwg;
-        run(BGCR_K_TSDOT, blkb, [&] {
-            if constexpr (!std::is_same<T, zd>::value) {
-                if (use_mx) return mfma_proj_gram<T, T, T>(st, P, n, R, bp({}), 0, nullptr, nullptr, part, nullptr, nr);
-            }
-            return L::update_dot(st, P, n, R, bp({}), 0, nullptr, nullptr, nullptr, 0, 1, part, nr, nullptr);
-        });
+        // enlarged block (Section 3.1): the start block is (I - C C^H) [r, Z]
+        // with the same L - 1 enlarging vectors Z in every cycle; R's extra
+        // columns hold them (the update of R never touches them: Y has one
+        // column).  r is orthogonal to C already; the projection of Z takes a
+        // dot sweep and an update sweep whose Gram is the first CholQR pass.
+        const bool project_z = P > pu && withC && keff > 0;
+        if (P > pu) HIPCHK(fill_enlarging<T>(st, R, n, P, pu, 0));
+        if (project_z) {
+            std::vector<const void*> qc;
+            for (int b = 0; b < KB; ++b) qc.push_back(cblk(cur, b));
+            const BlockPtrs QC = bp(qc);
+            const double cbytes = (double)sizeof(TB) * n * KP;
+            run(BGCR_K_TSDOT, blkb + cbytes, [&] {  // T = C^H R
+                if constexpr (!std::is_same<T, zd>::value) {
+                    if (use_mx) return mfma_dot<T, T, TB>(st, P, n, bp({R}), 1, QC, KB, part, nullptr, nr);
+                }
+                if constexpr (half) {
+                    return hipErrorNotSupported;
+                } else {
+                    return L::update_dot(st, P, n, R, QC, KB, nullptr, nullptr, nullptr, 1, 0, part, nr, nullptr);
+                }
+            });
+            run(BGCR_K_SMALL, 0.0, [&] {
+                HIPCHK(reduce_partials<A>(st, part, nr, KP * P, nullptr, S1, nullptr));
+                return zero_cols<A>(st, S1, KP, P, pu);
+            });
+            run(BGCR_K_TSDOT, 2.0 * blkb + cbytes, [&] {  // R <- R - C T in place, with its Gram
+                if constexpr (!std::is_same<T, zd>::value) {
+                    if (use_mx) return mfma_proj_gram<T, TB, T>(st, P, n, R, QC, KB, S1, R, part, nullptr, nr);
+                }
+                if constexpr (half) {
+                    return hipErrorNotSupported;
+                } else {
+                    return L::update_dot(st, P, n, R, QC, KB, S1, nullptr, R, 0, 1, part, nr, nullptr);
+                }
+            });
+        } else {
+            run(BGCR_K_TSDOT, blkb, [&] {
+                if constexpr (!std::is_same<T, zd>::value) {
+                    if (use_mx)
+                        return mfma_proj_gram<T, T, T>(st, P, n, R, bp({}), 0, nullptr, nullptr, part, nullptr, nr);
+                }
+                return L::update_dot(st, P, n, R, bp({}), 0, nullptr, nullptr, nullptr, 0, 1, part, nr, nullptr);
+            });
+        }
         run(BGCR_K_SMALL, 0.0, [&] {
             HIPCHK(reduce_partials<A>(st, part, nr, P2, nullptr, Sf, nullptr));
-            return cholqr_first<A>(st, P, Sf, Z1, Z1i, ctl);
+            return cholqr_first<A>(st, P, Sf, Z1, Z1i, pu, ctl);
         });
         run(BGCR_K_TSDOT, 2.0 * blkb, [&] {
             if constexpr (!std::is_same<T, zd>::value) {
@@ -666,13 +717,13 @@ struct Seq final : bgcr_sequence {
         });
         run(BGCR_K_SMALL, 0.0, [&] {
             HIPCHK(reduce_partials<A>(st, part, nr, P2, nullptr, Sf, nullptr));
-            return cholqr_second<A>(st, P, Sf, Z1, RinvAll, g, m, ctl);
+            return cholqr_second<A>(st, P, Sf, Z1, RinvAll, g, m, pu, ctl);
         });
     }
 
     CycleOut cycle(const bgcr_csr* Am, const T* avT, bool withC, double thresh, bool prologue_done = false) {
         const int P2 = P * P;
-        if (!prologue_done) cycle_prologue();
+        if (!prologue_done) cycle_prologue(withC);
         const double sT = (double)sizeof(T), blkb = sT * (double)n * P;
         const double sB = (double)sizeof(TB), vblkb = sB * (double)n * P;  // basis scalar, basis block
         const int ncb = withC ? KB : 0;
@@ -1146,11 +1197,17 @@ struct Seq final : bgcr_sequence {
         int status = BGCR_OK;
         double rel = 0.0, relmax = 0.0;
         try {
-            if (!Am || !Bv || !Xv || Am->n != n || !Am->row_ptr || !Am->col_idx || !Am->values || ldb < P ||
-                ldx < P || !(tol > 0.0) || Am->nnz < 0)
+            if (!Am || !Bv || !Xv || Am->n != n || !Am->row_ptr || !Am->col_idx || !Am->values || ldb < pu ||
+                ldx < pu || !(tol > 0.0) || Am->nnz < 0)
                 throw Fail{BGCR_ERR_INVALID};
             const A* B = (const A*)Bv;
             A* Xu = (A*)Xv;
+            if (P > pu) {
+                // enlarged block: B and X padded with zero columns to the block size
+                HIPCHK(copy_block<A, A>(st, n, pu, B, ldb, Bpad, P, P));
+                B = Bpad;
+                ldb = P;
+            }
             const T* avT = (const T*)Am->values;
             if (mixed) {
                 if ((size_t)Am->nnz > av32_cap) {
@@ -1165,7 +1222,7 @@ struct Seq final : bgcr_sequence {
                 HIPCHK(cast_values(st, (const double*)Am->values, av32, Am->nnz));
                 avT = (const T*)av32;
             }
-            HIPCHK(copy_block<A, A>(st, n, P, Xu, ldx, X, P, P));
+            HIPCHK(copy_block<A, A>(st, n, pu, Xu, ldx, X, P, P));
             std::vector<double> rn2, bn2;
             residual_norms(Am, B, ldb, R, rn2, bn2);
             double bn = 0.0, rn = 0.0;
@@ -1198,7 +1255,7 @@ struct Seq final : bgcr_sequence {
                         status = run_mixed(Am, avT, B, ldb, thresh, rn2, bn2, finish_norms);
                 }
             }
-            HIPCHK(copy_block<A, A>(st, n, P, X, P, Xu, ldx, P));
+            HIPCHK(copy_block<A, A>(st, n, pu, X, P, Xu, ldx, pu));
             sync();
             if (!std::isfinite(rel)) status = BGCR_ERR_NONFINITE;
         } catch (const Fail& f) {
@@ -1232,9 +1289,10 @@ struct Seq final : bgcr_sequence {
             residual_enqueue(Am, B, ldb, nullptr);
             queued = true;
             // the prologue writes the start block into W2, which off matrix
-            // cores still holds V_{m+1} for the refresh: there it waits
-            if (use_mx) {
-                cycle_prologue();  // wasted once per system, on the converged cycle
+            // cores still holds V_{m+1} for the refresh, and an enlarged start
+            // block is projected against the refreshed C: there it waits
+            if (use_mx && P == pu) {
+                cycle_prologue(false);  // wasted once per system, on the converged cycle
                 prologued = true;
             }
         };

@@ -180,56 +180,73 @@ __device__ inline void xcd_tiles(int64_t ntiles, int64_t& first, int64_t& step, 
     }
 }
 
-// raw[0..C-1] = sum over row `rowc` of A of a_rk Vin[k][c0 .. c0 + C - 1].
+// raw[r][0..C-1] = sum over row rowc[r] of A of a_rk Vin[k][c0 .. c0 + C - 1]
+// for RR rows at once, their loads issued together (measured: two rows per
+// lane are no faster than one on the 7-point stencil; both kernels use one).
 // Nonzeros are taken in batches of NB = 8 with indices clamped to nzl =
 // nnz - 1 and padding entries cancelled by a 0/1 factor; with SHARE (4 lanes
 // per row, `prt` the lane's position) each lane loads 2 entries of a batch
 // and the batch is assembled by quad broadcasts.
-template <class T, class TI, int P, int C, bool SHARE>
-__device__ inline void row_product(T (&raw)[C], const int* __restrict__ rp, const int* __restrict__ ci,
-                                   const T* __restrict__ av, const TI* __restrict__ Vin, int64_t rowc, int prt, int c0,
-                                   int64_t nzl) {
+template <class T, class TI, int P, int C, bool SHARE, int RR>
+__device__ inline void row_product(T (&raw)[RR][C], const int* __restrict__ rp, const int* __restrict__ ci,
+                                   const T* __restrict__ av, const TI* __restrict__ Vin, const int64_t (&rowc)[RR],
+                                   int prt, int c0, int64_t nzl) {
     using R = typename std::conditional<std::is_same<T, zd>::value, double, T>::type;  // real scalar of T
     constexpr int NB = 8;
+    int beg[RR], e[RR], len = 0;
 #pragma unroll
-    for (int j = 0; j < C; ++j) raw[j] = tzero<T>();
-    const int beg = __builtin_nontemporal_load(rp + rowc), e = __builtin_nontemporal_load(rp + rowc + 1);
-    for (int kb = beg; kb < e; kb += NB) {
-        int cols[NB];
-        T vals[NB];
-        if constexpr (SHARE) {
-            int mc[2];
-            T mv[2];
+    for (int r = 0; r < RR; ++r) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int64_t kk = (int64_t)kb + 2 * prt + h < nzl ? (int64_t)kb + 2 * prt + h : nzl;
-                mc[h] = __builtin_nontemporal_load(ci + kk);
-                mv[h] = ld_nt(av + kk);
-            }
+        for (int j = 0; j < C; ++j) raw[r][j] = tzero<T>();
+        beg[r] = __builtin_nontemporal_load(rp + rowc[r]);
+        e[r] = __builtin_nontemporal_load(rp + rowc[r] + 1);
+    }
 #pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                cols[u] = quad_bcast(mc[u & 1], u >> 1);
-                vals[u] = quad_bcast(mv[u & 1], u >> 1);
-            }
-        } else {
+    for (int r = 0; r < RR; ++r) len = e[r] - beg[r] > len ? e[r] - beg[r] : len;
+    for (int kb0 = 0; kb0 < len; kb0 += NB) {
+        int cols[RR][NB];
+        T vals[RR][NB];
 #pragma unroll
-            for (int u = 0; u < NB; ++u) {
-                const int64_t kk = (int64_t)kb + u < nzl ? (int64_t)kb + u : nzl;
-                cols[u] = __builtin_nontemporal_load(ci + kk);
-                vals[u] = ld_nt(av + kk);
+        for (int r = 0; r < RR; ++r) {
+            const int kb = beg[r] + kb0;
+            if constexpr (SHARE) {
+                int mc[2];
+                T mv[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int64_t kk = (int64_t)kb + 2 * prt + h < nzl ? (int64_t)kb + 2 * prt + h : nzl;
+                    mc[h] = __builtin_nontemporal_load(ci + kk);
+                    mv[h] = ld_nt(av + kk);
+                }
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    cols[r][u] = quad_bcast(mc[u & 1], u >> 1);
+                    vals[r][u] = quad_bcast(mv[u & 1], u >> 1);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    const int64_t kk = (int64_t)kb + u < nzl ? (int64_t)kb + u : nzl;
+                    cols[r][u] = __builtin_nontemporal_load(ci + kk);
+                    vals[r][u] = ld_nt(av + kk);
+                }
             }
         }
         // all gathers of the batch are issued before the first product, so
         // that their latencies overlap
-        T g[NB][C];
+        T g[RR][NB][C];
 #pragma unroll
-        for (int u = 0; u < NB; ++u) load_as<T, TI, C, P>(g[u], Vin + (int64_t)cols[u] * P + c0);
+        for (int r = 0; r < RR; ++r)
 #pragma unroll
-        for (int u = 0; u < NB; ++u) {
-            const T a = mscale(vals[u], (R)(kb + u < e ? 1 : 0));
+            for (int u = 0; u < NB; ++u) load_as<T, TI, C, P>(g[r][u], Vin + (int64_t)cols[r][u] * P + c0);
 #pragma unroll
-            for (int j = 0; j < C; ++j) raw[j] += a * g[u][j];
-        }
+        for (int r = 0; r < RR; ++r)
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const T a = mscale(vals[r][u], (R)(beg[r] + kb0 + u < e[r] ? 1 : 0));
+#pragma unroll
+                for (int j = 0; j < C; ++j) raw[r][j] += a * g[r][u][j];
+            }
     }
 }
 
@@ -291,11 +308,11 @@ __global__ __launch_bounds__(256) void k_spmm_rinv(int64_t n, int64_t nnz, const
     // (with nnz = 0 every row is empty and no index is loaded)
     for (int64_t tile = first; tile < end; tile += step) {
         const int64_t row = tile * ROWS + r;
-        const int64_t rowc = clamp_row(row, n);
-        T raw[C], vb[C];
-        if constexpr (SCALE) load_as<T, TI, C, P>(vb, Vin + rowc * P + c0);
-        row_product<T, TI, P, C, SHARE>(raw, rp, ci, av, Vin, rowc, part, c0, nzl);
-        finish(raw, vb, row);
+        const int64_t rowc[1] = {clamp_row(row, n)};
+        T raw[1][C], vb[C];
+        if constexpr (SCALE) load_as<T, TI, C, P>(vb, Vin + rowc[0] * P + c0);
+        row_product<T, TI, P, C, SHARE, 1>(raw, rp, ci, av, Vin, rowc, part, c0, nzl);
+        finish(raw[0], vb, row);
     }
 }
 
@@ -320,15 +337,16 @@ __global__ __launch_bounds__(256) void k_residual_rows(int64_t n, int64_t nnz, c
     for (int64_t tile = first; tile < end; tile += step) {
         const int64_t row = tile * ROWS + r;
         const int64_t rowc = clamp_row(row, n);
-        TA ax[C], bv[C];
-        row_product<TA, TA, P, C, SHARE>(ax, rp, ci, av, X, rowc, prt, c0, nzl);
+        TA ax[1][C], bv[C];
+        const int64_t rows1[1] = {rowc};
+        row_product<TA, TA, P, C, SHARE, 1>(ax, rp, ci, av, X, rows1, prt, c0, nzl);
 #pragma unroll
         for (int j = 0; j < C; ++j) bv[j] = B[rowc * ldb + c0 + j];
         const double f = row < n ? 1.0 : 0.0;  // rows past n count nothing
         TR ro[C];
 #pragma unroll
         for (int j = 0; j < C; ++j) {
-            const TA rv = bv[j] - ax[j];
+            const TA rv = bv[j] - ax[0][j];
             rs[j] += f * absq(rv);
             bs[j] += f * absq(bv[j]);
             ro[j] = narrow<TR>(rv);

@@ -69,6 +69,22 @@ def test_bf16_basis_footprint_and_limits_without_gpu(lib):
         assert lib.bgcr_create_sequence(ctypes.byref(bad), n, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID
 
 
+def test_enlarged_block_parameters_without_gpu(lib):
+    n = 32**3
+    f1 = bg.bgcr_footprint_bytes(bg.bgcr_params(1, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0), n, 7 * n)
+    f8 = bg.bgcr_footprint_bytes(bg.bgcr_params(1, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 8), n, 7 * n)
+    assert 0 < f1 < f8   # n x 8 blocks instead of n x 1, plus B padded
+    h = ctypes.c_void_p()
+    for bad in (bg.bgcr_params(1, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 3),
+                bg.bgcr_params(2, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 8),
+                bg.bgcr_params(1, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 32)):
+        assert bg.bgcr_footprint_bytes(bad, n, 7 * n) == 0
+        assert lib.bgcr_create_sequence(ctypes.byref(bad), n, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID
+    same = bg.bgcr_params(4, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 4)   # block_size = p: no enlargement
+    assert bg.bgcr_footprint_bytes(same, n, 7 * n) == bg.bgcr_footprint_bytes(
+        bg.bgcr_params(4, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0), n, 7 * n)
+
+
 def test_invalid_arguments_are_rejected_without_a_gpu(lib):
     h = ctypes.c_void_p()
     assert lib.bgcr_create_sequence(None, 10, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID

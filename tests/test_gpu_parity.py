@@ -29,14 +29,15 @@ def _dev():
     return torch.device("cuda:0")
 
 
-def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=1000, select_largest=False):
+def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=1000, select_largest=False,
+                  block_size=0):
     bg = _bg()
     dev = _dev()
     n = systems[0][0].shape[0]
     cplx = np.iscomplexobj(systems[0][1]) or np.iscomplexobj(systems[0][0].data)
     dt = bg.BGCR_C128 if cplx else bg.BGCR_F64
     seq = bg.Sequence(n, p, m, k, dtype=dt, precision=precision, max_cycles=max_cycles,
-                      select_largest=select_largest)
+                      select_largest=select_largest, block_size=block_size)
     out = []
     for (A, B, X0) in systems:
         Ad = bg.DeviceCSR.from_scipy(A, dev)
@@ -197,6 +198,32 @@ def test_select_largest_matches_oracle():
         assert rg <= w.tol * 1.0001
         assert rel <= PARITY
         assert abs(st["cycles"] - so["cycles"]) <= 1
+    seq.release()
+
+
+@pytest.mark.parametrize("L,precision", [(4, 0), (8, 0), (16, 0), (8, 1)])
+def test_enlarged_block_matches_oracle(L, precision):
+    """One right-hand side with the block enlarged to L (Section 3.1, eq.
+    1rhs-block-gmres-min); both sides draw the same SplitMix64 enlarging
+    vectors, so the cycle counts agree with the oracle's."""
+    w = problems.cfg2(N=13, nsys=2, p=1, m=6, k=10)
+    tol = w.tol if precision == 0 else 1e-10
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    seq, gpu = _run_sequence(systems, 1, w.m, w.k, tol, precision=precision, block_size=L)
+    orc, _ = oracle.solve_sequence(systems, tol, w.m, w.k, block_size=L)
+    orc1, _ = oracle.solve_sequence(systems, tol, w.m, w.k)
+    for i, ((Xg, st, log), (Xo, so)) in enumerate(zip(gpu, orc)):
+        A, B, _ = systems[i]
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+        print(f"enlarged L={L} prec={precision} sys{i}: gpu cycles={st['cycles']} relres={rg:.2e} | "
+              f"oracle cycles={so['cycles']} (L=1: {orc1[i][1]['cycles']}) | rel diff={rel:.2e}", flush=True)
+        assert st["status"] == 0
+        assert Xg.shape == B.shape
+        assert rg <= tol * 1.0001
+        assert rel <= PARITY
+        if precision == 0:
+            assert abs(st["cycles"] - so["cycles"]) <= 1
     seq.release()
 
 
