@@ -149,6 +149,50 @@ def bench_precision(args, torch, problems, bg, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_enlarged(args, torch, problems, bg, dev):
+    """One right-hand side per system (p = 1) on the headline sequence's
+    matrices: block size 1 (single-vector GCRO-DR) against enlarged blocks
+    L = 8 and 16 (Section 3.1), same tolerance, recycling across the sequence."""
+    nsys = args.nsys if args.nsys != 10 else 4
+    w = problems.cfg2(N=args.grid, nsys=nsys, p=1)
+    systems = [(s_.A, s_.B) for s_ in w.systems]
+    n, nnz = systems[0][0].shape[0], systems[0][0].nnz
+    log(f"[bench] enlarged: {nsys} systems n={n} nnz={nnz} p=1 m={w.m} k={w.k} tol={w.tol}")
+    dA = [bg.DeviceCSR.from_scipy(A, dev) for (A, _) in systems]
+    dB = [torch.from_numpy(B).to(dev) for (_, B) in systems]
+    out = {}
+    for L in (1, 8, 16):
+        seq = bg.Sequence(n, 1, w.m, w.k, max_cycles=20000, block_size=L)
+        seq.set_profiling(True)
+        dX = [torch.zeros_like(b) for b in dB]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc, steps = [], []
+        for i in range(nsys):
+            st = seq.solve(dA[i], dB[i], dX[i], w.tol)
+            if st.status != 0:
+                raise RuntimeError(f"L={L} system {i}: {st.as_dict()}")
+            cyc.append(st.cycles)
+            steps.append(st.block_steps)
+            log(f"[bench] L={L} system {i}: cycles={st.cycles} block steps={st.block_steps}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = seq.profile()
+        seq.release()
+        worst = max(_host_check(A, B, x.cpu().numpy()) for (A, B), x in zip(systems, dX))
+        arn = [c for c in ("arn_spmm", "arn_dot", "proj_dot", "proj_gram")]
+        ms = sum(prof[c]["ms"] for c in arn)
+        by = sum(prof[c]["bytes"] for c in arn)
+        out[f"L{L}"] = {"systems_per_s": round(nsys / el, 4), "seconds": round(el, 2), "cycles_per_system": cyc,
+                        "block_steps_per_system": steps, "max_rel_res_fp64_check": worst,
+                        "arnoldi_hbm_GBs": round(by / ms / 1e6, 1) if ms > 0 else None}
+    res = {"metric": "systems/s with one right-hand side: block size 1 vs enlarged blocks", "unit": "systems/s",
+           "config": {"workload": f"convdiff3d_{args.grid}^3_seq{nsys}_p1_m{w.m}_k{w.k}", "n": n, "nnz": nnz,
+                      "tol": w.tol},
+           "data": "synthetic", "n_gpus": 1, **out}
+    print(json.dumps(res), flush=True)
+
+
 def bench_serving(args, torch, problems, bg, dev):
     """A seeded request stream: serial plain FP64 (one request after the other)
     vs the served form (continuous batching, HBM-budget admission)."""
@@ -237,9 +281,10 @@ def main():
     ap.add_argument("--nsys", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
-    ap.add_argument("--workload", choices=["cfg2", "precision", "serving"], default="cfg2",
+    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged"], default="cfg2",
                     help="cfg2: the headline sequence (default); precision: plain FP64 vs the FP32-in-FP64 form on "
-                         "the anisotropic 192^3 sequence; serving: a request stream, served vs serial")
+                         "the anisotropic 192^3 sequence; serving: a request stream, served vs serial; enlarged: one "
+                         "right-hand side, block size 1 vs 8 and 16")
     ap.add_argument("--requests", type=int, default=24, help="serving: number of requests")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (scale factor of the PMC byte counters)")
@@ -261,6 +306,8 @@ def main():
         return bench_precision(args, torch, problems, bg, dev)
     if args.workload == "serving":
         return bench_serving(args, torch, problems, bg, dev)
+    if args.workload == "enlarged":
+        return bench_enlarged(args, torch, problems, bg, dev)
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20
