@@ -315,13 +315,16 @@ def recycle_import(A, U, X, R):
 
 
 def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, trace=False, block_size=None,
-          seed=0):
+          seed=0, enlarged_cycles=None):
     """Algorithm 1 (block RGMRES / block GCRO-DR) for one system A X = B.
 
     Returns (X, U, stats).  stats holds per-cycle block-step counts, the LSQ
     residual history, true relative residuals and (with trace=True) the cycle
     internals used by the pins.  block_size L > 1 with one right-hand side
-    enlarges the block with enlarging_vectors(n, L, seed).
+    enlarges the block with enlarging_vectors(n, L, seed).  enlarged_cycles:
+    with an enlarged block, only the first enlarged_cycles cycles of this
+    call use it and every later cycle is non-block (L = 1), the hybrid of
+    Section 4.1.3; None: every cycle uses it.
     """
     A = A.tocsr() if hasattr(A, "tocsr") else A
     B = np.asarray(B)
@@ -349,11 +352,16 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
     if np.linalg.norm(R) <= thresh:
         stats["rel_res"] = float(np.linalg.norm(R)) / bn
         return X, U, stats
+    def extra_now():
+        if enlarged_cycles is None or stats["cycles"] < enlarged_cycles:
+            return extra
+        return None
+
     C = None
     if U is not None:
         U, C, X, R = recycle_import(A, U.astype(dt), X, R)
     else:
-        cyc = block_arnoldi_cycle(A, R, None, m, thresh, extra)
+        cyc = block_arnoldi_cycle(A, R, None, m, thresh, extra_now())
         me = cyc["m_eff"]
         Wm = np.hstack(cyc["V"][:me])
         Wm1 = np.hstack(cyc["V"])
@@ -366,7 +374,7 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
         if np.linalg.norm(Rt) <= thresh or stats["cycles"] >= max_cycles:
             break
         Uold, Cold = U, C
-        cyc = block_arnoldi_cycle(A, R, C, m, thresh, extra)
+        cyc = block_arnoldi_cycle(A, R, C, m, thresh, extra_now())
         me = cyc["m_eff"]
         Wm = np.hstack(cyc["V"][:me])
         Wm1 = np.hstack(cyc["V"])
@@ -394,18 +402,29 @@ def _log(stats, cyc, A, B, X, R, bn, trace, U, C, Uold=None, Cold=None):
     stats["true_rel_res"].append(float(np.linalg.norm(Rt)) / bn)
     stats["recur_drift"].append(float(np.linalg.norm(R - Rt)) / bn)
     stats["k_eff"].append(0 if U is None else U.shape[1])
+    stats.setdefault("block_size", []).append(cyc["V"][0].shape[1])
     if trace:
         stats["trace"].append({"cyc": cyc, "U": U, "C": C, "U_in": Uold, "C_in": Cold,
                                "X": X.copy(), "R": R.copy()})
 
 
-def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False, block_size=None, seed=0):
+def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False, block_size=None, seed=0,
+                   enlarge_cycles=None):
     """Solve a sequence A^[i] X = B^[i], carrying U from each system to the next
-    (Algorithm 1, last line).  `systems` is a list of (A, B, X0)."""
+    (Algorithm 1, last line).  `systems` is a list of (A, B, X0).
+    enlarge_cycles (with block_size L > p = 1): the first enlarge_cycles
+    cycles of the whole sequence use the enlarged block, every later cycle
+    L = 1 (Section 4.1.3: inflate the block for the first cycles to obtain a
+    good recycled space quickly, then switch at a restart to non-block
+    GCRO-DR); None: every cycle is enlarged."""
     U = None
     out = []
+    left = enlarge_cycles
     for (A, B, X0) in systems:
         X, U, st = solve(A, B, X0, tol, m, k, U=U, max_cycles=max_cycles,
-                         select_largest=select_largest, block_size=block_size, seed=seed)
+                         select_largest=select_largest, block_size=block_size, seed=seed,
+                         enlarged_cycles=left)
+        if left is not None:
+            left = max(0, left - st["cycles"])
         out.append((X, st))
     return out, U

@@ -230,6 +230,60 @@ def test_enlarged_block_basis_is_orthogonal_to_C():
         assert np.linalg.norm(Wm1.conj().T @ Wm1 - np.eye(Wm1.shape[1])) < 1e-12
 
 
+def _augmented_min_residual(Ad, U, C, r, Z, m):
+    """Brute force: the smallest ||r - A S y|| over S = [U, K], K the Krylov
+    space of (I - C C^H) A from the start block (I - C C^H) [r, Z] (Z may have
+    no columns), built from explicit powers."""
+    proj = (lambda M: M - C @ (C.conj().T @ M)) if C is not None else (lambda M: M)
+    blk = proj(np.hstack([r, Z]))
+    K = [blk]
+    for _ in range(m - 1):
+        K.append(proj(Ad @ K[-1]))
+    S = np.hstack(([U] if U is not None else []) + K)
+    Q, _ = np.linalg.qr(S)
+    z, *_ = np.linalg.lstsq(Ad @ Q, r, rcond=None)
+    return Q @ z
+
+
+def test_hybrid_enlarged_then_single_cycles_are_min_residual():
+    """Section 4.1.3 hybrid: the first cycles of the sequence enlarge the block
+    (p = 1, L = 4), every later one is non-block GCRO-DR.  Each traced cycle's
+    correction equals the brute-force minimiser over span(U) plus the Krylov
+    space of its own block size; the final X matches dense LU."""
+    A, B = _small(N=10, p=1)
+    A2 = (A + 0.05 * sp.identity(A.shape[0])).tocsr()
+    m, k, L, E = 4, 5, 4, 3
+    n = A.shape[0]
+    Z = O.enlarging_vectors(n, L)
+    sizes, checked = [], 0
+    U = None
+    left = E
+    for Ai, Bi in ((A, B), (A2, B[::-1].copy())):
+        Ad = Ai.toarray()
+        X, U, st = O.solve(Ai, Bi, np.zeros_like(Bi), 1e-10, m, k, U=U, block_size=L, trace=True,
+                           enlarged_cycles=left)
+        left = max(0, left - st["cycles"])
+        sizes += st["block_size"]
+        # cycles after the first of a system: the previous trace holds X, R before it
+        for prev, tr in zip(st["trace"], st["trace"][1:]):
+            r = Bi - Ad @ prev["X"]
+            Lc = tr["cyc"]["V"][0].shape[1]
+            d = _augmented_min_residual(Ad, tr["U_in"], tr["C_in"], r, Z if Lc == L else Z[:, :0], m)
+            if tr["cyc"]["m_eff"] == m:
+                # relative to the correction, plus rounding of X itself
+                tol_d = 1e-8 * np.linalg.norm(d) + 1e-13 * np.linalg.norm(tr["X"])
+                assert np.linalg.norm(tr["X"] - prev["X"] - d) < tol_d
+                checked += 1
+        Xd = np.linalg.solve(Ad, Bi)
+        assert np.linalg.norm(X - Xd) <= 1e-8 * np.linalg.norm(Xd)
+    assert sizes[:E] == [L] * E and all(b == 1 for b in sizes[E:]) and len(sizes) > E
+    assert checked >= 3
+    # the sequence driver counts the enlarged cycles over the whole sequence
+    out, _ = O.solve_sequence([(A, B, np.zeros_like(B)), (A2, B[::-1].copy(), np.zeros_like(B))], 1e-10, m, k,
+                              block_size=L, enlarge_cycles=E)
+    assert sum((st["block_size"] for _, st in out), []) == sizes
+
+
 # ---- P10: harmonic Ritz ----------------------------------------------------
 
 def _toeplitz_tridiag(n, a, b, c):
