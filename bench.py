@@ -152,7 +152,10 @@ def bench_precision(args, torch, problems, bg, dev):
 def bench_enlarged(args, torch, problems, bg, dev):
     """One right-hand side per system (p = 1) on the headline sequence's
     matrices: block size 1 (single-vector GCRO-DR) against enlarged blocks
-    L = 8 and 16 (Section 3.1), same tolerance, recycling across the sequence."""
+    L = 8 and 16 (Section 3.1), same tolerance, recycling across the sequence;
+    then the hybrid of Section 4.1.3 (L = 8 for the first E cycles of the
+    sequence, L = 1 after), with E half and all of the first system's cycles
+    at L = 8."""
     nsys = args.nsys if args.nsys != 10 else 4
     w = problems.cfg2(N=args.grid, nsys=nsys, p=1)
     systems = [(s_.A, s_.B) for s_ in w.systems]
@@ -161,8 +164,13 @@ def bench_enlarged(args, torch, problems, bg, dev):
     dA = [bg.DeviceCSR.from_scipy(A, dev) for (A, _) in systems]
     dB = [torch.from_numpy(B).to(dev) for (_, B) in systems]
     out = {}
-    for L in (1, 8, 16):
-        seq = bg.Sequence(n, 1, w.m, w.k, max_cycles=20000, block_size=L)
+    runs = [(1, 0), (8, 0), (16, 0), (8, "half"), (8, "all")]
+    for L, E in runs:
+        if E in ("half", "all"):
+            c0 = out["L8"]["cycles_per_system"][0]
+            E = max(1, c0 // 2) if E == "half" else c0
+        name = f"L{L}" + (f"_E{E}" if E else "")
+        seq = bg.Sequence(n, 1, w.m, w.k, max_cycles=20000, block_size=L, enlarge_cycles=E)
         seq.set_profiling(True)
         dX = [torch.zeros_like(b) for b in dB]
         torch.cuda.synchronize()
@@ -171,10 +179,10 @@ def bench_enlarged(args, torch, problems, bg, dev):
         for i in range(nsys):
             st = seq.solve(dA[i], dB[i], dX[i], w.tol)
             if st.status != 0:
-                raise RuntimeError(f"L={L} system {i}: {st.as_dict()}")
+                raise RuntimeError(f"{name} system {i}: {st.as_dict()}")
             cyc.append(st.cycles)
             steps.append(st.block_steps)
-            log(f"[bench] L={L} system {i}: cycles={st.cycles} block steps={st.block_steps}")
+            log(f"[bench] {name} system {i}: cycles={st.cycles} block steps={st.block_steps}")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         prof = seq.profile()
@@ -183,10 +191,11 @@ def bench_enlarged(args, torch, problems, bg, dev):
         arn = [c for c in ("arn_spmm", "arn_dot", "proj_dot", "proj_gram")]
         ms = sum(prof[c]["ms"] for c in arn)
         by = sum(prof[c]["bytes"] for c in arn)
-        out[f"L{L}"] = {"systems_per_s": round(nsys / el, 4), "seconds": round(el, 2), "cycles_per_system": cyc,
+        out[name] = {"systems_per_s": round(nsys / el, 4), "seconds": round(el, 2), "cycles_per_system": cyc,
                         "block_steps_per_system": steps, "max_rel_res_fp64_check": worst,
                         "arnoldi_hbm_GBs": round(by / ms / 1e6, 1) if ms > 0 else None}
-    res = {"metric": "systems/s with one right-hand side: block size 1 vs enlarged blocks", "unit": "systems/s",
+    res = {"metric": "systems/s with one right-hand side: block size 1 vs enlarged blocks (and the hybrid "
+                     "switching to 1 after E cycles)", "unit": "systems/s",
            "config": {"workload": f"convdiff3d_{args.grid}^3_seq{nsys}_p1_m{w.m}_k{w.k}", "n": n, "nnz": nnz,
                       "tol": w.tol},
            "data": "synthetic", "n_gpus": 1, **out}

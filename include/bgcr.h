@@ -77,6 +77,14 @@ typedef struct {
                                 i + 2^40 c, mapped to [-1, 1)), and minimises the
                                 single residual; U, C and the basis are n x L blocks,
                                 B and X stay n x 1.  Other values: BGCR_ERR_INVALID */
+    int32_t enlarge_cycles;  /* hybrid of Section 4.1.3 (needs an enlarged block,
+                                block_size > p = 1): the first enlarge_cycles
+                                restart cycles of the sequence, counted over all its
+                                solves, use block size L and every later cycle is
+                                non-block GCRO-DR (L = 1); at the switch the
+                                recycled U is handed to the L = 1 basis and imported
+                                there (A U = C S).  0: every cycle uses L.  Not with
+                                BGCR_MIXED_FP32_BF16; negative: BGCR_ERR_INVALID */
 } bgcr_params;
 
 typedef struct {

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <new>
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
@@ -29,6 +30,7 @@ struct bgcr_sequence {
     virtual int recycle_dim() const = 0;
     virtual void set_profiling(int on) = 0;
     virtual void get_profile(double* ms, double* bytes, int64_t* launches, int nclass) const = 0;
+    virtual void set_cycle_limit(int cycles) = 0;  // restart cycles per solve from now on
     std::vector<int> log_steps;
     std::vector<double> log_res;
 };
@@ -69,6 +71,9 @@ bool valid_params(const bgcr_params* prm, int64_t n) {
     // BF16 basis storage runs on the matrix-core sweeps only (P = 8 or 16)
     if (prm->precision == BGCR_MIXED_FP32_BF16 && !(p == 8 || p == 16)) return false;
     if (prm->max_cycles < 1) return false;
+    // the hybrid needs an enlarged block and a basis type the L = 1 basis has
+    if (prm->enlarge_cycles < 0) return false;
+    if (prm->enlarge_cycles > 0 && (p == pu || prm->precision == BGCR_MIXED_FP32_BF16)) return false;
     const int KB = (prm->k + (prm->dtype == BGCR_F64 ? 1 : 0) + p - 1) / p;
     if (KB + prm->m + 1 > MAXB) return false;
     if ((KB + prm->m) * p * p > MAXI * NT) return false;
@@ -1372,6 +1377,8 @@ struct Seq final : bgcr_sequence {
 
     int recycle_dim() const override { return keff; }
 
+    void set_cycle_limit(int cycles) override { prm.max_cycles = std::max(1, cycles); }
+
     void get_profile(double* ms, double* bytes, int64_t* launches, int nclass) const override {
         for (int c = 0; c < nclass && c < BGCR_K_NCLASS; ++c) {
             if (ms) ms[c] = pms[c];
@@ -1422,6 +1429,119 @@ struct Seq final : bgcr_sequence {
 
 // ---------------------------------------------------------------------------
 // C ABI
+namespace {
+
+// ---------------------------------------------------------------------------
+// Hybrid of Section 4.1.3 (p = 1): the first `budget` restart cycles of the
+// sequence run on an enlarged-block sequence (block size L), every later
+// cycle on a non-block one (L = 1); both share the caller's stream.  The
+// switch happens at a restart: the enlarged sequence stops at its cycle
+// limit, X holds its iterate, and the recycled U is handed over (as FP64
+// columns) and imported by the L = 1 sequence at the start of its solve
+// (A U = C S, T = C^H R), which is the identity up to rounding because the
+// refreshed C satisfies C = A U, C^H C = I and C^H R = 0.
+// ---------------------------------------------------------------------------
+struct Hybrid final : bgcr_sequence {
+    bgcr_sequence* big = nullptr;  // block size L
+    bgcr_sequence* one = nullptr;  // block size 1
+    int budget = 0;                // enlarged cycles left in the sequence
+    int max_cycles = 1;
+    bool moved = false;            // the recycled space lives in `one`
+    void* ubuf = nullptr;          // n x ldu FP64 (complex128) columns of U
+    int64_t ldu = 0;
+
+    ~Hybrid() override {
+        delete big;
+        delete one;
+        if (ubuf) (void)hipFree(ubuf);
+    }
+    bgcr_sequence* holder() const { return moved ? one : big; }
+
+    int hand_over() {
+        moved = true;
+        const int ke = big->recycle_dim();
+        if (ke <= 0) return BGCR_OK;
+        const int rc = big->get_recycle(ubuf, nullptr, ldu);
+        return rc != BGCR_OK ? rc : one->set_recycle(ubuf, ldu, ke);
+    }
+
+    int solve(const bgcr_csr* Am, const void* B, int64_t ldb, void* X, int64_t ldx, double tol,
+              bgcr_stats* stt) override {
+        const auto t0 = std::chrono::steady_clock::now();
+        log_steps.clear();
+        log_res.clear();
+        bgcr_stats s1, s2;
+        std::memset(&s1, 0, sizeof(s1));
+        std::memset(&s2, 0, sizeof(s2));
+        int status = BGCR_OK;
+        bool second = false;
+        auto take_log = [&](const bgcr_sequence* q) {
+            log_steps.insert(log_steps.end(), q->log_steps.begin(), q->log_steps.end());
+            log_res.insert(log_res.end(), q->log_res.begin(), q->log_res.end());
+        };
+        bool done = false;
+        if (budget > 0) {
+            big->set_cycle_limit(std::min(max_cycles, budget));
+            status = big->solve(Am, B, ldb, X, ldx, tol, &s1);
+            take_log(big);
+            budget -= s1.cycles;
+            // only a stop at the enlarged cycle limit continues with L = 1
+            done = status != BGCR_NOT_CONVERGED || s1.cycles >= max_cycles || budget > 0;
+        }
+        if (!done) {
+            if (!moved) status = hand_over();
+            if (status == BGCR_OK || status == BGCR_NOT_CONVERGED) {
+                one->set_cycle_limit(max_cycles - s1.cycles);
+                status = one->solve(Am, B, ldb, X, ldx, tol, &s2);
+                take_log(one);
+                second = true;
+            }
+        }
+        if (stt) {
+            *stt = second ? s2 : s1;
+            stt->status = status;
+            stt->cycles = s1.cycles + s2.cycles;
+            stt->block_steps = s1.block_steps + s2.block_steps;
+            stt->spmm_calls = s1.spmm_calls + s2.spmm_calls;
+            stt->alg_bytes = s1.alg_bytes + s2.alg_bytes;
+            stt->refine_steps = s1.refine_steps + s2.refine_steps;
+            stt->k_eff = holder()->recycle_dim();
+            stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return status;
+    }
+    int get_recycle(void* U, void* C, int64_t ld) const override { return holder()->get_recycle(U, C, ld); }
+    int set_recycle(const void* U, int64_t ld, int k_in) override { return holder()->set_recycle(U, ld, k_in); }
+    int recycle_dim() const override { return holder()->recycle_dim(); }
+    void set_profiling(int on) override {
+        big->set_profiling(on);
+        one->set_profiling(on);
+    }
+    void get_profile(double* ms, double* bytes, int64_t* launches, int nclass) const override {
+        const int nc = std::max(0, std::min(nclass, (int)BGCR_K_NCLASS));
+        double m1[BGCR_K_NCLASS] = {}, b1[BGCR_K_NCLASS] = {}, m2[BGCR_K_NCLASS] = {}, b2[BGCR_K_NCLASS] = {};
+        int64_t l1[BGCR_K_NCLASS] = {}, l2[BGCR_K_NCLASS] = {};
+        big->get_profile(m1, b1, l1, nc);
+        one->get_profile(m2, b2, l2, nc);
+        for (int c = 0; c < nc; ++c) {
+            if (ms) ms[c] = m1[c] + m2[c];
+            if (bytes) bytes[c] = b1[c] + b2[c];
+            if (launches) launches[c] = l1[c] + l2[c];
+        }
+    }
+    void set_cycle_limit(int cycles) override { max_cycles = std::max(1, cycles); }
+};
+
+// the two halves of a hybrid: enlarged block without a switch, and L = 1
+void hybrid_parts(const bgcr_params* prm, bgcr_params& big, bgcr_params& one) {
+    big = *prm;
+    big.enlarge_cycles = 0;
+    one = big;
+    one.block_size = 0;
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 extern "C" {
 
@@ -1432,6 +1552,25 @@ int bgcr_create_sequence(const bgcr_params* prm, int64_t n, void* hip_stream, bg
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BGCR_ERR_HIP;
     bgcr_sequence* s = nullptr;
+    if (prm->enlarge_cycles > 0) {
+        bgcr_params pb, p1;
+        hybrid_parts(prm, pb, p1);
+        auto* h = new (std::nothrow) Hybrid();
+        if (!h) return BGCR_ERR_NOMEM;
+        h->budget = prm->enlarge_cycles;
+        h->max_cycles = prm->max_cycles;
+        h->ldu = std::max(1, sizes_of(&pb, n).KP);
+        int rc = bgcr_create_sequence(&pb, n, hip_stream, &h->big);
+        if (rc == BGCR_OK) rc = bgcr_create_sequence(&p1, n, hip_stream, &h->one);
+        if (rc == BGCR_OK && hipMalloc(&h->ubuf, (size_t)n * h->ldu * (prm->dtype == BGCR_C128 ? 16 : 8)) != hipSuccess)
+            rc = BGCR_ERR_NOMEM;
+        if (rc != BGCR_OK) {
+            delete h;
+            return rc;
+        }
+        *out = h;
+        return BGCR_OK;
+    }
     try {
         hipStream_t st = (hipStream_t)hip_stream;
         if (prm->dtype == BGCR_C128) {
@@ -1479,6 +1618,12 @@ int bgcr_release(bgcr_sequence* s) {
 
 size_t bgcr_footprint_bytes(const bgcr_params* prm, int64_t n, int64_t nnz) {
     if (!valid_params(prm, n) || nnz < 0) return 0;
+    if (prm->enlarge_cycles > 0) {
+        bgcr_params pb, p1;
+        hybrid_parts(prm, pb, p1);
+        const size_t ub = (size_t)n * std::max(1, sizes_of(&pb, n).KP) * (prm->dtype == BGCR_C128 ? 16 : 8);
+        return bgcr_footprint_bytes(&pb, n, nnz) + bgcr_footprint_bytes(&p1, n, nnz) + ub;
+    }
     const Sizes z = sizes_of(prm, n);
     size_t b = z.total_fixed;
     if (prm->precision != BGCR_PLAIN_FP64) b += (size_t)nnz * sizeof(float);

@@ -85,6 +85,25 @@ def test_enlarged_block_parameters_without_gpu(lib):
         bg.bgcr_params(4, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0), n, 7 * n)
 
 
+def test_hybrid_parameters_without_gpu(lib):
+    """enlarge_cycles > 0 (Section 4.1.3 hybrid) holds an L-block and an
+    L = 1 sequence plus one n x k' FP64 hand-over buffer; it needs an
+    enlarged block and a basis type the L = 1 sequence has."""
+    n = 32**3
+    P = lambda bs, ec, prec=bg.BGCR_PLAIN_FP64, p=1: bg.bgcr_params(p, 10, 20, bg.BGCR_F64, prec, 100, 0, bs, ec)
+    f1 = bg.bgcr_footprint_bytes(P(0, 0), n, 7 * n)
+    f8 = bg.bgcr_footprint_bytes(P(8, 0), n, 7 * n)
+    fh = bg.bgcr_footprint_bytes(P(8, 3), n, 7 * n)
+    assert fh == f1 + f8 + n * 24 * 8   # ceil(21 / 8) * 8 = 24 hand-over columns
+    fm = bg.bgcr_footprint_bytes(P(8, 3, bg.BGCR_MIXED_FP32), n, 7 * n)
+    assert fm == (bg.bgcr_footprint_bytes(P(0, 0, bg.BGCR_MIXED_FP32), n, 7 * n)
+                  + bg.bgcr_footprint_bytes(P(8, 0, bg.BGCR_MIXED_FP32), n, 7 * n) + n * 24 * 8)
+    h = ctypes.c_void_p()
+    for bad in (P(0, 3), P(1, 3), P(4, 3, p=4), P(8, -1), P(8, 3, bg.BGCR_MIXED_FP32_BF16)):
+        assert bg.bgcr_footprint_bytes(bad, n, 7 * n) == 0
+        assert lib.bgcr_create_sequence(ctypes.byref(bad), n, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID
+
+
 def test_invalid_arguments_are_rejected_without_a_gpu(lib):
     h = ctypes.c_void_p()
     assert lib.bgcr_create_sequence(None, 10, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID

@@ -30,14 +30,14 @@ def _dev():
 
 
 def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=1000, select_largest=False,
-                  block_size=0):
+                  block_size=0, enlarge_cycles=0):
     bg = _bg()
     dev = _dev()
     n = systems[0][0].shape[0]
     cplx = np.iscomplexobj(systems[0][1]) or np.iscomplexobj(systems[0][0].data)
     dt = bg.BGCR_C128 if cplx else bg.BGCR_F64
     seq = bg.Sequence(n, p, m, k, dtype=dt, precision=precision, max_cycles=max_cycles,
-                      select_largest=select_largest, block_size=block_size)
+                      select_largest=select_largest, block_size=block_size, enlarge_cycles=enlarge_cycles)
     out = []
     for (A, B, X0) in systems:
         Ad = bg.DeviceCSR.from_scipy(A, dev)
@@ -224,6 +224,33 @@ def test_enlarged_block_matches_oracle(L, precision):
         assert rel <= PARITY
         if precision == 0:
             assert abs(st["cycles"] - so["cycles"]) <= 1
+    seq.release()
+
+
+@pytest.mark.parametrize("L,precision,E", [(8, 0, 3), (4, 0, 1), (8, 0, 13), (8, 1, 3)])
+def test_hybrid_enlarged_then_single_matches_oracle(L, precision, E):
+    """Section 4.1.3 hybrid: the first E cycles of the sequence use the block
+    enlarged to L, every later one L = 1.  E = 13 puts the switch inside the
+    second system (the first takes 11 cycles), the others inside the first."""
+    w = problems.cfg2(N=13, nsys=3, p=1, m=6, k=10)
+    tol = w.tol if precision == 0 else 1e-10
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    seq, gpu = _run_sequence(systems, 1, w.m, w.k, tol, precision=precision, block_size=L, enlarge_cycles=E)
+    orc, _ = oracle.solve_sequence(systems, tol, w.m, w.k, block_size=L, enlarge_cycles=E)
+    for i, ((Xg, st, log), (Xo, so)) in enumerate(zip(gpu, orc)):
+        A, B, _ = systems[i]
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+        print(f"hybrid L={L} E={E} prec={precision} sys{i}: gpu cycles={st['cycles']} relres={rg:.2e} | "
+              f"oracle cycles={so['cycles']} blocks={so['block_size']} | rel diff={rel:.2e}", flush=True)
+        assert st["status"] == 0
+        assert Xg.shape == B.shape
+        assert rg <= tol * 1.0001
+        assert rel <= PARITY
+        assert len(log[0]) == st["cycles"]
+        if precision == 0:
+            assert abs(st["cycles"] - so["cycles"]) <= 1
+    assert seq.recycle_dim() in (w.k, w.k + 1)
     seq.release()
 
 
