@@ -113,21 +113,27 @@ __device__ inline void write_gram_partials(d4v g, double* red, double* part, int
 }
 
 // Per-lane source of the row-major ("RC") operand: lane l reads column
-// c = 16 ch + l % 16 of [Q_0 .. Q_{nq-1}].  Columns past the last block read
-// block 0 (their dot products are never written).  Block pointers are
-// selected with compile-time indices only (wave-uniform scalar loads).
+// c = 16 ch + l % 16 of [Q_0 .. Q_{nq-1}], i.e. column c % P of block c / P
+// (a 16-column chunk spans 16 / P blocks).  Columns past the last block read
+// block 0 (their dot products are never written).  Block pointers are read
+// with compile-time indices only (wave-uniform scalar loads) and the lane's
+// one is picked by selects, once per kernel.
 template <class T, int P, int NC>
 __device__ inline void rc_pointers(const T* (&qp)[NC], const BlockPtrs& Q, int nq, int lane) {
+    static_assert(P == 1 || P == 2 || P == 4 || P == 8 || P == 16, "block width");
+    constexpr int BPC = 16 / P;  // blocks per 16-column chunk
+    static_assert(NC * BPC <= MAXB, "chunks beyond the block list");
     const int cl = lane & 15;
 #pragma unroll
     for (int ch = 0; ch < NC; ++ch) {
-        if constexpr (P == 16) {
-            qp[ch] = (const T*)(ch < nq ? Q.p[ch] : Q.p[0]) + cl;
-        } else {
-            const T* p0 = (const T*)(2 * ch < nq ? Q.p[2 * ch] : Q.p[0]);
-            const T* p1 = (const T*)(2 * ch + 1 < nq ? Q.p[2 * ch + 1] : Q.p[0]);
-            qp[ch] = ((cl >> 3) ? p1 : p0) + (cl & 7);
+        const T* sel = (const T*)Q.p[0];
+#pragma unroll
+        for (int u = 0; u < BPC; ++u) {
+            const int b = BPC * ch + u;
+            const T* pb = (const T*)(b < nq ? Q.p[b] : Q.p[0]);
+            sel = (cl / P == u) ? pb : sel;
         }
+        qp[ch] = sel + (cl % P);
     }
 }
 
@@ -722,16 +728,20 @@ hipError_t launch_dot(hipStream_t st, int64_t n, const BlockPtrs& W, int nw, con
                       int nwg, const Ctl* ctl) {
     const int nc = (nq * P + 15) / 16, ng = (nw * P + 15) / 16;
     const size_t lds = (size_t)1024 * sizeof(double);
+    // a chunk of narrow blocks spans 16 / P block pointers: at most MAXB in all
+    if (nc * (16 / P) > MAXB || ng * (16 / P) > MAXB) return hipErrorNotSupported;
     if (ng == 1) {
 #define L(NC)                                                                                                      \
-    hipLaunchKernelGGL((k_dot_mfma<T, TW, TQ, P, NC, dot_ks<NC>(), 1>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, part, \
-                       ctl)
+    if constexpr ((NC) * (16 / P) <= MAXB)                                                                         \
+        hipLaunchKernelGGL((k_dot_mfma<T, TW, TQ, P, NC, dot_ks<NC>(), 1>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, \
+                           part, ctl)
         BGCR_MX_NC_DISPATCH(nc, L)
 #undef L
     } else if (ng == 2 && nc <= 9) {
 #define L(NC)                                                                                                      \
-    hipLaunchKernelGGL((k_dot_mfma<T, TW, TQ, P, NC, dot_ks<2 * NC>(), 2>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, \
-                       part, ctl)
+    if constexpr ((NC) * (16 / P) <= MAXB)                                                                         \
+        hipLaunchKernelGGL((k_dot_mfma<T, TW, TQ, P, NC, dot_ks<2 * NC>(), 2>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, \
+                           nq, part, ctl)
         switch (nc) {
             case 1: L(1); break;
             case 2: L(2); break;
@@ -1087,6 +1097,12 @@ hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw
     }
     if (P == 8) return mx::launch_dot<T, TW, TQ, 8>(st, n, W, nw, Q, nq, part, nwg, ctl);
     if (P == 16) return mx::launch_dot<T, TW, TQ, 16>(st, n, W, nw, Q, nq, part, nwg, ctl);
+    // narrow blocks (P < 8, FP64 or FP32 storage): 16 / P blocks per chunk
+    if constexpr (std::is_same<TW, T>::value && std::is_same<TQ, T>::value) {
+        if (P == 1) return mx::launch_dot<T, T, T, 1>(st, n, W, nw, Q, nq, part, nwg, ctl);
+        if (P == 2) return mx::launch_dot<T, T, T, 2>(st, n, W, nw, Q, nq, part, nwg, ctl);
+        if (P == 4) return mx::launch_dot<T, T, T, 4>(st, n, W, nw, Q, nq, part, nwg, ctl);
+    }
     return hipErrorNotSupported;
 }
 

@@ -484,15 +484,19 @@ struct Seq final : bgcr_sequence {
         job.nw = (int)W.size();
         const int nq = job.nq, nw = job.nw;
         // per launch: wg W blocks (32 columns on matrix cores, so that one pass
-        // over a Q chunk serves them all) against a chunk of Q blocks
-        const int wg = use_mx ? std::max(1, 32 / P) : 1;
-        const int nr = use_mx ? nwg_mx : nwg;
+        // over a Q chunk serves them all) against a chunk of Q blocks.  The
+        // matrix-core dot also serves narrow real blocks (P < 8), where a
+        // 16-column chunk spans 16 / P blocks (at most MAXB per launch).
+        const bool mxd = use_mx || (!std::is_same<T, zd>::value && !half && P < 8);
+        const int wg = mxd ? std::max(1, 32 / P) : 1;
+        const int nr = mxd ? nwg_mx : nwg;
         if ((size_t)nq * P * P * nw > dots_cap) throw Fail{BGCR_ERR_INVALID};
         size_t off = 0;
         for (int w0 = 0; w0 < nw; w0 += wg) {
             const int wn = std::min(wg, nw - w0);
             const int ng = (wn * P + 15) / 16;
-            const int chunk = use_mx ? std::max(1, (ng == 2 ? 9 : 16) * 16 / P) : std::max(1, (MAXI * NT) / (P * P));
+            const int chunk = mxd ? std::max(1, std::min((ng == 2 ? 9 : 16) * 16 / P, MAXB))
+                                  : std::max(1, (MAXI * NT) / (P * P));
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = std::min(chunk, nq - q0);
                 const int nout = wn * qn * P * P;
@@ -501,7 +505,7 @@ struct Seq final : bgcr_sequence {
                 std::vector<const void*> ws(W.begin() + w0, W.begin() + w0 + wn);
                 run(BGCR_K_TSDOT, (double)n * P * ((double)sizeof(TW) * wn + (double)sizeof(TB) * qn), [&] {
                     if constexpr (!std::is_same<T, zd>::value) {
-                        if (use_mx) return mfma_dot<T, TW, TB>(st, P, n, bp(ws), wn, bp(sub), qn, part, nullptr, nr);
+                        if (mxd) return mfma_dot<T, TW, TB>(st, P, n, bp(ws), wn, bp(sub), qn, part, nullptr, nr);
                     }
                     if constexpr (half) {
                         return hipErrorNotSupported;
