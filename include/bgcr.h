@@ -61,7 +61,11 @@ typedef struct bgcr_sequence bgcr_sequence;   /* opaque; owns U, C and workspace
 
 typedef struct {
     int32_t p;               /* number of right-hand sides = block size: 1, 2, 4, 8 or 16 */
-    int32_t m;               /* block Arnoldi steps per cycle (1..64) */
+    int32_t m;               /* block Arnoldi steps per cycle (1..64); with KB =
+                                ceil((k+1)/L) blocks of the recycled space (ceil(k/L)
+                                for complex data, L the block size), 2 KB + m + 1 <= 64:
+                                the refresh combines [U, C, V_1 .. V_{m+1}] in one
+                                launch.  Otherwise BGCR_ERR_INVALID */
     int32_t k;               /* recycled dimension (0..128); with real data k+1 columns
                                 are kept when a conjugate pair straddles the cut */
     int32_t dtype;           /* bgcr_dtype */

@@ -1,5 +1,6 @@
 // Matrix-core (MFMA) versions of the three block-Arnoldi sweeps for block
-// sizes P = 8 and 16 with real FP64, FP32 or BF16 basis storage (templates;
+// sizes P = 8 and 16 with real FP64, FP32 or BF16 basis storage, the update
+// sweeps also for P = 4 and the dot sweep for P = 1, 2, 4 (templates;
 // the instantiations live in their own translation units).  BF16 blocks are
 // widened to FP32 as they are loaded; all arithmetic is FP32 or FP64.
 //
@@ -1121,6 +1122,9 @@ hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const B
     }
     if (P == 8) return mx::launch_proj_dot<T, TQ, 8>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
     if (P == 16) return mx::launch_proj_dot<T, TQ, 16>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
+    if constexpr (std::is_same<TQ, T>::value) {
+        if (P == 4) return mx::launch_proj_dot<T, T, 4>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
+    }
     return hipErrorNotSupported;
 }
 
@@ -1140,6 +1144,9 @@ hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const 
     }
     if (P == 8) return mx::launch_proj_gram<T, TQ, TO, 8>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
     if (P == 16) return mx::launch_proj_gram<T, TQ, TO, 16>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+    if constexpr (std::is_same<TQ, T>::value && std::is_same<TO, T>::value) {
+        if (P == 4) return mx::launch_proj_gram<T, T, T, 4>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+    }
     return hipErrorNotSupported;
 }
 

@@ -75,7 +75,8 @@ bool valid_params(const bgcr_params* prm, int64_t n) {
     if (prm->enlarge_cycles < 0) return false;
     if (prm->enlarge_cycles > 0 && (p == pu || prm->precision == BGCR_MIXED_FP32_BF16)) return false;
     const int KB = (prm->k + (prm->dtype == BGCR_F64 ? 1 : 0) + p - 1) / p;
-    if (KB + prm->m + 1 > MAXB) return false;
+    // the refresh combines [U, C, V_1 .. V_{m+1}] in one launch
+    if (2 * KB + prm->m + 1 > MAXB) return false;
     if ((KB + prm->m) * p * p > MAXI * NT) return false;
     return true;
 }
@@ -140,6 +141,8 @@ struct Seq final : bgcr_sequence {
     int pu = 0;  // right-hand sides of the caller (P > pu: enlarged block, pu = 1)
     int nwg_mx = 0;      // workgroups of the matrix-core sweeps (64-row tiles)
     bool use_mx = false; // Arnoldi sweeps on matrix cores
+    bool mx_dot = false; // dot sweeps on matrix cores (also narrow real blocks, P < 8)
+    bool mx_upd = false; // update sweeps on matrix cores (also P = 4, without the PIP step order)
     bool mixed, cplx;
     hipStream_t st;
     Sizes sz;
@@ -264,6 +267,9 @@ struct Seq final : bgcr_sequence {
         const bool off = e && e[0] == '1';
         use_mx = !off && !std::is_same<T, zd>::value && (P == 8 || P == 16) &&
                  (KB + m) * P <= (P == 16 && sizeof(T) == 8 ? 224 : 256);
+        const bool realb = !std::is_same<T, zd>::value && !half;
+        mx_dot = use_mx || (realb && !off && P < 8);
+        mx_upd = use_mx || (realb && !off && P == 4 && (KB + m) * P <= 256);
         // BF16 basis blocks have matrix-core kernels only; every basis
         // combination has to fit one launch (at most 64 output columns)
         if (half && (!use_mx || 2 * KP > 64 ||
@@ -487,7 +493,7 @@ struct Seq final : bgcr_sequence {
         // over a Q chunk serves them all) against a chunk of Q blocks.  The
         // matrix-core dot also serves narrow real blocks (P < 8), where a
         // 16-column chunk spans 16 / P blocks (at most MAXB per launch).
-        const bool mxd = use_mx || (!std::is_same<T, zd>::value && !half && P < 8);
+        const bool mxd = mx_dot;
         const int wg = mxd ? std::max(1, 32 / P) : 1;
         const int nr = mxd ? nwg_mx : nwg;
         if ((size_t)nq * P * P * nw > dots_cap) throw Fail{BGCR_ERR_INVALID};
@@ -750,7 +756,7 @@ struct Seq final : bgcr_sequence {
             for (int i = 0; i < j - 1; ++i) Q.push_back(vblk(i));
             const int nq = (int)Q.size();
             const BlockPtrs Q1 = bp(Q);
-            const int na = use_mx ? nwg_mx : nwg;
+            const int na = mx_upd ? nwg_mx : nwg;
             // sweep 1a: W = A V_j with V_j = W2 R^{-1} (reads A, gathers W2, writes W and V_j)
             // algorithmic bytes per launch follow the byte model of a block step,
             // (s_A + 4) nnz + 4 (n + 1) + 5 s n p + 3 s n q_j: A read and V_j
@@ -780,7 +786,7 @@ struct Seq final : bgcr_sequence {
             // sweep 1b: first block-CGS dots [C V_1..V_j]^H W (reads W and Q)
             run(BGCR_K_ARN_DOT, qbytes, [&] {  // Q
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na);
+                    if (mx_dot) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
             });
@@ -788,7 +794,7 @@ struct Seq final : bgcr_sequence {
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
             run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {  // W, Q
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx) return mfma_proj_dot<T, TB>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip);
+                    if (mx_upd) return mfma_proj_dot<T, TB>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, na, ctl, 1);
             });
@@ -810,7 +816,7 @@ struct Seq final : bgcr_sequence {
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, S1, Sf, ctl); });
             run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {  // W, V_{j+1}, Q
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (use_mx) return mfma_proj_gram<T>(st, P, n, Wb, QB, nq + 1, Sf, W2, part, ctl, na);
+                    if (mx_upd) return mfma_proj_gram<T>(st, P, n, Wb, QB, nq + 1, Sf, W2, part, ctl, na);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, Sf, nullptr, W2, 0, 1, part, na, ctl, 2);
             });

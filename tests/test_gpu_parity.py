@@ -105,7 +105,9 @@ def test_reduced_3d_convdiff_parity():
 
 @pytest.mark.parametrize("p,m,k", [(1, 12, 6), (4, 6, 5), (16, 4, 8), (2, 5, 0),
                                    # wide bases: every chunk count of the matrix-core sweeps up to 15
-                                   (8, 16, 24), (8, 26, 20), (16, 12, 20)])
+                                   (8, 16, 24), (8, 26, 20), (16, 12, 20),
+                                   # p = 4 update sweeps on matrix cores up to 13 chunks; narrow dots
+                                   (4, 40, 20), (1, 20, 20), (2, 24, 12)])
 def test_block_sizes_and_k0(p, m, k):
     A = problems.convdiff(17, 2, conv=(8.0, -3.0, 0.0))  # n = 289
     rng = np.random.default_rng(10 + p)
@@ -123,7 +125,7 @@ def test_complex_helmholtz_parity():
     _compare("cfg3-41^2", systems, w.p, w.m, w.k, w.tol)
 
 
-@pytest.mark.parametrize("p", [16, 8])
+@pytest.mark.parametrize("p", [16, 8, 4, 1])
 def test_mixed_precision_matches_fp64_oracle(p):
     w = problems.cfg4(N=14, nsys=2, p=p, m=10, k=24)   # n = 2744, target 1e-10
     systems = [(s.A, s.B, s.X0) for s in w.systems]
