@@ -209,6 +209,14 @@ hipError_t mfma_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, i
                         const double* coef, int accumulate, int nwg);
 
 hipError_t cast_values(hipStream_t st, const double* in, float* out, int64_t nnz);
+// Block-CGS sweep of a one-column block (P = 1, real data, nq <= 32 blocks in
+// Q, nwg workgroups): w' = w - Q s (S: nq FP64 coefficients, or null for no
+// update); dot: partial Q^T w' (part[wg][nq]); otherwise w' stored in Wout
+// and partial w'^T w' (part[wg][1]).  hipErrorNotSupported outside that range.
+template <class T>
+hipError_t narrow_sweep(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S, T* Wout,
+                        double* part, int nwg, const Ctl* ctl, bool dot);
+
 template <class TI, class TO>
 hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ldi, TO* out,
                       int64_t ldo, int zero_pad_to);

@@ -290,6 +290,79 @@ BGCR_UPDATE_KERNEL(k_tsdot)
 #undef BGCR_UPDATE_KERNEL
 
 // ---------------------------------------------------------------------------
+// block-CGS sweeps of a one-column block (P = 1, real data): one lane per
+// row, the next row's NQ + 1 loads in flight while the current row is
+// computed.  w' = w - sum_i q_i s_i in FP64 (S null: no update), then DOT:
+// partial q_i^T w' (i < nq); otherwise w' stored (as T) and partial w'^T w'.
+// The accumulators stay in registers; at the end they are summed over the
+// wave with cross-lane exchanges and over the 4 waves in LDS (fixed order).
+// Blocks past nq read block 0 with coefficient 0 and their dots are not
+// written; rows past n load row n - 1 and are weighted 0.
+// ---------------------------------------------------------------------------
+template <class T, int NQ, bool DOT>
+__global__ __launch_bounds__(NT) void k_narrow_sweep(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq,
+                                                     const double* __restrict__ S, T* __restrict__ Wout,
+                                                     double* __restrict__ part, const Ctl* ctl) {
+    static_assert(NT == 256, "4 waves per workgroup");
+    constexpr int NO = DOT ? NQ : 1;
+    if (ctl && ctl->active == 0) return;
+    __shared__ double Ss[NQ];
+    __shared__ double red[4][NO];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    for (int e = t; e < NQ; e += NT) Ss[e] = (S && e < nq) ? S[e] : 0.0;
+    const T* qp[NQ];
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) qp[i] = (const T*)(i < nq ? Q.p[i] : Q.p[0]);
+    double acc[NO];
+#pragma unroll
+    for (int o = 0; o < NO; ++o) acc[o] = 0.0;
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_range((n + NT - 1) / NT, lw, t0, t1);
+    T qn[NQ];
+    T wn = T(0);
+    auto load = [&](int64_t tile) {
+        const int64_t r = tile * NT + t;
+        const int64_t row = r < n ? r : n - 1;
+        wn = Win[row];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) qn[i] = qp[i][row];
+    };
+    if (t0 < t1) load(t0);
+    __syncthreads();
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t row = tile * NT + t;
+        T qc[NQ];
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) qc[i] = qn[i];
+        const T wc = wn;
+        if (tile + 1 < t1) load(tile + 1);
+        double w = (double)wc;
+#pragma unroll
+        for (int i = 0; i < NQ; ++i) w -= (double)qc[i] * Ss[i];
+        const T wt = narrow<T>(w);
+        if (!DOT && row < n) Wout[row] = wt;
+        const double wv = (double)wt * (row < n ? 1.0 : 0.0);
+        if constexpr (DOT) {
+#pragma unroll
+            for (int i = 0; i < NQ; ++i) acc[i] += (double)qc[i] * wv;
+        } else {
+            acc[0] += wv * wv;
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < NO; ++o)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[o] += __shfl_xor(acc[o], off, 64);
+    if (lane == 0)
+#pragma unroll
+        for (int o = 0; o < NO; ++o) red[wave][o] = acc[o];
+    __syncthreads();
+    const int nout = DOT ? nq : 1;
+    for (int e = t; e < nout; e += NT) part[(int64_t)lw * nout + e] = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+}
+
+// ---------------------------------------------------------------------------
 // out_o (+)= sum_i in_i coef[i][o]  (basis updates: solution, residual, recycle refresh)
 // ---------------------------------------------------------------------------
 // One lane per row: the lane reads the P entries of its row of every input
@@ -881,7 +954,31 @@ hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ld
     return hipGetLastError();
 }
 
+template <class T>
+hipError_t narrow_sweep(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S, T* Wout,
+                        double* part, int nwg, const Ctl* ctl, bool dot) {
+    if (nq < 1 || nq > 32 || n < 1 || (!dot && !Wout)) return hipErrorNotSupported;
+    const int nb = nq <= 8 ? 8 : (nq <= 16 ? 16 : (nq <= 24 ? 24 : 32));
+#define L(NB)                                                                                                      \
+    if (dot)                                                                                                       \
+        hipLaunchKernelGGL((k_narrow_sweep<T, NB, true>), dim3(nwg), dim3(NT), 0, st, n, Win, Q, nq, S, Wout, part, ctl); \
+    else                                                                                                           \
+        hipLaunchKernelGGL((k_narrow_sweep<T, NB, false>), dim3(nwg), dim3(NT), 0, st, n, Win, Q, nq, S, Wout, part, ctl)
+    switch (nb) {
+        case 8: L(8); break;
+        case 16: L(16); break;
+        case 24: L(24); break;
+        default: L(32); break;
+    }
+#undef L
+    return hipGetLastError();
+}
+
 // explicit instantiations
+template hipError_t narrow_sweep<double>(hipStream_t, int64_t, const double*, const BlockPtrs&, int, const double*,
+                                         double*, double*, int, const Ctl*, bool);
+template hipError_t narrow_sweep<float>(hipStream_t, int64_t, const float*, const BlockPtrs&, int, const double*,
+                                        float*, double*, int, const Ctl*, bool);
 template struct Launch<double>;
 template struct Launch<float>;
 template struct Launch<zd>;

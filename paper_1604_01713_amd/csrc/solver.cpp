@@ -784,7 +784,12 @@ struct Seq final : bgcr_sequence {
             const BlockPtrs QB = bp(Q);
             const double qbytes = sB * n * (kc + (double)j * P);
             // sweep 1b: first block-CGS dots [C V_1..V_j]^H W (reads W and Q)
+            // one-column blocks take the streaming P = 1 sweeps (up to 32 blocks)
+            const bool narrow = !std::is_same<T, zd>::value && !half && P == 1 && nq + 1 <= 32;
             run(BGCR_K_ARN_DOT, qbytes, [&] {  // Q
+                if constexpr (!std::is_same<T, zd>::value && !half) {
+                    if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, nullptr, nullptr, part, na, ctl, true);
+                }
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (mx_dot) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na);
                 }
@@ -793,6 +798,9 @@ struct Seq final : bgcr_sequence {
             const int nout = (nq + 1) * P2;
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
             run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {  // W, Q
+                if constexpr (!std::is_same<T, zd>::value && !half) {
+                    if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, S1, nullptr, part, na, ctl, true);
+                }
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (mx_upd) return mfma_proj_dot<T, TB>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip);
                 }
@@ -815,6 +823,9 @@ struct Seq final : bgcr_sequence {
             }
             run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, S1, Sf, ctl); });
             run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {  // W, V_{j+1}, Q
+                if constexpr (!std::is_same<T, zd>::value && !half) {
+                    if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, Sf, W2, part, na, ctl, false);
+                }
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (mx_upd) return mfma_proj_gram<T>(st, P, n, Wb, QB, nq + 1, Sf, W2, part, ctl, na);
                 }
