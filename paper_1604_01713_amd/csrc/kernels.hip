@@ -372,29 +372,42 @@ __global__ __launch_bounds__(NT) void k_narrow_sweep(int64_t n, const T* __restr
 // [nin][P][nout][P], i.e. for input i and its column a the nout*P
 // coefficients are contiguous.  Outputs are done in chunks of OC blocks; the
 // first `accumulate` output blocks are accumulated, the others overwritten.
+// The rows of IG input blocks are loaded together before their products
+// (indices past nin load the last block and are skipped, a wave-uniform
+// test), so that IG loads per lane are in flight at once.
 template <class TI, class TO, int P, int OC>
 __global__ __launch_bounds__(NT) void k_combine(int64_t n, BlockPtrs in, int nin, BlockPtrs out, int nout,
                                                 const acc_t<TI>* __restrict__ coef, int accumulate) {
     using A = acc_t<TI>;
+    constexpr int IG = P <= 2 ? 8 : (P <= 4 ? 4 : 1);
     const int64_t stride = (int64_t)gridDim.x * NT;
     for (int64_t row = (int64_t)blockIdx.x * NT + threadIdx.x; row < n; row += stride) {
         for (int o0 = 0; o0 < nout; o0 += OC) {
             A acc[OC * P];
 #pragma unroll
             for (int e = 0; e < OC * P; ++e) acc[e] = zero<A>();
-            for (int i = 0; i < nin; ++i) {
-                const TI* x = (const TI*)in.p[i] + row * P;
-                A xv[P];
+            for (int i0 = 0; i0 < nin; i0 += IG) {
+                A xv[IG][P];
 #pragma unroll
-                for (int a = 0; a < P; ++a) xv[a] = widen(x[a]);
-                const A* cf = coef + (int64_t)i * P * nout * P + (int64_t)o0 * P;
+                for (int g = 0; g < IG; ++g) {
+                    const int i = i0 + g < nin ? i0 + g : nin - 1;
+                    const TI* x = (const TI*)in.p[i] + row * P;
 #pragma unroll
-                for (int a = 0; a < P; ++a) {
+                    for (int a = 0; a < P; ++a) xv[g][a] = widen(x[a]);
+                }
 #pragma unroll
-                    for (int oo = 0; oo < OC; ++oo) {
-                        if (o0 + oo < nout) {
+                for (int g = 0; g < IG; ++g) {
+                    if (i0 + g >= nin) break;
+                    const A* cf = coef + (int64_t)(i0 + g) * P * nout * P + (int64_t)o0 * P;
 #pragma unroll
-                            for (int b = 0; b < P; ++b) acc[oo * P + b] += xv[a] * cf[(int64_t)a * nout * P + oo * P + b];
+                    for (int a = 0; a < P; ++a) {
+#pragma unroll
+                        for (int oo = 0; oo < OC; ++oo) {
+                            if (o0 + oo < nout) {
+#pragma unroll
+                                for (int b = 0; b < P; ++b)
+                                    acc[oo * P + b] += xv[g][a] * cf[(int64_t)a * nout * P + oo * P + b];
+                            }
                         }
                     }
                 }
@@ -878,9 +891,11 @@ hipError_t Launch<T>::combine(hipStream_t st, int P, int64_t n, const BlockPtrs&
     const int nwg = (int)(blocks < 2048 ? blocks : 2048);
     // output blocks per pass: 32 accumulators per lane (16 for complex)
     constexpr int ACC = sizeof(A) == 16 ? 16 : 32;
-#define L(PP) hipLaunchKernelGGL((k_combine<T, TO, PP, (ACC / PP > 0 ? ACC / PP : 1)>), dim3(nwg), dim3(NT), 0, st, n, in, nin, out, nout, coef, accumulate);
+#define OCP(PP) (ACC / PP > 0 ? ACC / PP : 1)
+#define L(PP) hipLaunchKernelGGL((k_combine<T, TO, PP, OCP(PP)>), dim3(nwg), dim3(NT), 0, st, n, in, nin, out, nout, coef, accumulate);
     BGCR_DISPATCH_P(P, L)
 #undef L
+#undef OCP
     return hipGetLastError();
 }
 
