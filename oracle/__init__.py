@@ -5,7 +5,7 @@ link this package: only the tests, the smoke check and the CPU-baseline leg of
 the benchmark use it.  It shares no code with the HIP library.
 """
 from .bgcrodr import (  # noqa: F401
-    qr_pos, block_arnoldi_cycle, harmonic_ritz_first, harmonic_ritz_augmented,
+    qr_pos, block_arnoldi_cycle, harmonic_ritz_first, harmonic_ritz_augmented, ritz_augmented,
     select_ritz, refresh_first, refresh_augmented, recycle_import, solve, solve_sequence,
     splitmix64, enlarging_vectors,
 )

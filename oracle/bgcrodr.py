@@ -251,10 +251,21 @@ def harmonic_ritz_augmented(G, Wt, Wh):
     return theta, T
 
 
-def refresh_first(cyc, k, largest=False, real=True):
+def ritz_augmented(G, Wt, Wh):
+    """Ritz pairs on range(Wh) (Section 4.1.3 alternative to harmonic Ritz
+    vectors): Galerkin condition (A y - theta y) orthogonal to range(Wh) for
+    y = Wh t, with A Wh = Wt G, i.e. (Wh^H Wt G) t = theta (Wh^H Wh) t; both
+    products are formed explicitly."""
+    theta, T = sla.eig(Wh.conj().T @ Wt @ G, Wh.conj().T @ Wh)
+    return theta, T
+
+
+def refresh_first(cyc, k, largest=False, real=True, ritz=False):
     """First system, no U given (Algorithm 1, else-branch): select U in the block
     Krylov space from the first cycle, with C = A U orthonormal.
-    [Q, rho] = qr(H P), C = W_{m+1} Q, U = W_m P rho^{-1}."""
+    [Q, rho] = qr(H P), C = W_{m+1} Q, U = W_m P rho^{-1}.  With `ritz` the
+    selected vectors are Ritz vectors of the block Krylov space: the
+    eigenvectors of its square Hessenberg block H_m = W_m^H A W_m."""
     V, H = cyc["V"], cyc["H"]
     p = V[0].shape[1]
     mp = H.shape[1]
@@ -262,7 +273,9 @@ def refresh_first(cyc, k, largest=False, real=True):
     if k_t == 0:
         return None, None, np.array([])
     Hm = H[:mp, :]
-    if np.linalg.cond(Hm) > 1e14:
+    if ritz:
+        theta, T = sla.eig(Hm)
+    elif np.linalg.cond(Hm) > 1e14:
         W = np.hstack(V)
         theta, T = harmonic_ritz_augmented(H, W, W[:, :mp])
     else:
@@ -275,10 +288,10 @@ def refresh_first(cyc, k, largest=False, real=True):
     return U, C, vals
 
 
-def refresh_augmented(U, C, cyc, k, largest=False, real=True):
+def refresh_augmented(U, C, cyc, k, largest=False, real=True, ritz=False):
     """Algorithm 1, end of a cycle: D scales U to unit columns, G = [[D, F],[0, H]],
-    harmonic Ritz on U + K_m (eq. harm-ritz-gen-eig), then
-    [Q, rho] = qr(G P), C = [C W_{m+1}] Q, U = [U D  W_m] P rho^{-1}."""
+    harmonic Ritz on U + K_m (eq. harm-ritz-gen-eig; Ritz pairs with `ritz`),
+    then [Q, rho] = qr(G P), C = [C W_{m+1}] Q, U = [U D  W_m] P rho^{-1}."""
     V, H, F = cyc["V"], cyc["H"], cyc["F"]
     kk = U.shape[1]
     mp = H.shape[1]
@@ -291,7 +304,7 @@ def refresh_augmented(U, C, cyc, k, largest=False, real=True):
     G[kk:, kk:] = H
     Wt = np.hstack([C] + V)
     Wh = np.hstack([Ut] + V[:-1])
-    theta, T = harmonic_ritz_augmented(G, Wt, Wh)
+    theta, T = (ritz_augmented if ritz else harmonic_ritz_augmented)(G, Wt, Wh)
     k_t = min(k, kk + mp)
     P, vals = select_ritz(theta, T, k_t, largest=largest, real=real)
     Q, rho = qr_pos(G @ P)
@@ -315,7 +328,7 @@ def recycle_import(A, U, X, R):
 
 
 def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, trace=False, block_size=None,
-          seed=0, enlarged_cycles=None):
+          seed=0, enlarged_cycles=None, ritz=False):
     """Algorithm 1 (block RGMRES / block GCRO-DR) for one system A X = B.
 
     Returns (X, U, stats).  stats holds per-cycle block-step counts, the LSQ
@@ -324,7 +337,8 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
     enlarges the block with enlarging_vectors(n, L, seed).  enlarged_cycles:
     with an enlarged block, only the first enlarged_cycles cycles of this
     call use it and every later cycle is non-block (L = 1), the hybrid of
-    Section 4.1.3; None: every cycle uses it.
+    Section 4.1.3; None: every cycle uses it.  ritz: recycle Ritz instead of
+    harmonic Ritz vectors (Section 4.1.3).
     """
     A = A.tocsr() if hasattr(A, "tocsr") else A
     B = np.asarray(B)
@@ -367,7 +381,7 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
         Wm1 = np.hstack(cyc["V"])
         X = X + Wm @ cyc["Y"]
         R = R - Wm1 @ (cyc["H"] @ cyc["Y"])
-        U, C, _ = refresh_first(cyc, k, largest=select_largest, real=real)
+        U, C, _ = refresh_first(cyc, k, largest=select_largest, real=real, ritz=ritz)
         _log(stats, cyc, A, B, X, R, bn, trace, U, C)
     while True:
         Rt = B - A @ X
@@ -385,9 +399,9 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
             X = X + Wm @ Y
         R = R - Wm1 @ (cyc["H"] @ Y)
         if C is not None:
-            U, C, _ = refresh_augmented(U, C, cyc, k, largest=select_largest, real=real)
+            U, C, _ = refresh_augmented(U, C, cyc, k, largest=select_largest, real=real, ritz=ritz)
         elif k > 0:
-            U, C, _ = refresh_first(cyc, k, largest=select_largest, real=real)
+            U, C, _ = refresh_first(cyc, k, largest=select_largest, real=real, ritz=ritz)
         _log(stats, cyc, A, B, X, R, bn, trace, U, C, Uold, Cold)
     stats["rel_res"] = float(np.linalg.norm(B - A @ X)) / bn
     return X, U, stats
@@ -409,7 +423,7 @@ def _log(stats, cyc, A, B, X, R, bn, trace, U, C, Uold=None, Cold=None):
 
 
 def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False, block_size=None, seed=0,
-                   enlarge_cycles=None):
+                   enlarge_cycles=None, ritz=False):
     """Solve a sequence A^[i] X = B^[i], carrying U from each system to the next
     (Algorithm 1, last line).  `systems` is a list of (A, B, X0).
     enlarge_cycles (with block_size L > p = 1): the first enlarge_cycles
@@ -423,7 +437,7 @@ def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False, bl
     for (A, B, X0) in systems:
         X, U, st = solve(A, B, X0, tol, m, k, U=U, max_cycles=max_cycles,
                          select_largest=select_largest, block_size=block_size, seed=seed,
-                         enlarged_cycles=left)
+                         enlarged_cycles=left, ritz=ritz)
         if left is not None:
             left = max(0, left - st["cycles"])
         out.append((X, st))

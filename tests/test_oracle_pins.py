@@ -308,6 +308,76 @@ def test_harmonic_ritz_exact_when_krylov_space_is_whole_space():
     assert np.linalg.norm(X - Xs) < 1e-10 * np.linalg.norm(Xs)
 
 
+# ---- NEXT-3: Ritz vectors as the recycled space (Section 4.1.3) -------------
+
+def _galerkin_check(Ad, Wh, Y, k_sel, largest=False):
+    """Y spans Ritz vectors of A on range(Wh): Wh^H (A Y - Y S) = 0 for the
+    small S, and S's eigenvalues are the k_sel Ritz values of smallest modulus
+    of the pencil (Wh^H A Wh, Wh^H Wh), all formed from the explicit A."""
+    Qh, _ = np.linalg.qr(Wh)
+    S, *_ = np.linalg.lstsq(Qh.conj().T @ Y, Qh.conj().T @ (Ad @ Y), rcond=None)
+    res = Qh.conj().T @ (Ad @ Y - Y @ S)
+    assert np.linalg.norm(res) < 1e-8 * np.linalg.norm(Ad) * np.linalg.norm(Y)
+    allv = np.linalg.eigvals(Qh.conj().T @ Ad @ Qh)
+    mags = np.sort(np.abs(allv))
+    if largest:
+        mags = mags[::-1]
+    got = np.sort(np.abs(np.linalg.eigvals(S)))
+    want = np.sort(mags[: len(got)])
+    assert len(got) >= k_sel
+    assert np.allclose(got, want, rtol=1e-7, atol=1e-9)
+
+
+@pytest.mark.parametrize("largest", [False, True])
+def test_ritz_selection_satisfies_galerkin_condition(largest):
+    """Every cycle's new U (first cycle: from the block Krylov space; later:
+    from U + K_m) spans the selected Ritz vectors of A on the searched space."""
+    A, B = _small(N=10, p=2)
+    Ad = A.toarray()
+    m, k = 4, 4
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-10, m, k, ritz=True, trace=True, select_largest=largest,
+                       max_cycles=4)
+    assert len(st["trace"]) >= 3
+    for i, tr in enumerate(st["trace"]):
+        me = tr["cyc"]["m_eff"]
+        Wm = np.hstack(tr["cyc"]["V"][:me])
+        Wh = Wm if tr["U_in"] is None else np.hstack([tr["U_in"], Wm])
+        _galerkin_check(Ad, Wh, tr["U"], k, largest)
+    # and U is not the harmonic choice (whose vectors fail the check above)
+    Xh, Uh, sth = O.solve(A, B, np.zeros_like(B), 1e-10, m, k, trace=True, max_cycles=1, select_largest=largest)
+    Y1, Y2 = st["trace"][0]["U"], sth["trace"][0]["U"]
+    Q1, _ = np.linalg.qr(Y1)
+    Q2, _ = np.linalg.qr(Y2)
+    assert np.linalg.norm(Q2 - Q1 @ (Q1.T @ Q2)) > 1e-6
+
+
+def test_ritz_values_exact_when_krylov_space_is_whole_space():
+    """n = m p: W_m spans C^n, so H_m is similar to A and the Ritz values are the
+    eigenvalues of A (closed form for a tridiagonal Toeplitz matrix)."""
+    n, p, m, k = 12, 3, 4, 4
+    a, b, c = 4.0, 1.5, 0.6
+    A = _toeplitz_tridiag(n, a, b, c)
+    B = np.random.default_rng(3).uniform(-1, 1, (n, p))
+    cyc = O.block_arnoldi_cycle(A, B, None, m, 0.0)
+    exact = a + 2 * np.sqrt(b * c) * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    U, C, vals = O.refresh_first(cyc, k, ritz=True)
+    assert np.allclose(np.sort(vals.real), np.sort(exact)[:k], atol=1e-9)
+    # A U = C holds for the Ritz choice as well (C = A U orthonormal)
+    assert np.linalg.norm(A @ U - C) < 1e-10 * np.linalg.norm(C)
+    assert np.linalg.norm(C.T @ C - np.eye(C.shape[1])) < 1e-12
+
+
+def test_ritz_recycling_sequence_matches_dense_lu():
+    A, B = _small(N=10, p=2)
+    systems = [(A, B, np.zeros_like(B)),
+               ((A + 0.05 * sp.identity(A.shape[0])).tocsr(), B[::-1].copy(), np.zeros_like(B))]
+    out, U = O.solve_sequence(systems, 1e-10, 4, 5, ritz=True)
+    for (Ai, Bi, _), (X, st) in zip(systems, out):
+        Xd = np.linalg.solve(Ai.toarray(), Bi)
+        assert np.linalg.norm(X - Xd) <= 1e-8 * np.linalg.norm(Xd)
+    assert U.shape[1] in (5, 6)
+
+
 def test_harmonic_ritz_standard_equals_generalized_at_k0():
     """Proposition block-harm-ritz vs eq. harm-ritz-gen-eig with no recycled space."""
     A, B = _small(N=10, p=3)
