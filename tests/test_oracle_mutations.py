@@ -44,10 +44,10 @@ def test_unmutated_oracle_passes():
 def test_dropped_F_block_in_G_is_caught(monkeypatch):
     orig = ob.refresh_augmented
 
-    def bad(U, C, cyc, k, largest=False, real=True):
+    def bad(U, C, cyc, k, largest=False, real=True, ritz=False):
         cyc = dict(cyc)
         cyc["F"] = np.zeros_like(cyc["F"])          # G = [[D, 0], [0, H]]
-        return orig(U, C, cyc, k, largest, real)
+        return orig(U, C, cyc, k, largest, real, ritz)
 
     monkeypatch.setattr(ob, "refresh_augmented", bad)
     assert _caught(_invariants(*_problem()))
