@@ -89,6 +89,13 @@ typedef struct {
                                 recycled U is handed to the L = 1 basis and imported
                                 there (A U = C S).  0: every cycle uses L.  Not with
                                 BGCR_MIXED_FP32_BF16; negative: BGCR_ERR_INVALID */
+    int32_t ritz_vectors;    /* recycled space: 0 harmonic Ritz vectors (Section 4.1.2);
+                                1 Ritz vectors (Section 4.1.3): the first cycle takes
+                                eigenvectors of the square block Hessenberg H_m, later
+                                cycles the Galerkin pencil on U + K_m,
+                                (What^H A What) t = theta (What^H What) t with
+                                What = [U D, V_1 .. V_m].  The selection by modulus
+                                follows select_largest.  Other values: BGCR_ERR_INVALID */
 } bgcr_params;
 
 typedef struct {

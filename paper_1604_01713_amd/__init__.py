@@ -51,7 +51,7 @@ class bgcr_params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
                 ("select_largest", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("enlarge_cycles", ctypes.c_int32)]
+                ("enlarge_cycles", ctypes.c_int32), ("ritz_vectors", ctypes.c_int32)]
 
 
 class bgcr_csr(ctypes.Structure):
@@ -225,9 +225,9 @@ class Sequence:
     """One sequence of related systems sharing a device-resident recycle space."""
 
     def __init__(self, n, p, m, k, dtype=BGCR_F64, precision=BGCR_PLAIN_FP64, max_cycles=1000,
-                 select_largest=False, stream=None, block_size=0, enlarge_cycles=0):
+                 select_largest=False, stream=None, block_size=0, enlarge_cycles=0, ritz_vectors=False):
         self.params = bgcr_params(p, m, k, dtype, precision, max_cycles, int(bool(select_largest)), int(block_size),
-                                  int(enlarge_cycles))
+                                  int(enlarge_cycles), int(bool(ritz_vectors)))
         self.n = n
         self.stream = stream
         self.handle = bgcr_create_sequence(self.params, n, stream)

@@ -73,6 +73,7 @@ bool valid_params(const bgcr_params* prm, int64_t n) {
     if (prm->max_cycles < 1) return false;
     // the hybrid needs an enlarged block and a basis type the L = 1 basis has
     if (prm->enlarge_cycles < 0) return false;
+    if (prm->ritz_vectors != 0 && prm->ritz_vectors != 1) return false;
     if (prm->enlarge_cycles > 0 && (p == pu || prm->precision == BGCR_MIXED_FP32_BF16)) return false;
     const int KB = (prm->k + (prm->dtype == BGCR_F64 ? 1 : 0) + p - 1) / p;
     // the refresh combines [U, C, V_1 .. V_{m+1}] in one launch
@@ -1044,8 +1045,10 @@ struct Seq final : bgcr_sequence {
         std::vector<std::vector<cd>> vecs;
         dense::Selection sel;
         Mat Pm, Qg, rg;
-        const bool standard = dense::solve_lu(dense::adjoint(Hm), rhs, Xs);
-        if (standard)
+        // Ritz vectors (Section 4.1.3): eigenvectors of H_m = W_m^H A W_m itself
+        const bool ritz = prm.ritz_vectors != 0;
+        const bool standard = ritz || dense::solve_lu(dense::adjoint(Hm), rhs, Xs);
+        if (standard && !ritz)
             for (int i = 0; i < mp; ++i)
                 for (int b = 0; b < P; ++b) K(i, mp - P + b) += Xs(i, b);
         for (int attempt = 0; attempt < 2; ++attempt) {
@@ -1113,6 +1116,26 @@ struct Seq final : bgcr_sequence {
         }
     }
 
+    // Ritz pairs of the pencil (Ah, Bh), Bh Hermitian positive definite:
+    // Bh = Rb^H Rb, eigenpairs (theta, s) of Rb^{-H} Ah Rb^{-1}, t = Rb^{-1} s
+    void gen_ritz(const Mat& Ah, const Mat& Bh, int kt, std::vector<cd>& theta, dense::Selection& sel,
+                  std::vector<std::vector<cd>>& vecs, bool robust) {
+        Mat Rb;
+        if (!dense::chol_upper(Bh, Rb)) throw Fail{BGCR_ERR_NUMERICAL};
+        const Mat Rbi = dense::tri_inv_upper(Rb);
+        const Mat K = dense::matmul(dense::matmul(dense::adjoint(Rbi), Ah), Rbi);
+        std::vector<std::vector<cd>> svecs;
+        eig_select(K, false, kt, robust, theta, sel, svecs);
+        const int nn = Ah.c;
+        vecs.clear();
+        for (const auto& sv : svecs) {
+            std::vector<cd> tv(nn, cd(0.0, 0.0));
+            for (int r = 0; r < nn; ++r)
+                for (int c = r; c < nn; ++c) tv[r] += Rbi(r, c) * sv[c];
+            vecs.push_back(tv);
+        }
+    }
+
     // Algorithm 1, end of a cycle with recycling: D, G_m, harmonic Ritz on
     // U + K_m, then C <- [C W_{m+1}] Q, U <- [U D  W_m] P rho^{-1}
     void refresh_aug(const CycleOut& co, RefreshPlan& rp) {
@@ -1155,8 +1178,26 @@ struct Seq final : bgcr_sequence {
         dense::Selection sel;
         std::vector<std::vector<cd>> vecs;
         Mat Pm, Qg, rg;
+        // Ritz vectors (Section 4.1.3): What = [U D  W_m], A What = [C W_{m+1}] G,
+        // (M^H G) t = theta (What^H What) t with What^H What from the dots
+        Mat Ah, Bh;
+        if (prm.ritz_vectors) {
+            Ah = dense::matmul(dense::adjoint(M), G);
+            Bh = Mat(cols, cols);
+            for (int i = 0; i < ke; ++i)
+                for (int j = 0; j < ke; ++j) Bh(i, j) = d[i] * Dm(i, j) * d[j];
+            for (int i = 0; i < mp; ++i)
+                for (int j = 0; j < ke; ++j) {
+                    Bh(ke + i, j) = M(ke + i, j);
+                    Bh(j, ke + i) = std::conj(M(ke + i, j));
+                }
+            for (int i = 0; i < mp; ++i) Bh(ke + i, ke + i) = 1.0;
+        }
         for (int attempt = 0; attempt < 2; ++attempt) {
-            gen_harmonic(G, M, kt, theta, sel, vecs, attempt == 1);
+            if (prm.ritz_vectors)
+                gen_ritz(Ah, Bh, kt, theta, sel, vecs, attempt == 1);
+            else
+                gen_harmonic(G, M, kt, theta, sel, vecs, attempt == 1);
             ritz_basis(sel, vecs, Pm);
             dense::qr_pos(dense::matmul(G, Pm), Qg, rg);
             if (well_conditioned_r(rg)) break;

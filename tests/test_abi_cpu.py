@@ -108,6 +108,11 @@ def test_invalid_arguments_are_rejected_without_a_gpu(lib):
     h = ctypes.c_void_p()
     # the recycle refresh combines [U, C, V_1 .. V_{m+1}]: 2 ceil((k+1)/p) + m + 1 <= 64 blocks
     assert bg.bgcr_footprint_bytes(bg.bgcr_params(1, 21, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0), 4096, 0) > 0
+    ritz = bg.bgcr_params(8, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0, 0, 1)
+    assert bg.bgcr_footprint_bytes(ritz, 4096, 0) == bg.bgcr_footprint_bytes(
+        bg.bgcr_params(8, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0), 4096, 0)
+    bad_ritz = bg.bgcr_params(8, 10, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0, 0, 2)
+    assert bg.bgcr_footprint_bytes(bad_ritz, 4096, 0) == 0
     too_wide = bg.bgcr_params(1, 22, 20, bg.BGCR_F64, bg.BGCR_PLAIN_FP64, 100, 0, 0)
     assert bg.bgcr_footprint_bytes(too_wide, 4096, 0) == 0
     assert lib.bgcr_create_sequence(ctypes.byref(too_wide), 4096, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID

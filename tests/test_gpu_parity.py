@@ -30,14 +30,15 @@ def _dev():
 
 
 def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=1000, select_largest=False,
-                  block_size=0, enlarge_cycles=0):
+                  block_size=0, enlarge_cycles=0, ritz_vectors=False):
     bg = _bg()
     dev = _dev()
     n = systems[0][0].shape[0]
     cplx = np.iscomplexobj(systems[0][1]) or np.iscomplexobj(systems[0][0].data)
     dt = bg.BGCR_C128 if cplx else bg.BGCR_F64
     seq = bg.Sequence(n, p, m, k, dtype=dt, precision=precision, max_cycles=max_cycles,
-                      select_largest=select_largest, block_size=block_size, enlarge_cycles=enlarge_cycles)
+                      select_largest=select_largest, block_size=block_size, enlarge_cycles=enlarge_cycles,
+                      ritz_vectors=ritz_vectors)
     out = []
     for (A, B, X0) in systems:
         Ad = bg.DeviceCSR.from_scipy(A, dev)
@@ -253,6 +254,45 @@ def test_hybrid_enlarged_then_single_matches_oracle(L, precision, E):
         if precision == 0:
             assert abs(st["cycles"] - so["cycles"]) <= 1
     assert seq.recycle_dim() in (w.k, w.k + 1)
+    seq.release()
+
+
+@pytest.mark.parametrize("p,largest,precision", [(4, False, 0), (8, False, 0), (8, True, 0), (1, False, 0),
+                                                 (8, False, 1)])
+def test_ritz_vectors_match_oracle(p, largest, precision):
+    """Recycling Ritz instead of harmonic Ritz vectors (Section 4.1.3): the
+    solutions, the cycle counts and the final recycled space (principal
+    angles, S18) agree with the oracle's."""
+    bg = _bg()
+    dev = _dev()
+    w = problems.cfg2(N=13, nsys=3, p=p, m=6, k=8)
+    tol = w.tol if precision == 0 else 1e-10
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    seq, gpu = _run_sequence(systems, p, w.m, w.k, tol, precision=precision, select_largest=largest,
+                             ritz_vectors=True)
+    orc, Uo = oracle.solve_sequence(systems, tol, w.m, w.k, select_largest=largest, ritz=True)
+    orc_h, _ = oracle.solve_sequence(systems, tol, w.m, w.k, select_largest=largest)
+    for i, ((Xg, st, log), (Xo, so)) in enumerate(zip(gpu, orc)):
+        A, B, _ = systems[i]
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+        print(f"ritz p={p} largest={largest} prec={precision} sys{i}: gpu cycles={st['cycles']} relres={rg:.2e} | "
+              f"oracle cycles={so['cycles']} (harmonic: {orc_h[i][1]['cycles']}) | rel diff={rel:.2e}", flush=True)
+        assert st["status"] == 0
+        assert rg <= tol * 1.0001
+        assert rel <= PARITY
+        if precision == 0:
+            assert abs(st["cycles"] - so["cycles"]) <= 1
+    ke = seq.recycle_dim()
+    assert ke == Uo.shape[1]
+    if precision == 0:
+        Ug = torch.zeros((w.systems[0].A.shape[0], ke), dtype=torch.float64, device=dev)
+        seq.get_recycle(Ug, None)
+        Qg, _ = np.linalg.qr(Ug.cpu().numpy())
+        Qo, _ = np.linalg.qr(Uo)
+        gap = np.linalg.norm(Qg - Qo @ (Qo.T @ Qg), 2)
+        print(f"ritz p={p}: sin of the largest principal angle between recycled spaces {gap:.1e}", flush=True)
+        assert gap <= 1e-5
     seq.release()
 
 
