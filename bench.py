@@ -202,6 +202,44 @@ def bench_enlarged(args, torch, problems, bg, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_selection(args, torch, problems, bg, dev):
+    """Recycle-space selection on the headline sequence's matrices (p = 8):
+    harmonic Ritz vectors (Section 4.1.2, the default) against Ritz vectors
+    (Section 4.1.3), each with the smallest- and the largest-modulus values."""
+    nsys = args.nsys if args.nsys != 10 else 4
+    w = problems.cfg2(N=args.grid, nsys=nsys)
+    systems = [(s_.A, s_.B) for s_ in w.systems]
+    n, nnz = systems[0][0].shape[0], systems[0][0].nnz
+    log(f"[bench] selection: {nsys} systems n={n} nnz={nnz} p={w.p} m={w.m} k={w.k} tol={w.tol}")
+    dA = [bg.DeviceCSR.from_scipy(A, dev) for (A, _) in systems]
+    dB = [torch.from_numpy(B).to(dev) for (_, B) in systems]
+    out = {}
+    for name, ritz, largest in (("harmonic_smallest", False, False), ("harmonic_largest", False, True),
+                                ("ritz_smallest", True, False), ("ritz_largest", True, True)):
+        seq = bg.Sequence(n, w.p, w.m, w.k, max_cycles=20000, select_largest=largest, ritz_vectors=ritz)
+        dX = [torch.zeros_like(b) for b in dB]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc = []
+        for i in range(nsys):
+            st = seq.solve(dA[i], dB[i], dX[i], w.tol)
+            if st.status != 0:
+                raise RuntimeError(f"{name} system {i}: {st.as_dict()}")
+            cyc.append(st.cycles)
+            log(f"[bench] {name} system {i}: cycles={st.cycles}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        seq.release()
+        worst = max(_host_check(A, B, x.cpu().numpy()) for (A, B), x in zip(systems, dX))
+        out[name] = {"systems_per_s": round(nsys / el, 4), "seconds": round(el, 2), "cycles_per_system": cyc,
+                     "max_rel_res_fp64_check": worst}
+    res = {"metric": "systems/s by recycle-space selection (harmonic Ritz vs Ritz vectors)", "unit": "systems/s",
+           "config": {"workload": f"convdiff3d_{args.grid}^3_seq{nsys}_p{w.p}_m{w.m}_k{w.k}", "n": n, "nnz": nnz,
+                      "tol": w.tol},
+           "data": "synthetic", "n_gpus": 1, **out}
+    print(json.dumps(res), flush=True)
+
+
 def bench_serving(args, torch, problems, bg, dev):
     """A seeded request stream: serial plain FP64 (one request after the other)
     vs the served form (continuous batching, HBM-budget admission)."""
@@ -290,7 +328,7 @@ def main():
     ap.add_argument("--nsys", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
-    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged"], default="cfg2",
+    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection"], default="cfg2",
                     help="cfg2: the headline sequence (default); precision: plain FP64 vs the FP32-in-FP64 form on "
                          "the anisotropic 192^3 sequence; serving: a request stream, served vs serial; enlarged: one "
                          "right-hand side, block size 1 vs 8 and 16")
@@ -317,6 +355,8 @@ def main():
         return bench_serving(args, torch, problems, bg, dev)
     if args.workload == "enlarged":
         return bench_enlarged(args, torch, problems, bg, dev)
+    if args.workload == "selection":
+        return bench_selection(args, torch, problems, bg, dev)
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20

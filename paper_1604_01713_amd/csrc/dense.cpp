@@ -125,6 +125,41 @@ bool chol_upper(const Mat& G, Mat& R) {
     return true;
 }
 
+int chol_pivoted(const Mat& G, double tau, std::vector<int>& piv, Mat& R) {
+    const int n = G.r;
+    Mat W = G, Rf(n, n);  // W: Schur complement, in the current column order
+    piv.resize(n);
+    for (int i = 0; i < n; ++i) piv[i] = i;
+    double gmax = 0.0;
+    for (int i = 0; i < n; ++i) gmax = std::max(gmax, G(i, i).real());
+    int r = 0;
+    if (gmax > 0.0 && std::isfinite(gmax)) {
+        for (int j = 0; j < n; ++j) {
+            int q = j;
+            for (int i = j + 1; i < n; ++i)
+                if (W(i, i).real() > W(q, q).real()) q = i;
+            if (q != j) {
+                for (int c = 0; c < n; ++c) std::swap(W(j, c), W(q, c));
+                for (int c = 0; c < n; ++c) std::swap(W(c, j), W(c, q));
+                for (int l = 0; l < j; ++l) std::swap(Rf(l, j), Rf(l, q));
+                std::swap(piv[j], piv[q]);
+            }
+            const double d = W(j, j).real();
+            if (!(d > tau * gmax) || !std::isfinite(d)) break;
+            const double rjj = std::sqrt(d);
+            Rf(j, j) = rjj;
+            for (int i = j + 1; i < n; ++i) Rf(j, i) = W(j, i) / rjj;
+            for (int i = j + 1; i < n; ++i)
+                for (int l = j + 1; l < n; ++l) W(i, l) -= std::conj(Rf(j, i)) * Rf(j, l);
+            r = j + 1;
+        }
+    }
+    R = Mat(r, r);
+    for (int i = 0; i < r; ++i)
+        for (int j = i; j < r; ++j) R(i, j) = Rf(i, j);
+    return r;
+}
+
 Mat tri_inv_upper(const Mat& R) {
     const int n = R.r;
     if (all_real(R)) {

@@ -37,6 +37,11 @@ double fro(const Mat& A);
 // G = R^H R, R upper triangular with real positive diagonal; false if G is
 // not numerically positive definite.
 bool chol_upper(const Mat& G, Mat& R);
+// Pivoted Cholesky of a Hermitian positive semidefinite G: with the column
+// order piv, G(piv, piv) = R^H R on the leading r rows, stopping at the first
+// pivot at or below tau times the largest diagonal entry.  Returns r (piv[0..r)
+// are the numerically independent columns); R is r x r upper triangular.
+int chol_pivoted(const Mat& G, double tau, std::vector<int>& piv, Mat& R);
 Mat tri_inv_upper(const Mat& R);
 // X with R X = B, R upper triangular (leading n x n of R is used)
 Mat solve_upper(const Mat& R, const Mat& B);

@@ -470,7 +470,10 @@ __device__ inline double dabs(zd a) { return sqrt(a.x * a.x + a.y * a.y); }
 // not above 1e-24 of the largest diagonal entry of G (columns numerically
 // dependent to about 1e-12).
 template <class A>
-__device__ bool chol_upper(const A* G, A* R, int P) {
+__device__ bool chol_upper(const A* G, A* R, int P, double rel = 0.0) {
+    // fails on a pivot below 1e-24 of the largest diagonal entry, or below
+    // `rel` times its own diagonal entry (a column that is numerically in the
+    // span of the previous ones; scale invariant)
     double maxd = 0.0;
     for (int i = 0; i < P; ++i) maxd = fmax(maxd, re(G[i * P + i]));
     if (!(maxd > 0.0) || !isfinite(maxd)) return false;
@@ -479,7 +482,7 @@ __device__ bool chol_upper(const A* G, A* R, int P) {
         A d = G[i * P + i];
         for (int l = 0; l < i; ++l) d -= cj(R[l * P + i]) * R[l * P + i];
         const double dd = re(d);
-        if (!(dd > 1e-24 * maxd) || !isfinite(dd)) return false;
+        if (!(dd > 1e-24 * maxd) || !(dd > rel * re(G[i * P + i])) || !isfinite(dd)) return false;
         const double rii = sqrt(dd);
         R[i * P + i] = from_real<A>(rii);
         const double ir = 1.0 / rii;
@@ -543,7 +546,7 @@ __global__ void k_cholqr_first(const A* gram, A* Z1, A* Z1inv, int nrhs, Ctl* ct
     for (int e = threadIdx.x; e < P * P; e += blockDim.x) Gs[e] = scale_by(dsc[e / P] * dsc[e % P], gram[e]);
     __syncthreads();
     if (threadIdx.x == 0) {
-        okf = chol_upper(Gs, Rs, P);
+        okf = chol_upper(Gs, Rs, P, 1e-14);  // CholQR2 needs cond(start block) below about 1e7
         if (okf) tri_inv_upper(Rs, Ri, P);
     }
     __syncthreads();

@@ -737,7 +737,110 @@ struct Seq final : bgcr_sequence {
         });
     }
 
-    CycleOut cycle(const bgcr_csr* Am, const T* avT, bool withC, double thresh, bool prologue_done = false) {
+    // Start block with numerically dependent columns (its CholQR failed): the
+    // breakdown rule of the block steps applied to the start block.  A pivoted
+    // Cholesky of R's Gram on the host keeps the r independent columns
+    // (pivots above 1e-14 of the largest), the other P - r columns become
+    // seeded SplitMix64 vectors; the block is projected against C and
+    // orthonormalised by CholQR2 into V_1, and the LSQ right-hand side is
+    // E V_1^H R.  Real data with the basis in the work type only (false
+    // otherwise).  Work buffers: Wb (the block before the first CholQR pass)
+    // and W2 (the start block, as the prologue leaves it).
+    int deflations = 0;
+    bool deflated_prologue(bool withC) {
+        if constexpr (std::is_same<T, zd>::value || half) {
+            (void)withC;
+            return false;
+        } else {
+            const int P2 = P * P;
+            const size_t hb = (size_t)(m + 1) * P * m * P * sizeof(A);
+            HIPCHK(hipMemsetAsync(H, 0, hb, st));
+            HIPCHK(hipMemsetAsync(Rh, 0, hb, st));
+            const double blkb = (double)sizeof(T) * n * P;
+            const int nr = use_mx ? nwg_mx : nwg;
+            auto gram_only = [&](T* Y) {
+                run(BGCR_K_TSDOT, blkb, [&] {
+                    if (use_mx) return mfma_proj_gram<T, T, T>(st, P, n, Y, bp({}), 0, nullptr, nullptr, part, nullptr, nr);
+                    return L::update_dot(st, P, n, Y, bp({}), 0, nullptr, nullptr, nullptr, 0, 1, part, nr, nullptr);
+                });
+            };
+            gram_only(R);
+            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nr, P2, nullptr, Sf, nullptr); });
+            std::vector<A> G(P2);
+            d2h(G.data(), Sf, P2 * sizeof(A));
+            // pivoted Cholesky G(piv, piv) = R11^T R11 on the leading r columns
+            Mat Gm(P, P);
+            for (int a = 0; a < P; ++a)
+                for (int b = 0; b < P; ++b) Gm(a, b) = to_cd(G[a * P + b]);
+            std::vector<int> piv;
+            Mat R11m;
+            const int r = dense::chol_pivoted(Gm, 1e-14, piv, R11m);
+            if (r == 0) return false;
+            // T: column c < r of R (Pi R11^{-1}), zero beyond
+            const Mat R11i = dense::tri_inv_upper(R11m);
+            Mat Tm(P, P);
+            for (int a = 0; a < r; ++a)
+                for (int c = 0; c < r; ++c) Tm(piv[a], c) = R11i(a, c);
+            combine<T>({R}, {Wb}, Tm, 0);
+            HIPCHK(fill_enlarging<T>(st, Wb, n, P, r, (uint64_t)(1 + (deflations++ % 200))));
+            if (withC && keff > 0) {
+                std::vector<const void*> qc;
+                for (int b = 0; b < KB; ++b) qc.push_back(cblk(cur, b));
+                const BlockPtrs QC = bp(qc);
+                const double cbytes = (double)sizeof(TB) * n * KP;
+                run(BGCR_K_TSDOT, blkb + cbytes, [&] {
+                    if (mx_dot) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QC, KB, part, nullptr, nr);
+                    return L::update_dot(st, P, n, Wb, QC, KB, nullptr, nullptr, nullptr, 1, 0, part, nr, nullptr);
+                });
+                run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nr, KP * P, nullptr, S1, nullptr); });
+                run(BGCR_K_TSDOT, 2.0 * blkb + cbytes, [&] {  // Wb <- Wb - C T in place, with its Gram
+                    if (use_mx) return mfma_proj_gram<T, TB, T>(st, P, n, Wb, QC, KB, S1, Wb, part, nullptr, nr);
+                    return L::update_dot(st, P, n, Wb, QC, KB, S1, nullptr, Wb, 0, 1, part, nr, nullptr);
+                });
+            } else {
+                gram_only(Wb);
+            }
+            run(BGCR_K_SMALL, 0.0, [&] {
+                HIPCHK(reduce_partials<A>(st, part, nr, P2, nullptr, Sf, nullptr));
+                return cholqr_first<A>(st, P, Sf, Z1, Z1i, r, ctl);
+            });
+            run(BGCR_K_TSDOT, 2.0 * blkb, [&] {
+                if (use_mx) {
+                    HIPCHK(i_minus(st, Z1i, S1, P));
+                    return mfma_proj_gram<T>(st, P, n, Wb, bp({Wb}), 1, S1, W2, part, nullptr, nr);
+                }
+                return L::update_dot(st, P, n, Wb, bp({}), 0, nullptr, Z1i, W2, 0, 1, part, nr, nullptr);
+            });
+            run(BGCR_K_SMALL, 0.0, [&] {
+                HIPCHK(reduce_partials<A>(st, part, nr, P2, nullptr, Sf, nullptr));
+                return cholqr_second<A>(st, P, Sf, Z1, RinvAll, g, m, P, ctl);
+            });
+            // right-hand side: V_1^H R = Z2^{-H} (W2^H R), Z2^{-1} = RinvAll[0]
+            run(BGCR_K_TSDOT, 2.0 * blkb, [&] {
+                if (mx_dot) return mfma_dot<T, T, T>(st, P, n, bp({R}), 1, bp({W2}), 1, part, nullptr, nr);
+                return L::update_dot(st, P, n, R, bp({W2}), 1, nullptr, nullptr, nullptr, 1, 0, part, nr, nullptr);
+            });
+            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nr, P2, nullptr, S1, nullptr); });
+            std::vector<A> hS(P2), hRi0(P2);
+            Ctl hc;
+            d2h(&hc, ctl, sizeof(Ctl));
+            if (hc.active == 0 || hc.status != 0) return false;
+            d2h(hS.data(), S1, P2 * sizeof(A));
+            d2h(hRi0.data(), RinvAll, P2 * sizeof(A));
+            std::vector<A> hg((size_t)(m + 1) * P2, A(0));
+            for (int i = 0; i < P; ++i)
+                for (int j = 0; j < P; ++j) {
+                    double z = 0.0;
+                    for (int l = 0; l <= i; ++l) z += hRi0[l * P + i] * hS[l * P + j];  // (Z2^{-1})^T is lower
+                    hg[i * P + j] = z;
+                }
+            h2d(g, hg.data(), hg.size() * sizeof(A));
+            return true;
+        }
+    }
+
+    CycleOut cycle(const bgcr_csr* Am, const T* avT, bool withC, double thresh, bool prologue_done = false,
+                   bool deflated = false) {
         const int P2 = P * P;
         if (!prologue_done) cycle_prologue(withC);
         const double sT = (double)sizeof(T), blkb = sT * (double)n * P;
@@ -869,7 +972,12 @@ struct Seq final : bgcr_sequence {
         CycleOut co;
         co.meff = hc.meff;
         co.breakdown = hc.status != 0;
-        if (co.meff == 0) throw Fail{BGCR_ERR_NUMERICAL};
+        if (co.meff == 0) {
+            // the start block was rank deficient: one retry with a deflated start block
+            if (deflated || !deflated_prologue(withC)) throw Fail{BGCR_ERR_NUMERICAL};
+            breakdown_seen = true;
+            return cycle(Am, avT, withC, thresh, true, true);
+        }
         const int me = co.meff, mp = me * P, ldH = m * P;
         HostPhase hp(this, BGCR_K_HOST);
         if (spec.valid && me == m && !co.breakdown) {

@@ -296,6 +296,37 @@ def test_ritz_vectors_match_oracle(p, largest, precision):
     seq.release()
 
 
+@pytest.mark.parametrize("p,precision", [(8, 0), (4, 0), (16, 0), (8, 1)])
+def test_duplicate_rhs_columns_deflated_start_block(p, precision):
+    """A rank-deficient start block (duplicate right-hand sides): its CholQR
+    breaks down; the start block is rebuilt from its independent columns and
+    seeded vectors (the breakdown rule of the block steps), and the solve
+    converges to the dense-LU solution with equal duplicated columns."""
+    w = problems.cfg2(N=13, nsys=2, p=p, m=6, k=8)
+    tol = w.tol if precision == 0 else 1e-10
+    systems = []
+    for s_ in w.systems:
+        B = s_.B.copy()
+        B[:, p - 1] = B[:, 0]
+        B[:, p // 2] = 2.0 * B[:, 0] - B[:, 1]
+        systems.append((s_.A, B, np.zeros_like(B)))
+    seq, gpu = _run_sequence(systems, p, w.m, w.k, tol, precision=precision)
+    orc, _ = oracle.solve_sequence(systems, tol, w.m, w.k)
+    for i, ((Xg, st, log), (Xo, so)) in enumerate(zip(gpu, orc)):
+        A, B, _ = systems[i]
+        Xd = np.linalg.solve(A.toarray(), B)
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+        reld = np.linalg.norm(Xg - Xd) / np.linalg.norm(Xd)
+        print(f"deflated start p={p} prec={precision} sys{i}: gpu cycles={st['cycles']} relres={rg:.2e} | "
+              f"oracle cycles={so['cycles']} | rel diff oracle {rel:.2e} dense {reld:.2e}", flush=True)
+        assert st["status"] == 0
+        assert rg <= tol * 1.0001
+        assert rel <= PARITY and reld <= PARITY
+        assert np.linalg.norm(Xg[:, p - 1] - Xg[:, 0]) <= 1e-6 * np.linalg.norm(Xg[:, 0])
+    seq.release()
+
+
 def test_recycle_pair_satisfies_AU_equals_C():
     bg = _bg()
     dev = _dev()
