@@ -7,5 +7,5 @@ the benchmark use it.  It shares no code with the HIP library.
 from .bgcrodr import (  # noqa: F401
     qr_pos, block_arnoldi_cycle, harmonic_ritz_first, harmonic_ritz_augmented, ritz_augmented,
     select_ritz, refresh_first, refresh_augmented, recycle_import, solve, solve_sequence,
-    splitmix64, enlarging_vectors,
+    splitmix64, enlarging_vectors, apply_projected,
 )

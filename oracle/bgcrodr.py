@@ -442,3 +442,16 @@ def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False, bl
             left = max(0, left - st["cycles"])
         out.append((X, st))
     return out, U
+
+
+# ----------------------------------------------------------------------------
+# Projected operator of the data-movement study (Section 6.3)
+# ----------------------------------------------------------------------------
+
+def apply_projected(A, C, V):
+    """(I - C C^H) A V for a C with orthonormal columns (Section 6.3 applies
+    the projected operator (I - Phi) A with Phi = C C^H to blocks of vectors):
+    the plain definition, one product after the other."""
+    W = A @ V
+    return W - C @ (C.conj().T @ W)
+

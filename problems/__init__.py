@@ -231,6 +231,22 @@ def request_system(req, i):
     return System(A, B, np.zeros_like(B))
 
 
+def banded(n, bw, seed):
+    """Synthetic banded matrix of the data-movement study (Section 6.3 used
+    rand/spdiags-built banded matrices): 2 bw + 1 diagonals with seeded
+    U[-1, 1] entries, the diagonal replaced by the row's off-diagonal
+    magnitude sum plus 1 (diagonally dominant); CSR with sorted indices."""
+    rng = np.random.default_rng(seed)
+    offs = list(range(-bw, bw + 1))
+    diags = [rng.uniform(-1.0, 1.0, n - abs(o)) for o in offs]
+    A = sp.diags(diags, offs, shape=(n, n), format="csr")
+    off = np.asarray(abs(A).sum(axis=1)).ravel() - np.abs(A.diagonal())
+    A.setdiag(off + 1.0)
+    A = A.tocsr()
+    A.sort_indices()
+    return A
+
+
 def reduced(cfg_fn, **kw):
     """Same recipe at a reduced grid (parity-test size)."""
     return cfg_fn(**kw)

@@ -485,3 +485,32 @@ def test_duplicate_rhs_columns_still_converge():
     X, U, st = O.solve(A, B, np.zeros_like(B), 1e-9, 5, 4)
     assert st["rel_res"] <= 1e-9
     assert np.linalg.norm(X[:, 2] - X[:, 0]) < 1e-6 * np.linalg.norm(X[:, 0])
+
+
+# ---- NEXT-2: projected operator of the data-movement study (Section 6.3) ----
+
+def test_projected_operator_against_explicit_projector():
+    """(I - C C^H) A V: the result is orthogonal to C, equals the explicit
+    n x n projector times the dense product on a small case, and a block is
+    the columns applied one at a time."""
+    A = P.banded(200, 4, seed=11)
+    rng = np.random.default_rng(12)
+    C, _ = np.linalg.qr(rng.uniform(-1, 1, (200, 10)))
+    V = rng.uniform(-1, 1, (200, 8))
+    W = O.apply_projected(A, C, V)
+    assert np.linalg.norm(C.T @ W) < 1e-12 * np.linalg.norm(W)
+    Pi = np.eye(200) - C @ C.T
+    Wd = Pi @ (A.toarray() @ V)
+    assert np.linalg.norm(W - Wd) < 1e-12 * np.linalg.norm(Wd)
+    for j in range(8):
+        wj = O.apply_projected(A, C, V[:, j:j + 1])
+        assert np.linalg.norm(wj[:, 0] - W[:, j]) < 1e-12 * np.linalg.norm(W[:, j])
+
+
+def test_banded_generator_recipe():
+    A = P.banded(300, 5, seed=4)
+    Ad = A.toarray()
+    i, j = np.nonzero(Ad)
+    assert np.max(np.abs(i - j)) == 5 and A.nnz == 300 * 11 - 5 * 6
+    off = np.abs(Ad).sum(axis=1) - np.abs(np.diag(Ad))
+    assert np.allclose(np.diag(Ad), off + 1.0)
