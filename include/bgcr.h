@@ -175,6 +175,30 @@ int bgcr_get_cycle_log(const bgcr_sequence* s, int32_t* steps, double* rel_res,
 int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* W,
               void* hip_stream);
 
+/* Projected operator of the data-movement study (Section 6.3), real FP64:
+ * W = (I - C C^T) A V, where C has orthonormal columns.
+ *   A: CSR of order n (device arrays).
+ *   V, W: device, n x p row-major (leading dimension p), p in {1, 2, 4, 8, 16}; W
+ *         is overwritten and must not alias V.
+ *   C: device, kc >= 0 blocks of n x p row-major stored one after the other (block
+ *      b at C + b n p); zero columns are allowed as padding.
+ *   variant: 0 two passes of block classical Gram-Schmidt over all of C (each pass:
+ *            all dots C^T W, then W -= C S), the multi-pass CGS of Section 6.3;
+ *            1 block modified Gram-Schmidt, one pass, one block of C after the
+ *            other (s_b = C_b^T W, W -= C_b s_b); with p = 1 it is the
+ *            column-wise MGS of Section 6.3.
+ *   work: device scratch of at least bgcr_apply_projected_work_bytes(n, p, kc) bytes
+ *         (partials and coefficients; owned by the caller, contents ignored).
+ * Enqueued on hip_stream (may be NULL); returns once enqueued.  Errors: INVALID
+ * (NULL pointers, unsupported p or variant, kc < 0, short workspace, nnz < 0), HIP. */
+int bgcr_apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double* C,
+                         const double* V, double* W, int32_t variant, void* work,
+                         size_t work_bytes, void* hip_stream);
+
+/* Workspace bytes bgcr_apply_projected needs for (n, p, kc); 0 for invalid p or
+ * kc < 0. */
+size_t bgcr_apply_projected_work_bytes(int64_t n, int32_t p, int32_t kc);
+
 /* Kernel classes of the per-kernel profile. */
 typedef enum {
     BGCR_K_ARN_SPMM = 0,     /* Arnoldi sweep 1a: W = A V_j with V_j = W'' R^{-1} */

@@ -17,7 +17,8 @@ __all__ = [
     "BGCR_MIXED_FP32", "BGCR_MIXED_FP32_BF16", "BgcrError", "bgcr_params", "bgcr_csr", "bgcr_stats", "lib", "LIB_PATH",
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_strerror",
-    "bgcr_set_profiling", "bgcr_get_profile", "KERNEL_CLASSES",
+    "bgcr_set_profiling", "bgcr_get_profile", "bgcr_apply_projected", "bgcr_apply_projected_work_bytes",
+    "KERNEL_CLASSES",
     "DeviceCSR", "Sequence", "EXPORTED_SYMBOLS",
 ]
 
@@ -39,7 +40,7 @@ BGCR_MIXED_FP32_BF16 = 2
 EXPORTED_SYMBOLS = [
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_set_profiling",
-    "bgcr_get_profile", "bgcr_strerror",
+    "bgcr_get_profile", "bgcr_strerror", "bgcr_apply_projected", "bgcr_apply_projected_work_bytes",
 ]
 
 # kernel classes of the per-kernel profile (bgcr_kernel_class)
@@ -98,6 +99,10 @@ def lib():
         L.bgcr_get_cycle_log.argtypes = [c.c_void_p, c.POINTER(c.c_int32), c.POINTER(c.c_double), c.c_int32,
                                          c.POINTER(c.c_int32)]
         L.bgcr_spmm.argtypes = [c.POINTER(bgcr_csr), c.c_int32, c.c_int32, c.c_void_p, c.c_void_p, c.c_void_p]
+        L.bgcr_apply_projected.argtypes = [c.POINTER(bgcr_csr), c.c_int32, c.c_int32, c.c_void_p, c.c_void_p,
+                                           c.c_void_p, c.c_int32, c.c_void_p, c.c_size_t, c.c_void_p]
+        L.bgcr_apply_projected_work_bytes.argtypes = [c.c_int64, c.c_int32, c.c_int32]
+        L.bgcr_apply_projected_work_bytes.restype = c.c_size_t
         L.bgcr_set_profiling.argtypes = [c.c_void_p, c.c_int]
         L.bgcr_get_profile.argtypes = [c.c_void_p, c.POINTER(c.c_double), c.POINTER(c.c_double),
                                        c.POINTER(c.c_int64), c.c_int32]
@@ -105,7 +110,7 @@ def lib():
         L.bgcr_strerror.restype = c.c_char_p
         for name in ["bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_recycle_dim", "bgcr_get_recycle",
                      "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_set_profiling",
-                     "bgcr_get_profile"]:
+                     "bgcr_get_profile", "bgcr_apply_projected"]:
             getattr(L, name).restype = c.c_int
         _lib = L
     return _lib
@@ -184,6 +189,22 @@ def bgcr_spmm(A: "DeviceCSR", V, W, stream=None):
     dtype = BGCR_C128 if V.is_complex() else BGCR_F64
     _check(lib().bgcr_spmm(ctypes.byref(A.csr), dtype, int(V.shape[1]), _ptr(V), _ptr(W), _stream_handle(stream)),
            "bgcr_spmm")
+
+
+def bgcr_apply_projected_work_bytes(n: int, p: int, kc: int) -> int:
+    return int(lib().bgcr_apply_projected_work_bytes(int(n), int(p), int(kc)))
+
+
+def bgcr_apply_projected(A: "DeviceCSR", C, V, W, variant: int, work, stream=None):
+    """W = (I - C C^T) A V; C holds kc blocks of n x p (tensor of shape (kc, n, p),
+    or None for kc = 0); work: device tensor of at least
+    bgcr_apply_projected_work_bytes(n, p, kc) bytes."""
+    p = int(V.shape[1])
+    kc = 0 if C is None else int(C.shape[0])
+    nbytes = work.numel() * work.element_size()
+    _check(lib().bgcr_apply_projected(ctypes.byref(A.csr), p, kc, None if C is None else _ptr(C), _ptr(V), _ptr(W),
+                                      int(variant), _ptr(work), nbytes, _stream_handle(stream)),
+           "bgcr_apply_projected")
 
 
 def bgcr_set_profiling(seq, on: bool):

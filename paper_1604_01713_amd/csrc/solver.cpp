@@ -1849,6 +1849,76 @@ int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* 
     return e == hipSuccess ? BGCR_OK : BGCR_ERR_HIP;
 }
 
+// blocks of C per dot or update launch, and workgroups, of bgcr_apply_projected
+static int proj_chunk(int p) { return p >= 8 ? 16 : 32; }
+static constexpr int PROJ_NWG = 512;
+
+size_t bgcr_apply_projected_work_bytes(int64_t n, int32_t p, int32_t kc) {
+    if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16) || kc < 0 || n < 0) return 0;
+    const size_t ch = (size_t)std::max(1, std::min(kc, proj_chunk(p)));
+    // S (kc p x p) and the partials of one launch (PROJ_NWG x chunk p x p; the
+    // update sweeps also write a p x p Gram per workgroup)
+    return sizeof(double) * ((size_t)std::max(kc, 1) * p * p + (size_t)PROJ_NWG * (ch + 1) * p * p);
+}
+
+int bgcr_apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double* C, const double* V, double* W,
+                         int32_t variant, void* work, size_t work_bytes, void* hip_stream) {
+    if (!A || !V || !W || V == W || !work || A->n <= 0 || A->nnz < 0 || !A->row_ptr || !A->col_idx || !A->values)
+        return BGCR_ERR_INVALID;
+    if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16) || kc < 0 || (kc > 0 && !C) ||
+        (variant != 0 && variant != 1))
+        return BGCR_ERR_INVALID;
+    if (work_bytes < bgcr_apply_projected_work_bytes(A->n, p, kc)) return BGCR_ERR_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BGCR_ERR_HIP;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t n = A->n;
+    const int P2 = p * p;
+    double* S = (double*)work;
+    double* part = S + (size_t)std::max(kc, 1) * P2;
+    BlockPtrs none;
+    std::memset(&none, 0, sizeof(none));
+    auto blocks = [&](int b0, int nb) {
+        BlockPtrs q;
+        std::memset(&q, 0, sizeof(q));
+        for (int b = 0; b < nb; ++b) q.p[b] = C + (size_t)(b0 + b) * n * p;
+        return q;
+    };
+    // S[b0 ..] = C_{b0 ..}^T W for nb blocks
+    auto dots = [&](int b0, int nb) -> hipError_t {
+        BlockPtrs w;
+        std::memset(&w, 0, sizeof(w));
+        w.p[0] = W;
+        const hipError_t e = mfma_dot<double>(st, p, n, w, 1, blocks(b0, nb), nb, part, nullptr, PROJ_NWG);
+        if (e != hipSuccess) return e;
+        return reduce_partials<double>(st, part, PROJ_NWG, nb * P2, nullptr, S + (size_t)b0 * P2, nullptr);
+    };
+    // W -= C_{b0 ..} S[b0 ..] in place
+    auto update = [&](int b0, int nb) -> hipError_t {
+        const double* Sb = S + (size_t)b0 * P2;
+        if (p == 1) return narrow_sweep<double>(st, n, W, blocks(b0, nb), nb, Sb, W, part, PROJ_NWG, nullptr, false);
+        if (p == 2)
+            return Launch<double>::update_dot(st, p, n, W, blocks(b0, nb), nb, Sb, nullptr, W, 0, 1, part, PROJ_NWG,
+                                              nullptr, 2);
+        return mfma_proj_gram<double>(st, p, n, W, blocks(b0, nb), nb, Sb, W, part, nullptr, PROJ_NWG);
+    };
+    hipError_t e = Launch<double>::spmm_dot(st, p, n, A->row_ptr, A->col_idx, (const double*)A->values, V, nullptr,
+                                             nullptr, W, none, 0, 0, nullptr, nwg_for(n, p), nullptr);
+    const int ch = proj_chunk(p);
+    if (variant == 0) {
+        for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
+            for (int b0 = 0; b0 < kc && e == hipSuccess; b0 += ch) e = dots(b0, std::min(ch, kc - b0));
+            for (int b0 = 0; b0 < kc && e == hipSuccess; b0 += ch) e = update(b0, std::min(ch, kc - b0));
+        }
+    } else {
+        for (int b = 0; b < kc && e == hipSuccess; ++b) {
+            e = dots(b, 1);
+            if (e == hipSuccess) e = update(b, 1);
+        }
+    }
+    return e == hipSuccess ? BGCR_OK : BGCR_ERR_HIP;
+}
+
 int bgcr_set_profiling(bgcr_sequence* s, int on) {
     if (!s) return BGCR_ERR_INVALID;
     try {

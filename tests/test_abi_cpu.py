@@ -104,6 +104,17 @@ def test_hybrid_parameters_without_gpu(lib):
         assert lib.bgcr_create_sequence(ctypes.byref(bad), n, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID
 
 
+def test_projected_operator_arguments_without_gpu(lib):
+    """bgcr_apply_projected validates before touching the device; its workspace
+    holds S (kc p^2) and one launch's partials."""
+    wb = bg.bgcr_apply_projected_work_bytes
+    assert wb(1000, 3, 4) == 0 and wb(1000, 8, -1) == 0
+    assert wb(1000, 8, 13) == 8 * (13 * 64 + 512 * 14 * 64)
+    assert wb(1000, 1, 100) == 8 * (100 + 512 * 33)
+    csr = bg.bgcr_csr(100, 0, None, None, None)
+    assert lib.bgcr_apply_projected(ctypes.byref(csr), 8, 0, None, None, None, 0, None, 0, None) == bg.BGCR_ERR_INVALID
+
+
 def test_invalid_arguments_are_rejected_without_a_gpu(lib):
     h = ctypes.c_void_p()
     # the recycle refresh combines [U, C, V_1 .. V_{m+1}]: 2 ceil((k+1)/p) + m + 1 <= 64 blocks
