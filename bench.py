@@ -240,6 +240,90 @@ def bench_selection(args, torch, problems, bg, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_datamove(args, torch, problems, bg, dev):
+    """The data-movement study of Section 6.3 on one MI355X: a banded matrix
+    applied to a block of p vectors at once vs one vector at a time, then the
+    projected operator (I - C C^T) A with two-pass block CGS (DGKS) or block MGS,
+    again all at once vs one at a time.  Reported per configuration: the time
+    of one application (HIP events, mean of `reps`), its ratio to one
+    single-vector application (the paper's ratio plots), and the rate on model
+    bytes.  Cache behaviour is read from rocprofv3 counters of the same
+    workload (TCC hits and misses, FETCH_SIZE / WRITE_SIZE)."""
+    import numpy as np
+    ps = (1, 2, 4, 8, 16)
+    mats = [(10**4, 4), (10**5, 4), (10**6, 4), (10**6, 16), (10**6, 50), (10**7, 4), (10**7, 16)]
+    if args.datamove_small:
+        mats, ps = [(10**6, 16)], (1, 8)
+    kdims = (10,) if args.datamove_small else (10, 50, 100)
+    reps = 5
+    st = torch.cuda.current_stream()
+
+    def timed(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            fn()
+        e1.record(st)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    out = []
+    rng = np.random.default_rng(31)
+    for (n, bw) in mats:
+        t0 = time.perf_counter()
+        A = problems.banded(n, bw, seed=30)
+        dA = bg.DeviceCSR.from_scipy(A, dev)
+        nnz = A.nnz
+        del A
+        log(f"[bench] datamove: n={n} bandwidth={bw} nnz={nnz} (built in {time.perf_counter() - t0:.1f} s)")
+        Vall = torch.from_numpy(rng.uniform(-1, 1, (n, max(ps)))).to(dev)
+        Cfull = None
+        if n >= 10**5:
+            Cfull = torch.linalg.qr(torch.rand((n, max(kdims)), dtype=torch.float64, device=dev) - 0.5)[0]
+        cols = [Vall[:, j:j + 1].contiguous() for j in range(max(ps))]
+        outs = [torch.empty_like(c) for c in cols]
+        abytes = 12.0 * nnz + 4.0 * (n + 1)
+        t1 = timed(lambda: bg.bgcr_spmm(dA, cols[0], outs[0]))
+        row = {"n": n, "bandwidth": bw, "nnz": nnz, "spmv_s": t1, "spmm": {}, "projected": {}}
+        for p in ps:
+            V = Vall[:, :p].contiguous()
+            W = torch.empty_like(V)
+            tb = timed(lambda: bg.bgcr_spmm(dA, V, W))
+            ts = timed(lambda: [bg.bgcr_spmm(dA, cols[j], outs[j]) for j in range(p)])
+            row["spmm"][p] = {"block_s": tb, "one_at_a_time_s": ts, "block_over_single": tb / t1,
+                              "block_GBs": (abytes + 16.0 * n * p) / tb * 1e-9}
+        if Cfull is not None:
+            for kd in kdims:
+                for p in ps:
+                    kc = -(-kd // p)
+                    Cb = torch.zeros((kc * p, n), dtype=torch.float64, device=dev)
+                    Cb[:kd] = Cfull[:, :kd].T
+                    Cb = Cb.reshape(kc, p, n).transpose(1, 2).contiguous()   # kc blocks of n x p
+                    C1 = Cfull[:, :kd].T.contiguous().reshape(kd, n, 1)      # kd blocks of n x 1
+                    V = Vall[:, :p].contiguous()
+                    W = torch.empty_like(V)
+                    wk = torch.empty(max(bg.bgcr_apply_projected_work_bytes(n, p, kc),
+                                         bg.bgcr_apply_projected_work_bytes(n, 1, kd)), dtype=torch.uint8, device=dev)
+                    for var, name in ((0, "cgs2"), (1, "mgs")):
+                        tb = timed(lambda: bg.bgcr_apply_projected(dA, Cb, V, W, var, wk))
+                        ts = timed(lambda: [bg.bgcr_apply_projected(dA, C1, cols[j], outs[j], var, wk)
+                                            for j in range(p)])
+                        t1p = timed(lambda: bg.bgcr_apply_projected(dA, C1, cols[0], outs[0], var, wk))
+                        row["projected"][f"{name}_k{kd}_p{p}"] = {
+                            "block_s": tb, "one_at_a_time_s": ts, "block_over_single": tb / t1p}
+        out.append(row)
+        log(f"[bench] datamove n={n} bw={bw}: " + ", ".join(
+            f"p{p} {row['spmm'][p]['block_over_single']:.2f}x" for p in ps))
+        del dA, Vall, Cfull
+        torch.cuda.empty_cache()
+    res = {"metric": "block vs one-at-a-time application of A and of (I - C C^T) A (time ratio to one vector)",
+           "unit": "s", "config": {"workload": "banded_datamove", "block_sizes": list(ps),
+                                  "dim_C": list(kdims), "reps": reps},
+           "data": "synthetic", "n_gpus": 1, "results": out}
+    print(json.dumps(res), flush=True)
+
+
 def bench_serving(args, torch, problems, bg, dev):
     """A seeded request stream: serial plain FP64 (one request after the other)
     vs the served form (continuous batching, HBM-budget admission)."""
@@ -328,7 +412,9 @@ def main():
     ap.add_argument("--nsys", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
-    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection"], default="cfg2",
+    ap.add_argument("--datamove-small", action="store_true", help="datamove: one matrix, p in {1, 8} (profiling)")
+    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection", "datamove"],
+                    default="cfg2",
                     help="cfg2: the headline sequence (default); precision: plain FP64 vs the FP32-in-FP64 form on "
                          "the anisotropic 192^3 sequence; serving: a request stream, served vs serial; enlarged: one "
                          "right-hand side, block size 1 vs 8 and 16")
@@ -357,6 +443,8 @@ def main():
         return bench_enlarged(args, torch, problems, bg, dev)
     if args.workload == "selection":
         return bench_selection(args, torch, problems, bg, dev)
+    if args.workload == "datamove":
+        return bench_datamove(args, torch, problems, bg, dev)
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20
