@@ -1828,22 +1828,20 @@ int bgcr_get_cycle_log(const bgcr_sequence* s, int32_t* steps, double* rel_res, 
 }
 
 int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* W, void* hip_stream) {
-    if (!A || !V || !W || A->n <= 0 || !A->row_ptr || !A->col_idx || !A->values) return BGCR_ERR_INVALID;
+    if (!A || !V || !W || A->n <= 0 || A->nnz < 0 || !A->row_ptr || !A->col_idx || !A->values)
+        return BGCR_ERR_INVALID;
     if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16)) return BGCR_ERR_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return BGCR_ERR_HIP;
     hipStream_t st = (hipStream_t)hip_stream;
-    const int nwg = nwg_for(A->n, p);
-    BlockPtrs none;
-    std::memset(&none, 0, sizeof(none));
     hipError_t e;
+    // the block SpMM of the Arnoldi step (row-layout kernel, 16 bytes of a row per lane)
     if (dtype == BGCR_F64)
-        e = Launch<double>::spmm_dot(st, p, A->n, A->row_ptr, A->col_idx, (const double*)A->values,
-                                     (const double*)V, nullptr, nullptr, (double*)W, none, 0, 0, nullptr, nwg,
-                                     nullptr);
+        e = Launch<double>::spmm_rinv(st, p, A->n, A->nnz, A->row_ptr, A->col_idx, (const double*)A->values,
+                                      (const double*)V, nullptr, nullptr, (double*)W, nullptr);
     else if (dtype == BGCR_C128)
-        e = Launch<zd>::spmm_dot(st, p, A->n, A->row_ptr, A->col_idx, (const zd*)A->values, (const zd*)V, nullptr,
-                                 nullptr, (zd*)W, none, 0, 0, nullptr, nwg, nullptr);
+        e = Launch<zd>::spmm_rinv(st, p, A->n, A->nnz, A->row_ptr, A->col_idx, (const zd*)A->values, (const zd*)V,
+                                  nullptr, nullptr, (zd*)W, nullptr);
     else
         return BGCR_ERR_INVALID;
     return e == hipSuccess ? BGCR_OK : BGCR_ERR_HIP;
@@ -1876,8 +1874,6 @@ int bgcr_apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double*
     const int P2 = p * p;
     double* S = (double*)work;
     double* part = S + (size_t)std::max(kc, 1) * P2;
-    BlockPtrs none;
-    std::memset(&none, 0, sizeof(none));
     auto blocks = [&](int b0, int nb) {
         BlockPtrs q;
         std::memset(&q, 0, sizeof(q));
@@ -1902,8 +1898,8 @@ int bgcr_apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double*
                                               nullptr, 2);
         return mfma_proj_gram<double>(st, p, n, W, blocks(b0, nb), nb, Sb, W, part, nullptr, PROJ_NWG);
     };
-    hipError_t e = Launch<double>::spmm_dot(st, p, n, A->row_ptr, A->col_idx, (const double*)A->values, V, nullptr,
-                                             nullptr, W, none, 0, 0, nullptr, nwg_for(n, p), nullptr);
+    hipError_t e = Launch<double>::spmm_rinv(st, p, n, A->nnz, A->row_ptr, A->col_idx, (const double*)A->values, V,
+                                              nullptr, nullptr, W, nullptr);
     const int ch = proj_chunk(p);
     if (variant == 0) {
         for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {
