@@ -367,6 +367,107 @@ __global__ __launch_bounds__(256) void k_residual_rows(int64_t n, int64_t nnz, c
     }
 }
 
+// Narrow real blocks (P <= 4): S lanes per row, each lane taking every S-th
+// nonzero of its row (NB per lane and batch, all P columns), the partial sums
+// combined over the S lanes by cross-lane exchanges; the row's first lane
+// scales (SCALE: W = raw R^{-1}, V_j = Vin R^{-1}) and stores.  Indices past
+// the row are clamped and cancelled by a 0/1 factor.
+template <class T, class TI, class TV, class TW, int P, int S, int NB, bool SCALE>
+__global__ __launch_bounds__(256) void k_spmm_split(int64_t n, int64_t nnz, const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, const T* __restrict__ av,
+                                                    const TI* __restrict__ Vin, const acc_t<T>* __restrict__ Rinv,
+                                                    TV* __restrict__ Vout, TW* __restrict__ Wout, const Ctl* ctl) {
+    static_assert(std::is_same<T, double>::value || std::is_same<T, float>::value, "real blocks");
+    static_assert(64 % S == 0, "rows must not straddle a wave");
+    using A = acc_t<T>;
+    constexpr int ROWS = 256 / S;
+    if (ctl && ctl->active == 0) return;
+    __shared__ A Rs[SCALE ? P * P : 1];
+    const int t = threadIdx.x, r = t / S, prt = t % S;
+    if constexpr (SCALE) {
+        for (int e = t; e < P * P; e += 256) Rs[e] = Rinv ? Rinv[e] : (e / P == e % P ? A{1.0} : A{});
+        __syncthreads();
+    }
+    const int64_t ntiles = (n + ROWS - 1) / ROWS;
+    int64_t first, step, end;
+    xcd_tiles(ntiles, first, step, end);
+    const int64_t nzl = nnz - 1;
+    for (int64_t tile = first; tile < end; tile += step) {
+        const int64_t row = tile * ROWS + r;
+        const int64_t rowc = clamp_row(row, n);
+        const int beg = __builtin_nontemporal_load(rp + rowc);
+        const int e = __builtin_nontemporal_load(rp + rowc + 1);
+        T acc[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) acc[j] = T(0);
+        for (int kb = beg; kb < e; kb += S * NB) {
+            int cols[NB];
+            T vals[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int64_t kk = (int64_t)kb + prt + S * u;
+                const int64_t kc = kk < nzl ? kk : nzl;
+                cols[u] = __builtin_nontemporal_load(ci + kc);
+                vals[u] = ld_nt(av + kc);
+            }
+            T g[NB][P];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) load_as<T, TI, P, P>(g[u], Vin + (int64_t)cols[u] * P);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const T a = mscale(vals[u], (T)((int64_t)kb + prt + S * u < e ? 1 : 0));
+#pragma unroll
+                for (int j = 0; j < P; ++j) acc[j] += a * g[u][j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+#pragma unroll
+            for (int off = 1; off < S; off <<= 1) acc[j] += __shfl_xor(acc[j], off, 64);
+        if (prt == 0 && row < n) {
+            if constexpr (!SCALE) {
+                store_as<T, TW, P, P>(Wout + row * P, acc);
+            } else {
+                T vb[P];
+                load_as<T, TI, P, P>(vb, Vin + row * P);
+                T wo[P], vo[P];
+#pragma unroll
+                for (int j = 0; j < P; ++j) {
+                    A w = A{}, v = A{};
+#pragma unroll
+                    for (int a = 0; a < P; ++a) {
+                        w += widen(acc[a]) * Rs[a * P + j];
+                        v += widen(vb[a]) * Rs[a * P + j];
+                    }
+                    wo[j] = narrow<T>(w);
+                    vo[j] = narrow<T>(v);
+                }
+                store_as<T, TW, P, P>(Wout + row * P, wo);
+                store_as<T, TV, P, P>(Vout + row * P, vo);
+            }
+        }
+    }
+}
+
+template <class T, class TI, class TV, class TW, int P>
+hipError_t launch_spmm_split(hipStream_t st, int64_t n, int64_t nnz, const int* rp, const int* ci, const T* av,
+                             const TI* Vin, const acc_t<T>* Rinv, TV* Vout, TW* Wout, const Ctl* ctl, int max_wg) {
+    constexpr int S = 4, NB = 2, ROWS = 256 / S;
+    const int64_t tiles = (n + ROWS - 1) / ROWS;
+    int64_t g = tiles < max_wg ? tiles : max_wg;
+    if (g >= 8) g -= g % 8;
+    const int nwg = (int)(g < 1 ? 1 : g);
+    if (Vout)
+        hipLaunchKernelGGL((k_spmm_split<T, TI, TV, TW, P, S, NB, true>), dim3(nwg), dim3(256), 0, st, n, nnz, rp, ci,
+                           av, Vin, Rinv, Vout, Wout, ctl);
+    else if (Rinv)
+        return hipErrorInvalidValue;
+    else
+        hipLaunchKernelGGL((k_spmm_split<T, TI, TV, TW, P, S, NB, false>), dim3(nwg), dim3(256), 0, st, n, nnz, rp,
+                           ci, av, Vin, Rinv, Vout, Wout, ctl);
+    return hipGetLastError();
+}
+
 // columns per lane: 16 bytes, so that a load instruction of a wave reads one
 // contiguous span of the block (measured fastest on the 7-point stencil:
 // about 1.5x the throughput of one lane per column or per row)
@@ -429,6 +530,12 @@ hipError_t spmm_block(hipStream_t st, int P, int64_t n, int64_t nnz, const int* 
     if (P == 8) BGCR_SP_L(8)
     if (P == 16) BGCR_SP_L(16)
     if constexpr (!half) {
+        // real blocks of up to 4 columns: rows split over 4 lanes
+        if constexpr (std::is_same<T, double>::value || std::is_same<T, float>::value) {
+            if (P == 1) return sp::launch_spmm_split<T, TI, TV, TW, 1>(st, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl, 2048);
+            if (P == 2) return sp::launch_spmm_split<T, TI, TV, TW, 2>(st, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl, 2048);
+            if (P == 4) return sp::launch_spmm_split<T, TI, TV, TW, 4>(st, n, nnz, rp, ci, av, Vin, Rinv, Vout, Wout, ctl, 2048);
+        }
         if (P == 1) BGCR_SP_L(1)
         if (P == 2) BGCR_SP_L(2)
         if (P == 4) BGCR_SP_L(4)
