@@ -888,13 +888,15 @@ __global__ __launch_bounds__(256) void k_combine_scalar(int64_t n, BlockPtrs in,
             for (int oc = 0; oc < NCO; ++oc) {
                 const int col = 16 * oc + bl;
                 const int ob = col / P, b = col % P;
-                TO* ybase;
-                if constexpr (P == 16) {
-                    ybase = (TO*)out.p[oc];
-                } else {
-                    TO* y0 = (TO*)out.p[2 * oc];
-                    TO* y1 = (TO*)out.p[2 * oc + 1 < nout ? 2 * oc + 1 : 2 * oc];
-                    ybase = (ob & 1) ? y1 : y0;
+                // output block of this lane's column: one of the 16 / P blocks of the
+                // chunk, picked by selects over compile-time indices (blocks past
+                // nout fall back to the chunk's first and are never written)
+                constexpr int BPC = 16 / P;
+                TO* ybase = (TO*)out.p[BPC * oc];
+#pragma unroll
+                for (int u = 1; u < BPC; ++u) {
+                    TO* pu = (TO*)out.p[BPC * oc + u < nout ? BPC * oc + u : BPC * oc];
+                    ybase = (ob % BPC == u) ? pu : ybase;
                 }
                 double old[4] = {0, 0, 0, 0};
                 if (16 * oc < accumulate * P) {  // some output block of this chunk is accumulated
@@ -989,13 +991,15 @@ __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, i
             for (int oc = 0; oc < NCO; ++oc) {
                 const int col = 16 * oc + bl;
                 const int ob = col / P, b = col % P;
-                TO* ybase;
-                if constexpr (P == 16) {
-                    ybase = (TO*)out.p[oc];
-                } else {
-                    TO* y0 = (TO*)out.p[2 * oc];
-                    TO* y1 = (TO*)out.p[2 * oc + 1 < nout ? 2 * oc + 1 : 2 * oc];
-                    ybase = (ob & 1) ? y1 : y0;
+                // output block of this lane's column: one of the 16 / P blocks of the
+                // chunk, picked by selects over compile-time indices (blocks past
+                // nout fall back to the chunk's first and are never written)
+                constexpr int BPC = 16 / P;
+                TO* ybase = (TO*)out.p[BPC * oc];
+#pragma unroll
+                for (int u = 1; u < BPC; ++u) {
+                    TO* pu = (TO*)out.p[BPC * oc + u < nout ? BPC * oc + u : BPC * oc];
+                    ybase = (ob % BPC == u) ? pu : ybase;
                 }
                 double old[4] = {0, 0, 0, 0};
                 if (16 * oc < accumulate * P) {  // some output block of this chunk is accumulated
@@ -1155,6 +1159,10 @@ hipError_t mfma_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, i
                         const double* coef, int accumulate, int nwg) {
     if (P == 8) return mx::launch_combine<TI, TO, 8>(st, n, in, nin, out, nout, coef, accumulate, nwg);
     if (P == 16) return mx::launch_combine<TI, TO, 16>(st, n, in, nin, out, nout, coef, accumulate, nwg);
+    // four-column FP64 blocks: the scalar-load kernel (a chunk spans 4 output blocks)
+    if constexpr (std::is_same<TI, double>::value) {
+        if (P == 4) return mx::launch_combine<TI, TO, 4>(st, n, in, nin, out, nout, coef, accumulate, nwg);
+    }
     return hipErrorNotSupported;
 }
 

@@ -454,7 +454,8 @@ struct Seq final : bgcr_sequence {
         const double by = (double)n * P * ((double)sizeof(TB) * nin + (double)sizeof(TO) * (nout + accumulate));
         run(BGCR_K_COMBINE, by, [&] {
             if constexpr (!std::is_same<T, zd>::value) {
-                if (use_mx) {
+                // matrix cores: the Arnoldi configurations, and four-column FP64 blocks
+                if (use_mx || (P == 4 && std::is_same<TB, double>::value)) {
                     const hipError_t e =
                         mfma_combine<TB, TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate, nwg_mx);
                     if (e != hipErrorNotSupported) return e;
