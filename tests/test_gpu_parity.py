@@ -90,6 +90,34 @@ def test_block_spmm_matches_dense_product(p, cplx):
     assert np.linalg.norm(W - ref) <= 1e-14 * np.linalg.norm(ref) * 10
 
 
+@pytest.mark.parametrize("p", [1, 2, 4, 8])
+@pytest.mark.parametrize("bw", [50, 0])
+def test_block_spmm_long_and_empty_rows(p, bw):
+    """Rows of 101 nonzeros (13 batches of the split-row kernel for p <= 4) and
+    a matrix with empty rows (bw = 0: only every third diagonal entry kept),
+    against the dense product; ragged row count."""
+    bg = _bg()
+    dev = _dev()
+    n = 3001
+    if bw:
+        A = problems.banded(n, bw, seed=41)
+    else:
+        d = np.arange(n, dtype=np.float64) + 1.0
+        d[np.arange(n) % 3 != 0] = 0.0
+        A = sp.diags(d, 0, format="csr")
+        A.eliminate_zeros()
+    rng = np.random.default_rng(42 + p)
+    V = rng.uniform(-1, 1, (n, p))
+    Ad = bg.DeviceCSR.from_scipy(A, dev)
+    Vd = torch.from_numpy(V).to(dev)
+    Wd = torch.full_like(Vd, 7.0)
+    bg.bgcr_spmm(Ad, Vd, Wd)
+    torch.cuda.synchronize()
+    W = Wd.cpu().numpy()
+    ref = A.toarray() @ V
+    assert np.linalg.norm(W - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
 # ---- whole method ------------------------------------------------------------
 
 def test_cfg1_sequence_parity():
