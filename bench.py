@@ -328,14 +328,22 @@ def bench_serving(args, torch, problems, bg, dev):
     """A seeded request stream: serial plain FP64 (one request after the other)
     vs the served form (continuous batching, HBM-budget admission)."""
     from paper_1604_01713_amd import serving as sv
-    descs = problems.serving_requests(seed=5, nreq=args.requests, sides=(32, 48, 64, 80), ps=(1, 4, 8, 16),
-                                      nsys_range=(2, 5))
+    if args.serving_full:
+        # the stream's own size distributions (grids 64^3..160^3, 4-16 systems per request, 32 GB admission
+        # budget), with fewer requests so that the run takes minutes
+        sides, nsys_range, budget = tuple(range(64, 161, 16)), (4, 16), 32 << 30
+    else:
+        sides, nsys_range, budget = (32, 48, 64, 80), (2, 5), 4 << 30
+    descs = problems.serving_requests(seed=5, nreq=args.requests, sides=sides, ps=(1, 4, 8, 16),
+                                      nsys_range=nsys_range)
     cache = {}
     t0 = time.perf_counter()
     for d in descs:
         for i in range(d["nsys"]):
             s_ = problems.request_system(d, i)
             cache[(d["id"], i)] = (s_.A, s_.B)
+        if args.serving_full:
+            log(f"[bench] serving: request {d['id']} generated ({d['nsys']} systems, {d['side']}^3, p={d['p']})")
     log(f"[bench] serving: generated {len(cache)} systems for {len(descs)} requests in {time.perf_counter() - t0:.1f}s")
 
     def make(prec, arrivals=None):
@@ -348,7 +356,6 @@ def bench_serving(args, torch, problems, bg, dev):
                                    m=10, k=20, tol=1e-8, precision=prec))
         return reqs
 
-    budget = 4 << 30
     nb = lambda r: sv.device_bytes(r, sv.library_footprint)
     run = sv.gpu_runner(device=dev, keep_solutions=True)
 
@@ -393,8 +400,9 @@ def bench_serving(args, torch, problems, bg, dev):
     log(f"[bench] served mixed, Poisson arrivals: {out['served_mixed_poisson']}")
     nsys = sum(d["nsys"] for d in descs)
     resj = {"metric": "served stream: systems/s and p50/p99 request latency vs serial plain FP64", "unit": "systems/s",
-            "config": {"workload": f"served_convdiff3d_{len(descs)}req", "requests": len(descs), "systems": nsys,
-                       "sides": [32, 48, 64, 80], "p": [1, 4, 8, 16], "systems_per_request": [2, 5],
+            "config": {"workload": f"served_convdiff3d_{len(descs)}req" + ("_full_sizes" if args.serving_full else ""),
+                       "requests": len(descs), "systems": nsys,
+                       "sides": list(sides), "p": [1, 4, 8, 16], "systems_per_request": list(nsys_range),
                        "m": 10, "k": 20, "tol": 1e-8, "slots": 8, "hbm_budget_bytes": budget},
             **out,
             "speedup_served_mixed_over_serial_fp64": round(out["served_mixed"]["systems_per_s"] /
@@ -419,6 +427,8 @@ def main():
                          "the anisotropic 192^3 sequence; serving: a request stream, served vs serial; enlarged: one "
                          "right-hand side, block size 1 vs 8 and 16")
     ap.add_argument("--requests", type=int, default=24, help="serving: number of requests")
+    ap.add_argument("--serving-full", action="store_true",
+                    help="serving: the full size distributions (64^3..160^3 grids, 4-16 systems, 32 GB budget)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB 5 times (scale factor of the PMC byte counters)")
     args = ap.parse_args()
