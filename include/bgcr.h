@@ -181,7 +181,7 @@ int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* 
  *   V, W: device, n x p row-major (leading dimension p), p in {1, 2, 4, 8, 16}; W
  *         is overwritten and must not alias V.
  *   C: device, kc >= 0 blocks of n x p row-major stored one after the other (block
- *      b at C + b n p); zero columns are allowed as padding.
+ *      b at C + b n p); zero columns are allowed as padding; must not overlap W.
  *   variant: 0 two passes of block classical Gram-Schmidt over all of C (each pass:
  *            all dots C^T W, then W -= C S), the multi-pass CGS of Section 6.3;
  *            1 block modified Gram-Schmidt, one pass, one block of C after the
