@@ -324,6 +324,39 @@ def bench_datamove(args, torch, problems, bg, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_blocksizes(args, torch, problems, bg, dev):
+    """Per-cycle time and per-kernel-class split by block size: one system of
+    the headline sequence's matrices with p = 1, 4, 8 right-hand sides, a fixed
+    number of restart cycles (`--cycles`), the library's per-launch HIP-event
+    profile (kernel classes of bgcr_kernel_class)."""
+    out = {}
+    for p in (1, 4, 8):
+        w = problems.cfg2(N=args.grid, nsys=1, p=p)
+        A, B = w.systems[0].A, w.systems[0].B
+        dA = bg.DeviceCSR.from_scipy(A, dev)
+        dB = torch.from_numpy(B).to(dev)
+        seq = bg.Sequence(A.shape[0], p, w.m, w.k, max_cycles=args.cycles)
+        seq.set_profiling(True)
+        dX = torch.zeros_like(dB)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = seq.solve(dA, dB, dX, w.tol)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prof = seq.profile()
+        seq.release()
+        c = st.cycles
+        out[f"p{p}"] = {"cycles": c, "ms_per_cycle": round(1e3 * el / c, 3),
+                        "classes_ms_per_cycle": {k: round(v["ms"] / c, 3) for k, v in prof.items() if v["launches"]},
+                        "classes_GBs": {k: round(v["bytes"] / v["ms"] / 1e6, 0) for k, v in prof.items()
+                                        if v["ms"] > 0 and v["bytes"] > 0}}
+        log(f"[bench] blocksizes p={p}: {out[f'p{p}']['ms_per_cycle']} ms/cycle over {c} cycles")
+    res = {"metric": "ms per restart cycle by block size (one system, fixed cycle count)", "unit": "ms",
+           "config": {"workload": f"convdiff3d_{args.grid}^3_p1_4_8_m10_k20_{args.cycles}cycles"},
+           "data": "synthetic", "n_gpus": 1, **out}
+    print(json.dumps(res), flush=True)
+
+
 def bench_serving(args, torch, problems, bg, dev):
     """A seeded request stream: serial plain FP64 (one request after the other)
     vs the served form (continuous batching, HBM-budget admission)."""
@@ -421,7 +454,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--datamove-small", action="store_true", help="datamove: one matrix, p in {1, 8} (profiling)")
-    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection", "datamove"],
+    ap.add_argument("--cycles", type=int, default=40, help="blocksizes: restart cycles per block size")
+    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection", "datamove",
+                                           "blocksizes"],
                     default="cfg2",
                     help="cfg2: the headline sequence (default); precision: plain FP64 vs the FP32-in-FP64 form on "
                          "the anisotropic 192^3 sequence; serving: a request stream, served vs serial; enlarged: one "
@@ -455,6 +490,8 @@ def main():
         return bench_selection(args, torch, problems, bg, dev)
     if args.workload == "datamove":
         return bench_datamove(args, torch, problems, bg, dev)
+    if args.workload == "blocksizes":
+        return bench_blocksizes(args, torch, problems, bg, dev)
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20
