@@ -15,7 +15,7 @@ the generalized form eq. harm-ritz-gen-eig, exact eigenvalues when the block
 Krylov space is the whole space, the Petrov-Galerkin condition by brute
 force), the Vital containment bound (Section 5) and equivariance.
 
-Readings of points the paper leaves open (each one is listed in the design doc):
+Readings of points the paper leaves open:
   * E in Algorithm 1 is the first p columns of the identity of order (m+1)p
     (the block GMRES right-hand side E_1 F_0 of eq. true-block-gmres-min).
   * The stopping test is relative: ||B - A X||_F <= tol ||B||_F.  Inside a cycle
