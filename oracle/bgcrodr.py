@@ -13,7 +13,10 @@ residual over U + K_m by brute force, reduction to restarted GMRES at k=0, p=1
 (against scipy's gmres), harmonic-Ritz checks (Proposition block-harm-ritz vs
 the generalized form eq. harm-ritz-gen-eig, exact eigenvalues when the block
 Krylov space is the whole space, the Petrov-Galerkin condition by brute
-force), the Vital containment bound (Section 5) and equivariance.
+force), which vectors every refresh recycles (the refreshed U spans the
+selected pairs of the harmonic problem formed again from explicit products of
+A on [U, W_m], smallest or largest modulus), the Vital containment bound
+(Section 5) and equivariance.
 
 Readings of points the paper leaves open:
   * E in Algorithm 1 is the first p columns of the identity of order (m+1)p

@@ -1,11 +1,13 @@
 """Plant plausible mistakes in the oracle (on the CPU only) and check that the
-pins catch each one: a dropped term, a wrong sign, a transposed operand and a
-wrong index.  This shows the pins are strong enough to be trusted."""
+pins catch each one: a dropped term, a wrong sign, a transposed operand, a
+wrong index, the wrong end of the harmonic Ritz selection and a pencil without
+the metric W~^H W^.  This shows the pins are strong enough to be trusted."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
 
 import oracle.bgcrodr as ob
+import pinlib
 import problems as P
 
 
@@ -112,3 +114,52 @@ def test_wrong_rhs_block_index_is_caught(monkeypatch):
     finally:
         monkeypatch.setattr(ob.np.linalg, "lstsq", orig_lstsq)
     assert _caught(viol)
+
+
+# ---- which harmonic Ritz vectors are recycled (Section 4.1.2) ---------------
+
+def _selection_violation(largest=False):
+    A, B = _problem()
+    X, U, st = ob.solve(A, B, np.zeros_like(B), 1e-12, 4, 3, max_cycles=4, trace=True, select_largest=largest)
+    return pinlib.recycle_selection_violation(A.toarray(), st["trace"], 3, largest)
+
+
+def test_unmutated_selection_passes():
+    for largest in (False, True):
+        worst, checked = _selection_violation(largest)
+        assert checked >= 3 and worst <= 1e-8
+
+
+@pytest.mark.parametrize("largest", [False, True])
+def test_flipped_selection_in_augmented_refresh_is_caught(monkeypatch, largest):
+    """refresh_augmented keeping the other end of the spectrum."""
+    orig = ob.refresh_augmented
+
+    def bad(U, C, cyc, k, largest=False, real=True, ritz=False):
+        return orig(U, C, cyc, k, not largest, real, ritz)
+
+    monkeypatch.setattr(ob, "refresh_augmented", bad)
+    assert _selection_violation(largest)[0] > 1e-3
+
+
+@pytest.mark.parametrize("largest", [False, True])
+def test_flipped_selection_in_first_refresh_is_caught(monkeypatch, largest):
+    """refresh_first (Proposition block-harm-ritz) keeping the other end."""
+    orig = ob.refresh_first
+
+    def bad(cyc, k, largest=False, real=True, ritz=False):
+        return orig(cyc, k, not largest, real, ritz)
+
+    monkeypatch.setattr(ob, "refresh_first", bad)
+    assert _selection_violation(largest)[0] > 1e-3
+
+
+def test_pencil_without_metric_is_caught(monkeypatch):
+    """eq. harm-ritz-gen-eig solved as G^H G t = theta G^H [I; 0] t, i.e. with
+    W~^H W^ replaced by the identity it would be for an orthonormal W^."""
+    def bad(G, Wt, Wh):
+        M = np.eye(Wt.shape[1], Wh.shape[1], dtype=G.dtype)
+        return sla.eig(G.conj().T @ G, G.conj().T @ M)
+
+    monkeypatch.setattr(ob, "harmonic_ritz_augmented", bad)
+    assert _selection_violation()[0] > 1e-3

@@ -10,6 +10,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 import oracle as O
+import pinlib
 import problems as P
 
 
@@ -420,6 +421,40 @@ def test_harmonic_ritz_petrov_galerkin_bruteforce(cplx):
         y = Wh @ t
         r = Ad @ y - th * y
         assert np.linalg.norm(AW.conj().T @ r) <= 1e-8 * np.linalg.norm(AW) * np.linalg.norm(y) * max(1, abs(th))
+
+
+@pytest.mark.parametrize("cplx,largest,p,m,k", [
+    (False, False, 3, 5, 4), (False, True, 3, 5, 4), (False, False, 1, 8, 5), (False, True, 1, 8, 5),
+    (False, False, 2, 4, 3), (True, False, 2, 4, 3), (True, True, 3, 5, 4)])
+def test_harmonic_selection_spans_selected_pairs_of_explicit_problem(cplx, largest, p, m, k):
+    """Which harmonic Ritz vectors are recycled (Section 4.1.2: the refresh
+    after Proposition block-harm-ritz in the first cycle and after eq.
+    harm-ritz-gen-eig later; smallest modulus by default, largest as in
+    Section 6.2).  For every traced cycle the harmonic problem is formed again
+    from explicit dense products of A on the searched space What = [U, W_m]
+    (W_m in the first cycle):  (A What)^H (A What) t = theta (A What)^H What t,
+    the k values of smallest (largest) modulus are taken, conjugate pairs whole,
+    and the refreshed U must span What t_sel: sine of the largest principal
+    angle <= 1e-8."""
+    A, B = _small(p=p, cplx=cplx)
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-10, m, k, max_cycles=5, trace=True, select_largest=largest)
+    worst, checked = pinlib.recycle_selection_violation(A.toarray(), st["trace"], k, largest, real=not cplx)
+    assert checked >= 4 and checked >= len(st["trace"]) - 1
+    assert st["trace"][0]["U_in"] is None            # the first-cycle (no U) refresh is among them
+    assert worst <= 1e-8
+
+
+def test_harmonic_selection_after_recycle_import():
+    """The same pin on the second system of a sequence, whose first cycle
+    refreshes a U that came from the previous system and was imported
+    (A U = C S, Algorithm 1)."""
+    A, B = _small(p=2)
+    A2 = (A + 0.05 * sp.identity(A.shape[0])).tocsr()
+    X, U, st = O.solve(A, B, np.zeros_like(B), 1e-10, 4, 3)
+    X2, U2, st2 = O.solve(A2, B[::-1].copy(), np.zeros_like(B), 1e-10, 4, 3, U=U, trace=True, max_cycles=4)
+    assert st2["trace"][0]["U_in"] is not None
+    worst, checked = pinlib.recycle_selection_violation(A2.toarray(), st2["trace"], 3)
+    assert checked >= 3 and worst <= 1e-8
 
 
 def test_select_ritz_keeps_conjugate_pairs_whole():
