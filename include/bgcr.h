@@ -199,6 +199,29 @@ int bgcr_apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double*
  * kc < 0. */
 size_t bgcr_apply_projected_work_bytes(int64_t n, int32_t p, int32_t kc);
 
+/* Size of the library's own device workspace used by
+ * bgcr_apply_projected_noalloc (20 MiB; each GPU the library runs on holds one
+ * until the process ends). */
+#define BGCR_NOALLOC_SCRATCH_BYTES (20u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation as bgcr_apply_projected, with the same kernels and results, but
+ * the workspace is a device array inside the library, so no call allocates
+ * (no hipMalloc, hipFree or allocating library routine).
+ *   A, p, kc, C, V, W, variant, hip_stream: as for bgcr_apply_projected; the
+ *   caller still owns and passes the inputs and the output.
+ * Limit: bgcr_apply_projected_work_bytes(n, p, kc) must not exceed
+ * BGCR_NOALLOC_SCRATCH_BYTES (p = 16: kc <= 1536 blocks; p <= 8: kc <= 32250),
+ * else BGCR_ERR_INVALID before anything is enqueued.
+ * Every call on one GPU shares that GPU's workspace, which keeps the last
+ * call's contents (nothing in it needs to start at zero): calls that overlap on
+ * one GPU, from several streams or threads, race and give undefined results.
+ * Errors: INVALID (as bgcr_apply_projected, or the size limit), HIP (no device,
+ * or the workspace address could not be looked up). */
+int bgcr_apply_projected_noalloc(const bgcr_csr* A, int32_t p, int32_t kc, const double* C,
+                                 const double* V, double* W, int32_t variant, void* hip_stream);
+
 /* Kernel classes of the per-kernel profile. */
 typedef enum {
     BGCR_K_ARN_SPMM = 0,     /* Arnoldi sweep 1a: W = A V_j with V_j = W'' R^{-1} */

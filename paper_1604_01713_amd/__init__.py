@@ -18,7 +18,7 @@ __all__ = [
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_strerror",
     "bgcr_set_profiling", "bgcr_get_profile", "bgcr_apply_projected", "bgcr_apply_projected_work_bytes",
-    "KERNEL_CLASSES",
+    "bgcr_apply_projected_noalloc", "BGCR_NOALLOC_SCRATCH_BYTES", "KERNEL_CLASSES",
     "DeviceCSR", "Sequence", "EXPORTED_SYMBOLS",
 ]
 
@@ -41,7 +41,11 @@ EXPORTED_SYMBOLS = [
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_set_profiling",
     "bgcr_get_profile", "bgcr_strerror", "bgcr_apply_projected", "bgcr_apply_projected_work_bytes",
+    "bgcr_apply_projected_noalloc",
 ]
+
+# bytes of the library's own workspace of bgcr_apply_projected_noalloc (bgcr.h)
+BGCR_NOALLOC_SCRATCH_BYTES = 20 << 20
 
 # kernel classes of the per-kernel profile (bgcr_kernel_class)
 KERNEL_CLASSES = ["arn_spmm", "arn_dot", "proj_dot", "proj_gram", "small", "combine", "residual", "tsdot", "spmm",
@@ -101,6 +105,8 @@ def lib():
         L.bgcr_spmm.argtypes = [c.POINTER(bgcr_csr), c.c_int32, c.c_int32, c.c_void_p, c.c_void_p, c.c_void_p]
         L.bgcr_apply_projected.argtypes = [c.POINTER(bgcr_csr), c.c_int32, c.c_int32, c.c_void_p, c.c_void_p,
                                            c.c_void_p, c.c_int32, c.c_void_p, c.c_size_t, c.c_void_p]
+        L.bgcr_apply_projected_noalloc.argtypes = [c.POINTER(bgcr_csr), c.c_int32, c.c_int32, c.c_void_p,
+                                                   c.c_void_p, c.c_void_p, c.c_int32, c.c_void_p]
         L.bgcr_apply_projected_work_bytes.argtypes = [c.c_int64, c.c_int32, c.c_int32]
         L.bgcr_apply_projected_work_bytes.restype = c.c_size_t
         L.bgcr_set_profiling.argtypes = [c.c_void_p, c.c_int]
@@ -110,7 +116,7 @@ def lib():
         L.bgcr_strerror.restype = c.c_char_p
         for name in ["bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_recycle_dim", "bgcr_get_recycle",
                      "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_set_profiling",
-                     "bgcr_get_profile", "bgcr_apply_projected"]:
+                     "bgcr_get_profile", "bgcr_apply_projected", "bgcr_apply_projected_noalloc"]:
             getattr(L, name).restype = c.c_int
         _lib = L
     return _lib
@@ -205,6 +211,16 @@ def bgcr_apply_projected(A: "DeviceCSR", C, V, W, variant: int, work, stream=Non
     _check(lib().bgcr_apply_projected(ctypes.byref(A.csr), p, kc, None if C is None else _ptr(C), _ptr(V), _ptr(W),
                                       int(variant), _ptr(work), nbytes, _stream_handle(stream)),
            "bgcr_apply_projected")
+
+
+def bgcr_apply_projected_noalloc(A: "DeviceCSR", C, V, W, variant: int, stream=None):
+    """As bgcr_apply_projected, with the library's own device workspace (no
+    allocation in the call; calls overlapping on one GPU race)."""
+    p = int(V.shape[1])
+    kc = 0 if C is None else int(C.shape[0])
+    _check(lib().bgcr_apply_projected_noalloc(ctypes.byref(A.csr), p, kc, None if C is None else _ptr(C), _ptr(V),
+                                              _ptr(W), int(variant), _stream_handle(stream)),
+           "bgcr_apply_projected_noalloc")
 
 
 def bgcr_set_profiling(seq, on: bool):

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <cstdlib>
 #include <cstring>
@@ -1714,6 +1715,33 @@ void hybrid_parts(const bgcr_params* prm, bgcr_params& big, bgcr_params& one) {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// Workspace of bgcr_apply_projected_noalloc: one array per GPU, resident until
+// the process ends.  Host code never passes the array's name to a kernel (on
+// the host it is only a stand-in for the symbol); it uses the device address
+// that hipGetSymbolAddress returns for the current device, looked up once per
+// device on the first call there.
+static __device__ __align__(256) unsigned char scratch[BGCR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[kMaxDevices] = {};
+
+int noalloc_scratch(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return BGCR_ERR_HIP;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return BGCR_ERR_HIP;
+        scratch_ptr[dev] = ptr;
+    }
+    *out = scratch_ptr[dev];
+    return BGCR_OK;
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 extern "C" {
 
 int bgcr_create_sequence(const bgcr_params* prm, int64_t n, void* hip_stream, bgcr_sequence** out) {
@@ -1860,8 +1888,8 @@ size_t bgcr_apply_projected_work_bytes(int64_t n, int32_t p, int32_t kc) {
     return sizeof(double) * ((size_t)std::max(kc, 1) * p * p + (size_t)PROJ_NWG * (ch + 1) * p * p);
 }
 
-int bgcr_apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double* C, const double* V, double* W,
-                         int32_t variant, void* work, size_t work_bytes, void* hip_stream) {
+static int apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double* C, const double* V, double* W,
+                           int32_t variant, void* work, size_t work_bytes, void* hip_stream) {
     if (!A || !V || !W || V == W || !work || A->n <= 0 || A->nnz < 0 || !A->row_ptr || !A->col_idx || !A->values)
         return BGCR_ERR_INVALID;
     if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16) || kc < 0 || (kc > 0 && !C) ||
@@ -1914,6 +1942,22 @@ int bgcr_apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double*
         }
     }
     return e == hipSuccess ? BGCR_OK : BGCR_ERR_HIP;
+}
+
+int bgcr_apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double* C, const double* V, double* W,
+                         int32_t variant, void* work, size_t work_bytes, void* hip_stream) {
+    return apply_projected(A, p, kc, C, V, W, variant, work, work_bytes, hip_stream);
+}
+
+int bgcr_apply_projected_noalloc(const bgcr_csr* A, int32_t p, int32_t kc, const double* C, const double* V,
+                                 double* W, int32_t variant, void* hip_stream) {
+    if (!A || A->n <= 0) return BGCR_ERR_INVALID;
+    const size_t need = bgcr_apply_projected_work_bytes(A->n, p, kc);
+    if (need == 0 || need > (size_t)BGCR_NOALLOC_SCRATCH_BYTES) return BGCR_ERR_INVALID;
+    void* ptr = nullptr;
+    const int rc = noalloc_scratch(&ptr);
+    if (rc != BGCR_OK) return rc;
+    return apply_projected(A, p, kc, C, V, W, variant, ptr, (size_t)BGCR_NOALLOC_SCRATCH_BYTES, hip_stream);
 }
 
 int bgcr_set_profiling(bgcr_sequence* s, int on) {

@@ -113,6 +113,13 @@ def test_projected_operator_arguments_without_gpu(lib):
     assert wb(1000, 1, 100) == 8 * (100 + 512 * 33)
     csr = bg.bgcr_csr(100, 0, None, None, None)
     assert lib.bgcr_apply_projected(ctypes.byref(csr), 8, 0, None, None, None, 0, None, 0, None) == bg.BGCR_ERR_INVALID
+    # the allocation-free variant checks its size limit before anything else
+    # touches the device: p = 16 fits 1536 blocks of C in its 20 MiB
+    assert wb(1000, 16, 1536) <= bg.BGCR_NOALLOC_SCRATCH_BYTES < wb(1000, 16, 1537)
+    na = lib.bgcr_apply_projected_noalloc
+    assert na(ctypes.byref(csr), 16, 1537, None, None, None, 0, None) == bg.BGCR_ERR_INVALID
+    assert na(ctypes.byref(csr), 3, 1, None, None, None, 0, None) == bg.BGCR_ERR_INVALID
+    assert na(None, 8, 1, None, None, None, 0, None) == bg.BGCR_ERR_INVALID
 
 
 def test_invalid_arguments_are_rejected_without_a_gpu(lib):
