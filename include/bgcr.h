@@ -14,6 +14,8 @@
  *     interleaved (re, im) doubles.
  *   - Sparse matrices are 0-based CSR with int32 row_ptr[n+1] and col_idx[nnz];
  *     values are double (BGCR_F64) or interleaved complex double (BGCR_C128).
+ *     The indices are 32-bit only: a matrix with nnz >= 2^31 is rejected with
+ *     BGCR_ERR_INVALID before anything is enqueued.
  *   - The caller owns every array it passes in; the library never frees them
  *     and keeps no pointer to them after the call returns.
  *   - Every function returns a status code (BGCR_OK = 0, see bgcr_status);
@@ -35,10 +37,16 @@ extern "C" {
 typedef enum {
     BGCR_OK = 0,
     BGCR_NOT_CONVERGED = 1,        /* max_cycles reached; X holds the last iterate */
+    BGCR_BREAKDOWN_DEFLATED = 2,   /* converged (X valid, as for BGCR_OK), and on the way
+                                      at least one block was numerically rank deficient
+                                      and handled: a start block rebuilt from its
+                                      independent columns and seeded vectors, or a
+                                      cycle ended at a block-step breakdown (count in
+                                      bgcr_stats.deflations) */
     BGCR_ERR_INVALID = -1,         /* NULL/ill-sized argument, n or p mismatch, tol <= 0 */
     BGCR_ERR_NOMEM = -2,           /* device allocation failed */
     BGCR_ERR_HIP = -3,             /* HIP runtime error, including no visible device */
-    BGCR_ERR_NONFINITE = -4,       /* NaN/Inf in B or X0, or produced during the solve */
+    BGCR_ERR_NONFINITE = -4,       /* NaN/Inf in A, B or X0, or produced during the solve */
     BGCR_ERR_NUMERICAL = -5        /* rank-deficient Krylov block (Cholesky breakdown)
                                       or eigensolver failure */
 } bgcr_status;
@@ -117,6 +125,8 @@ typedef struct {
     double alg_bytes;        /* algorithmic HBM bytes of the block Arnoldi sweeps executed */
     int32_t k_eff;           /* columns of the recycled space stored at return */
     int32_t refine_steps;    /* FP64 refinement steps (BGCR_MIXED_FP32), else 0 */
+    int32_t deflations;      /* rank-deficient blocks handled in this call: start blocks
+                                rebuilt plus cycles ended at a block-step breakdown */
 } bgcr_stats;
 
 /* Create a sequence for systems of order n (Algorithm 1 parameters m, k and
@@ -136,8 +146,10 @@ int bgcr_create_sequence(const bgcr_params* prm, int64_t n, void* hip_stream,
  * The first call takes the no-U branch of Algorithm 1 (one block GMRES cycle,
  * then harmonic Ritz selection); later calls import the stored U (A U = C S).
  * Blocks the calling thread until the result is in X.
- * Returns OK, NOT_CONVERGED (X holds the last iterate), INVALID, HIP,
- * NONFINITE or NUMERICAL. */
+ * Returns OK, BREAKDOWN_DEFLATED (converged after handling a rank-deficient
+ * block), NOT_CONVERGED (X holds the last iterate), INVALID (including
+ * A->nnz >= 2^31), HIP, NONFINITE (NaN or Inf in A, B or X0, or produced
+ * during the solve) or NUMERICAL. */
 int bgcr_solve(bgcr_sequence* s, const bgcr_csr* A, const void* B, int64_t ldb,
                void* X, int64_t ldx, double tol, bgcr_stats* st);
 

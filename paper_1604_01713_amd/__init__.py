@@ -12,7 +12,7 @@ import ctypes
 import os
 
 __all__ = [
-    "BGCR_OK", "BGCR_NOT_CONVERGED", "BGCR_ERR_INVALID", "BGCR_ERR_NOMEM", "BGCR_ERR_HIP",
+    "BGCR_OK", "BGCR_NOT_CONVERGED", "BGCR_BREAKDOWN_DEFLATED", "BGCR_ERR_INVALID", "BGCR_ERR_NOMEM", "BGCR_ERR_HIP",
     "BGCR_ERR_NONFINITE", "BGCR_ERR_NUMERICAL", "BGCR_F64", "BGCR_C128", "BGCR_PLAIN_FP64",
     "BGCR_MIXED_FP32", "BGCR_MIXED_FP32_BF16", "BgcrError", "bgcr_params", "bgcr_csr", "bgcr_stats", "lib", "LIB_PATH",
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbgcr.so"
 
 BGCR_OK = 0
 BGCR_NOT_CONVERGED = 1
+BGCR_BREAKDOWN_DEFLATED = 2
 BGCR_ERR_INVALID = -1
 BGCR_ERR_NOMEM = -2
 BGCR_ERR_HIP = -3
@@ -68,7 +69,7 @@ class bgcr_stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("cycles", ctypes.c_int32), ("block_steps", ctypes.c_int32),
                 ("spmm_calls", ctypes.c_int32), ("rel_res", ctypes.c_double), ("rel_res_max_col", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("alg_bytes", ctypes.c_double), ("k_eff", ctypes.c_int32),
-                ("refine_steps", ctypes.c_int32)]
+                ("refine_steps", ctypes.c_int32), ("deflations", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

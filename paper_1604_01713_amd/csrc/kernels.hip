@@ -213,7 +213,7 @@ __global__ __launch_bounds__(NT) void k_spmm(int64_t n, const int* __restrict__ 
 // Q^H W' and/or Gram W'^H W'
 // ---------------------------------------------------------------------------
 template <class T, int P>
-__device__ __forceinline__ void update_dot_body(int64_t n, const T* __restrict__ Win, const BlockPtrs& Q, int nq,
+__device__ __forceinline__ void update_dot_body(int64_t n, const T* Win, const BlockPtrs& Q, int nq,
                                                 const acc_t<T>* __restrict__ S, const acc_t<T>* __restrict__ Rmul,
                                                 T* Wout, int dot_q, int gram, acc_t<T>* __restrict__ part,
                                                 const Ctl* ctl) {
@@ -275,7 +275,7 @@ __device__ __forceinline__ void update_dot_body(int64_t n, const T* __restrict__
 
 #define BGCR_UPDATE_KERNEL(NAME)                                                                                   \
     template <class T, int P>                                                                                      \
-    __global__ __launch_bounds__(NT) void NAME(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq,          \
+    __global__ __launch_bounds__(NT) void NAME(int64_t n, const T* Win, BlockPtrs Q, int nq,                       \
                                                const acc_t<T>* __restrict__ S, const acc_t<T>* __restrict__ Rmul,  \
                                                T* Wout, int dot_q, int gram, acc_t<T>* __restrict__ part,           \
                                                const Ctl* ctl) {                                                    \
@@ -300,8 +300,8 @@ BGCR_UPDATE_KERNEL(k_tsdot)
 // written; rows past n load row n - 1 and are weighted 0.
 // ---------------------------------------------------------------------------
 template <class T, int NQ, bool DOT>
-__global__ __launch_bounds__(NT) void k_narrow_sweep(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq,
-                                                     const double* __restrict__ S, T* __restrict__ Wout,
+__global__ __launch_bounds__(NT) void k_narrow_sweep(int64_t n, const T* Win, BlockPtrs Q, int nq,
+                                                     const double* __restrict__ S, T* Wout,
                                                      double* __restrict__ part, const Ctl* ctl) {
     static_assert(NT == 256, "4 waves per workgroup");
     constexpr int NO = DOT ? NQ : 1;

@@ -373,8 +373,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
 // registers, double-buffered.
 // ---------------------------------------------------------------------------
 template <class T, class TQ, class TO, int P, int NC, bool NORM>
-__global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq,
-                                                        const double* __restrict__ S, TO* __restrict__ Wout,
+__global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* Win, BlockPtrs Q, int nq,
+                                                        const double* __restrict__ S, TO* Wout,
                                                         double* __restrict__ part, const double* __restrict__ Rinv,
                                                         const Ctl* ctl, int step) {
     using M = MX<T>;
@@ -576,8 +576,8 @@ constexpr int sweep_waves() {
 
 template <class T, class TQ, class TO, int P, int NC, bool UPD, bool DOT, bool GRAM, bool NORM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sweep_waves<T, P, NC, TQ, UPD, DOT>()))) void
-k_sweep_mfma(int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq, const double* __restrict__ S,
-             TO* __restrict__ Wout, double* __restrict__ part, const double* __restrict__ Rinv, const Ctl* ctl,
+k_sweep_mfma(int64_t n, const T* Win, BlockPtrs Q, int nq, const double* __restrict__ S,
+             TO* Wout, double* __restrict__ part, const double* __restrict__ Rinv, const Ctl* ctl,
              int step) {
     using M = MX<T>;
     constexpr int NQ = NC * 16 / P, NQA = NQ > 0 ? NQ : 1, KK = P / 4, QLD = 32 * ((NC + 1) / 2);

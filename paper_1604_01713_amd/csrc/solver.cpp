@@ -174,7 +174,7 @@ struct Seq final : bgcr_sequence {
     // per-solve counters
     int n_spmm = 0, n_steps = 0, n_cycles = 0, n_refine = 0;
     double alg_bytes = 0.0;
-    bool breakdown_seen = false;
+    int n_deflated = 0;  // rank-deficient blocks handled: start blocks rebuilt, cycles ended at a breakdown
 
     std::vector<void*> allocs;
 
@@ -977,7 +977,7 @@ struct Seq final : bgcr_sequence {
         if (co.meff == 0) {
             // the start block was rank deficient: one retry with a deflated start block
             if (deflated || !deflated_prologue(withC)) throw Fail{BGCR_ERR_NUMERICAL};
-            breakdown_seen = true;
+            ++n_deflated;
             return cycle(Am, avT, withC, thresh, true, true);
         }
         const int me = co.meff, mp = me * P, ldH = m * P;
@@ -1013,7 +1013,7 @@ struct Seq final : bgcr_sequence {
             for (int a = 0; a < P; ++a)
                 for (int b = 0; b < P; ++b) co.RinvLast(a, b) = to_cd(hRi[(size_t)me * P2 + a * P + b]);
         }
-        if (co.breakdown) breakdown_seen = true;
+        if (co.breakdown) ++n_deflated;
         if (prof) prof_resolve(hc.meff);
         // model-M algorithmic bytes of the executed Arnoldi sweeps: V_j
         // gathered and V_{j+1} written in the basis type, W written once and
@@ -1368,14 +1368,14 @@ struct Seq final : bgcr_sequence {
         const auto t0 = std::chrono::steady_clock::now();
         n_spmm = n_steps = n_cycles = n_refine = 0;
         alg_bytes = 0.0;
-        breakdown_seen = false;
+        n_deflated = 0;
         log_steps.clear();
         log_res.clear();
         int status = BGCR_OK;
         double rel = 0.0, relmax = 0.0;
         try {
             if (!Am || !Bv || !Xv || Am->n != n || !Am->row_ptr || !Am->col_idx || !Am->values || ldb < pu ||
-                ldx < pu || !(tol > 0.0) || Am->nnz < 0)
+                ldx < pu || !(tol > 0.0) || Am->nnz < 0 || Am->nnz > INT32_MAX)
                 throw Fail{BGCR_ERR_INVALID};
             const A* B = (const A*)Bv;
             A* Xu = (A*)Xv;
@@ -1435,6 +1435,8 @@ struct Seq final : bgcr_sequence {
             HIPCHK(copy_block<A, A>(st, n, pu, X, P, Xu, ldx, pu));
             sync();
             if (!std::isfinite(rel)) status = BGCR_ERR_NONFINITE;
+            // converged, with a rank-deficient block handled on the way
+            if (status == BGCR_OK && n_deflated > 0) status = BGCR_BREAKDOWN_DEFLATED;
         } catch (const Fail& f) {
             status = f.code;
             (void)hipStreamSynchronize(st);
@@ -1452,6 +1454,7 @@ struct Seq final : bgcr_sequence {
             stt->alg_bytes = alg_bytes;
             stt->k_eff = keff;
             stt->refine_steps = n_refine;
+            stt->deflations = n_deflated;
         }
         return status;
     }
@@ -1659,6 +1662,7 @@ struct Hybrid final : bgcr_sequence {
             budget -= s1.cycles;
             // only a stop at the enlarged cycle limit continues with L = 1
             done = status != BGCR_NOT_CONVERGED || s1.cycles >= max_cycles || budget > 0;
+            if (status == BGCR_BREAKDOWN_DEFLATED) status = BGCR_OK;
         }
         if (!done) {
             if (!moved) status = hand_over();
@@ -1667,8 +1671,10 @@ struct Hybrid final : bgcr_sequence {
                 status = one->solve(Am, B, ldb, X, ldx, tol, &s2);
                 take_log(one);
                 second = true;
+                if (status == BGCR_BREAKDOWN_DEFLATED) status = BGCR_OK;
             }
         }
+        if (status == BGCR_OK && s1.deflations + s2.deflations > 0) status = BGCR_BREAKDOWN_DEFLATED;
         if (stt) {
             *stt = second ? s2 : s1;
             stt->status = status;
@@ -1677,6 +1683,7 @@ struct Hybrid final : bgcr_sequence {
             stt->spmm_calls = s1.spmm_calls + s2.spmm_calls;
             stt->alg_bytes = s1.alg_bytes + s2.alg_bytes;
             stt->refine_steps = s1.refine_steps + s2.refine_steps;
+            stt->deflations = s1.deflations + s2.deflations;
             stt->k_eff = holder()->recycle_dim();
             stt->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         }
@@ -1857,7 +1864,8 @@ int bgcr_get_cycle_log(const bgcr_sequence* s, int32_t* steps, double* rel_res, 
 }
 
 int bgcr_spmm(const bgcr_csr* A, int32_t dtype, int32_t p, const void* V, void* W, void* hip_stream) {
-    if (!A || !V || !W || A->n <= 0 || A->nnz < 0 || !A->row_ptr || !A->col_idx || !A->values)
+    if (!A || !V || !W || A->n <= 0 || A->nnz < 0 || A->nnz > INT32_MAX || !A->row_ptr || !A->col_idx ||
+        !A->values)
         return BGCR_ERR_INVALID;
     if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16)) return BGCR_ERR_INVALID;
     int ndev = 0;
@@ -1890,7 +1898,8 @@ size_t bgcr_apply_projected_work_bytes(int64_t n, int32_t p, int32_t kc) {
 
 static int apply_projected(const bgcr_csr* A, int32_t p, int32_t kc, const double* C, const double* V, double* W,
                            int32_t variant, void* work, size_t work_bytes, void* hip_stream) {
-    if (!A || !V || !W || V == W || !work || A->n <= 0 || A->nnz < 0 || !A->row_ptr || !A->col_idx || !A->values)
+    if (!A || !V || !W || V == W || !work || A->n <= 0 || A->nnz < 0 || A->nnz > INT32_MAX || !A->row_ptr ||
+        !A->col_idx || !A->values)
         return BGCR_ERR_INVALID;
     if (!(p == 1 || p == 2 || p == 4 || p == 8 || p == 16) || kc < 0 || (kc > 0 && !C) ||
         (variant != 0 && variant != 1))
@@ -1980,6 +1989,7 @@ const char* bgcr_strerror(int status) {
     switch (status) {
         case BGCR_OK: return "ok";
         case BGCR_NOT_CONVERGED: return "not converged within max_cycles";
+        case BGCR_BREAKDOWN_DEFLATED: return "converged; a rank-deficient block was handled on the way";
         case BGCR_ERR_INVALID: return "invalid argument";
         case BGCR_ERR_NOMEM: return "device out of memory";
         case BGCR_ERR_HIP: return "HIP runtime error";

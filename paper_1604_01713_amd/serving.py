@@ -148,7 +148,7 @@ def gpu_runner(device="cuda:0", keep_solutions=False, precision: Optional[int] =
     solved in order with the recycle space kept on the device in between."""
     import torch
 
-    from . import DeviceCSR, Sequence
+    from . import BGCR_BREAKDOWN_DEFLATED, BGCR_OK, DeviceCSR, Sequence, bgcr_strerror
 
     def run(req: Request, res: Result):
         stream = torch.cuda.Stream(device=device)
@@ -165,6 +165,11 @@ def gpu_runner(device="cuda:0", keep_solutions=False, precision: Optional[int] =
                     res.stats.append(st.as_dict())
                     if keep_solutions:
                         res.solutions.append(dX.cpu().numpy())
+                    # only a converged system counts (OK, or converged after
+                    # handling a rank-deficient block)
+                    if st.status not in (BGCR_OK, BGCR_BREAKDOWN_DEFLATED):
+                        res.error = f"system {i}: status {st.status} ({bgcr_strerror(st.status)})"
+                        break
                 stream.synchronize()
             finally:
                 seq.release()
@@ -175,6 +180,7 @@ def gpu_runner(device="cuda:0", keep_solutions=False, precision: Optional[int] =
 def summarize(results: Seq[Result], wall: float) -> dict:
     ok = [r for r in results if r.error is None]
     lat = np.array([r.latency for r in ok]) if ok else np.zeros(1)
+    # systems of requests that finished without error; every one converged
     nsys = sum(len(r.stats) for r in ok)
     return {"requests": len(results), "failed": len(results) - len(ok), "systems": nsys,
             "wall_s": round(wall, 3), "systems_per_s": round(nsys / wall, 4) if wall > 0 else 0.0,

@@ -25,7 +25,6 @@ import scipy.sparse as sp
 __all__ = [
     "convdiff", "helmholtz2d", "Workload", "System",
     "cfg1", "cfg2", "cfg3", "cfg4", "serving_requests", "reduced",
-    "csr_arrays",
 ]
 
 
@@ -245,15 +244,3 @@ def banded(n, bw, seed):
     A = A.tocsr()
     A.sort_indices()
     return A
-
-
-def reduced(cfg_fn, **kw):
-    """Same recipe at a reduced grid (parity-test size)."""
-    return cfg_fn(**kw)
-
-
-def csr_arrays(A):
-    """(row_ptr int32, col_idx int32, values) of a CSR matrix, contiguous."""
-    return (np.ascontiguousarray(A.indptr, dtype=np.int32),
-            np.ascontiguousarray(A.indices, dtype=np.int32),
-            np.ascontiguousarray(A.data))

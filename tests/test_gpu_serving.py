@@ -1,8 +1,11 @@
 """Serving form on the GPU: requests served concurrently give the same results
-as each request solved alone, and every result meets its tolerance."""
+as each request solved alone, every result meets its tolerance, and every
+served result matches the FP64 oracle solving the request's sequence (the
+recycled space carried from system to system, Algorithm 1 last line)."""
 import numpy as np
 import pytest
 
+import oracle
 import problems
 
 pytestmark = pytest.mark.gpu
@@ -45,14 +48,23 @@ def test_results_are_the_same_alone_and_in_the_mix(precision):
     for q in reqs:
         a, b = mixed[q.rid], alone[q.rid]
         assert a.error is None and b.error is None, (a.error, b.error)
+        systems = [(*q.system(i), np.zeros((q.n, q.p))) for i in range(q.nsys)]
+        orc, _ = oracle.solve_sequence(systems, q.tol, q.m, q.k)
         for i in range(q.nsys):
             A, B = q.system(i)
             Xm, Xa = a.solutions[i], b.solutions[i]
+            Xo, so = orc[i]
             rel = np.linalg.norm(B - A @ Xm) / np.linalg.norm(B)
             diff = np.linalg.norm(Xm - Xa) / max(np.linalg.norm(Xa), 1e-300)
+            dorc = np.linalg.norm(Xm - Xo) / np.linalg.norm(Xo)
             print(f"req {q.rid} sys {i} p={q.p} n={q.n} prec={precision}: rel.res {rel:.2e}, "
-                  f"mix vs alone {diff:.1e}, cycles {a.stats[i]['cycles']}/{b.stats[i]['cycles']}", flush=True)
+                  f"mix vs alone {diff:.1e}, vs oracle {dorc:.1e}, cycles {a.stats[i]['cycles']}/"
+                  f"{b.stats[i]['cycles']} (oracle {so['cycles']})", flush=True)
             assert a.stats[i]["status"] == 0
             assert rel <= q.tol * 1.0001
             # same kernels, same launch shapes, fixed reduction order: identical
             assert diff == 0.0
+            # the method's parity bar; plain FP64 follows the oracle's iteration
+            assert dorc <= 1e-6
+            if precision == 0:
+                assert dorc <= 1e-10 and a.stats[i]["cycles"] == so["cycles"]
