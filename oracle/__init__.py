@@ -9,3 +9,4 @@ from .bgcrodr import (  # noqa: F401
     select_ritz, refresh_first, refresh_augmented, recycle_import, solve, solve_sequence,
     splitmix64, enlarging_vectors, apply_projected,
 )
+from .ilu import ilu0, apply_inverse, right_preconditioned  # noqa: F401

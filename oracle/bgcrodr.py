@@ -53,6 +53,8 @@ from __future__ import annotations
 import numpy as np
 import scipy.linalg as sla
 
+from . import ilu
+
 
 # ----------------------------------------------------------------------------
 # small dense helpers
@@ -331,7 +333,7 @@ def recycle_import(A, U, X, R):
 
 
 def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, trace=False, block_size=None,
-          seed=0, enlarged_cycles=None, ritz=False):
+          seed=0, enlarged_cycles=None, ritz=False, precond=None):
     """Algorithm 1 (block RGMRES / block GCRO-DR) for one system A X = B.
 
     Returns (X, U, stats).  stats holds per-cycle block-step counts, the LSQ
@@ -341,8 +343,25 @@ def solve(A, B, X0, tol, m, k, U=None, max_cycles=1000, select_largest=False, tr
     with an enlarged block, only the first enlarged_cycles cycles of this
     call use it and every later cycle is non-block (L = 1), the hybrid of
     Section 4.1.3; None: every cycle uses it.  ritz: recycle Ritz instead of
-    harmonic Ritz vectors (Section 4.1.3).
+    harmonic Ritz vectors (Section 4.1.3).  precond="ilu0": right
+    preconditioning with the ILU(0) of this A (oracle/ilu.py): the same
+    algorithm on A M^{-1} in the variable M X, X returned unpreconditioned,
+    U in the preconditioned variable.
     """
+    if precond is not None:
+        if precond != "ilu0":
+            raise ValueError(f"unknown preconditioner {precond!r}")
+        Lf, Uf = ilu.ilu0(A)
+        X0 = np.asarray(X0)
+        Xh, U, stats = solve(ilu.right_preconditioned(A, Lf, Uf), B, Lf @ (Uf @ X0), tol, m, k, U=U,
+                             max_cycles=max_cycles, select_largest=select_largest, trace=trace,
+                             block_size=block_size, seed=seed, enlarged_cycles=enlarged_cycles, ritz=ritz)
+        X = ilu.apply_inverse(Lf, Uf, Xh)
+        bn = float(np.linalg.norm(B))
+        stats["rel_res"] = float(np.linalg.norm(B - A @ X)) / bn if bn > 0 else 0.0
+        if trace:
+            stats["precond_factors"] = (Lf, Uf)
+        return X, U, stats
     A = A.tocsr() if hasattr(A, "tocsr") else A
     B = np.asarray(B)
     n, p = B.shape
@@ -426,7 +445,7 @@ def _log(stats, cyc, A, B, X, R, bn, trace, U, C, Uold=None, Cold=None):
 
 
 def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False, block_size=None, seed=0,
-                   enlarge_cycles=None, ritz=False):
+                   enlarge_cycles=None, ritz=False, precond=None):
     """Solve a sequence A^[i] X = B^[i], carrying U from each system to the next
     (Algorithm 1, last line).  `systems` is a list of (A, B, X0).
     enlarge_cycles (with block_size L > p = 1): the first enlarge_cycles
@@ -440,7 +459,7 @@ def solve_sequence(systems, tol, m, k, max_cycles=1000, select_largest=False, bl
     for (A, B, X0) in systems:
         X, U, st = solve(A, B, X0, tol, m, k, U=U, max_cycles=max_cycles,
                          select_largest=select_largest, block_size=block_size, seed=seed,
-                         enlarged_cycles=left, ritz=ritz)
+                         enlarged_cycles=left, ritz=ritz, precond=precond)
         if left is not None:
             left = max(0, left - st["cycles"])
         out.append((X, st))
