@@ -65,6 +65,23 @@ typedef enum {
                                       bgcr_create_sequence returns BGCR_ERR_INVALID */
 } bgcr_precision;
 
+typedef enum {
+    BGCR_PRECOND_NONE = 0,
+    BGCR_PRECOND_ILU0 = 1          /* right preconditioning with the zero-fill incomplete LU
+                                      factorization of each system's A (the preconditioner of
+                                      the paper's experiments, Sections 6.1 and 6.2): the
+                                      cycles run on A M^{-1}, M = L U with L unit lower and U
+                                      upper triangular on the pattern of A and (L U)_ij = A_ij
+                                      there; X stays the unpreconditioned unknown, the
+                                      stopping test uses B - A X, and the recycled U lives in
+                                      the preconditioned variable.  Every row of A needs its
+                                      diagonal entry and sorted column indices (else
+                                      BGCR_ERR_INVALID at bgcr_solve); a zero pivot gives
+                                      BGCR_ERR_NUMERICAL.  Plain FP64 (real or complex) with
+                                      block_size 0 or p and no hybrid; otherwise
+                                      bgcr_create_sequence returns BGCR_ERR_INVALID */
+} bgcr_precond;
+
 typedef struct bgcr_sequence bgcr_sequence;   /* opaque; owns U, C and workspaces */
 
 typedef struct {
@@ -104,6 +121,10 @@ typedef struct {
                                 (What^H A What) t = theta (What^H What) t with
                                 What = [U D, V_1 .. V_m].  The selection by modulus
                                 follows select_largest.  Other values: BGCR_ERR_INVALID */
+    int32_t precond;         /* bgcr_precond.  The factorization of each system is computed
+                                on the device at every bgcr_solve; the level schedule of its
+                                triangular solves is computed on the host when the pattern
+                                differs from the last one the sequence analysed */
 } bgcr_params;
 
 typedef struct {
@@ -247,7 +268,9 @@ typedef enum {
     BGCR_K_SPMM = 8,         /* plain block SpMM (recycle import A U) */
     BGCR_K_HOST = 9,         /* host: small dense algebra of a cycle (wall clock, includes BGCR_K_HOST_EIG) */
     BGCR_K_HOST_EIG = 10,    /* host: harmonic-Ritz eigenproblem (wall clock) */
-    BGCR_K_NCLASS = 11
+    BGCR_K_PRECOND = 11,     /* triangular solves of M^{-1} (ILU(0) preconditioning) */
+    BGCR_K_ILU = 12,         /* ILU(0): pattern check and analysis, numeric factorization */
+    BGCR_K_NCLASS = 13
 } bgcr_kernel_class;
 
 /* Turn per-kernel timing on (1) or off (0) and reset the counters.  When on,

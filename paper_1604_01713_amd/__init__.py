@@ -14,7 +14,7 @@ import os
 __all__ = [
     "BGCR_OK", "BGCR_NOT_CONVERGED", "BGCR_BREAKDOWN_DEFLATED", "BGCR_ERR_INVALID", "BGCR_ERR_NOMEM", "BGCR_ERR_HIP",
     "BGCR_ERR_NONFINITE", "BGCR_ERR_NUMERICAL", "BGCR_F64", "BGCR_C128", "BGCR_PLAIN_FP64",
-    "BGCR_MIXED_FP32", "BGCR_MIXED_FP32_BF16", "BgcrError", "bgcr_params", "bgcr_csr", "bgcr_stats", "lib", "LIB_PATH",
+    "BGCR_MIXED_FP32", "BGCR_MIXED_FP32_BF16", "BGCR_PRECOND_NONE", "BGCR_PRECOND_ILU0", "BgcrError", "bgcr_params", "bgcr_csr", "bgcr_stats", "lib", "LIB_PATH",
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_strerror",
     "bgcr_set_profiling", "bgcr_get_profile", "bgcr_apply_projected", "bgcr_apply_projected_work_bytes",
@@ -37,6 +37,8 @@ BGCR_C128 = 1
 BGCR_PLAIN_FP64 = 0
 BGCR_MIXED_FP32 = 1
 BGCR_MIXED_FP32_BF16 = 2
+BGCR_PRECOND_NONE = 0
+BGCR_PRECOND_ILU0 = 1
 
 EXPORTED_SYMBOLS = [
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
@@ -50,14 +52,14 @@ BGCR_NOALLOC_SCRATCH_BYTES = 20 << 20
 
 # kernel classes of the per-kernel profile (bgcr_kernel_class)
 KERNEL_CLASSES = ["arn_spmm", "arn_dot", "proj_dot", "proj_gram", "small", "combine", "residual", "tsdot", "spmm",
-                  "host", "host_eig"]
+                  "host", "host_eig", "precond", "ilu"]
 
 
 class bgcr_params(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("m", ctypes.c_int32), ("k", ctypes.c_int32),
                 ("dtype", ctypes.c_int32), ("precision", ctypes.c_int32), ("max_cycles", ctypes.c_int32),
                 ("select_largest", ctypes.c_int32), ("block_size", ctypes.c_int32),
-                ("enlarge_cycles", ctypes.c_int32), ("ritz_vectors", ctypes.c_int32)]
+                ("enlarge_cycles", ctypes.c_int32), ("ritz_vectors", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class bgcr_csr(ctypes.Structure):
@@ -263,9 +265,10 @@ class Sequence:
     """One sequence of related systems sharing a device-resident recycle space."""
 
     def __init__(self, n, p, m, k, dtype=BGCR_F64, precision=BGCR_PLAIN_FP64, max_cycles=1000,
-                 select_largest=False, stream=None, block_size=0, enlarge_cycles=0, ritz_vectors=False):
+                 select_largest=False, stream=None, block_size=0, enlarge_cycles=0, ritz_vectors=False,
+                 precond=BGCR_PRECOND_NONE):
         self.params = bgcr_params(p, m, k, dtype, precision, max_cycles, int(bool(select_largest)), int(block_size),
-                                  int(enlarge_cycles), int(bool(ritz_vectors)))
+                                  int(enlarge_cycles), int(bool(ritz_vectors)), int(precond))
         self.n = n
         self.stream = stream
         self.handle = bgcr_create_sequence(self.params, n, stream)

@@ -221,4 +221,27 @@ template <class TI, class TO>
 hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ldi, TO* out,
                       int64_t ldo, int zero_pad_to);
 
+// ---------------------------------------------------------------------------
+// ILU(0) right preconditioning (ilu.hip).  The factors live in `lu`, an array
+// with the CSR pattern (rp, ci) of A: strictly lower part of L (unit diagonal
+// implied) and the upper part of U; diag[i] is the position of (i, i).  Every
+// launch handles the rows rows[0 .. nrows) of one level; T is double or zd.
+// ---------------------------------------------------------------------------
+// numeric factorization of one level in place (lu starts as a copy of A's
+// values); *err = 1 on a zero or non-finite pivot
+template <class T>
+hipError_t ilu0_level(hipStream_t st, const int* rows, int nrows, const int* rp, const int* ci, const int* diag,
+                      T* lu, int* err);
+// one level of L y = in (lower) or U x = in (upper) for P right-hand sides
+// (row-major n x P); in may alias out; skipped while the cycle is inactive
+template <class T>
+hipError_t trsv_level(hipStream_t st, int P, bool lower, const int* rows, int nrows, const int* rp, const int* ci,
+                      const int* diag, const T* lu, const T* in, T* out, const Ctl* ctl);
+// *diff = 1 where the CSR patterns (rpa, cia) and (rpb, cib) differ (same n, nnz)
+hipError_t pattern_diff(hipStream_t st, int64_t n, int64_t nnz, const int* rpa, const int* cia, const int* rpb,
+                        const int* cib, int* diff);
+// out = in M row by row (M P x P, row-major); skipped while the cycle is inactive
+template <class T>
+hipError_t rows_times(hipStream_t st, int P, int64_t n, const T* in, const acc_t<T>* M, T* out, const Ctl* ctl);
+
 }  // namespace bgcr

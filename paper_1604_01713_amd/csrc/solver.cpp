@@ -75,6 +75,11 @@ bool valid_params(const bgcr_params* prm, int64_t n) {
     // the hybrid needs an enlarged block and a basis type the L = 1 basis has
     if (prm->enlarge_cycles < 0) return false;
     if (prm->ritz_vectors != 0 && prm->ritz_vectors != 1) return false;
+    if (prm->precond != BGCR_PRECOND_NONE && prm->precond != BGCR_PRECOND_ILU0) return false;
+    // ILU(0): plain FP64 (real or complex), no enlarged block, no hybrid
+    if (prm->precond == BGCR_PRECOND_ILU0 &&
+        (prm->precision != BGCR_PLAIN_FP64 || p != pu || prm->enlarge_cycles != 0))
+        return false;
     if (prm->enlarge_cycles > 0 && (p == pu || prm->precision == BGCR_MIXED_FP32_BF16)) return false;
     const int KB = (prm->k + (prm->dtype == BGCR_F64 ? 1 : 0) + p - 1) / p;
     // the refresh combines [U, C, V_1 .. V_{m+1}] in one launch
@@ -123,6 +128,11 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     const bool enlarged = z.P > prm->p;
     z.total_fixed = z.basis + 3 * (size_t)n * z.P * z.sw /* W2, Wb, R */ +
                     (size_t)n * z.P * z.sa * (enlarged ? 2 : 1) /* X (and B padded) */ + z.recyc + z.part + z.small_;
+    // ILU(0): the M^{-1} work block, diagonal positions, two level orders, the
+    // analysed row pointers and a flag (the nnz-sized arrays are counted by
+    // bgcr_footprint_bytes)
+    if (prm->precond == BGCR_PRECOND_ILU0)
+        z.total_fixed += (size_t)n * z.P * z.sw + sizeof(int) * (4 * (size_t)n + 2);
     return z;
 }
 
@@ -175,6 +185,17 @@ struct Seq final : bgcr_sequence {
     int n_spmm = 0, n_steps = 0, n_cycles = 0, n_refine = 0;
     double alg_bytes = 0.0;
     int n_deflated = 0;  // rank-deficient blocks handled: start blocks rebuilt, cycles ended at a breakdown
+
+    // ILU(0) right preconditioning: level schedule of the analysed pattern,
+    // the factors of the current system, and the M^{-1} work block
+    bool pc = false;
+    int *d_rp = nullptr, *d_ci = nullptr, *d_diag = nullptr, *d_ordL = nullptr, *d_ordU = nullptr,
+        *d_flag = nullptr;
+    int64_t pat_nnz = -1;   // nnz of the analysed pattern (-1: none yet)
+    size_t ci_cap = 0, lu_cap = 0;
+    std::vector<int> lvlL, lvlU;  // level pointers into the L and U row orders
+    A* lu = nullptr;
+    T* Zb = nullptr;
 
     std::vector<void*> allocs;
 
@@ -256,6 +277,7 @@ struct Seq final : bgcr_sequence {
     Seq(const bgcr_params* p_, int64_t n_, hipStream_t s_) : prm(*p_), n(n_), st(s_) {
         P = block_of(&prm);
         pu = prm.p;
+        pc = prm.precond == BGCR_PRECOND_ILU0;
         m = prm.m;
         k = prm.k;
         cplx = prm.dtype == BGCR_C128;
@@ -350,6 +372,14 @@ struct Seq final : bgcr_sequence {
         coef = dalloc<A>(coef_cap);
         rho = dalloc<double>(m);
         dpart = dalloc<double>((size_t)NWG_MAX * 2 * P);
+        if (pc) {
+            Zb = dalloc<T>(blk);
+            d_rp = dalloc<int>((size_t)n + 1);
+            d_diag = dalloc<int>((size_t)n);
+            d_ordL = dalloc<int>((size_t)n);
+            d_ordU = dalloc<int>((size_t)n);
+            d_flag = dalloc<int>(1);
+        }
         hcap = std::max({(size_t)4 << 20, 2 * coef_cap * sizeof(A) + (64 << 10), hr_bytes + (64 << 10)});
         if (hipHostMalloc((void**)&hbuf, hcap, hipHostMallocDefault) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
         if (hipHostMalloc((void**)&rbuf, (size_t)NWG_MAX * 2 * P * sizeof(double), hipHostMallocDefault) != hipSuccess)
@@ -586,13 +616,15 @@ struct Seq final : bgcr_sequence {
     void import_basis(const bgcr_csr* Am, const T* avT) {
         const int o = 1 - cur;
         for (int b = 0; b < KB; ++b) {
+            // right preconditioning: the operator is A M^{-1}
+            if (pc) apply_minv((const T*)ublk(cur, b), Zb, nullptr);
             run(BGCR_K_SPMM, (double)(sizeof(T) + 4) * Am->nnz + 4.0 * (n + 1) + 2.0 * sizeof(TB) * n * P, [&] {
                 if constexpr (half) {
                     return spmm_block<T, TB, TB, TB>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, ublk(cur, b),
                                                      nullptr, nullptr, cblk(o, b), nullptr);
                 } else {
-                    return L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, ublk(cur, b), nullptr, nullptr,
-                                       cblk(o, b), bp({}), 0, 0, part, nwg, nullptr);
+                    return L::spmm_dot(st, P, n, Am->row_ptr, Am->col_idx, avT, pc ? (const TB*)Zb : ublk(cur, b),
+                                       nullptr, nullptr, cblk(o, b), bp({}), 0, 0, part, nwg, nullptr);
                 }
             });
             ++n_spmm;
@@ -644,10 +676,152 @@ struct Seq final : bgcr_sequence {
             inU.push_back(ublk(cur, b));
             inC.push_back(cblk(cur, b));
         }
-        combine<A>(inU, {X}, Tm, 1);
+        add_to_X(inU, Tm);
         Mat mT = Tm;
         for (cd& v : mT.a) v = -v;
         combine<T>(inC, {R}, mT, 1);
+    }
+
+    // ---- ILU(0) right preconditioning ----------------------------------------
+    // (re)allocate a lazily sized device array
+    template <class U_>
+    void regrow(U_*& ptr, size_t& cap, size_t count) {
+        if (count <= cap) return;
+        if (ptr) {
+            sync();
+            (void)hipFree(ptr);
+            allocs.erase(std::find(allocs.begin(), allocs.end(), (void*)ptr));
+            ptr = nullptr;
+            cap = 0;
+        }
+        ptr = dalloc<U_>(count);
+        cap = count;
+    }
+
+    // Level schedule of A's pattern, on the host: validated CSR (sorted,
+    // in-range columns, a diagonal entry in every row), diagonal positions,
+    // and the rows of L and of U ordered by level (a row's level is one more
+    // than the largest level among the rows its strictly lower, resp. upper,
+    // part refers to).  The pattern is kept on the device to recognise it.
+    void ilu_analyse(const bgcr_csr* Am) {
+        const int64_t nnz = Am->nnz;
+        std::vector<int> rp(n + 1), ci((size_t)nnz);
+        d2h(rp.data(), Am->row_ptr, (n + 1) * sizeof(int));
+        d2h(ci.data(), Am->col_idx, (size_t)nnz * sizeof(int));
+        if (rp[0] != 0 || rp[n] != nnz) throw Fail{BGCR_ERR_INVALID};
+        std::vector<int> diag(n), lev(n), ordL(n), ordU(n);
+        for (int64_t i = 0; i < n; ++i) {
+            if (rp[i + 1] < rp[i]) throw Fail{BGCR_ERR_INVALID};
+            int d = -1;
+            for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                if (ci[e] < 0 || ci[e] >= n || (e > rp[i] && ci[e] <= ci[e - 1])) throw Fail{BGCR_ERR_INVALID};
+                if (ci[e] == i) d = e;
+            }
+            if (d < 0) throw Fail{BGCR_ERR_INVALID};
+            diag[i] = d;
+        }
+        auto order = [&](std::vector<int>& ord, std::vector<int>& ptr) {
+            int nl = 0;
+            for (int64_t i = 0; i < n; ++i) nl = std::max(nl, lev[i] + 1);
+            ptr.assign(nl + 1, 0);
+            for (int64_t i = 0; i < n; ++i) ++ptr[lev[i] + 1];
+            for (int l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
+            std::vector<int> pos(ptr.begin(), ptr.end() - 1);
+            for (int64_t i = 0; i < n; ++i) ord[pos[lev[i]]++] = (int)i;
+        };
+        for (int64_t i = 0; i < n; ++i) {
+            int l = 0;
+            for (int e = rp[i]; e < diag[i]; ++e) l = std::max(l, lev[ci[e]] + 1);
+            lev[i] = l;
+        }
+        order(ordL, lvlL);
+        for (int64_t i = n - 1; i >= 0; --i) {
+            int l = 0;
+            for (int e = diag[i] + 1; e < rp[i + 1]; ++e) l = std::max(l, lev[ci[e]] + 1);
+            lev[i] = l;
+        }
+        order(ordU, lvlU);
+        regrow(d_ci, ci_cap, std::max<size_t>(1, (size_t)nnz));
+        h2d_big(d_diag, diag.data(), n * sizeof(int));
+        h2d_big(d_ordL, ordL.data(), n * sizeof(int));
+        h2d_big(d_ordU, ordU.data(), n * sizeof(int));
+        HIPCHK(hipMemcpyAsync(d_rp, Am->row_ptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, st));
+        if (nnz > 0)
+            HIPCHK(hipMemcpyAsync(d_ci, Am->col_idx, (size_t)nnz * sizeof(int), hipMemcpyDeviceToDevice, st));
+        pat_nnz = nnz;
+    }
+
+    // larger host -> device copies through the pinned staging buffer
+    void h2d_big(void* dst, const void* src, size_t bytes) {
+        size_t done = 0;
+        while (done < bytes) {
+            const size_t c = std::min(bytes - done, hcap);
+            sync();
+            std::memcpy(hbuf, (const char*)src + done, c);
+            HIPCHK(hipMemcpyAsync((char*)dst + done, hbuf, c, hipMemcpyHostToDevice, st));
+            done += c;
+        }
+        sync();
+    }
+
+    // Factors of this system: the level schedule (analysed again only when
+    // the pattern differs from the last one), then ILU(0) level by level on
+    // a copy of A's values.  A zero or non-finite pivot: BGCR_ERR_NUMERICAL.
+    void ilu_setup(const bgcr_csr* Am) {
+        HostPhase hp(this, BGCR_K_ILU);
+        bool same = false;
+        if (pat_nnz == Am->nnz) {
+            HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), st));
+            HIPCHK(pattern_diff(st, n, Am->nnz, Am->row_ptr, Am->col_idx, d_rp, d_ci, d_flag));
+            int f = 1;
+            d2h(&f, d_flag, sizeof(int));
+            same = f == 0;
+        }
+        if (!same) ilu_analyse(Am);
+        regrow(lu, lu_cap, std::max<size_t>(1, (size_t)Am->nnz));
+        if (Am->nnz > 0)
+            HIPCHK(hipMemcpyAsync(lu, Am->values, (size_t)Am->nnz * sizeof(A), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), st));
+        for (size_t l = 0; l + 1 < lvlL.size(); ++l)
+            HIPCHK(ilu0_level<A>(st, d_ordL + lvlL[l], lvlL[l + 1] - lvlL[l], d_rp, d_ci, d_diag, lu, d_flag));
+        int f = 0;
+        d2h(&f, d_flag, sizeof(int));
+        if (f) throw Fail{BGCR_ERR_NUMERICAL};
+    }
+
+    // out = M^{-1} in = U^{-1} (L^{-1} in) for a P-column block (in may be out);
+    // skipped on the device while `ctl` says the cycle has stopped
+    void apply_minv(const T* in, T* out, const Ctl* c) {
+        if constexpr (std::is_same<T, A>::value) {
+            const double by = (double)(sizeof(A) + 4) * pat_nnz + 4.0 * (n + 1) * 2 + 4.0 * n * 4 +
+                              4.0 * sizeof(T) * n * P;
+            run(BGCR_K_PRECOND, by, [&] {
+                for (size_t l = 0; l + 1 < lvlL.size(); ++l)
+                    HIPCHK(trsv_level<A>(st, P, true, d_ordL + lvlL[l], lvlL[l + 1] - lvlL[l], d_rp, d_ci, d_diag,
+                                         lu, in, out, c));
+                for (size_t l = 0; l + 1 < lvlU.size(); ++l)
+                    HIPCHK(trsv_level<A>(st, P, false, d_ordU + lvlU[l], lvlU[l + 1] - lvlU[l], d_rp, d_ci, d_diag,
+                                         lu, out, out, c));
+                return hipSuccess;
+            });
+        } else {
+            (void)in;
+            (void)out;
+            (void)c;
+            throw Fail{BGCR_ERR_INVALID};
+        }
+    }
+
+    // X += [in..] K, or with right preconditioning X += M^{-1} ([in..] K): the
+    // Krylov and recycled blocks live in the preconditioned variable
+    void add_to_X(const std::vector<const void*>& in, const Mat& K) {
+        if (!pc) {
+            combine<A>(in, {X}, K, 1);
+            return;
+        }
+        combine<A>(in, {(void*)Zb}, K, 0);
+        apply_minv(Zb, Zb, nullptr);
+        combine<A>({(const void*)Zb}, {X}, Mat::eye(P), 1);
     }
 
     struct CycleOut {
@@ -871,6 +1045,18 @@ struct Seq final : bgcr_sequence {
             // two more blocks per step than the model (the first dots re-read W,
             // and W'' is stored raw then normalised in the next SpMM); they are
             // not counted.  SpMM: A, V_j, W.
+            if constexpr (std::is_same<T, A>::value) {
+                if (pc) {
+                    // V_j as a stored block (off matrix cores, and at j = 1, it
+                    // is W2 R^{-1}), then M^{-1} V_j into Zb; the SpMM reads Zb
+                    if (!(pip && j > 1))
+                        run(BGCR_K_COMBINE, vblkb + blkb, [&] {
+                            return rows_times<T>(st, P, n, (const T*)W2, RinvAll + (size_t)(j - 1) * P2,
+                                                 (T*)vblk(j - 1), ctl);
+                        });
+                    apply_minv((const T*)vblk(j - 1), Zb, ctl);
+                }
+            }
             run(BGCR_K_ARN_SPMM, abytes + vblkb + blkb, [&] {
                 if constexpr (half) {
                     if (j > 1)
@@ -879,6 +1065,9 @@ struct Seq final : bgcr_sequence {
                     return spmm_block<T, T, TB, T>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, W2, RinvAll,
                                                    vblk(0), Wb, ctl);
                 } else {
+                    if (pc)
+                        return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, Zb, nullptr, nullptr, Wb,
+                                            ctl);
                     if (pip && j > 1)
                         return L::spmm_rinv(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, vblk(j - 1), nullptr,
                                             nullptr, Wb, ctl);
@@ -1040,7 +1229,7 @@ struct Seq final : bgcr_sequence {
             KX.set_block(mp, 0, FY);
             for (int b = 0; b < KB; ++b) in.push_back(ublk(cur, b));
         }
-        combine<A>(in, {X}, KX, 1);
+        add_to_X(in, KX);
         if (update_R) {
             Mat HY = dense::matmul(co.H, co.Y);
             Mat KR((me + 1) * P, P);
@@ -1426,6 +1615,7 @@ struct Seq final : bgcr_sequence {
                 const double thresh = tol * bn;
                 finish_norms(rn2, bn2);
                 if (rn > thresh) {
+                    if (pc) ilu_setup(Am);
                     if (!mixed)
                         status = run_plain(Am, avT, B, ldb, thresh, rn2, bn2, finish_norms);
                     else
@@ -1833,6 +2023,8 @@ size_t bgcr_footprint_bytes(const bgcr_params* prm, int64_t n, int64_t nnz) {
     const Sizes z = sizes_of(prm, n);
     size_t b = z.total_fixed;
     if (prm->precision != BGCR_PLAIN_FP64) b += (size_t)nnz * sizeof(float);
+    // ILU(0): the factors (A's pattern) and the analysed column indices
+    if (prm->precond == BGCR_PRECOND_ILU0) b += (size_t)nnz * (z.sa + sizeof(int));
     return b;
 }
 

@@ -36,6 +36,32 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, name), name
 
 
+def test_library_resolves_every_symbol_at_load(lib):
+    """Loaded with immediate binding, the library has no undefined symbol (a
+    kernel launcher declared but never instantiated would only fail at its
+    first call otherwise)."""
+    ctypes.CDLL(bg.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)
+
+
+def test_ilu0_parameters_without_gpu(lib):
+    """Right preconditioning with ILU(0): plain FP64 (real or complex), no
+    enlarged block or hybrid; its footprint adds the M^{-1} work block, the
+    level orders and the factors on A's pattern."""
+    n, nnz = 32**3, 7 * 32**3
+    P = lambda pc, **kw: bg.bgcr_params(kw.get("p", 8), 10, 20, kw.get("dtype", bg.BGCR_F64),
+                                        kw.get("prec", bg.BGCR_PLAIN_FP64), 100, 0, kw.get("bs", 0), 0, 0, pc)
+    f0 = bg.bgcr_footprint_bytes(P(0), n, nnz)
+    f1 = bg.bgcr_footprint_bytes(P(1), n, nnz)
+    assert f1 - f0 == n * 8 * 8 + 4 * (4 * n + 2) + nnz * (8 + 4)
+    fc = bg.bgcr_footprint_bytes(P(1, dtype=bg.BGCR_C128, p=16), n, nnz)
+    assert fc - bg.bgcr_footprint_bytes(P(0, dtype=bg.BGCR_C128, p=16), n, nnz) == \
+        n * 16 * 16 + 4 * (4 * n + 2) + nnz * (16 + 4)
+    h = ctypes.c_void_p()
+    for bad in (P(1, prec=bg.BGCR_MIXED_FP32), P(1, p=1, bs=8), P(2)):
+        assert bg.bgcr_footprint_bytes(bad, n, nnz) == 0
+        assert lib.bgcr_create_sequence(ctypes.byref(bad), n, None, ctypes.byref(h)) == bg.BGCR_ERR_INVALID
+
+
 def test_strerror_and_footprint_without_gpu(lib):
     assert bg.bgcr_strerror(0) == "ok"
     assert "invalid" in bg.bgcr_strerror(-1)

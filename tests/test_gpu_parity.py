@@ -38,7 +38,7 @@ def _dev():
 
 
 def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=1000, select_largest=False,
-                  block_size=0, enlarge_cycles=0, ritz_vectors=False, capture_U=False):
+                  block_size=0, enlarge_cycles=0, ritz_vectors=False, capture_U=False, precond=0):
     bg = _bg()
     dev = _dev()
     n = systems[0][0].shape[0]
@@ -46,7 +46,7 @@ def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=100
     dt = bg.BGCR_C128 if cplx else bg.BGCR_F64
     seq = bg.Sequence(n, p, m, k, dtype=dt, precision=precision, max_cycles=max_cycles,
                       select_largest=select_largest, block_size=block_size, enlarge_cycles=enlarge_cycles,
-                      ritz_vectors=ritz_vectors)
+                      ritz_vectors=ritz_vectors, precond=precond)
     out = []
     for (A, B, X0) in systems:
         Ad = bg.DeviceCSR.from_scipy(A, dev)
@@ -66,12 +66,12 @@ def _run_sequence(systems, p, m, k, tol, dtype=None, precision=0, max_cycles=100
     return seq, out
 
 
-def _oracle_sequence(systems, tol, m, k, select_largest=False, U=None):
+def _oracle_sequence(systems, tol, m, k, select_largest=False, U=None, precond=None):
     """The oracle over the sequence, U carried from system to system
     (Algorithm 1, last line): [(X, stats, U after the system)]."""
     out = []
     for (A, B, X0) in systems:
-        X, U, so = oracle.solve(A, B, X0, tol, m, k, U=U, select_largest=select_largest)
+        X, U, so = oracle.solve(A, B, X0, tol, m, k, U=U, select_largest=select_largest, precond=precond)
         out.append((X, so, U))
     return out
 
@@ -117,12 +117,14 @@ def _check_exact(name, i, st, so, Xg, Xo, Ug, Uo, Up=None, sp_=None):
     assert ang <= bar
 
 
-def _compare(name, systems, p, m, k, tol, precision=0, bar=PARITY, select_largest=False):
+def _compare(name, systems, p, m, k, tol, precision=0, bar=PARITY, select_largest=False, ilu=False):
     exact = precision == 0
     seq, gpu = _run_sequence(systems, p, m, k, tol, precision=precision, select_largest=select_largest,
-                             capture_U=exact)
-    orc = _oracle_sequence(systems, tol, m, k, select_largest=select_largest)
-    pert = _oracle_sequence(_perturbed(systems), tol, m, k, select_largest=select_largest) if exact else None
+                             capture_U=exact, precond=1 if ilu else 0)
+    pc = "ilu0" if ilu else None
+    orc = _oracle_sequence(systems, tol, m, k, select_largest=select_largest, precond=pc)
+    pert = _oracle_sequence(_perturbed(systems), tol, m, k, select_largest=select_largest,
+                            precond=pc) if exact else None
     for i, ((Xg, st, log, Ug), (Xo, so, Uo)) in enumerate(zip(gpu, orc)):
         A, B, _ = systems[i]
         rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
@@ -650,3 +652,101 @@ def test_32bit_index_limit():
     with pytest.raises(bg.BgcrError) as e:
         bg.bgcr_spmm(Ad, B, X)
     assert e.value.code == bg.BGCR_ERR_INVALID
+
+
+# ---- right preconditioning with ILU(0) (Sections 6.1, 6.2) --------------------
+
+def test_ilu0_cfg1_sequence_parity():
+    w = problems.cfg1()
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    _compare("ilu0-cfg1", systems, w.p, w.m, w.k, w.tol, ilu=True)
+
+
+def test_ilu0_reduced_3d_convdiff_parity():
+    w = problems.cfg2(N=21, nsys=3)   # n = 9261, p = 8, m = 10, k = 20
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    _compare("ilu0-cfg2-21^3", systems, w.p, w.m, w.k, w.tol, ilu=True)
+
+
+@pytest.mark.parametrize("p,m,k", [(1, 12, 6), (2, 5, 0), (4, 6, 5), (16, 4, 8)])
+def test_ilu0_block_sizes(p, m, k):
+    A = problems.convdiff(17, 2, conv=(8.0, -3.0, 0.0))  # n = 289
+    rng = np.random.default_rng(30 + p)
+    systems = []
+    for i in range(2):
+        Ai = (A + sp.diags(0.05 * i * np.ones(A.shape[0]))).tocsr()
+        B = rng.uniform(-1, 1, (A.shape[0], p))
+        systems.append((Ai, B, np.zeros_like(B)))
+    _compare(f"ilu0-p{p}m{m}k{k}", systems, p, m, k, 1e-8, ilu=True)
+
+
+def test_ilu0_complex_helmholtz_parity():
+    w = problems.cfg3(N=41, nsys=2, p=16, m=8, k=16, kappa0=6.0)   # n = 1681, complex128
+    systems = [(s.A, s.B, s.X0) for s in w.systems]
+    _compare("ilu0-cfg3-41^2", systems, w.p, w.m, w.k, w.tol, ilu=True)
+
+
+def test_ilu0_pattern_change_between_systems():
+    """The second system has a different sparsity pattern (extra diagonals,
+    same n): the level schedule is analysed again and the result still follows
+    the oracle; the third returns to the first pattern."""
+    A = problems.convdiff(15, 2, conv=(6.0, 2.0, 0.0))
+    n = A.shape[0]
+    rng = np.random.default_rng(8)
+    extra = sp.diags([0.3 * np.ones(n - 3), -0.2 * np.ones(n - 5)], [3, -5], format="csr")
+    mats = [A, (A + extra).tocsr(), (A + sp.diags(0.1 * np.ones(n))).tocsr()]
+    systems = []
+    for Ai in mats:
+        Ai.sort_indices()
+        B = rng.uniform(-1, 1, (n, 4))
+        systems.append((Ai, B, np.zeros_like(B)))
+    assert systems[1][0].nnz != systems[0][0].nnz
+    _compare("ilu0-pattern", systems, 4, 6, 6, 1e-8, ilu=True)
+
+
+def test_ilu0_exact_factorization_takes_one_block_step():
+    """Tridiagonal A: ILU(0) is exact, A M^{-1} = I, one block step per system."""
+    bg = _bg()
+    A0 = problems.convdiff(300, 1, conv=(30.0, 0.0, 0.0))
+    rng = np.random.default_rng(2)
+    systems = []
+    for i in range(3):
+        A = (A0 + sp.diags(0.1 * i * rng.uniform(0, 1, A0.shape[0]))).tocsr()
+        B = rng.uniform(-1, 1, (A.shape[0], 4))
+        systems.append((A, B, np.zeros_like(B)))
+    seq, gpu = _run_sequence(systems, 4, 5, 2, 1e-10, precond=bg.BGCR_PRECOND_ILU0)
+    for i, (Xg, st, log, _) in enumerate(gpu):
+        A, B, _ = systems[i]
+        rg = np.linalg.norm(B - A @ Xg) / np.linalg.norm(B)
+        print(f"exact ILU sys{i}: block steps {st['block_steps']} relres {rg:.1e}", flush=True)
+        assert st["status"] == 0 and st["block_steps"] == 1 and rg <= 1e-10
+    seq.release()
+
+
+def test_ilu0_rejects_matrices_it_cannot_factor():
+    """A row without its diagonal entry: BGCR_ERR_INVALID; a zero pivot:
+    BGCR_ERR_NUMERICAL; and invalid parameter combinations at creation."""
+    bg = _bg()
+    dev = _dev()
+    A = problems.convdiff(8, 2, conv=(2.0, 1.0, 0.0)).tolil()
+    n = A.shape[0]
+    A[5, 5] = 0.0
+    A = A.tocsr()
+    A.eliminate_zeros()
+    B = torch.ones((n, 4), dtype=torch.float64, device=dev)
+    with bg.Sequence(n, 4, 5, 3, precond=bg.BGCR_PRECOND_ILU0) as seq:
+        with pytest.raises(bg.BgcrError) as e:
+            seq.solve(bg.DeviceCSR.from_scipy(A, dev), B, torch.zeros_like(B), 1e-8)
+        assert e.value.code == bg.BGCR_ERR_INVALID
+        # a structurally present but zero diagonal entry: zero pivot in row 0
+        Z = problems.convdiff(8, 2, conv=(2.0, 1.0, 0.0)).tocsr()
+        Z.data[Z.indptr[0]] = 0.0   # (0, 0) is the first entry of row 0
+        with pytest.raises(bg.BgcrError) as e:
+            seq.solve(bg.DeviceCSR.from_scipy(Z, dev), B, torch.zeros_like(B), 1e-8)
+        assert e.value.code == bg.BGCR_ERR_NUMERICAL
+    for kw in ({"precision": bg.BGCR_MIXED_FP32}, {"p": 1, "block_size": 8}):
+        args = dict(n=n, p=4, m=5, k=3)
+        args.update({k_: v for k_, v in kw.items() if k_ == "p"})
+        with pytest.raises(bg.BgcrError):
+            bg.Sequence(args["n"], args["p"], 5, 3, precond=bg.BGCR_PRECOND_ILU0,
+                        **{k_: v for k_, v in kw.items() if k_ != "p"})
