@@ -240,6 +240,62 @@ def bench_selection(args, torch, problems, bg, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_ilu(args, torch, problems, bg, dev):
+    """Right preconditioning with ILU(0) (the paper's experiments precondition
+    every system, Sections 6.1 and 6.2) on the headline sequence's matrices:
+    the same systems solved without and with ILU(0); systems/s, cycles and
+    block steps per system, ms per cycle, and (in a second, profiled pass) the
+    per-class split with the triangular solves and the factorization."""
+    nsys = args.nsys if args.nsys != 10 else 4
+    w = problems.cfg2(N=args.grid, nsys=nsys)
+    systems = [(s_.A, s_.B) for s_ in w.systems]
+    n, nnz = systems[0][0].shape[0], systems[0][0].nnz
+    log(f"[bench] ilu: {nsys} systems n={n} nnz={nnz} p={w.p} m={w.m} k={w.k} tol={w.tol}")
+    dA = [bg.DeviceCSR.from_scipy(A, dev) for (A, _) in systems]
+    dB = [torch.from_numpy(B).to(dev) for (_, B) in systems]
+    out = {}
+    for name, pc in (("none", bg.BGCR_PRECOND_NONE), ("ilu0", bg.BGCR_PRECOND_ILU0)):
+        for profiled in (False, True):
+            seq = bg.Sequence(n, w.p, w.m, w.k, max_cycles=20000, precond=pc)
+            if profiled:
+                seq.set_profiling(True)
+            dX = [torch.zeros_like(b) for b in dB]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cyc, steps, lat = [], [], []
+            for i in range(nsys):
+                ts = time.perf_counter()
+                st = seq.solve(dA[i], dB[i], dX[i], w.tol)
+                lat.append(time.perf_counter() - ts)
+                if st.status not in (bg.BGCR_OK, bg.BGCR_BREAKDOWN_DEFLATED):
+                    raise RuntimeError(f"{name} system {i}: {st.as_dict()}")
+                cyc.append(st.cycles)
+                steps.append(st.block_steps)
+                log(f"[bench] {name}{' (profiled)' if profiled else ''} system {i}: {lat[-1]:.2f}s "
+                    f"cycles={st.cycles} block steps={st.block_steps}")
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            if profiled:
+                prof = seq.profile()
+                tc = sum(cyc)
+                out[name]["profiled_classes_ms_per_cycle"] = {k: round(v["ms"] / tc, 3) for k, v in prof.items()
+                                                             if v["launches"]}
+                seq.release()
+                continue
+            seq.release()
+            worst = max(_host_check(A, B, x.cpu().numpy()) for (A, B), x in zip(systems, dX))
+            out[name] = {"systems_per_s": round(nsys / el, 4), "seconds": round(el, 2),
+                         "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                         "cycles_per_system": cyc, "block_steps_per_system": steps,
+                         "ms_per_cycle": round(1e3 * el / sum(cyc), 3), "max_rel_res_fp64_check": worst}
+    res = {"metric": "systems/s with and without ILU(0) right preconditioning", "unit": "systems/s",
+           "config": {"workload": f"convdiff3d_{args.grid}^3_seq{nsys}_p{w.p}_m{w.m}_k{w.k}_ilu0", "n": n,
+                      "nnz": nnz, "tol": w.tol},
+           "speedup_ilu0": round(out["ilu0"]["systems_per_s"] / out["none"]["systems_per_s"], 3),
+           "data": "synthetic", "n_gpus": 1, **out}
+    print(json.dumps(res), flush=True)
+
+
 def bench_datamove(args, torch, problems, bg, dev):
     """The data-movement study of Section 6.3 on one MI355X: a banded matrix
     applied to a block of p vectors at once vs one vector at a time, then the
@@ -458,7 +514,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--datamove-small", action="store_true", help="datamove: one matrix, p in {1, 8} (profiling)")
     ap.add_argument("--cycles", type=int, default=40, help="blocksizes: restart cycles per block size")
-    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection", "datamove",
+    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection", "datamove", "ilu",
                                            "blocksizes"],
                     default="cfg2",
                     help="cfg2: the headline sequence (default); precision: plain FP64 vs the FP32-in-FP64 form on "
@@ -495,6 +551,8 @@ def main():
         return bench_datamove(args, torch, problems, bg, dev)
     if args.workload == "blocksizes":
         return bench_blocksizes(args, torch, problems, bg, dev)
+    if args.workload == "ilu":
+        return bench_ilu(args, torch, problems, bg, dev)
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20

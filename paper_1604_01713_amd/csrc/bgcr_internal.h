@@ -228,15 +228,26 @@ hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ld
 // launch handles the rows rows[0 .. nrows) of one level; T is double or zd.
 // ---------------------------------------------------------------------------
 // numeric factorization of one level in place (lu starts as a copy of A's
-// values); *err = 1 on a zero or non-finite pivot
+// values; entries -1 of rows are padding); *err = 1 on a zero or non-finite
+// pivot
 template <class T>
 hipError_t ilu0_level(hipStream_t st, const int* rows, int nrows, const int* rp, const int* ci, const int* diag,
                       T* lu, int* err);
-// one level of L y = in (lower) or U x = in (upper) for P right-hand sides
-// (row-major n x P); in may alias out; skipped while the cycle is inactive
+// The whole triangular solve (lower: L y = in; upper: U x = in) in one launch,
+// rows taken in level order by the ticket counter `tick` and every entry of
+// `out` waited for by value: `ord` (npad entries) lists the rows level by
+// level, each level padded with -1 to a multiple of 256 / P entries; `out`
+// must hold PENDING everywhere and *tick must be 0.  The launch re-arms
+// `rearm` (its entries set to PENDING after `in` is read, so in may be rearm)
+// and *tick_next = 0 for the next solve; *err = 1 if a bounded wait expired
+// (the row then holds a NaN).  Skipped while the cycle is inactive.
 template <class T>
-hipError_t trsv_level(hipStream_t st, int P, bool lower, const int* rows, int nrows, const int* rp, const int* ci,
-                      const int* diag, const T* lu, const T* in, T* out, const Ctl* ctl);
+hipError_t trsv_flow(hipStream_t st, int P, bool lower, int64_t npad, const int* ord, const int* rp, const int* ci,
+                     const int* diag, const T* lu, const T* in, T* out, T* rearm, unsigned* tick, unsigned* tick_next,
+                     int* err, const Ctl* ctl);
+// count entries of y set to PENDING (the initial state of the two solve blocks)
+template <class T>
+hipError_t fill_pending(hipStream_t st, int64_t count, T* y);
 // *diff = 1 where the CSR patterns (rpa, cia) and (rpb, cib) differ (same n, nnz)
 hipError_t pattern_diff(hipStream_t st, int64_t n, int64_t nnz, const int* rpa, const int* cia, const int* rpb,
                         const int* cib, int* diff);

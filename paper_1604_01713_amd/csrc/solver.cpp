@@ -128,11 +128,11 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     const bool enlarged = z.P > prm->p;
     z.total_fixed = z.basis + 3 * (size_t)n * z.P * z.sw /* W2, Wb, R */ +
                     (size_t)n * z.P * z.sa * (enlarged ? 2 : 1) /* X (and B padded) */ + z.recyc + z.part + z.small_;
-    // ILU(0): the M^{-1} work block, diagonal positions, two level orders, the
-    // analysed row pointers and a flag (the nnz-sized arrays are counted by
-    // bgcr_footprint_bytes)
+    // ILU(0): the two blocks of M^{-1}, diagonal positions, the analysed row
+    // pointers, a flag and two ticket counters (the nnz-sized arrays and the
+    // level orders are counted by bgcr_footprint_bytes)
     if (prm->precond == BGCR_PRECOND_ILU0)
-        z.total_fixed += (size_t)n * z.P * z.sw + sizeof(int) * (4 * (size_t)n + 2);
+        z.total_fixed += 2 * (size_t)n * z.P * z.sw + sizeof(int) * (2 * (size_t)n + 4);
     return z;
 }
 
@@ -187,15 +187,18 @@ struct Seq final : bgcr_sequence {
     int n_deflated = 0;  // rank-deficient blocks handled: start blocks rebuilt, cycles ended at a breakdown
 
     // ILU(0) right preconditioning: level schedule of the analysed pattern,
-    // the factors of the current system, and the M^{-1} work block
+    // the factors of the current system, and the two blocks of M^{-1} (Yb
+    // holds L^{-1} in, Zb the result)
     bool pc = false;
     int *d_rp = nullptr, *d_ci = nullptr, *d_diag = nullptr, *d_ordL = nullptr, *d_ordU = nullptr,
         *d_flag = nullptr;
-    int64_t pat_nnz = -1;   // nnz of the analysed pattern (-1: none yet)
-    size_t ci_cap = 0, lu_cap = 0;
-    std::vector<int> lvlL, lvlU;  // level pointers into the L and U row orders
+    unsigned* d_tick = nullptr;   // ticket counters of the L and U solves
+    bool ilu_used = false;        // this solve factored its system
+    int64_t pat_nnz = -1;         // nnz of the analysed pattern (-1: none yet)
+    size_t ci_cap = 0, lu_cap = 0, ordL_cap = 0, ordU_cap = 0;
+    std::vector<int> lvlL, lvlU;  // level pointers into the padded L and U row orders
     A* lu = nullptr;
-    T* Zb = nullptr;
+    T *Zb = nullptr, *Yb = nullptr;
 
     std::vector<void*> allocs;
 
@@ -374,11 +377,11 @@ struct Seq final : bgcr_sequence {
         dpart = dalloc<double>((size_t)NWG_MAX * 2 * P);
         if (pc) {
             Zb = dalloc<T>(blk);
+            Yb = dalloc<T>(blk);
             d_rp = dalloc<int>((size_t)n + 1);
             d_diag = dalloc<int>((size_t)n);
-            d_ordL = dalloc<int>((size_t)n);
-            d_ordU = dalloc<int>((size_t)n);
             d_flag = dalloc<int>(1);
+            d_tick = dalloc<unsigned>(2);
         }
         hcap = std::max({(size_t)4 << 20, 2 * coef_cap * sizeof(A) + (64 << 10), hr_bytes + (64 << 10)});
         if (hipHostMalloc((void**)&hbuf, hcap, hipHostMallocDefault) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
@@ -617,7 +620,7 @@ struct Seq final : bgcr_sequence {
         const int o = 1 - cur;
         for (int b = 0; b < KB; ++b) {
             // right preconditioning: the operator is A M^{-1}
-            if (pc) apply_minv((const T*)ublk(cur, b), Zb, nullptr);
+            if (pc) apply_minv((const T*)ublk(cur, b), nullptr);
             run(BGCR_K_SPMM, (double)(sizeof(T) + 4) * Am->nnz + 4.0 * (n + 1) + 2.0 * sizeof(TB) * n * P, [&] {
                 if constexpr (half) {
                     return spmm_block<T, TB, TB, TB>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, ublk(cur, b),
@@ -709,7 +712,7 @@ struct Seq final : bgcr_sequence {
         d2h(rp.data(), Am->row_ptr, (n + 1) * sizeof(int));
         d2h(ci.data(), Am->col_idx, (size_t)nnz * sizeof(int));
         if (rp[0] != 0 || rp[n] != nnz) throw Fail{BGCR_ERR_INVALID};
-        std::vector<int> diag(n), lev(n), ordL(n), ordU(n);
+        std::vector<int> diag(n), lev(n), ordL, ordU;
         for (int64_t i = 0; i < n; ++i) {
             if (rp[i + 1] < rp[i]) throw Fail{BGCR_ERR_INVALID};
             int d = -1;
@@ -720,12 +723,17 @@ struct Seq final : bgcr_sequence {
             if (d < 0) throw Fail{BGCR_ERR_INVALID};
             diag[i] = d;
         }
+        // rows by level, in increasing index within a level, each level
+        // padded with -1 to whole chunks of the single-launch solve
+        const int chunk = 256 / P;
         auto order = [&](std::vector<int>& ord, std::vector<int>& ptr) {
             int nl = 0;
             for (int64_t i = 0; i < n; ++i) nl = std::max(nl, lev[i] + 1);
+            std::vector<int64_t> cnt(nl, 0);
+            for (int64_t i = 0; i < n; ++i) ++cnt[lev[i]];
             ptr.assign(nl + 1, 0);
-            for (int64_t i = 0; i < n; ++i) ++ptr[lev[i] + 1];
-            for (int l = 0; l < nl; ++l) ptr[l + 1] += ptr[l];
+            for (int l = 0; l < nl; ++l) ptr[l + 1] = ptr[l] + (int)((cnt[l] + chunk - 1) / chunk * chunk);
+            ord.assign(ptr[nl], -1);
             std::vector<int> pos(ptr.begin(), ptr.end() - 1);
             for (int64_t i = 0; i < n; ++i) ord[pos[lev[i]]++] = (int)i;
         };
@@ -742,9 +750,11 @@ struct Seq final : bgcr_sequence {
         }
         order(ordU, lvlU);
         regrow(d_ci, ci_cap, std::max<size_t>(1, (size_t)nnz));
+        regrow(d_ordL, ordL_cap, ordL.size());
+        regrow(d_ordU, ordU_cap, ordU.size());
         h2d_big(d_diag, diag.data(), n * sizeof(int));
-        h2d_big(d_ordL, ordL.data(), n * sizeof(int));
-        h2d_big(d_ordU, ordU.data(), n * sizeof(int));
+        h2d_big(d_ordL, ordL.data(), ordL.size() * sizeof(int));
+        h2d_big(d_ordU, ordU.data(), ordU.size() * sizeof(int));
         HIPCHK(hipMemcpyAsync(d_rp, Am->row_ptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, st));
         if (nnz > 0)
             HIPCHK(hipMemcpyAsync(d_ci, Am->col_idx, (size_t)nnz * sizeof(int), hipMemcpyDeviceToDevice, st));
@@ -769,6 +779,7 @@ struct Seq final : bgcr_sequence {
     // a copy of A's values.  A zero or non-finite pivot: BGCR_ERR_NUMERICAL.
     void ilu_setup(const bgcr_csr* Am) {
         HostPhase hp(this, BGCR_K_ILU);
+        ilu_used = true;
         bool same = false;
         if (pat_nnz == Am->nnz) {
             HIPCHK(hipMemsetAsync(d_flag, 0, sizeof(int), st));
@@ -787,26 +798,38 @@ struct Seq final : bgcr_sequence {
         int f = 0;
         d2h(&f, d_flag, sizeof(int));
         if (f) throw Fail{BGCR_ERR_NUMERICAL};
+        // the single-launch solves start from PENDING blocks and zero tickets
+        if constexpr (std::is_same<T, A>::value) {
+            HIPCHK(fill_pending<T>(st, (int64_t)n * P, Yb));
+            HIPCHK(fill_pending<T>(st, (int64_t)n * P, Zb));
+        }
+        HIPCHK(hipMemsetAsync(d_tick, 0, 2 * sizeof(unsigned), st));
     }
 
-    // out = M^{-1} in = U^{-1} (L^{-1} in) for a P-column block (in may be out);
-    // skipped on the device while `ctl` says the cycle has stopped
-    void apply_minv(const T* in, T* out, const Ctl* c) {
+    // a bounded wait of a triangular solve expired during this solve
+    bool ilu_wait_expired() {
+        int f = 0;
+        d2h(&f, d_flag, sizeof(int));
+        return f != 0;
+    }
+
+    // Zb = M^{-1} in = U^{-1} (L^{-1} in) for a P-column block (in may be Zb):
+    // L^{-1} in into Yb, then U^{-1} Yb into Zb, one launch each, each
+    // re-arming the other block; skipped on the device while `ctl` says the
+    // cycle has stopped
+    void apply_minv(const T* in, const Ctl* c) {
         if constexpr (std::is_same<T, A>::value) {
             const double by = (double)(sizeof(A) + 4) * pat_nnz + 4.0 * (n + 1) * 2 + 4.0 * n * 4 +
                               4.0 * sizeof(T) * n * P;
             run(BGCR_K_PRECOND, by, [&] {
-                for (size_t l = 0; l + 1 < lvlL.size(); ++l)
-                    HIPCHK(trsv_level<A>(st, P, true, d_ordL + lvlL[l], lvlL[l + 1] - lvlL[l], d_rp, d_ci, d_diag,
-                                         lu, in, out, c));
-                for (size_t l = 0; l + 1 < lvlU.size(); ++l)
-                    HIPCHK(trsv_level<A>(st, P, false, d_ordU + lvlU[l], lvlU[l + 1] - lvlU[l], d_rp, d_ci, d_diag,
-                                         lu, out, out, c));
-                return hipSuccess;
+                const int64_t nL = lvlL.empty() ? 0 : lvlL.back(), nU = lvlU.empty() ? 0 : lvlU.back();
+                HIPCHK(trsv_flow<A>(st, P, true, nL, d_ordL, d_rp, d_ci, d_diag, lu, in, Yb, Zb, d_tick, d_tick + 1,
+                                    d_flag, c));
+                return trsv_flow<A>(st, P, false, nU, d_ordU, d_rp, d_ci, d_diag, lu, Yb, Zb, Yb, d_tick + 1, d_tick,
+                                    d_flag, c);
             });
         } else {
             (void)in;
-            (void)out;
             (void)c;
             throw Fail{BGCR_ERR_INVALID};
         }
@@ -820,7 +843,7 @@ struct Seq final : bgcr_sequence {
             return;
         }
         combine<A>(in, {(void*)Zb}, K, 0);
-        apply_minv(Zb, Zb, nullptr);
+        apply_minv(Zb, nullptr);
         combine<A>({(const void*)Zb}, {X}, Mat::eye(P), 1);
     }
 
@@ -1054,7 +1077,7 @@ struct Seq final : bgcr_sequence {
                             return rows_times<T>(st, P, n, (const T*)W2, RinvAll + (size_t)(j - 1) * P2,
                                                  (T*)vblk(j - 1), ctl);
                         });
-                    apply_minv((const T*)vblk(j - 1), Zb, ctl);
+                    apply_minv((const T*)vblk(j - 1), ctl);
                 }
             }
             run(BGCR_K_ARN_SPMM, abytes + vblkb + blkb, [&] {
@@ -1558,6 +1581,7 @@ struct Seq final : bgcr_sequence {
         n_spmm = n_steps = n_cycles = n_refine = 0;
         alg_bytes = 0.0;
         n_deflated = 0;
+        ilu_used = false;
         log_steps.clear();
         log_res.clear();
         int status = BGCR_OK;
@@ -1625,6 +1649,7 @@ struct Seq final : bgcr_sequence {
             HIPCHK(copy_block<A, A>(st, n, pu, X, P, Xu, ldx, pu));
             sync();
             if (!std::isfinite(rel)) status = BGCR_ERR_NONFINITE;
+            if (ilu_used && ilu_wait_expired()) status = BGCR_ERR_NUMERICAL;
             // converged, with a rank-deficient block handled on the way
             if (status == BGCR_OK && n_deflated > 0) status = BGCR_BREAKDOWN_DEFLATED;
         } catch (const Fail& f) {
@@ -2023,8 +2048,10 @@ size_t bgcr_footprint_bytes(const bgcr_params* prm, int64_t n, int64_t nnz) {
     const Sizes z = sizes_of(prm, n);
     size_t b = z.total_fixed;
     if (prm->precision != BGCR_PLAIN_FP64) b += (size_t)nnz * sizeof(float);
-    // ILU(0): the factors (A's pattern) and the analysed column indices
-    if (prm->precond == BGCR_PRECOND_ILU0) b += (size_t)nnz * (z.sa + sizeof(int));
+    // ILU(0): the factors (A's pattern), the analysed column indices, and the
+    // two level orders (n rows each, every level padded to chunks of 256 / P
+    // rows; the analysis grows them when a pattern has many small levels)
+    if (prm->precond == BGCR_PRECOND_ILU0) b += (size_t)nnz * (z.sa + sizeof(int)) + 2 * sizeof(int) * (size_t)n;
     return b;
 }
 

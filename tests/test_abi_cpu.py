@@ -52,10 +52,12 @@ def test_ilu0_parameters_without_gpu(lib):
                                         kw.get("prec", bg.BGCR_PLAIN_FP64), 100, 0, kw.get("bs", 0), 0, 0, pc)
     f0 = bg.bgcr_footprint_bytes(P(0), n, nnz)
     f1 = bg.bgcr_footprint_bytes(P(1), n, nnz)
-    assert f1 - f0 == n * 8 * 8 + 4 * (4 * n + 2) + nnz * (8 + 4)
+    # two n x p solve blocks, diagonal positions, row pointers, flag and
+    # tickets, two level orders, the factors and column indices
+    assert f1 - f0 == 2 * n * 8 * 8 + 4 * (2 * n + 4) + 8 * n + nnz * (8 + 4)
     fc = bg.bgcr_footprint_bytes(P(1, dtype=bg.BGCR_C128, p=16), n, nnz)
     assert fc - bg.bgcr_footprint_bytes(P(0, dtype=bg.BGCR_C128, p=16), n, nnz) == \
-        n * 16 * 16 + 4 * (4 * n + 2) + nnz * (16 + 4)
+        2 * n * 16 * 16 + 4 * (2 * n + 4) + 8 * n + nnz * (16 + 4)
     h = ctypes.c_void_p()
     for bad in (P(1, prec=bg.BGCR_MIXED_FP32), P(1, p=1, bs=8), P(2)):
         assert bg.bgcr_footprint_bytes(bad, n, nnz) == 0
