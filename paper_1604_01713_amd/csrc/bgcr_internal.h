@@ -169,7 +169,9 @@ hipError_t step_small(hipStream_t st, int P, const A* gram, const A* S, const A*
 
 // matrix-core versions of the three Arnoldi sweeps (real FP64/FP32 storage,
 // P = 8 or 16); hipErrorNotSupported for other shapes.  nwg workgroups of
-// 64-row tiles (mfma_nwg gives the default).
+// 64-row tiles (mfma_nwg gives the default).  Each workgroup sweeps one
+// contiguous range of row tiles; rev = true walks it from its end (FP64
+// kernels), so that a sweep starts on the rows the previous one read last.
 int mfma_nwg(int64_t n);
 hipError_t i_minus(hipStream_t st, const double* M, double* out, int P);
 // T is the arithmetic type (FP64 or FP32); TW, TQ and TO the storage types of
@@ -180,18 +182,18 @@ hipError_t i_minus(hipStream_t st, const double* M, double* out, int P);
 // chunks of 16 Q columns, per launch (hipErrorNotSupported otherwise)
 template <class T, class TW = T, class TQ = T>
 hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq,
-                    double* part, const Ctl* ctl, int nwg);
+                    double* part, const Ctl* ctl, int nwg, bool rev = false);
 // sweep 2: partial Q^T (W - Q S) and, with gram, (W - Q S)^T (W - Q S) after it
 template <class T, class TQ = T>
 hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                         double* part, const Ctl* ctl, int nwg, bool gram = false);
+                         double* part, const Ctl* ctl, int nwg, bool gram = false, bool rev = false);
 // sweep 3: W'' = W - Q S stored with its Gram partials, or with Rinv given,
 // V = W'' Rinv stored (no Gram); with a control block it runs while the cycle
 // is active and also for block step `step` if the cycle just stopped there
 template <class T, class TQ = T, class TO = T>
 hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
                           const double* S, TO* Wout, double* part, const Ctl* ctl, int nwg,
-                          const double* Rinv = nullptr, int step = -1);
+                          const double* Rinv = nullptr, int step = -1, bool rev = false);
 
 // Sweep 1 of a block step with separate storage types: W = (A Vin) Rinv and
 // Vout = Vin Rinv, or W = A Vin alone (Rinv and Vout NULL).  T is the type of

@@ -9,20 +9,20 @@ namespace bgcr {
 
 // [C V_1 .. V_j]^T W with W in FP32 (Arnoldi sweep 1b, C^T R)
 template hipError_t mfma_dot<float, float, bf16>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&,
-                                                 int, double*, const Ctl*, int);
+                                                 int, double*, const Ctl*, int, bool);
 // dots of basis blocks with basis blocks (Gram of C, refresh dots against U)
 template hipError_t mfma_dot<float, bf16, bf16>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&,
-                                                int, double*, const Ctl*, int);
+                                                int, double*, const Ctl*, int, bool);
 template hipError_t mfma_proj_dot<float, bf16>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int,
-                                               const double*, double*, const Ctl*, int, bool);
+                                               const double*, double*, const Ctl*, int, bool, bool);
 template hipError_t mfma_proj_gram<float, bf16, bf16>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int,
                                                       const double*, bf16*, double*, const Ctl*, int, const double*,
-                                                      int);
+                                                      int, bool);
 
 // R - C T with C in BF16 (enlarged start block projected against C)
 template hipError_t mfma_proj_gram<float, bf16, float>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int,
                                                        const double*, float*, double*, const Ctl*, int, const double*,
-                                                       int);
+                                                       int, bool);
 
 template hipError_t mfma_combine<bf16, double>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int,
                                                const double*, int, int);

@@ -5,12 +5,12 @@
 namespace bgcr {
 
 template hipError_t mfma_dot<float>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int, double*,
-                                    const Ctl*, int);
+                                    const Ctl*, int, bool);
 template hipError_t mfma_proj_dot<float>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int,
-                                          const double*, double*, const Ctl*, int, bool);
+                                          const double*, double*, const Ctl*, int, bool, bool);
 template hipError_t mfma_proj_gram<float>(hipStream_t, int, int64_t, const float*, const BlockPtrs&, int,
                                            const double*, float*, double*, const Ctl*, int, const double*,
-                                           int);
+                                           int, bool);
 
 template hipError_t mfma_combine<float, float>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&,
                                                   int, const double*, int, int);

@@ -26,12 +26,12 @@ int mfma_nwg(int64_t n) {
 }
 
 template hipError_t mfma_dot<double>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int, double*,
-                                     const Ctl*, int);
+                                     const Ctl*, int, bool);
 template hipError_t mfma_proj_dot<double>(hipStream_t, int, int64_t, const double*, const BlockPtrs&, int,
-                                          const double*, double*, const Ctl*, int, bool);
+                                          const double*, double*, const Ctl*, int, bool, bool);
 template hipError_t mfma_proj_gram<double>(hipStream_t, int, int64_t, const double*, const BlockPtrs&, int,
                                            const double*, double*, double*, const Ctl*, int, const double*,
-                                           int);
+                                           int, bool);
 
 template hipError_t mfma_combine<double, double>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&,
                                                   int, const double*, int, int);

@@ -228,7 +228,7 @@ __device__ inline int qsw(int r, int c) {
 // ---------------------------------------------------------------------------
 template <class T, class TW, class TQ, int P, int NC, int KS, int NG>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 && NC * NG > 18 ? 1 : 2))) void
-k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restrict__ part, const Ctl* ctl) {
+k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restrict__ part, const Ctl* ctl, int rev) {
     using M = MX<T>;
     constexpr int WROWS = 4 * KS, TROWS = 4 * WROWS;
     if (ctl && ctl->active == 0) return;
@@ -248,12 +248,15 @@ k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restri
     const int lw = logical_wg();
     int64_t t0, t1;
     tile_span((n + TROWS - 1) / TROWS, lw, t0, t1);
+    const int64_t cnt = t1 - t0, dstep = rev ? -TROWS : TROWS;
     T qn[KS][NC], wn[KS][NG];
-    if (t0 < t1) {
-        load_rc<T, TQ, P, NC, KS>(qn, qp, t0 * TROWS + wave * WROWS, n, lane);
-        load_rc<T, TW, P, NG, KS>(wn, wp, t0 * TROWS + wave * WROWS, n, lane);
+    if (cnt > 0) {
+        const int64_t r0 = (rev ? t1 - 1 : t0) * TROWS + wave * WROWS;
+        load_rc<T, TQ, P, NC, KS>(qn, qp, r0, n, lane);
+        load_rc<T, TW, P, NG, KS>(wn, wp, r0, n, lane);
     }
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t tile = rev ? t1 - 1 - k : t0 + k;
         const int64_t rbase = tile * TROWS + wave * WROWS;
         T qc[KS][NC], wc[KS][NG];
 #pragma unroll
@@ -269,9 +272,9 @@ k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restri
 #pragma unroll
                 for (int g = 0; g < NG; ++g) wc[ks][g] = rbase + 4 * ks + (lane >> 4) < n ? wc[ks][g] : (T)0;
         }
-        if (tile + 1 < t1) {
-            load_rc<T, TQ, P, NC, KS>(qn, qp, rbase + TROWS, n, lane);
-            load_rc<T, TW, P, NG, KS>(wn, wp, rbase + TROWS, n, lane);
+        if (k + 1 < cnt) {
+            load_rc<T, TQ, P, NC, KS>(qn, qp, rbase + dstep, n, lane);
+            load_rc<T, TW, P, NG, KS>(wn, wp, rbase + dstep, n, lane);
         }
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
@@ -294,7 +297,7 @@ k_dot_mfma(int64_t n, BlockPtrs W, int nw, BlockPtrs Q, int nq, double* __restri
 template <class T, class TQ, int P, int NC, bool GRAM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) == 8 ? NC <= 7 : NC <= 10) ? 2 : 1))) void k_proj_dot_mfma(
     int64_t n, const T* __restrict__ Win, BlockPtrs Q, int nq, const double* __restrict__ S, double* __restrict__ part,
-    const Ctl* ctl) {
+    const Ctl* ctl, int rev) {
     using M = MX<T>;
     constexpr int NQ = NC * 16 / P, KK = P / 4, QLD = 32 * ((NC + 1) / 2);
     if (ctl && ctl->active == 0) return;
@@ -320,21 +323,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
     T* myW = Wt + wave * 16 * P;
     T qn[4][NC];
     typename M::acc wn = typename M::acc{0, 0, 0, 0};
-    if (t0 < t1) {
-        load_rc<T, TQ, P, NC, 4>(qn, qp, t0 * MROWS + wave * 16, n, lane);
-        wn = load_wt<T, P>(Win, t0 * MROWS + wave * 16, n, lane);
+    const int64_t cnt = t1 - t0, dstep = rev ? -MROWS : MROWS;
+    if (cnt > 0) {
+        const int64_t r0 = (rev ? t1 - 1 : t0) * MROWS + wave * 16;
+        load_rc<T, TQ, P, NC, 4>(qn, qp, r0, n, lane);
+        wn = load_wt<T, P>(Win, r0, n, lane);
     }
     __syncthreads();
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t tile = rev ? t1 - 1 - k : t0 + k;
         const int64_t rbase = tile * MROWS + wave * 16;
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch) myQ[qsw<QLD>(4 * ks + rq, 16 * ch + bl)] = qn[ks][ch];
         typename M::acc d = wn;
-        if (tile + 1 < t1) {
-            load_rc<T, TQ, P, NC, 4>(qn, qp, rbase + MROWS, n, lane);
-            wn = load_wt<T, P>(Win, rbase + MROWS, n, lane);
+        if (k + 1 < cnt) {
+            load_rc<T, TQ, P, NC, 4>(qn, qp, rbase + dstep, n, lane);
+            wn = load_wt<T, P>(Win, rbase + dstep, n, lane);
         }
         // D = W^T + (-S)^T Q^T over the columns of Q, 4 per instruction
         // (A rows past P repeat row b % P; those D rows are never stored)
@@ -376,7 +382,7 @@ template <class T, class TQ, class TO, int P, int NC, bool NORM>
 __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* Win, BlockPtrs Q, int nq,
                                                         const double* __restrict__ S, TO* Wout,
                                                         double* __restrict__ part, const double* __restrict__ Rinv,
-                                                        const Ctl* ctl, int step) {
+                                                        const Ctl* ctl, int step, int rev) {
     using M = MX<T>;
     constexpr int NQ = NC * 16 / P, KK = P / 4, NQV = NQ * KK, NQA = NQ > 0 ? NQ : 1;
     // runs while the cycle is active, and also for the step at which it just
@@ -414,26 +420,29 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* Win,
     };
     T qn[NQA * KK];
     typename M::acc wn = typename M::acc{0, 0, 0, 0};
-    if (t0 < t1) {
-        if constexpr (NQV > 0) load_cr(qn, t0 * MROWS + wave * 16);
-        wn = load_wt<T, P>(Win, t0 * MROWS + wave * 16, n, lane);
+    const int64_t cnt = t1 - t0, dstep = rev ? -MROWS : MROWS;
+    if (cnt > 0) {
+        const int64_t r0 = (rev ? t1 - 1 : t0) * MROWS + wave * 16;
+        if constexpr (NQV > 0) load_cr(qn, r0);
+        wn = load_wt<T, P>(Win, r0, n, lane);
     }
     __syncthreads();
-    for (int64_t tile = t0; tile < t1; ++tile) {
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t tile = rev ? t1 - 1 - k : t0 + k;
         const int64_t rbase = tile * MROWS + wave * 16;
         typename M::acc d = wn;
         if constexpr (NQV > 0) {
             T qc[NQA * KK];
 #pragma unroll
             for (int e = 0; e < NQV; ++e) qc[e] = qn[e];
-            if (tile + 1 < t1) load_cr(qn, rbase + MROWS);
+            if (k + 1 < cnt) load_cr(qn, rbase + dstep);
 #pragma unroll
             for (int blk = 0; blk < NQ; ++blk) {
 #pragma unroll
                 for (int kk = 0; kk < KK; ++kk) d = M::mma(Ss[(blk * P + 4 * kk + rq) * P + bc], qc[blk * KK + kk], d);
             }
         }
-        if (tile + 1 < t1) wn = load_wt<T, P>(Win, rbase + MROWS, n, lane);
+        if (k + 1 < cnt) wn = load_wt<T, P>(Win, rbase + dstep, n, lane);
         const int64_t row = rbase + bl;
         zero_tail<T>(d, rbase, n, lane);
         if constexpr (NORM) {
@@ -726,7 +735,7 @@ constexpr int dot_ks() {
 
 template <class T, class TW, class TQ, int P>
 hipError_t launch_dot(hipStream_t st, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq, double* part,
-                      int nwg, const Ctl* ctl) {
+                      int nwg, const Ctl* ctl, bool rev = false) {
     const int nc = (nq * P + 15) / 16, ng = (nw * P + 15) / 16;
     const size_t lds = (size_t)1024 * sizeof(double);
     // a chunk of narrow blocks spans 16 / P block pointers: at most MAXB in all
@@ -735,14 +744,14 @@ hipError_t launch_dot(hipStream_t st, int64_t n, const BlockPtrs& W, int nw, con
 #define L(NC)                                                                                                      \
     if constexpr ((NC) * (16 / P) <= MAXB)                                                                         \
         hipLaunchKernelGGL((k_dot_mfma<T, TW, TQ, P, NC, dot_ks<NC>(), 1>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, nq, \
-                           part, ctl)
+                           part, ctl, (int)rev)
         BGCR_MX_NC_DISPATCH(nc, L)
 #undef L
     } else if (ng == 2 && nc <= 9) {
 #define L(NC)                                                                                                      \
     if constexpr ((NC) * (16 / P) <= MAXB)                                                                         \
         hipLaunchKernelGGL((k_dot_mfma<T, TW, TQ, P, NC, dot_ks<2 * NC>(), 2>), dim3(nwg), dim3(256), lds, st, n, W, nw, Q, \
-                           nq, part, ctl)
+                           nq, part, ctl, (int)rev)
         switch (nc) {
             case 1: L(1); break;
             case 2: L(2); break;
@@ -764,7 +773,7 @@ hipError_t launch_dot(hipStream_t st, int64_t n, const BlockPtrs& W, int nw, con
 
 template <class T, class TQ, int P, bool GRAM>
 hipError_t launch_proj_dot_t(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                             double* part, int nwg, const Ctl* ctl) {
+                             double* part, int nwg, const Ctl* ctl, bool rev) {
     const int nc = (nq * P + 15) / 16;
 #define L(NC)                                                                                                   \
     {                                                                                                           \
@@ -775,7 +784,7 @@ hipError_t launch_proj_dot_t(hipStream_t st, int64_t n, const T* Win, const Bloc
         static std::once_flag fl;                                                                               \
         std::call_once(fl, [] { allow_lds(k_proj_dot_mfma<T, TQ, P, NC, GRAM>); });                             \
         hipLaunchKernelGGL((k_proj_dot_mfma<T, TQ, P, NC, GRAM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, \
-                           part, ctl);                                                                          \
+                           part, ctl, (int)rev);                                                                \
     }
     BGCR_MX_NC_DISPATCH(nc, L)
 #undef L
@@ -784,21 +793,21 @@ hipError_t launch_proj_dot_t(hipStream_t st, int64_t n, const T* Win, const Bloc
 
 template <class T, class TQ, int P>
 hipError_t launch_proj_dot(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                           double* part, int nwg, const Ctl* ctl, bool gram) {
-    return gram ? launch_proj_dot_t<T, TQ, P, true>(st, n, Win, Q, nq, S, part, nwg, ctl)
-                : launch_proj_dot_t<T, TQ, P, false>(st, n, Win, Q, nq, S, part, nwg, ctl);
+                           double* part, int nwg, const Ctl* ctl, bool gram, bool rev = false) {
+    return gram ? launch_proj_dot_t<T, TQ, P, true>(st, n, Win, Q, nq, S, part, nwg, ctl, rev)
+                : launch_proj_dot_t<T, TQ, P, false>(st, n, Win, Q, nq, S, part, nwg, ctl, rev);
 }
 
 template <class T, class TQ, class TO, int P, bool NORM>
 hipError_t launch_proj_gram_t(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                              TO* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step) {
+                              TO* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step, bool rev) {
     const int nc = (nq * P + 15) / 16;
 #define L(NC)                                                                                                    \
     {                                                                                                            \
         constexpr int NQA = NC * 16 / P > 0 ? NC * 16 / P : 1;                                                   \
         const size_t lds = std::max((size_t)(NQA * P * P + 4 * 16 * P) * sizeof(T), (size_t)1024 * sizeof(double)); \
         hipLaunchKernelGGL((k_proj_gram_mfma<T, TQ, TO, P, NC, NORM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, \
-                           Wout, part, Rinv, ctl, step);                                                         \
+                           Wout, part, Rinv, ctl, step, (int)rev);                                               \
     }
     if (nq == 0) {
         L(0);
@@ -811,9 +820,10 @@ hipError_t launch_proj_gram_t(hipStream_t st, int64_t n, const T* Win, const Blo
 
 template <class T, class TQ, class TO, int P>
 hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                            TO* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step) {
-    return Rinv ? launch_proj_gram_t<T, TQ, TO, P, true>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step)
-                : launch_proj_gram_t<T, TQ, TO, P, false>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+                            TO* Wout, double* part, const double* Rinv, int nwg, const Ctl* ctl, int step,
+                            bool rev = false) {
+    return Rinv ? launch_proj_gram_t<T, TQ, TO, P, true>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step, rev)
+                : launch_proj_gram_t<T, TQ, TO, P, false>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step, rev);
 }
 
 
@@ -1091,7 +1101,7 @@ hipError_t launch_sweep_t(hipStream_t st, int64_t n, const T* Win, const BlockPt
 // wide prefetch costs occupancy).
 template <class T, class TW, class TQ>
 hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw, const BlockPtrs& Q, int nq,
-                    double* part, const Ctl* ctl, int nwg) {
+                    double* part, const Ctl* ctl, int nwg, bool rev) {
     if constexpr (sizeof(T) == 4 && std::is_same<TW, T>::value) {
         if (nw == 1 && P == 8)
             return mx::launch_sweep_t<T, TQ, T, 8, false, true, false, false>(st, n, (const T*)W.p[0], Q, nq, nullptr,
@@ -1100,20 +1110,20 @@ hipError_t mfma_dot(hipStream_t st, int P, int64_t n, const BlockPtrs& W, int nw
             return mx::launch_sweep_t<T, TQ, T, 16, false, true, false, false>(st, n, (const T*)W.p[0], Q, nq, nullptr,
                                                                              (T*)nullptr, part, nullptr, nwg, ctl, -1);
     }
-    if (P == 8) return mx::launch_dot<T, TW, TQ, 8>(st, n, W, nw, Q, nq, part, nwg, ctl);
-    if (P == 16) return mx::launch_dot<T, TW, TQ, 16>(st, n, W, nw, Q, nq, part, nwg, ctl);
+    if (P == 8) return mx::launch_dot<T, TW, TQ, 8>(st, n, W, nw, Q, nq, part, nwg, ctl, rev);
+    if (P == 16) return mx::launch_dot<T, TW, TQ, 16>(st, n, W, nw, Q, nq, part, nwg, ctl, rev);
     // narrow blocks (P < 8, FP64 or FP32 storage): 16 / P blocks per chunk
     if constexpr (std::is_same<TW, T>::value && std::is_same<TQ, T>::value) {
-        if (P == 1) return mx::launch_dot<T, T, T, 1>(st, n, W, nw, Q, nq, part, nwg, ctl);
-        if (P == 2) return mx::launch_dot<T, T, T, 2>(st, n, W, nw, Q, nq, part, nwg, ctl);
-        if (P == 4) return mx::launch_dot<T, T, T, 4>(st, n, W, nw, Q, nq, part, nwg, ctl);
+        if (P == 1) return mx::launch_dot<T, T, T, 1>(st, n, W, nw, Q, nq, part, nwg, ctl, rev);
+        if (P == 2) return mx::launch_dot<T, T, T, 2>(st, n, W, nw, Q, nq, part, nwg, ctl, rev);
+        if (P == 4) return mx::launch_dot<T, T, T, 4>(st, n, W, nw, Q, nq, part, nwg, ctl, rev);
     }
     return hipErrorNotSupported;
 }
 
 template <class T, class TQ>
 hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq, const double* S,
-                         double* part, const Ctl* ctl, int nwg, bool gram) {
+                         double* part, const Ctl* ctl, int nwg, bool gram, bool rev) {
     if constexpr (sizeof(T) == 4) {
 #define BGCR_SWEEP2(PP)                                                                                             \
     return gram ? mx::launch_sweep_t<T, TQ, T, PP, true, true, true, false>(st, n, Win, Q, nq, S, (T*)nullptr, part, \
@@ -1124,10 +1134,10 @@ hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const B
         if (P == 16) BGCR_SWEEP2(16)
 #undef BGCR_SWEEP2
     }
-    if (P == 8) return mx::launch_proj_dot<T, TQ, 8>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
-    if (P == 16) return mx::launch_proj_dot<T, TQ, 16>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
+    if (P == 8) return mx::launch_proj_dot<T, TQ, 8>(st, n, Win, Q, nq, S, part, nwg, ctl, gram, rev);
+    if (P == 16) return mx::launch_proj_dot<T, TQ, 16>(st, n, Win, Q, nq, S, part, nwg, ctl, gram, rev);
     if constexpr (std::is_same<TQ, T>::value) {
-        if (P == 4) return mx::launch_proj_dot<T, T, 4>(st, n, Win, Q, nq, S, part, nwg, ctl, gram);
+        if (P == 4) return mx::launch_proj_dot<T, T, 4>(st, n, Win, Q, nq, S, part, nwg, ctl, gram, rev);
     }
     return hipErrorNotSupported;
 }
@@ -1135,7 +1145,7 @@ hipError_t mfma_proj_dot(hipStream_t st, int P, int64_t n, const T* Win, const B
 template <class T, class TQ, class TO>
 hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const BlockPtrs& Q, int nq,
                           const double* S, TO* Wout, double* part, const Ctl* ctl, int nwg, const double* Rinv,
-                          int step) {
+                          int step, bool rev) {
     if constexpr (sizeof(T) == 4) {
 #define BGCR_SWEEP3(PP)                                                                                              \
     return Rinv ? mx::launch_sweep_t<T, TQ, TO, PP, true, false, false, true>(st, n, Win, Q, nq, S, Wout, part, Rinv, \
@@ -1146,10 +1156,10 @@ hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const 
         if (P == 16) BGCR_SWEEP3(16)
 #undef BGCR_SWEEP3
     }
-    if (P == 8) return mx::launch_proj_gram<T, TQ, TO, 8>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
-    if (P == 16) return mx::launch_proj_gram<T, TQ, TO, 16>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+    if (P == 8) return mx::launch_proj_gram<T, TQ, TO, 8>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step, rev);
+    if (P == 16) return mx::launch_proj_gram<T, TQ, TO, 16>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step, rev);
     if constexpr (std::is_same<TQ, T>::value && std::is_same<TO, T>::value) {
-        if (P == 4) return mx::launch_proj_gram<T, T, T, 4>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step);
+        if (P == 4) return mx::launch_proj_gram<T, T, T, 4>(st, n, Win, Q, nq, S, Wout, part, Rinv, nwg, ctl, step, rev);
     }
     return hipErrorNotSupported;
 }
