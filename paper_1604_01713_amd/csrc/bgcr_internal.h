@@ -195,6 +195,15 @@ hipError_t mfma_proj_gram(hipStream_t st, int P, int64_t n, const T* Win, const 
                           const double* S, TO* Wout, double* part, const Ctl* ctl, int nwg,
                           const double* Rinv = nullptr, int step = -1, bool rev = false);
 
+// Sweeps 1a and 1b of a block step in one pass (real FP64, P = 8 or 16, at
+// most 12 chunks of 16 columns in Q; hipErrorNotSupported otherwise):
+// W = A Vin stored, and the partial first-pass dots [Q_0 .. Q_{nq-1}]^T W in
+// part[wg][c P + w] for spmm_dot_nwg(P, n) workgroups.  Skipped while the
+// cycle is inactive.
+int spmm_dot_nwg(int P, int64_t n);
+hipError_t spmm_dot_mfma(hipStream_t st, int P, int64_t n, int64_t nnz, const int* rp, const int* ci, const double* av,
+                         const double* Vin, double* Wout, const BlockPtrs& Q, int nq, double* part, const Ctl* ctl);
+
 // Sweep 1 of a block step with separate storage types: W = (A Vin) Rinv and
 // Vout = Vin Rinv, or W = A Vin alone (Rinv and Vout NULL).  T is the type of
 // the matrix values and of the arithmetic; TI, TV, TW those of Vin, Vout, W.

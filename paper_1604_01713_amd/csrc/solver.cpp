@@ -158,6 +158,8 @@ struct Seq final : bgcr_sequence {
     // before it read last, which the chip's memory-side cache still holds
     // (third sweep 295 -> 277 us, second 231 -> 226 us at 128^3, p = 8)
     static constexpr bool alt_dir = true;
+    // sweeps 1a and 1b fused into one pass (real FP64 on matrix cores)
+    bool fuse_dots = false;
     bool mx_dot = false; // dot sweeps on matrix cores (also narrow real blocks, P < 8)
     bool mx_upd = false; // update sweeps on matrix cores (also P = 4, without the PIP step order)
     bool mixed, cplx;
@@ -302,6 +304,7 @@ struct Seq final : bgcr_sequence {
         const bool realb = !std::is_same<T, zd>::value && !half;
         mx_dot = use_mx || (realb && !off && P < 8);
         mx_upd = use_mx || (realb && !off && P == 4 && (KB + m) * P <= 256);
+        fuse_dots = use_mx && std::is_same<T, double>::value && !half;
         // BF16 basis blocks have matrix-core kernels only; every basis
         // combination has to fit one launch (at most 64 output columns)
         if (half && (!use_mx || 2 * KP > 64 ||
@@ -1085,7 +1088,22 @@ struct Seq final : bgcr_sequence {
                     apply_minv((const T*)vblk(j - 1), ctl);
                 }
             }
-            run(BGCR_K_ARN_SPMM, abytes + vblkb + blkb, [&] {
+            // sweeps 1a and 1b in one pass (FP64 on matrix cores, from step 2:
+            // V_j is stored, normalised, by the previous step's third sweep)
+            std::vector<const void*> Qd(Q);
+            Qd.push_back(vblk(j - 1));
+            const double qbytes = sB * n * (kc + (double)j * P);
+            const bool fused = fuse_dots && pip && j > 1 && ((int)Qd.size() * P + 15) / 16 <= 12;
+            if (fused) {
+                run(BGCR_K_ARN_SPMM, abytes + vblkb + blkb + qbytes, [&] {
+                    if constexpr (std::is_same<T, double>::value && !half) {
+                        return spmm_dot_mfma(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT,
+                                             pc ? (const T*)Zb : (const T*)vblk(j - 1), Wb, bp(Qd), (int)Qd.size(),
+                                             part, ctl);
+                    }
+                    return hipErrorNotSupported;
+                });
+            } else run(BGCR_K_ARN_SPMM, abytes + vblkb + blkb, [&] {
                 if constexpr (half) {
                     if (j > 1)
                         return spmm_block<T, TB, TB, T>(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT, vblk(j - 1),
@@ -1105,11 +1123,10 @@ struct Seq final : bgcr_sequence {
             });
             Q.push_back(vblk(j - 1));
             const BlockPtrs QB = bp(Q);
-            const double qbytes = sB * n * (kc + (double)j * P);
             // sweep 1b: first block-CGS dots [C V_1..V_j]^H W (reads W and Q)
             // one-column blocks take the streaming P = 1 sweeps (up to 32 blocks)
             const bool narrow = !std::is_same<T, zd>::value && !half && P == 1 && nq + 1 <= 32;
-            run(BGCR_K_ARN_DOT, qbytes, [&] {  // Q
+            if (!fused) run(BGCR_K_ARN_DOT, qbytes, [&] {  // Q
                 if constexpr (!std::is_same<T, zd>::value && !half) {
                     if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, nullptr, nullptr, part, na, ctl, true);
                 }
@@ -1119,7 +1136,8 @@ struct Seq final : bgcr_sequence {
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
             });
             const int nout = (nq + 1) * P2;
-            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, nullptr, S1, ctl); });
+            const int nd = fused ? spmm_dot_nwg(P, n) : na;
+            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nd, nout, nullptr, S1, ctl); });
             run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {  // W, Q
                 if constexpr (!std::is_same<T, zd>::value && !half) {
                     if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, S1, nullptr, part, na, ctl, true);
