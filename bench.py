@@ -296,6 +296,106 @@ def bench_ilu(args, torch, problems, bg, dev):
     print(json.dumps(res), flush=True)
 
 
+def bench_helmholtz(args, torch, problems, bg, dev):
+    """The complex Helmholtz sequence (2D shifted Laplacian, complex128, p = 16,
+    m = 8, k = 16, kappa 20 -> 27).  Unpreconditioned GMRES needs thousands of
+    restart cycles per system at 1024^2, so the full-size run takes a fixed
+    number of cycles per system (per-cycle time, Arnoldi bandwidth on the
+    byte model, per-class profile); convergence to 1e-8 is measured on a
+    reduced grid, without and with ILU(0)."""
+    N = args.grid if args.grid != 128 else 1024
+    nsys = args.nsys if args.nsys != 10 else 8
+    cyc_fixed = args.cycles
+    w = problems.cfg3(N=N, nsys=nsys)
+    systems = [(s_.A, s_.B) for s_ in w.systems]
+    n, nnz = systems[0][0].shape[0], systems[0][0].nnz
+    log(f"[bench] helmholtz: {nsys} systems n={n} nnz={nnz} p={w.p} m={w.m} k={w.k}, {cyc_fixed} cycles each")
+    dA = [bg.DeviceCSR.from_scipy(A, dev) for (A, _) in systems]
+    dB = [torch.from_numpy(B).to(dev) for (_, B) in systems]
+    out = {}
+    # full size, fixed cycles: unprofiled timing, then a profiled pass for the class split
+    for profiled in (False, True):
+        seq = bg.Sequence(n, w.p, w.m, w.k, dtype=bg.BGCR_C128, max_cycles=cyc_fixed)
+        if profiled:
+            seq.set_profiling(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, tc = [], 0
+        for i in range(nsys):
+            dX = torch.zeros_like(dB[i])
+            st = seq.solve(dA[i], dB[i], dX, w.tol)
+            if st.status not in (bg.BGCR_OK, bg.BGCR_NOT_CONVERGED, bg.BGCR_BREAKDOWN_DEFLATED):
+                raise RuntimeError(f"system {i}: {st.as_dict()}")
+            tc += st.cycles
+            res.append(st.rel_res)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        if not profiled:
+            out["full_size_fixed_cycles"] = {"cycles": tc, "ms_per_cycle": round(1e3 * el / tc, 3),
+                                             "rel_res_reached": [float(f"{r:.3e}") for r in res]}
+            log(f"[bench] helmholtz {N}^2: {1e3 * el / tc:.2f} ms/cycle over {tc} cycles")
+        else:
+            prof = seq.profile()
+            arn = ("arn_spmm", "arn_dot", "proj_dot", "proj_gram")
+            tb = sum(prof[c]["bytes"] for c in arn)
+            tm = sum(prof[c]["ms"] for c in arn)
+            out["full_size_fixed_cycles"]["arnoldi_alg_GBs"] = round(tb / (tm * 1e-3) / 1e9, 1) if tm else 0.0
+            out["full_size_fixed_cycles"]["arnoldi_frac"] = round(tb / (tm * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if tm else 0.0
+            out["full_size_fixed_cycles"]["arnoldi_GB_per_cycle"] = round(tb / tc / 1e9, 2)
+            out["full_size_fixed_cycles"]["classes_ms_per_cycle"] = {k_: round(v["ms"] / tc, 3)
+                                                                     for k_, v in prof.items() if v["launches"]}
+            out["full_size_fixed_cycles"]["classes_GBs"] = {k_: round(v["bytes"] / v["ms"] / 1e6, 0)
+                                                            for k_, v in prof.items() if v["ms"] > 0 and v["bytes"] > 0}
+        seq.release()
+    del dA, dB
+    # reduced grid, to the tolerance, without and with ILU(0)
+    Nr = args.helmholtz_reduced
+    wr = problems.cfg3(N=Nr, nsys=nsys)
+    rs = [(s_.A, s_.B) for s_ in wr.systems]
+    nr = rs[0][0].shape[0]
+    rA = [bg.DeviceCSR.from_scipy(A, dev) for (A, _) in rs]
+    rB = [torch.from_numpy(B).to(dev) for (_, B) in rs]
+    for name, pc in (("reduced_plain", bg.BGCR_PRECOND_NONE), ("reduced_ilu0", bg.BGCR_PRECOND_ILU0)):
+        seq = bg.Sequence(nr, wr.p, wr.m, wr.k, dtype=bg.BGCR_C128, max_cycles=20000, precond=pc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat, cyc, worst = [], [], 0.0
+        for i in range(nsys):
+            dX = torch.zeros_like(rB[i])
+            ts = time.perf_counter()
+            st = seq.solve(rA[i], rB[i], dX, wr.tol)
+            lat.append(time.perf_counter() - ts)
+            if st.status not in (bg.BGCR_OK, bg.BGCR_BREAKDOWN_DEFLATED):
+                raise RuntimeError(f"{name} system {i}: {st.as_dict()}")
+            cyc.append(st.cycles)
+            worst = max(worst, _host_check(rs[i][0], rs[i][1], dX.cpu().numpy()))
+            log(f"[bench] {name} {Nr}^2 system {i}: {lat[-1]:.2f}s cycles={st.cycles}")
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        seq.release()
+        lat_s = np.sort(np.array(lat))
+        out[name] = {"grid": f"{Nr}^2", "systems_per_s": round(nsys / el, 4), "cycles_per_system": cyc,
+                     "ms_per_cycle": round(1e3 * el / sum(cyc), 3),
+                     "p50_latency_s": round(float(np.percentile(lat_s, 50)), 4),
+                     "p99_latency_s": round(float(np.percentile(lat_s, 99)), 4), "max_rel_res_fp64_check": worst}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        A0, B0 = systems[0]
+        t0 = time.perf_counter()
+        _, _, so = oracle.solve(A0, B0, np.zeros_like(B0), w.tol, w.m, w.k, max_cycles=1)
+        dt = time.perf_counter() - t0
+        cpu = {"seconds_per_cycle": round(dt / max(1, so["cycles"]), 2), "kind": "oracle",
+               "sample": f"first restart cycle of the first {N}^2 system", "cores": os.cpu_count()}
+        log(f"[bench] oracle: {dt:.1f} s for one full-size cycle")
+    res = {"metric": "complex Helmholtz: ms per restart cycle at full size; systems/s to 1e-8 on a reduced grid",
+           "unit": "ms/cycle", "value": out["full_size_fixed_cycles"]["ms_per_cycle"],
+           "config": {"workload": f"helmholtz2d_{N}^2_seq{nsys}_p{w.p}_m{w.m}_k{w.k}_c128", "n": n, "nnz": nnz,
+                      "kappa": [20 + i for i in range(nsys)], "tol": w.tol, "cycles_per_system_full_size": cyc_fixed},
+           "dtype": "c128", "data": "synthetic", "n_gpus": 1, **out, "cpu_baseline": cpu}
+    print(json.dumps(res), flush=True)
+
+
 def bench_datamove(args, torch, problems, bg, dev):
     """The data-movement study of Section 6.3 on one MI355X: a banded matrix
     applied to a block of p vectors at once vs one vector at a time, then the
@@ -514,13 +614,15 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
     ap.add_argument("--datamove-small", action="store_true", help="datamove: one matrix, p in {1, 8} (profiling)")
     ap.add_argument("--cycles", type=int, default=40, help="blocksizes: restart cycles per block size")
-    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection", "datamove", "ilu",
+    ap.add_argument("--workload", choices=["cfg2", "precision", "serving", "enlarged", "selection", "datamove", "ilu", "helmholtz",
                                            "blocksizes"],
                     default="cfg2",
                     help="cfg2: the headline sequence (default); precision: plain FP64 vs the FP32-in-FP64 form on "
                          "the anisotropic 192^3 sequence; serving: a request stream, served vs serial; enlarged: one "
                          "right-hand side, block size 1 vs 8 and 16")
     ap.add_argument("--requests", type=int, default=24, help="serving: number of requests")
+    ap.add_argument("--helmholtz-reduced", type=int, default=256,
+                    help="helmholtz: side of the reduced grid solved to the tolerance")
     ap.add_argument("--serving-full", action="store_true",
                     help="serving: the full size distributions (64^3..160^3 grids, 4-16 systems, 32 GB budget)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -553,6 +655,8 @@ def main():
         return bench_blocksizes(args, torch, problems, bg, dev)
     if args.workload == "ilu":
         return bench_ilu(args, torch, problems, bg, dev)
+    if args.workload == "helmholtz":
+        return bench_helmholtz(args, torch, problems, bg, dev)
 
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20
