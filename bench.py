@@ -30,8 +30,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "systems solved/s at rel.res 1e-8; Arnoldi HBM GB/s vs peak; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
-ARNOLDI = ("arn_spmm", "arn_dot", "proj_dot", "proj_gram")
-KERNEL_SYMBOL = {"arn_spmm": "k_spmm_rinv", "arn_dot": "k_proj_dot_mfma (dot only)",
+ARNOLDI = ("arn_spmm", "arn_spmm_dot", "arn_dot", "proj_dot", "proj_gram")
+KERNEL_SYMBOL = {"arn_spmm": "k_spmm_rinv", "arn_spmm_dot": "k_spmm_dot_mfma", "arn_dot": "k_dot_mfma",
                  "proj_dot": "k_proj_dot_mfma", "proj_gram": "k_proj_gram_mfma"}
 
 
@@ -336,7 +336,7 @@ def bench_helmholtz(args, torch, problems, bg, dev):
             log(f"[bench] helmholtz {N}^2: {1e3 * el / tc:.2f} ms/cycle over {tc} cycles")
         else:
             prof = seq.profile()
-            arn = ("arn_spmm", "arn_dot", "proj_dot", "proj_gram")
+            arn = ARNOLDI
             tb = sum(prof[c]["bytes"] for c in arn)
             tm = sum(prof[c]["ms"] for c in arn)
             out["full_size_fixed_cycles"]["arnoldi_alg_GBs"] = round(tb / (tm * 1e-3) / 1e9, 1) if tm else 0.0

@@ -270,7 +270,9 @@ typedef enum {
     BGCR_K_HOST_EIG = 10,    /* host: harmonic-Ritz eigenproblem (wall clock) */
     BGCR_K_PRECOND = 11,     /* triangular solves of M^{-1} (ILU(0) preconditioning) */
     BGCR_K_ILU = 12,         /* ILU(0): pattern check and analysis, numeric factorization */
-    BGCR_K_NCLASS = 13
+    BGCR_K_ARN_SPMM_DOT = 13,/* Arnoldi sweeps 1a and 1b in one pass: W = A V_j and the first
+                                block-CGS dots (FP64 on matrix cores, from the second step) */
+    BGCR_K_NCLASS = 14
 } bgcr_kernel_class;
 
 /* Turn per-kernel timing on (1) or off (0) and reset the counters.  When on,

@@ -52,7 +52,7 @@ BGCR_NOALLOC_SCRATCH_BYTES = 20 << 20
 
 # kernel classes of the per-kernel profile (bgcr_kernel_class)
 KERNEL_CLASSES = ["arn_spmm", "arn_dot", "proj_dot", "proj_gram", "small", "combine", "residual", "tsdot", "spmm",
-                  "host", "host_eig", "precond", "ilu"]
+                  "host", "host_eig", "precond", "ilu", "arn_spmm_dot"]
 
 
 class bgcr_params(ctypes.Structure):

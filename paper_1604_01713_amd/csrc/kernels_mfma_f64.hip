@@ -36,8 +36,11 @@ int mfma_nwg(int64_t n) {
 // the SpMM gathers V; the W tile is staged in LDS (rows past n as zeros) and
 // read back as the A operand (W[row][w], w = l % 16; lanes w >= P repeat
 // column w % P and feed partial rows that are never written).  Each wave
-// takes ROWS / 4 rows of the tile, KS = ROWS / 16 slices of 4.  Tiles follow
-// the SpMM's XCD-local order (the stencil neighbours stay in the XCD's L2).
+// takes ROWS / 4 rows of the tile, KS = ROWS / 16 slices of 4: exactly the
+// rows its own lanes computed in the SpMM layout (P / 2 lanes per row), so
+// the staging is wave-private and the loop has no workgroup barrier.  Tiles
+// follow the SpMM's XCD-local order (the stencil neighbours stay in the
+// XCD's L2).
 // ---------------------------------------------------------------------------
 template <int P, int NC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 8 ? 2 : 1))) void k_spmm_dot_mfma(int64_t n, int64_t nnz, const int* __restrict__ rp,
@@ -48,6 +51,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 8 ? 2
     using M = mx::MX<double>;
     constexpr int C = 2, LPR = P / C, ROWS = 256 / LPR, WR = ROWS / 4, KS = WR / 4;
     static_assert(KS >= 1 && WR % 4 == 0, "whole 4-row slices per wave");
+    static_assert(WR * LPR == 64, "a wave's SpMM rows are the rows of its dot slices");
     if (ctl && ctl->active == 0) return;
     __shared__ double Wt[ROWS * P];
     __shared__ double red[1024];
@@ -74,14 +78,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 8 ? 2
         if (row < n) sp::store_as<double, double, C, P>(Wout + row * P + c0, raw[0]);
 #pragma unroll
         for (int j = 0; j < C; ++j) Wt[r * P + c0 + j] = row < n ? raw[0][j] : 0.0;
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const double a = Wt[(wave * WR + 4 * ks + (lane >> 4)) * P + wcol];
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch) acc[0][ch] = M::mma(a, qv[ks][ch], acc[0][ch]);
         }
-        __syncthreads();
+        // the next tile's staging overwrites this wave's rows only after every
+        // lane has read them
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     mx::write_dot_partials<double, P, 1, NC>(acc, q, 1, red, part, blockIdx.x);
 }

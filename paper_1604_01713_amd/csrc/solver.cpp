@@ -1095,7 +1095,7 @@ struct Seq final : bgcr_sequence {
             const double qbytes = sB * n * (kc + (double)j * P);
             const bool fused = fuse_dots && pip && j > 1 && ((int)Qd.size() * P + 15) / 16 <= 12;
             if (fused) {
-                run(BGCR_K_ARN_SPMM, abytes + vblkb + blkb + qbytes, [&] {
+                run(BGCR_K_ARN_SPMM_DOT, abytes + vblkb + blkb + qbytes, [&] {
                     if constexpr (std::is_same<T, double>::value && !half) {
                         return spmm_dot_mfma(st, P, n, Am->nnz, Am->row_ptr, Am->col_idx, avT,
                                              pc ? (const T*)Zb : (const T*)vblk(j - 1), Wb, bp(Qd), (int)Qd.size(),
@@ -1131,7 +1131,7 @@ struct Seq final : bgcr_sequence {
                     if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, nullptr, nullptr, part, na, ctl, true);
                 }
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (mx_dot) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na, alt_dir);
+                    if (mx_dot) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na, alt_dir && pip);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
             });
@@ -1263,6 +1263,34 @@ struct Seq final : bgcr_sequence {
     // X += W_m Y - U F Y ; (plain) R -= W_{m+1} H Y  (Algorithm 1)
     void update_solution(const CycleOut& co, bool withC, bool update_R) {
         const int me = co.meff, mp = me * P;
+        if constexpr (std::is_same<T, A>::value) {
+            if (update_R && !pc) {
+                // both in one pass over the basis: [X, R] += [V_1..V_me, U, V_{me+1}] K
+                std::vector<const void*> in2;
+                for (int i = 0; i < me; ++i) in2.push_back(vblk(i));
+                const int nu = withC ? KB : 0;
+                for (int b = 0; b < nu; ++b) in2.push_back(ublk(cur, b));
+                in2.push_back(co.last);
+                const int rows = mp + nu * P + P;
+                Mat K2(rows, 2 * P);
+                Mat HY = dense::matmul(co.H, co.Y);
+                Mat last = dense::matmul(co.RinvLast, HY.block(mp, 0, P, P));
+                for (int i = 0; i < mp; ++i)
+                    for (int b = 0; b < P; ++b) {
+                        K2(i, b) = co.Y(i, b);
+                        K2(i, P + b) = -HY(i, b);
+                    }
+                if (withC) {
+                    Mat FY = dense::matmul(co.F, co.Y);
+                    for (int i = 0; i < keff; ++i)
+                        for (int b = 0; b < P; ++b) K2(mp + i, b) = -FY(i, b);
+                }
+                for (int i = 0; i < P; ++i)
+                    for (int b = 0; b < P; ++b) K2(mp + nu * P + i, P + b) = -last(i, b);
+                combine<A>(in2, {(void*)X, (void*)R}, K2, 2);
+                return;
+            }
+        }
         std::vector<const void*> in;
         for (int i = 0; i < me; ++i) in.push_back(vblk(i));
         Mat KX(mp + (withC ? KP : 0), P);
