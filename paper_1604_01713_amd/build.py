@@ -26,7 +26,8 @@ HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-fcx-limit
 # complex products without the NaN-recovery path (operands are finite and checked)
 CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-march=x86-64-v3", "-fcx-limited-range", "-fopenmp", "-I", INCLUDE, "-I", CSRC]
 
-HIP_SOURCES = ["kernels.hip", "kernels_mfma_f64.hip", "kernels_mfma_f32.hip", "kernels_mfma_bf16.hip", "ilu.hip",
+HIP_SOURCES = ["kernels.hip", "kernels_mfma_f64.hip", "kernels_mfma_f32.hip", "kernels_mfma_bf16.hip",
+               "kernels_mfma_c128.hip", "ilu.hip",
                "solver.cpp"]
 CXX_SOURCES = ["dense.cpp"]
 

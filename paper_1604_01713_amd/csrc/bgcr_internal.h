@@ -232,6 +232,29 @@ template <class TI, class TO>
 hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ldi, TO* out,
                       int64_t ldo, int zero_pad_to);
 
+// The three block-CGS sweeps of complex128 blocks of P = 8 or 16 columns on
+// the FP64 matrix cores, the blocks seen as real blocks of 2P interleaved
+// (re, im) columns; nwg workgroups (mfma_nwg); at most cx_mfma_max_blocks(P)
+// blocks in Q, hipErrorNotSupported otherwise.  Partials are the real
+// products part[wg][r 2P + s] of the 2q x 2P real view (q = nq P), which
+// cx_reduce contracts into the complex q x P result.
+int cx_mfma_max_blocks(int P);
+// partial Q^T W
+hipError_t cx_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, double* part,
+                  const Ctl* ctl, int nwg, bool rev);
+// W' = W - Q S (S complex q x P) and partial Q^T W'; Sr (4 q P doubles) holds
+// the real form of S, Wtmp (n x P) receives W' for P = 16
+hipError_t cx_proj_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
+                       double* Sr, zd* Wtmp, double* part, const Ctl* ctl, int nwg);
+// W'' = W - Q S stored in Wout with its partial real Gram (part[wg][r 2P + s],
+// 2P x 2P); runs while the cycle is active and for block step `step` if it
+// just stopped there
+hipError_t cx_proj_gram(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
+                        double* Sr, zd* Wout, double* part, const Ctl* ctl, int nwg, int step);
+// out (q x P) = add (or 0) + contraction of the summed real partials
+hipError_t cx_reduce(hipStream_t st, const double* part, int nwg, int q, int P, const zd* add, zd* out,
+                     const Ctl* ctl);
+
 // ---------------------------------------------------------------------------
 // ILU(0) right preconditioning (ilu.hip).  The factors live in `lu`, an array
 // with the CSR pattern (rp, ci) of A: strictly lower part of L (unit diagonal

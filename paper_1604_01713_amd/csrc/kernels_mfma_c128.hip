@@ -1,0 +1,72 @@
+// complex128 block-CGS sweeps on the FP64 matrix cores (real views of the
+// interleaved blocks; the mapping is described in cplx_sweeps.h)
+#include "cplx_sweeps.h"
+
+namespace bgcr {
+
+// the 16-column real sweeps are instantiated with the other FP64 kernels
+extern template hipError_t mfma_dot<double>(hipStream_t, int, int64_t, const BlockPtrs&, int, const BlockPtrs&, int,
+                                            double*, const Ctl*, int, bool);
+extern template hipError_t mfma_proj_dot<double>(hipStream_t, int, int64_t, const double*, const BlockPtrs&, int,
+                                                 const double*, double*, const Ctl*, int, bool, bool);
+extern template hipError_t mfma_proj_gram<double>(hipStream_t, int, int64_t, const double*, const BlockPtrs&, int,
+                                                  const double*, double*, double*, const Ctl*, int, const double*,
+                                                  int, bool);
+
+int cx_mfma_max_blocks(int P) {
+    // P = 8: the 16-column real sweeps (their second pass holds at most 14
+    // chunks of Q in LDS); P = 16: the 32-column sweeps, dispatched up to 12
+    return P == 8 ? 14 : (P == 16 ? 12 : 0);
+}
+
+static hipError_t expand(hipStream_t st, const zd* S, int q, int P, double* Sr, const Ctl* ctl) {
+    hipLaunchKernelGGL(mx::k_cx_expand, dim3((q * P + 255) / 256), dim3(256), 0, st, S, q, P, Sr, ctl);
+    return hipGetLastError();
+}
+
+hipError_t cx_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, double* part,
+                  const Ctl* ctl, int nwg, bool rev) {
+    if (nq < 1 || nq > cx_mfma_max_blocks(P)) return hipErrorNotSupported;
+    if (P == 8) {
+        BlockPtrs Wp{};
+        Wp.p[0] = W;
+        return mfma_dot<double>(st, 16, n, Wp, 1, Q, nq, part, ctl, nwg, rev);
+    }
+    return mx::launch_dot_wide(st, n, (const double*)W, Q, nq, part, nwg, ctl, rev);
+}
+
+hipError_t cx_proj_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
+                       double* Sr, zd* Wtmp, double* part, const Ctl* ctl, int nwg) {
+    if (nq < 1 || nq > cx_mfma_max_blocks(P)) return hipErrorNotSupported;
+    if (P == 8) {
+        const hipError_t e = expand(st, S, nq * P, P, Sr, ctl);
+        if (e != hipSuccess) return e;
+        return mfma_proj_dot<double>(st, 16, n, (const double*)W, Q, nq, Sr, part, ctl, nwg, false, false);
+    }
+    const hipError_t e = mx::launch_update_wide_t<false>(st, n, (const double*)W, Q, nq, S, (double*)Wtmp, nullptr,
+                                                         nwg, ctl, -1, false);
+    if (e != hipSuccess) return e;
+    return mx::launch_dot_wide(st, n, (const double*)Wtmp, Q, nq, part, nwg, ctl, true);
+}
+
+hipError_t cx_proj_gram(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
+                        double* Sr, zd* Wout, double* part, const Ctl* ctl, int nwg, int step) {
+    if (nq < 1 || nq > cx_mfma_max_blocks(P)) return hipErrorNotSupported;
+    if (P == 8) {
+        const hipError_t e = expand(st, S, nq * P, P, Sr, ctl);
+        if (e != hipSuccess) return e;
+        return mfma_proj_gram<double>(st, 16, n, (const double*)W, Q, nq, Sr, (double*)Wout, part, ctl, nwg, nullptr,
+                                      step, false);
+    }
+    return mx::launch_update_wide_t<true>(st, n, (const double*)W, Q, nq, S, (double*)Wout, part, nwg, ctl, step,
+                                          false);
+}
+
+hipError_t cx_reduce(hipStream_t st, const double* part, int nwg, int q, int P, const zd* add, zd* out,
+                     const Ctl* ctl) {
+    if (q * P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mx::k_cx_reduce, dim3((q * P + 15) / 16), dim3(256), 0, st, part, nwg, q, P, add, out, ctl);
+    return hipGetLastError();
+}
+
+}  // namespace bgcr

@@ -97,10 +97,13 @@ struct Sizes {
 
 // outputs per workgroup of the largest reduction: an Arnoldi sweep (q x P)
 // or a recycle dot launch (up to 32 W columns, at most KB blocks, against q)
-size_t part_outputs(int P, int KB, int qmax) {
+size_t part_outputs(int P, int KB, int qmax, bool cplx, int m) {
     const size_t wg = (size_t)std::max(1, std::min(KB, std::max(1, 32 / P)));
     // the second pass of a block step writes its dots and the new block's Gram
-    return std::max({(size_t)qmax * P + (size_t)P * P, (size_t)KB * P * P, wg * qmax * P});
+    const size_t o = std::max({(size_t)qmax * P + (size_t)P * P, (size_t)KB * P * P, wg * qmax * P});
+    // complex sweeps on matrix cores write the real 2q x 2P products (twice
+    // the complex entries) for q up to (KB + m) P
+    return cplx ? std::max(o, 2 * (size_t)(KB + m) * P * P) : o;
 }
 
 Sizes sizes_of(const bgcr_params* prm, int64_t n) {
@@ -118,13 +121,14 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     z.basis = (size_t)(z.m + 1) * z.blk;  // V_1 .. V_{m+1}
     z.recyc = 4 * (size_t)z.KB * z.blk;
     const int qmax = (2 * z.KB + z.m + 1) * z.P;
-    z.nout = part_outputs(z.P, z.KB, qmax);
+    z.nout = part_outputs(z.P, z.KB, qmax, cplx, z.m);
     z.part = (size_t)NWG_MAX * z.nout * z.sa;
     const size_t mp = (size_t)z.m * z.P, m1p = (size_t)(z.m + 1) * z.P;
     z.small_ = z.sa * (2 * (size_t)qmax * z.P + (size_t)z.P * z.P + 2 * m1p * mp + (size_t)z.KP * mp + (size_t)z.m * 4 * z.P * z.P +
                        m1p * z.P + (size_t)(z.m + 1) * z.P * z.P + 2 * (size_t)z.P * z.P +
                        (size_t)(2 * z.KB + z.m + 1) * z.P * (2 * std::max(z.KP, z.P) + 2 * z.P)) +
-               sizeof(double) * ((size_t)z.m + (size_t)NWG_MAX * 2 * z.P) + sizeof(Ctl);
+               sizeof(double) * ((size_t)z.m + (size_t)NWG_MAX * 2 * z.P) + sizeof(Ctl) +
+               (cplx ? sizeof(double) * 4 * (size_t)(z.KB + z.m) * z.P * z.P : 0);
     const bool enlarged = z.P > prm->p;
     z.total_fixed = z.basis + 3 * (size_t)n * z.P * z.sw /* W2, Wb, R */ +
                     (size_t)n * z.P * z.sa * (enlarged ? 2 : 1) /* X (and B padded) */ + z.recyc + z.part + z.small_;
@@ -162,6 +166,8 @@ struct Seq final : bgcr_sequence {
     bool fuse_dots = false;
     bool mx_dot = false; // dot sweeps on matrix cores (also narrow real blocks, P < 8)
     bool mx_upd = false; // update sweeps on matrix cores (also P = 4, without the PIP step order)
+    bool cx_mx = false;  // complex block-CGS sweeps on the FP64 matrix cores (P = 8 or 16)
+    double* Sr = nullptr;  // real form of a complex coefficient matrix (cx_mx, P = 8)
     bool mixed, cplx;
     hipStream_t st;
     Sizes sz;
@@ -305,6 +311,7 @@ struct Seq final : bgcr_sequence {
         mx_dot = use_mx || (realb && !off && P < 8);
         mx_upd = use_mx || (realb && !off && P == 4 && (KB + m) * P <= 256);
         fuse_dots = use_mx && std::is_same<T, double>::value && !half;
+        cx_mx = !off && std::is_same<T, zd>::value && (P == 8 || P == 16) && KB + m <= cx_mfma_max_blocks(P);
         // BF16 basis blocks have matrix-core kernels only; every basis
         // combination has to fit one launch (at most 64 output columns)
         if (half && (!use_mx || 2 * KP > 64 ||
@@ -354,6 +361,7 @@ struct Seq final : bgcr_sequence {
         S1 = dalloc<A>((size_t)qmax * P);
         dots_cap = (size_t)qmax * P * std::max(KB, 1);
         Sf = dalloc<A>((size_t)qmax * P + (size_t)P * P);  // [S1 + S2 | W'^H W']
+        if (cx_mx) Sr = dalloc<double>(4 * (size_t)(KB + m) * P * P);
         const size_t mp = (size_t)m * P, m1p = (size_t)(m + 1) * P;
         // everything the host reads at the end of a cycle, contiguous so that
         // one copy brings it over: control block, H and its triangular factor,
@@ -1067,7 +1075,7 @@ struct Seq final : bgcr_sequence {
             for (int i = 0; i < j - 1; ++i) Q.push_back(vblk(i));
             const int nq = (int)Q.size();
             const BlockPtrs Q1 = bp(Q);
-            const int na = mx_upd ? nwg_mx : nwg;
+            const int na = (mx_upd || cx_mx) ? nwg_mx : nwg;
             // sweep 1a: W = A V_j with V_j = W2 R^{-1} (reads A, gathers W2, writes W and V_j)
             // algorithmic bytes per launch follow the byte model of a block step,
             // (s_A + 4) nnz + 4 (n + 1) + 5 s n p + 3 s n q_j: A read and V_j
@@ -1132,18 +1140,28 @@ struct Seq final : bgcr_sequence {
                 }
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (mx_dot) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na, alt_dir && pip);
+                } else {
+                    if (cx_mx) return cx_dot(st, P, n, Wb, QB, nq + 1, (double*)part, ctl, na, false);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
             });
             const int nout = (nq + 1) * P2;
             const int nd = fused ? spmm_dot_nwg(P, n) : na;
-            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nd, nout, nullptr, S1, ctl); });
+            run(BGCR_K_SMALL, 0.0, [&] {
+                if constexpr (std::is_same<A, zd>::value) {
+                    if (cx_mx) return cx_reduce(st, (const double*)part, nd, (nq + 1) * P, P, nullptr, S1, ctl);
+                }
+                return reduce_partials<A>(st, part, nd, nout, nullptr, S1, ctl);
+            });
             run(BGCR_K_PROJ_DOT, blkb + qbytes, [&] {  // W, Q
                 if constexpr (!std::is_same<T, zd>::value && !half) {
                     if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, S1, nullptr, part, na, ctl, true);
                 }
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (mx_upd) return mfma_proj_dot<T, TB>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip);
+                } else {
+                    // (P = 16 stores W' in W2, which the SpMM has consumed)
+                    if (cx_mx) return cx_proj_dot(st, P, n, Wb, QB, nq + 1, S1, Sr, W2, (double*)part, ctl, na);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, na, ctl, 1);
             });
@@ -1162,18 +1180,30 @@ struct Seq final : bgcr_sequence {
                 });
                 continue;
             }
-            run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, na, nout, S1, Sf, ctl); });
+            run(BGCR_K_SMALL, 0.0, [&] {
+                if constexpr (std::is_same<A, zd>::value) {
+                    if (cx_mx) return cx_reduce(st, (const double*)part, na, (nq + 1) * P, P, S1, Sf, ctl);
+                }
+                return reduce_partials<A>(st, part, na, nout, S1, Sf, ctl);
+            });
             run(BGCR_K_PROJ_GRAM, 2.0 * blkb + qbytes, [&] {  // W, V_{j+1}, Q
                 if constexpr (!std::is_same<T, zd>::value && !half) {
                     if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, Sf, W2, part, na, ctl, false);
                 }
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (mx_upd) return mfma_proj_gram<T>(st, P, n, Wb, QB, nq + 1, Sf, W2, part, ctl, na);
+                } else {
+                    if (cx_mx) return cx_proj_gram(st, P, n, Wb, QB, nq + 1, Sf, Sr, W2, (double*)part, ctl, na, j);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, Sf, nullptr, W2, 0, 1, part, na, ctl, 2);
             });
             run(BGCR_K_SMALL, 0.0, [&] {
-                HIPCHK(reduce_partials<A>(st, part, na, P2, nullptr, S1, ctl));
+                if constexpr (std::is_same<A, zd>::value) {
+                    if (cx_mx) HIPCHK(cx_reduce(st, (const double*)part, na, P, P, nullptr, S1, ctl));
+                    else HIPCHK(reduce_partials<A>(st, part, na, P2, nullptr, S1, ctl));
+                } else {
+                    HIPCHK(reduce_partials<A>(st, part, na, P2, nullptr, S1, ctl));
+                }
                 return step_small<A>(st, P, S1, Sf, nullptr, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl, thresh);
             });
         }

@@ -228,6 +228,24 @@ def test_complex_helmholtz_parity():
     _compare("cfg3-41^2", systems, w.p, w.m, w.k, w.tol)
 
 
+@pytest.mark.parametrize("p,m,k", [(16, 8, 16), (8, 10, 16), (4, 10, 8)])
+def test_complex_sequence_parity(p, m, k):
+    """A complex128 nonsymmetric sequence (2D convection-diffusion with a
+    complex diagonal shift that changes along the sequence, n = 1369: 21 full
+    64-row tiles and a ragged 25-row tail).  p = 16 and 8 run the block-CGS
+    sweeps on the FP64 matrix cores through the real views of the complex
+    blocks (32 and 16 real columns); p = 4 runs the vector sweeps."""
+    A0 = problems.convdiff(37, 2, conv=(10.0, -4.0, 0.0))
+    n = A0.shape[0]
+    rng = np.random.default_rng(21 + p)
+    systems = []
+    for i in range(3):
+        Ai = (A0.astype(np.complex128) + sp.diags((0.5 + 0.1 * i) * rng.uniform(0, 1, n) * (1 - 0.8j))).tocsr()
+        B = rng.uniform(-1, 1, (n, p)) + 1j * rng.uniform(-1, 1, (n, p))
+        systems.append((Ai, B, np.zeros_like(B)))
+    _compare(f"cplx-p{p}m{m}k{k}", systems, p, m, k, 1e-8)
+
+
 @pytest.mark.parametrize("p", [16, 8, 4, 1])
 def test_mixed_precision_matches_fp64_oracle(p):
     w = problems.cfg4(N=14, nsys=2, p=p, m=10, k=24)   # n = 2744, target 1e-10
