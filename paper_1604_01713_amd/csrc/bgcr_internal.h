@@ -242,8 +242,9 @@ int cx_mfma_max_blocks(int P);
 // partial Q^T W
 hipError_t cx_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, double* part,
                   const Ctl* ctl, int nwg, bool rev);
-// W' = W - Q S (S complex q x P) and partial Q^T W'; Sr (4 q P doubles) holds
-// the real form of S, Wtmp (n x P) receives W' for P = 16
+// W' = W - Q S (S complex q x P) and partial Q^T W'; Sr (4 q P doubles)
+// holds the real form of S (P = 8); Wtmp (n x P) receives W' for P = 16 with
+// more than 10 blocks in Q
 hipError_t cx_proj_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
                        double* Sr, zd* Wtmp, double* part, const Ctl* ctl, int nwg);
 // W'' = W - Q S stored in Wout with its partial real Gram (part[wg][r 2P + s],
@@ -251,6 +252,11 @@ hipError_t cx_proj_dot(hipStream_t st, int P, int64_t n, const zd* W, const Bloc
 // just stopped there
 hipError_t cx_proj_gram(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
                         double* Sr, zd* Wout, double* part, const Ctl* ctl, int nwg, int step);
+// Y (+)= [in..] C for complex blocks (P = 8 or 16) on the FP64 matrix cores,
+// C complex row-major (nin P) x (nout P), at most 64 real output columns; the
+// first `accumulate` output blocks are accumulated
+hipError_t cx_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
+                      const zd* coef, int accumulate, int nwg);
 // out (q x P) = add (or 0) + contraction of the summed real partials
 hipError_t cx_reduce(hipStream_t st, const double* part, int nwg, int q, int P, const zd* add, zd* out,
                      const Ctl* ctl);

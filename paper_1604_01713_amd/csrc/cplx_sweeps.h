@@ -252,6 +252,161 @@ __global__ __launch_bounds__(256) void k_dot_wide(int64_t n, const double* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// Second pass of a block step for 32-column FP64 blocks (complex P = 16) in
+// one sweep: W' = W - Q S (S complex, not stored) and the partial D = Q^T W'
+// in part[wg][c 32 + w] (c < 32 nq).  The four waves of a workgroup share a
+// 16-row tile and split the 2 nq chunks of 16 Q columns round-robin (wave w
+// takes chunks w, w + 4, ...), so each Q element is loaded once:
+//   * each wave forms the part of the update from its own chunks (column-major
+//     Q operands straight from memory; wave 0 also adds W), and the four
+//     partial W'^T tiles meet in LDS (one workgroup barrier per tile, slots
+//     double-buffered);
+//   * the wave's Q operands are turned into the row-major layout of the dot
+//     product through a small wave-private LDS tile, and the wave takes the
+//     dots of its chunks with the summed W' (A = W'[row][w], B = Q[row][c]).
+// The next tile's operands are loaded while the current one waits at the
+// barrier and takes its dots.
+// ---------------------------------------------------------------------------
+template <int NQ>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_proj_dot_wide(
+    int64_t n, const double* __restrict__ Win, BlockPtrs Q, int nq, const zd* __restrict__ S,
+    double* __restrict__ part, const Ctl* ctl, int rev) {
+    using M = MX<double>;
+    constexpr int P = 32, NC = 2 * NQ, NCW = (NC + 3) / 4, TS = 17;
+    if (ctl && ctl->active == 0) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double* Sc = (double*)smem;         // [NQ*16][16] complex S as (re, im)
+    double* slot = Sc + NQ * 512;       // [2][4 waves][16 rows][32]: partial W' tiles
+    double* tt = slot + 2 * 4 * 512;    // [4 waves][16][TS]: transpose tiles
+    double* red = (double*)smem;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int bl = lane & 15, rq = lane >> 4;
+    const int q = nq * P, nc = 2 * nq;
+    const double* Sd = (const double*)S;
+    for (int e = t; e < NQ * 512; e += 256) Sc[e] = (e < nq * 512) ? Sd[e] : 0.0;
+    // lane's entry of -S_r (as in k_update_wide)
+    const int ol = (rq ^ bl) & 1;
+    const double sg = ((rq & 1) && !(bl & 1)) ? 1.0 : -1.0;
+    const int sbase = 2 * ((rq >> 1) * 16 + (bl >> 1)) + ol;
+    // the wave's chunks ch = wave + 4 i: column 16 (ch % 2) + l % 16 of block ch / 2
+    const double* qp[NCW];
+    int chw[NCW];
+#pragma unroll
+    for (int i = 0; i < NCW; ++i) {
+        const int ch = wave + 4 * i;
+        chw[i] = ch;
+        const int chv = ch < nc ? ch : 0;
+        qp[i] = (const double*)Q.p[chv >> 1] + 16 * (chv & 1);
+    }
+    d4v acc[2][NCW];
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int i = 0; i < NCW; ++i) acc[g][i] = d4v{0, 0, 0, 0};
+    const int lw = logical_wg();
+    int64_t t0, t1;
+    tile_span((n + 15) / 16, lw, t0, t1);
+    const int64_t cnt = t1 - t0, dstep = rev ? -16 : 16;
+    double* mytt = tt + wave * 16 * TS;
+    // column-major operands of the update: [i][kk] = Q[rbase + l % 16][16 ch_i + 4 kk + l / 16]
+    auto load_q = [&](double (&qv)[NCW][4], int64_t rbase) {
+        const int64_t off = clamp_row(rbase + bl, n) * P + rq;
+#pragma unroll
+        for (int i = 0; i < NCW; ++i)
+            if (chw[i] < nc) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) qv[i][kk] = qp[i][off + 4 * kk];
+            }
+    };
+    // W^T tiles in the D layout (wave 0): tile g element v = W[row l % 16][16 g + drow(l, v)]
+    auto load_w = [&](d4v (&w)[2], int64_t rbase) {
+        const int64_t off = clamp_row(rbase + bl, n) * P;
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) w[g][v] = Win[off + 16 * g + M::drow(lane, v)];
+    };
+    double qc[NCW][4];
+    d4v wn[2] = {d4v{0, 0, 0, 0}, d4v{0, 0, 0, 0}};
+    if (cnt > 0) {
+        const int64_t r0 = (rev ? t1 - 1 : t0) * 16;
+        load_q(qc, r0);
+        if (wave == 0) load_w(wn, r0);
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int64_t k = 0; k < cnt; ++k) {
+        const int64_t rbase = (rev ? t1 - 1 - k : t0 + k) * 16;
+        // S is read from LDS in every tile (not kept in registers)
+        asm volatile("" ::: "memory");
+        d4v d[2] = {wn[0], wn[1]};
+#pragma unroll
+        for (int i = 0; i < NCW; ++i)
+            if (chw[i] < nc) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const double* sp = Sc + sbase + 2 * (8 * chw[i] + 2 * kk) * 16;
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) d[g] = M::mma(sg * sp[16 * g], qc[i][kk], d[g]);
+                }
+            }
+        // row-major dot operands of the wave's chunks: [i][ks] = Q[rbase + 4 ks + l / 16][16 ch_i + l % 16]
+        double qr[NCW][4];
+#pragma unroll
+        for (int i = 0; i < NCW; ++i)
+            if (chw[i] < nc) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) mytt[bl * TS + 4 * kk + rq] = qc[i][kk];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) qr[i][ks] = mytt[(4 * ks + rq) * TS + bl];
+            }
+        if (k + 1 < cnt) {
+            load_q(qc, rbase + dstep);
+            if (wave == 0) load_w(wn, rbase + dstep);
+        }
+        double* sl = slot + (k & 1) * 4 * 512;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            zero_tail<double>(d[g], rbase, n, lane);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sl[wave * 512 + bl * P + 16 * g + M::drow(lane, v)] = d[g][v];
+        }
+        __syncthreads();
+        // W'[rbase + 4 ks + l / 16][16 g + l % 16], the four partials added in order
+        double wa[4][2];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                const int e = (4 * ks + rq) * P + 16 * g + bl;
+                wa[ks][g] = ((sl[e] + sl[512 + e]) + sl[1024 + e]) + sl[1536 + e];
+            }
+#pragma unroll
+        for (int i = 0; i < NCW; ++i)
+            if (chw[i] < nc) {
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                    for (int g = 0; g < 2; ++g) acc[g][i] = M::mma(wa[ks][g], qr[i][ks], acc[g][i]);
+            }
+    }
+    // accumulator [g][i] element v: W column 16 g + drow(l, v), Q column 16 ch_i + l % 16
+    (void)red;
+    const int64_t nout = (int64_t)q * P;
+#pragma unroll
+    for (int i = 0; i < NCW; ++i) {
+        const int c = 16 * chw[i] + bl;
+        if (chw[i] < nc) {
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) part[(int64_t)lw * nout + (int64_t)c * P + 16 * g + M::drow(lane, v)] = acc[g][i][v];
+        }
+    }
+}
+
 // S_r (2q x 2P, FP64, row-major) = real form of the complex q x P matrix S
 __global__ void k_cx_expand(const zd* __restrict__ S, int q, int P, double* __restrict__ Sr, const Ctl* ctl) {
     if (ctl && ctl->active == 0) return;
@@ -308,6 +463,26 @@ hipError_t launch_update_wide_t(hipStream_t st, int64_t n, const double* Win, co
     }
     switch (nq) {
         L(1) L(2) L(3) L(4) L(5) L(6) L(7) L(8) L(9) L(10) L(11) L(12)
+        default: return hipErrorNotSupported;
+    }
+#undef L
+    return hipGetLastError();
+}
+
+inline hipError_t launch_proj_dot_wide(hipStream_t st, int64_t n, const double* Win, const BlockPtrs& Q, int nq,
+                                       const zd* S, double* part, int nwg, const Ctl* ctl, bool rev) {
+#define L(NQ)                                                                                                      \
+    case NQ: {                                                                                                     \
+        const size_t lds = (size_t)(NQ * 512 + 2 * 4 * 512 + 4 * 16 * 17) * sizeof(double);                       \
+        static std::once_flag fl;                                                                                  \
+        std::call_once(fl, [] { allow_lds(k_proj_dot_wide<NQ>); });                                                \
+        hipLaunchKernelGGL((k_proj_dot_wide<NQ>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, part, ctl,      \
+                           (int)rev);                                                                              \
+        break;                                                                                                     \
+    }
+    // (up to 10 blocks: beyond, the operands of the wave's chunks spill)
+    switch (nq) {
+        L(1) L(2) L(3) L(4) L(5) L(6) L(7) L(8) L(9) L(10)
         default: return hipErrorNotSupported;
     }
 #undef L

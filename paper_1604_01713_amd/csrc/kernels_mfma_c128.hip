@@ -43,6 +43,10 @@ hipError_t cx_proj_dot(hipStream_t st, int P, int64_t n, const zd* W, const Bloc
         if (e != hipSuccess) return e;
         return mfma_proj_dot<double>(st, 16, n, (const double*)W, Q, nq, Sr, part, ctl, nwg, false, false);
     }
+    // one fused sweep up to 10 blocks in Q; beyond, W' is stored and dotted
+    // in a second sweep
+    const hipError_t f = mx::launch_proj_dot_wide(st, n, (const double*)W, Q, nq, S, part, nwg, ctl, true);
+    if (f != hipErrorNotSupported) return f;
     const hipError_t e = mx::launch_update_wide_t<false>(st, n, (const double*)W, Q, nq, S, (double*)Wtmp, nullptr,
                                                          nwg, ctl, -1, false);
     if (e != hipSuccess) return e;
@@ -60,6 +64,13 @@ hipError_t cx_proj_gram(hipStream_t st, int P, int64_t n, const zd* W, const Blo
     }
     return mx::launch_update_wide_t<true>(st, n, (const double*)W, Q, nq, S, (double*)Wout, part, nwg, ctl, step,
                                           false);
+}
+
+hipError_t cx_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
+                      const zd* coef, int accumulate, int nwg) {
+    if (P == 8) return mx::launch_combine_cx<16>(st, n, in, nin, out, nout, (const double*)coef, accumulate, nwg);
+    if (P == 16) return mx::launch_combine_cx<32>(st, n, in, nin, out, nout, (const double*)coef, accumulate, nwg);
+    return hipErrorNotSupported;
 }
 
 hipError_t cx_reduce(hipStream_t st, const double* part, int nwg, int q, int P, const zd* add, zd* out,

@@ -837,20 +837,37 @@ hipError_t launch_proj_gram(hipStream_t st, int64_t n, const T* Win, const Block
 // one is multiplied; the step sequence runs across row tiles), B = C[k][j]
 // from LDS, padded to NCO chunks of 16 output columns.
 // ---------------------------------------------------------------------------
-template <class TI, class TO, int P, int NCO>
+// CX: complex blocks of P / 2 columns seen as real blocks of P interleaved
+// (re, im) columns, and complex coefficients ((K / 2) x (N / 2), row-major):
+// the real coefficient C_r[k][j] is the real part of the complex entry
+// (k / 2, j / 2) where k and j have the same parity, else its imaginary part,
+// negated for (k odd, j even); the LDS holds the complex matrix.
+template <class TI, class TO, int P, int NCO, bool CX = false>
 __global__ __launch_bounds__(256) void k_combine_scalar(int64_t n, BlockPtrs in, int nin, BlockPtrs out, int nout,
                                                       const double* __restrict__ coef, int accumulate) {
     using M = MX<double>;
     constexpr int KK = P / 4, G = 64 / P, NV = G * KK, NPAD = 16 * NCO;
     const int N = nout * P, K = nin * P;
     extern __shared__ __align__(16) unsigned char smem[];
-    double* Cs = (double*)smem;  // [K][NPAD]
-    for (int e = threadIdx.x; e < K * NPAD; e += 256) {
-        const int k = e / NPAD, j = e % NPAD;
-        Cs[e] = j < N ? coef[(int64_t)k * N + j] : 0.0;
+    double* Cs = (double*)smem;  // [K][NPAD], or with CX [K/2][NPAD/2] complex
+    if constexpr (CX) {
+        const int Nc = N / 2, NPc = NPAD / 2;
+        for (int e = threadIdx.x; e < (K / 2) * NPc; e += 256) {
+            const int k = e / NPc, j = e % NPc;
+            const bool ok = j < Nc;
+            Cs[2 * e] = ok ? coef[2 * ((int64_t)k * Nc + j)] : 0.0;
+            Cs[2 * e + 1] = ok ? coef[2 * ((int64_t)k * Nc + j) + 1] : 0.0;
+        }
+    } else {
+        for (int e = threadIdx.x; e < K * NPAD; e += 256) {
+            const int k = e / NPAD, j = e % NPAD;
+            Cs[e] = j < N ? coef[(int64_t)k * N + j] : 0.0;
+        }
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, bl = lane & 15, rq = lane >> 4;
+    const int ol = (rq ^ bl) & 1;
+    const double sg = (CX && (rq & 1) && !(bl & 1)) ? -1.0 : 1.0;
     const int nch = (nin + G - 1) / G;
     const int lw = logical_wg();
     int64_t t0, t1;
@@ -885,9 +902,15 @@ __global__ __launch_bounds__(256) void k_combine_scalar(int64_t n, BlockPtrs in,
             if (blk < nin) {
 #pragma unroll
                 for (int kk = 0; kk < KK; ++kk) {
-                    const double* cr = Cs + (blk * P + 4 * kk + rq) * NPAD + bl;
+                    if constexpr (CX) {
+                        const double* cr = Cs + ((blk * P + 4 * kk + rq) >> 1) * NPAD + 2 * (bl >> 1) + ol;
 #pragma unroll
-                    for (int oc = 0; oc < NCO; ++oc) acc[oc] = M::mma(ac[g * KK + kk], cr[16 * oc], acc[oc]);
+                        for (int oc = 0; oc < NCO; ++oc) acc[oc] = M::mma(ac[g * KK + kk], sg * cr[16 * oc], acc[oc]);
+                    } else {
+                        const double* cr = Cs + (blk * P + 4 * kk + rq) * NPAD + bl;
+#pragma unroll
+                        for (int oc = 0; oc < NCO; ++oc) acc[oc] = M::mma(ac[g * KK + kk], cr[16 * oc], acc[oc]);
+                    }
                 }
             }
         }
@@ -899,10 +922,11 @@ __global__ __launch_bounds__(256) void k_combine_scalar(int64_t n, BlockPtrs in,
                 const int col = 16 * oc + bl;
                 const int ob = col / P, b = col % P;
                 // output block of this lane's column: one of the 16 / P blocks of the
-                // chunk, picked by selects over compile-time indices (blocks past
-                // nout fall back to the chunk's first and are never written)
-                constexpr int BPC = 16 / P;
-                TO* ybase = (TO*)out.p[BPC * oc];
+                // chunk (a 32-column block spans two chunks), picked by selects over
+                // compile-time indices (blocks past nout fall back to the chunk's
+                // first and are never written)
+                constexpr int BPC = P >= 16 ? 1 : 16 / P;
+                TO* ybase = (TO*)out.p[(16 * oc) / P];
 #pragma unroll
                 for (int u = 1; u < BPC; ++u) {
                     TO* pu = (TO*)out.p[BPC * oc + u < nout ? BPC * oc + u : BPC * oc];
@@ -1027,6 +1051,32 @@ __global__ __launch_bounds__(256) void k_combine_mfma(int64_t n, BlockPtrs in, i
             }
         }
     }
+}
+
+// complex blocks of P / 2 columns with complex coefficients (k_combine_scalar
+// with CX), P = 16 or 32 real columns, at most 64 of them in the output
+template <int P>
+hipError_t launch_combine_cx(hipStream_t st, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
+                             const double* coef, int accumulate, int nwg) {
+    const int nco = (nout * P + 15) / 16;
+    const size_t lds = (size_t)nin * P * 16 * nco / 2 * sizeof(double);
+    if (nin < 1 || nout < 1 || lds > (size_t)160 * 1024) return hipErrorNotSupported;
+#define L(NCO)                                                                                                    \
+    {                                                                                                             \
+        static std::once_flag fl;                                                                                 \
+        std::call_once(fl, [] { allow_lds(k_combine_scalar<double, double, P, NCO, true>); });                    \
+        hipLaunchKernelGGL((k_combine_scalar<double, double, P, NCO, true>), dim3(nwg), dim3(256), lds, st, n, in, \
+                           nin, out, nout, coef, accumulate);                                                     \
+    }
+    switch (nco) {
+        case 1: L(1); break;
+        case 2: L(2); break;
+        case 3: L(3); break;
+        case 4: L(4); break;
+        default: return hipErrorNotSupported;
+    }
+#undef L
+    return hipGetLastError();
 }
 
 template <class TI, class TO, int P>

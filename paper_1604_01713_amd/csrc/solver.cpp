@@ -97,13 +97,13 @@ struct Sizes {
 
 // outputs per workgroup of the largest reduction: an Arnoldi sweep (q x P)
 // or a recycle dot launch (up to 32 W columns, at most KB blocks, against q)
-size_t part_outputs(int P, int KB, int qmax, bool cplx, int m) {
+size_t part_outputs(int P, int KB, int qmax, bool cplx) {
     const size_t wg = (size_t)std::max(1, std::min(KB, std::max(1, 32 / P)));
     // the second pass of a block step writes its dots and the new block's Gram
     const size_t o = std::max({(size_t)qmax * P + (size_t)P * P, (size_t)KB * P * P, wg * qmax * P});
     // complex sweeps on matrix cores write the real 2q x 2P products (twice
-    // the complex entries) for q up to (KB + m) P
-    return cplx ? std::max(o, 2 * (size_t)(KB + m) * P * P) : o;
+    // the complex entries)
+    return cplx ? std::max(o, 2 * (size_t)qmax * P) : o;
 }
 
 Sizes sizes_of(const bgcr_params* prm, int64_t n) {
@@ -121,7 +121,7 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
     z.basis = (size_t)(z.m + 1) * z.blk;  // V_1 .. V_{m+1}
     z.recyc = 4 * (size_t)z.KB * z.blk;
     const int qmax = (2 * z.KB + z.m + 1) * z.P;
-    z.nout = part_outputs(z.P, z.KB, qmax, cplx, z.m);
+    z.nout = part_outputs(z.P, z.KB, qmax, cplx);
     z.part = (size_t)NWG_MAX * z.nout * z.sa;
     const size_t mp = (size_t)z.m * z.P, m1p = (size_t)(z.m + 1) * z.P;
     z.small_ = z.sa * (2 * (size_t)qmax * z.P + (size_t)z.P * z.P + 2 * m1p * mp + (size_t)z.KP * mp + (size_t)z.m * 4 * z.P * z.P +
@@ -510,6 +510,11 @@ struct Seq final : bgcr_sequence {
                         mfma_combine<TB, TO>(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate, nwg_mx);
                     if (e != hipErrorNotSupported) return e;
                 }
+            } else {
+                if (cx_mx) {
+                    const hipError_t e = cx_combine(st, P, n, bp(in), nin, bp(outc), nout, cf, accumulate, nwg_mx);
+                    if (e != hipErrorNotSupported) return e;
+                }
             }
             if constexpr (half) {
                 return hipErrorNotSupported;
@@ -546,24 +551,29 @@ struct Seq final : bgcr_sequence {
         // matrix-core dot also serves narrow real blocks (P < 8), where a
         // 16-column chunk spans 16 / P blocks (at most MAXB per launch).
         const bool mxd = mx_dot;
+        const bool cxd = cx_mx;  // complex blocks on the FP64 matrix cores, one W block per launch
         const int wg = mxd ? std::max(1, 32 / P) : 1;
-        const int nr = mxd ? nwg_mx : nwg;
+        const int nr = (mxd || cxd) ? nwg_mx : nwg;
         if ((size_t)nq * P * P * nw > dots_cap) throw Fail{BGCR_ERR_INVALID};
         size_t off = 0;
         for (int w0 = 0; w0 < nw; w0 += wg) {
             const int wn = std::min(wg, nw - w0);
             const int ng = (wn * P + 15) / 16;
-            const int chunk = mxd ? std::max(1, std::min((ng == 2 ? 9 : 16) * 16 / P, MAXB))
-                                  : std::max(1, (MAXI * NT) / (P * P));
+            const int chunk = mxd   ? std::max(1, std::min((ng == 2 ? 9 : 16) * 16 / P, MAXB))
+                              : cxd ? cx_mfma_max_blocks(P)
+                                    : std::max(1, (MAXI * NT) / (P * P));
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = std::min(chunk, nq - q0);
                 const int nout = wn * qn * P * P;
-                if ((size_t)nr * nout > part_cap) throw Fail{BGCR_ERR_INVALID};
+                // (the real partials of complex blocks take twice the entries)
+                if ((size_t)nr * nout * (cxd ? 2 : 1) > part_cap) throw Fail{BGCR_ERR_INVALID};
                 std::vector<const void*> sub(Q.begin() + q0, Q.begin() + q0 + qn);
                 std::vector<const void*> ws(W.begin() + w0, W.begin() + w0 + wn);
                 run(BGCR_K_TSDOT, (double)n * P * ((double)sizeof(TW) * wn + (double)sizeof(TB) * qn), [&] {
                     if constexpr (!std::is_same<T, zd>::value) {
                         if (mxd) return mfma_dot<T, TW, TB>(st, P, n, bp(ws), wn, bp(sub), qn, part, nullptr, nr);
+                    } else {
+                        if (cxd) return cx_dot(st, P, n, (const zd*)W[w0], bp(sub), qn, (double*)part, nullptr, nr, false);
                     }
                     if constexpr (half) {
                         return hipErrorNotSupported;
@@ -572,7 +582,12 @@ struct Seq final : bgcr_sequence {
                                              part, nr, nullptr);
                     }
                 });
-                run(BGCR_K_SMALL, 0.0, [&] { return reduce_partials<A>(st, part, nr, nout, nullptr, dots + off, nullptr); });
+                run(BGCR_K_SMALL, 0.0, [&] {
+                    if constexpr (std::is_same<A, zd>::value) {
+                        if (cxd) return cx_reduce(st, (const double*)part, nr, qn * P, P, nullptr, dots + off, nullptr);
+                    }
+                    return reduce_partials<A>(st, part, nr, nout, nullptr, dots + off, nullptr);
+                });
                 job.pieces.push_back({w0, wn, q0, qn, off});
                 off += nout;
             }

@@ -470,9 +470,13 @@ hipError_t launch_spmm_split(hipStream_t st, int64_t n, int64_t nnz, const int* 
 
 // columns per lane: 16 bytes, so that a load instruction of a wave reads one
 // contiguous span of the block (measured fastest on the 7-point stencil:
-// about 1.5x the throughput of one lane per column or per row)
+// about 1.5x the throughput of one lane per column or per row).  Complex
+// blocks of 8 and 16 columns take 4 lanes per row instead (32 or 64 bytes per
+// lane): the row's nonzeros are then shared by quad broadcasts, and the
+// R^{-1} product needs a quarter of the cross-lane exchanges of 16 lanes.
 template <class T, int P>
 constexpr int spmm_cols() {
+    if constexpr (std::is_same<T, zd>::value) return P <= 4 ? 1 : P / 4;
     return P < (int)(16 / sizeof(T)) ? P : (int)(16 / sizeof(T));
 }
 

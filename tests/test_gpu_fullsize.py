@@ -86,6 +86,28 @@ def test_headline_first_cycle_matches_oracle_at_full_size():
     assert rel <= PARITY
 
 
+def test_helmholtz_two_cycles_match_oracle_at_full_size():
+    """Complex 1024^2 Helmholtz (n = 1,048,576, complex128), p = 16, m = 8,
+    k = 16: two restart cycles of the first system against the oracle's, the
+    second one augmented with the recycled pair of the first (Algorithm 1 with
+    C in the projections).  These are the matrix-core complex sweeps in the
+    launch configuration the benchmark times."""
+    bg = _bg()
+    dev = _dev()
+    w = problems.cfg3(nsys=1)
+    s = w.systems[0]
+    seq, Xg, st, log = _solve(bg, dev, s.A, s.B, w.p, w.m, w.k, w.tol, max_cycles=2)
+    seq.release()
+    Xo, _, so = oracle.solve(s.A, s.B, s.X0, w.tol, w.m, w.k, max_cycles=2)
+    rel = np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo)
+    col = max(np.linalg.norm(Xg[:, j] - Xo[:, j]) / np.linalg.norm(Xo[:, j]) for j in range(Xo.shape[1]))
+    print(f"cfg3 full size, two cycles: gpu steps {st['block_steps']} rel.res {st['rel_res']:.6e} | oracle steps "
+          f"{so['block_steps']} rel.res {so['rel_res']:.6e} | rel diff {rel:.2e}, worst column {col:.2e}", flush=True)
+    assert st["cycles"] == 2 and st["block_steps"] == so["block_steps"]
+    assert abs(st["rel_res"] - so["rel_res"]) <= 1e-8 * so["rel_res"]
+    assert col <= 1e-10
+
+
 @pytest.mark.parametrize("name", ["cfg2_128^3_fp64", "cfg3_1024^2_complex", "cfg4_192^3_fp32_in_fp64"])
 def test_full_size_properties(name):
     bg = _bg()
