@@ -415,6 +415,9 @@ def bench_datamove(args, torch, problems, bg, dev):
     import numpy as np
     ps = (1, 2, 4, 8, 16)
     mats = [(10**4, 4), (10**5, 4), (10**6, 4), (10**6, 16), (10**6, 50), (10**7, 4), (10**7, 16)]
+    if args.datamove_bandwidths:
+        # the bandwidth axis of Section 6.3 at n = 1e6
+        mats = [(10**6, bw) for bw in (4, 10, 20, 30, 40, 50)]
     if args.datamove_small:
         mats, ps = [(10**6, 16)], (1, 8)
     kdims = (10,) if args.datamove_small else (10, 50, 100)
@@ -628,6 +631,8 @@ def main():
                          "the anisotropic 192^3 sequence; serving: a request stream, served vs serial; enlarged: one "
                          "right-hand side, block size 1 vs 8 and 16")
     ap.add_argument("--requests", type=int, default=24, help="serving: number of requests")
+    ap.add_argument("--datamove-bandwidths", action="store_true",
+                    help="datamove: n = 1e6 with bandwidths 4, 10, 20, 30, 40 and 50")
     ap.add_argument("--helmholtz-reduced", type=int, default=256,
                     help="helmholtz: side of the reduced grid solved to the tolerance (0: skipped)")
     ap.add_argument("--serving-full", action="store_true",

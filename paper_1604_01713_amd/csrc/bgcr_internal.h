@@ -257,6 +257,9 @@ hipError_t cx_proj_gram(hipStream_t st, int P, int64_t n, const zd* W, const Blo
 // first `accumulate` output blocks are accumulated
 hipError_t cx_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
                       const zd* coef, int accumulate, int nwg);
+// out = I - M for a complex P x P matrix (the update form of a right
+// multiplication, W M = W - W (I - M))
+hipError_t cx_i_minus(hipStream_t st, const zd* M, zd* out, int P);
 // out (q x P) = add (or 0) + contraction of the summed real partials
 hipError_t cx_reduce(hipStream_t st, const double* part, int nwg, int q, int P, const zd* add, zd* out,
                      const Ctl* ctl);

@@ -466,46 +466,56 @@ __global__ __launch_bounds__(256) void k_reduce(const A* __restrict__ part, int 
 __device__ inline double dabs(double a) { return fabs(a); }
 __device__ inline double dabs(zd a) { return sqrt(a.x * a.x + a.y * a.y); }
 
-// G = R^H R with R upper triangular, positive diagonal.  Fails when a pivot is
-// not above 1e-24 of the largest diagonal entry of G (columns numerically
-// dependent to about 1e-12).
+// Cholesky factor G = R^H R (R upper triangular, positive diagonal) and its
+// inverse, by the whole group (P * P <= blockDim.x; thread t < P * P owns
+// entry (t / P, t % P)), right-looking: after pivot row i is final, every
+// trailing entry subtracts its term of that row, so each entry takes its
+// updates in the row order of the dot-product form.  The factorisation fails
+// on a pivot not above 1e-24 of the largest diagonal entry of G (columns
+// numerically dependent to about 1e-12), or not above `rel` times its own
+// diagonal entry (a column numerically in the span of the previous ones;
+// scale invariant).  *ok (shared) receives the result; sh (shared) holds two
+// doubles.  The inverse is formed row by row from the bottom.
 template <class A>
-__device__ bool chol_upper(const A* G, A* R, int P, double rel = 0.0) {
-    // fails on a pivot below 1e-24 of the largest diagonal entry, or below
-    // `rel` times its own diagonal entry (a column that is numerically in the
-    // span of the previous ones; scale invariant)
-    double maxd = 0.0;
-    for (int i = 0; i < P; ++i) maxd = fmax(maxd, re(G[i * P + i]));
-    if (!(maxd > 0.0) || !isfinite(maxd)) return false;
-    for (int i = 0; i < P; ++i) {
-        for (int j = 0; j < i; ++j) R[i * P + j] = zero<A>();
-        A d = G[i * P + i];
-        for (int l = 0; l < i; ++l) d -= cj(R[l * P + i]) * R[l * P + i];
-        const double dd = re(d);
-        if (!(dd > 1e-24 * maxd) || !(dd > rel * re(G[i * P + i])) || !isfinite(dd)) return false;
-        const double rii = sqrt(dd);
-        R[i * P + i] = from_real<A>(rii);
-        const double ir = 1.0 / rii;
-        for (int j = i + 1; j < P; ++j) {
-            A s = G[i * P + j];
-            for (int l = 0; l < i; ++l) s -= cj(R[l * P + i]) * R[l * P + j];
-            R[i * P + j] = scale_by(ir, s);
-        }
+__device__ void chol_inv_group(const A* G, A* R, A* Ri, int P, double rel, int* ok, double* sh) {
+    const int t = threadIdx.x, a = t / P, b = t % P;
+    const bool own = t < P * P;
+    if (t == 0) {
+        double maxd = 0.0;
+        for (int i = 0; i < P; ++i) maxd = fmax(maxd, re(G[i * P + i]));
+        sh[0] = maxd;
+        *ok = (maxd > 0.0) && isfinite(maxd);
     }
-    return true;
-}
-
-// inverse of an upper triangular matrix with real positive diagonal
-template <class A>
-__device__ void tri_inv_upper(const A* R, A* Ri, int P) {
-    for (int j = 0; j < P; ++j) {
-        for (int i = j + 1; i < P; ++i) Ri[i * P + j] = zero<A>();
-        Ri[j * P + j] = from_real<A>(1.0 / re(R[j * P + j]));
-        for (int i = j - 1; i >= 0; --i) {
-            A s = zero<A>();
-            for (int l = i + 1; l <= j; ++l) s += R[i * P + l] * Ri[l * P + j];
-            Ri[i * P + j] = scale_by(-1.0 / re(R[i * P + i]), s);
+    A w = own ? G[t] : zero<A>();
+    __syncthreads();
+    if (!*ok) return;
+    const double maxd = sh[0];
+    for (int i = 0; i < P; ++i) {
+        if (own && a == i && b == i) {
+            const double dd = re(w);
+            const bool good = (dd > 1e-24 * maxd) && (dd > rel * re(G[t])) && isfinite(dd);
+            *ok = good;
+            sh[1] = good ? sqrt(dd) : 1.0;
         }
+        __syncthreads();
+        if (!*ok) return;
+        if (own && a == i) {
+            const double rii = sh[1];
+            R[t] = b < i ? zero<A>() : (b == i ? from_real<A>(rii) : scale_by(1.0 / rii, w));
+        }
+        __syncthreads();
+        if (own && a > i && b > i) w -= cj(R[i * P + a]) * R[i * P + b];
+    }
+    // the inverse, row by row from the bottom
+    if (own) Ri[t] = a > b ? zero<A>() : (a == b ? from_real<A>(1.0 / re(R[t])) : zero<A>());
+    __syncthreads();
+    for (int i = P - 2; i >= 0; --i) {
+        if (own && a == i && b > i) {
+            A s = zero<A>();
+            for (int l = i + 1; l <= b; ++l) s += R[i * P + l] * Ri[l * P + b];
+            Ri[t] = scale_by(-1.0 / re(R[i * P + i]), s);
+        }
+        __syncthreads();
     }
 }
 
@@ -529,7 +539,7 @@ template <class A, int P>
 __global__ void k_cholqr_first(const A* gram, A* Z1, A* Z1inv, int nrhs, Ctl* ctl) {
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
     __shared__ int okf;
-    __shared__ double dsc[P];
+    __shared__ double dsc[P], shv[2];
     if (threadIdx.x == 0) {
         double s = 1.0;
         if (nrhs < P) {
@@ -545,10 +555,7 @@ __global__ void k_cholqr_first(const A* gram, A* Z1, A* Z1inv, int nrhs, Ctl* ct
     __syncthreads();
     for (int e = threadIdx.x; e < P * P; e += blockDim.x) Gs[e] = scale_by(dsc[e / P] * dsc[e % P], gram[e]);
     __syncthreads();
-    if (threadIdx.x == 0) {
-        okf = chol_upper(Gs, Rs, P, 1e-14);  // CholQR2 needs cond(start block) below about 1e7
-        if (okf) tri_inv_upper(Rs, Ri, P);
-    }
+    chol_inv_group(Gs, Rs, Ri, P, 1e-14, &okf, shv);  // CholQR2 needs cond(start block) below about 1e7
     __syncthreads();
     if (!okf) {
         if (threadIdx.x == 0) {
@@ -571,13 +578,11 @@ template <class A, int P>
 __global__ void k_cholqr_second(const A* gram, const A* Z1, A* Rinv0, A* g, int m, int nrhs, Ctl* ctl) {
     __shared__ A Gs[P * P], Rs[P * P], Ri[P * P];
     __shared__ int okf;
+    __shared__ double shv[2];
     if (ctl->status != 0) return;
     for (int e = threadIdx.x; e < P * P; e += blockDim.x) Gs[e] = gram[e];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        okf = chol_upper(Gs, Rs, P);
-        if (okf) tri_inv_upper(Rs, Ri, P);
-    }
+    chol_inv_group(Gs, Rs, Ri, P, 0.0, &okf, shv);
     __syncthreads();
     if (!okf) {
         if (threadIdx.x == 0) {
@@ -620,7 +625,7 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
     __shared__ A X[P2 * P], M[P2 * P2], tmp[P2 * P], V[P2];
     __shared__ A Sd[SROWS * P];
     A* const Qs = M;  // reflector of an earlier column; M is set up after the last use
-    __shared__ double vv, red[NT];
+    __shared__ double vv, red[NT], shv[2];
     __shared__ int okf;
     const int t = threadIdx.x;
     const int jc = j - 1;
@@ -646,10 +651,7 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
         for (int e = t; e < P * P; e += NT) Gs[e] = gram[e];
     }
     __syncthreads();
-    if (t == 0) {
-        okf = chol_upper(Gs, Rs, P);
-        if (okf) tri_inv_upper(Rs, Ri, P);
-    }
+    chol_inv_group(Gs, Rs, Ri, P, 0.0, &okf, shv);
     __syncthreads();
     if (!okf) {
         if (t == 0) {

@@ -73,6 +73,16 @@ hipError_t cx_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int
     return hipErrorNotSupported;
 }
 
+__global__ void k_cx_i_minus(const zd* __restrict__ M, zd* __restrict__ out, int P) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < P * P) out[e] = zd{((e / P) == (e % P) ? 1.0 : 0.0) - M[e].x, -M[e].y};
+}
+
+hipError_t cx_i_minus(hipStream_t st, const zd* M, zd* out, int P) {
+    hipLaunchKernelGGL(k_cx_i_minus, dim3((P * P + 255) / 256), dim3(256), 0, st, M, out, P);
+    return hipGetLastError();
+}
+
 hipError_t cx_reduce(hipStream_t st, const double* part, int nwg, int q, int P, const zd* add, zd* out,
                      const Ctl* ctl) {
     if (q * P <= 0) return hipSuccess;
