@@ -69,8 +69,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NC <= 8 ? 2
     const int wcol = (lane & 15) & (P - 1);
     for (int64_t tile = first; tile < end; tile += step) {
         const int64_t rb = tile * ROWS + wave * WR;
+        // Q streams through once: non-temporal loads, so that the L2 keeps the
+        // gathered neighbour rows of V
         double qv[KS][NC];
-        mx::load_rc<double, double, P, NC, KS>(qv, qp, rb, n, lane);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int64_t off = mx::clamp_row(rb + 4 * ks + (lane >> 4), n) * P;
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) qv[ks][ch] = __builtin_nontemporal_load(qp[ch] + off);
+        }
         const int64_t row = tile * ROWS + r;
         const int64_t rowc[1] = {mx::clamp_row(row, n)};
         double raw[1][C];
