@@ -1,6 +1,8 @@
 // Small dense FP64 linear algebra on the host (see dense.h).
 #include "dense.h"
 
+#include <functional>
+
 #include <omp.h>
 
 #include <algorithm>
@@ -872,11 +874,8 @@ static void inverse_iteration_real(const std::vector<double>& Hd, int n, double 
     }
 }
 
-std::vector<cd> EigSolver::vector_for(cd lambda, const std::vector<std::vector<cd>>& against) const {
-    // inverse iteration on the Hessenberg matrix with a slightly perturbed shift
-    const double pert = std::max(hnorm, 1e-300) * 1e-13;
-    const cd sh = lambda + cd(pert, 0.0);
-    // back to the basis of A: x <- H_0 H_1 ... H_{n-3} x
+// back to the basis of A: x <- H_0 H_1 ... H_{n-3} x
+std::vector<cd> EigSolver::to_basis(std::vector<cd> x) const {
     auto back = [&](std::vector<cd>& x) {
         for (int k = n - 3; k >= 0; --k) {
             if (reflvv[k] == 0.0) continue;
@@ -896,6 +895,14 @@ std::vector<cd> EigSolver::vector_for(cd lambda, const std::vector<std::vector<c
             }
         }
     };
+    back(x);
+    return x;
+}
+
+std::vector<cd> EigSolver::hess_vector(cd lambda, const std::vector<std::vector<cd>>& against) const {
+    // inverse iteration on the Hessenberg matrix with a slightly perturbed shift
+    const double pert = std::max(hnorm, 1e-300) * 1e-13;
+    const cd sh = lambda + cd(pert, 0.0);
     std::vector<cd> x(n);
     uint64_t st = 0x9E3779B97F4A7C15ull;
     std::vector<double> x0(n);
@@ -908,7 +915,6 @@ std::vector<cd> EigSolver::vector_for(cd lambda, const std::vector<std::vector<c
     if (real && lambda.imag() == 0.0 && against.empty()) {
         inverse_iteration_real(Hd, n, sh.real(), pert, x0);
         for (int i = 0; i < n; ++i) x[i] = cd(x0[i], 0.0);
-        back(x);
         return x;
     }
     std::vector<cd> U((size_t)n * n);
@@ -959,20 +965,48 @@ std::vector<cd> EigSolver::vector_for(cd lambda, const std::vector<std::vector<c
             for (cd& v : x) v /= nr;
     };
     for (int i = 0; i < n; ++i) x[i] = cd(x0[i], 0.0);
-    // vectors of nearby eigenvalues are carried in the Hessenberg basis
     orth_normalize(x);
     for (int it = 0; it < 3; ++it) {
         solve(x);
         orth_normalize(x);
     }
-    back(x);
     return x;
 }
 
 std::vector<std::vector<cd>> EigSolver::vectors_for(const std::vector<int>& idx) const {
-    std::vector<std::vector<cd>> out(idx.size());
-#pragma omp parallel for schedule(dynamic, 1) num_threads(team(20.0 * n * n * idx.size()))
-    for (int i = 0; i < (int)idx.size(); ++i) out[i] = vector_for(lam[idx[i]], {});
+    // clusters: eigenvalues closer than 1e-10 |H| (a thousand times the
+    // shift perturbation), joined transitively.  Inverse iteration cannot
+    // tell such eigenvalues apart and would return nearly the same vector for
+    // each; within a cluster the vectors are computed in turn, each kept
+    // orthogonal to the earlier ones (for a multiple eigenvalue an orthonormal
+    // basis of its eigenspace).  Clusters run concurrently.
+    const int k = (int)idx.size();
+    const double tol = 1e-10 * std::max(hnorm, 1e-300);
+    std::vector<int> root(k);
+    for (int i = 0; i < k; ++i) root[i] = i;
+    std::function<int(int)> find = [&](int i) { return root[i] == i ? i : root[i] = find(root[i]); };
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < i; ++j)
+            if (std::abs(lam[idx[i]] - lam[idx[j]]) <= tol) root[find(i)] = find(j);
+    std::vector<std::vector<int>> groups;
+    std::vector<int> gof(k, -1);
+    for (int i = 0; i < k; ++i) {
+        const int r = find(i);
+        if (gof[r] < 0) {
+            gof[r] = (int)groups.size();
+            groups.emplace_back();
+        }
+        groups[gof[r]].push_back(i);
+    }
+    std::vector<std::vector<cd>> out(k);
+#pragma omp parallel for schedule(dynamic, 1) num_threads(team(20.0 * n * n * k))
+    for (int g = 0; g < (int)groups.size(); ++g) {
+        std::vector<std::vector<cd>> hv;
+        for (int i : groups[g]) {
+            hv.push_back(hess_vector(lam[idx[i]], hv));
+            out[i] = to_basis(hv.back());
+        }
+    }
     return out;
 }
 

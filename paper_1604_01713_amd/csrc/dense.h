@@ -79,10 +79,15 @@ struct EigSolver {
     bool ok = false;
     // A: n x n; real selects the real double-shift path (A must be real)
     void compute(const Mat& A, bool real_input);
-    // eigenvector for eigenvalue lambda (unit 2-norm, in the basis of A);
-    // `against`: vectors already chosen for nearby eigenvalues (kept apart)
-    std::vector<cd> vector_for(cd lambda, const std::vector<std::vector<cd>>& against) const;
-    // vector_for(lam[i], {}) for each i in idx, computed concurrently
+    // eigenvector for eigenvalue lambda in the Hessenberg basis (unit 2-norm),
+    // orthogonal to `against` (vectors in that basis already chosen for
+    // eigenvalues of the same cluster)
+    std::vector<cd> hess_vector(cd lambda, const std::vector<std::vector<cd>>& against) const;
+    // a Hessenberg-basis vector in the basis of A
+    std::vector<cd> to_basis(std::vector<cd> x) const;
+    // eigenvectors for lam[i], i in idx, in the basis of A; eigenvalues that
+    // inverse iteration cannot separate are taken as one cluster whose vectors
+    // are mutually orthogonal
     std::vector<std::vector<cd>> vectors_for(const std::vector<int>& idx) const;
 };
 
