@@ -93,6 +93,34 @@ Mat matmul(const Mat& A, const Mat& B) {
     return C;
 }
 
+Mat matmul_upper(const Mat& A, const Mat& B) {
+    if (all_real(A) && all_real(B)) {
+        const std::vector<double> a = real_part(A), b = real_part(B);
+        std::vector<double> c((size_t)A.r * B.c, 0.0);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(team(1.0 * A.r * A.c * B.c))
+        for (int j = 0; j < B.c; ++j)
+            for (int l = 0; l <= std::min(j, A.c - 1); ++l) {
+                const double bl = b[(size_t)j * A.c + l];
+                if (bl == 0.0) continue;
+                const double* al = &a[(size_t)l * A.r];
+                double* cj = &c[(size_t)j * A.r];
+                for (int i = 0; i < A.r; ++i) cj[i] += al[i] * bl;
+            }
+        return from_real(A.r, B.c, c);
+    }
+    Mat C(A.r, B.c);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(team(4.0 * A.r * A.c * B.c))
+    for (int j = 0; j < B.c; ++j)
+        for (int l = 0; l <= std::min(j, A.c - 1); ++l) {
+            const cd b = B(l, j);
+            if (b == cd(0.0, 0.0)) continue;
+            const cd* a = &A.a[(size_t)l * A.r];
+            cd* c = &C.a[(size_t)j * C.r];
+            for (int i = 0; i < A.r; ++i) c[i] += a[i] * b;
+        }
+    return C;
+}
+
 Mat adjoint(const Mat& A) {
     Mat B(A.c, A.r);
     for (int j = 0; j < A.c; ++j)
@@ -180,13 +208,20 @@ Mat tri_inv_upper(const Mat& R) {
         }
         return from_real(n, n, x);
     }
+    // rows of R contiguous; the columns of the inverse are independent
+    std::vector<cd> rt((size_t)n * n);
+    for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) rt[(size_t)i * n + j] = R(i, j);
     Mat X(n, n);
+#pragma omp parallel for schedule(dynamic, 4) num_threads(team(4.0 * n * n * n / 6.0))
     for (int j = 0; j < n; ++j) {
-        X(j, j) = 1.0 / R(j, j);
+        cd* xj = &X.a[(size_t)j * n];
+        xj[j] = 1.0 / rt[(size_t)j * n + j];
         for (int i = j - 1; i >= 0; --i) {
+            const cd* ri = &rt[(size_t)i * n];
             cd s = 0.0;
-            for (int l = i + 1; l <= j; ++l) s += R(i, l) * X(l, j);
-            X(i, j) = -s / R(i, i);
+            for (int l = i + 1; l <= j; ++l) s += ri[l] * xj[l];
+            xj[i] = -s / ri[i];
         }
     }
     return X;

@@ -31,6 +31,8 @@ struct Mat {
 };
 
 Mat matmul(const Mat& A, const Mat& B);
+// A B with B upper triangular (entries below its diagonal not read)
+Mat matmul_upper(const Mat& A, const Mat& B);
 Mat adjoint(const Mat& A);
 double fro(const Mat& A);
 

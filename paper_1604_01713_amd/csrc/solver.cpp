@@ -157,10 +157,12 @@ struct Seq final : bgcr_sequence {
     int pu = 0;  // right-hand sides of the caller (P > pu: enlarged block, pu = 1)
     int nwg_mx = 0;      // workgroups of the matrix-core sweeps (64-row tiles)
     bool use_mx = false; // Arnoldi sweeps on matrix cores
-    // the first-pass dots and the third sweep walk each workgroup's rows from
-    // the end: every sweep of a block step then starts on the rows the one
-    // before it read last, which the chip's memory-side cache still holds
-    // (third sweep 295 -> 277 us, second 231 -> 226 us at 128^3, p = 8)
+    // Sweep directions alternate, so that every sweep of a block step starts
+    // on the rows the one before it read last, which the chip's memory-side
+    // cache still holds (third sweep 295 -> 277 us, second 231 -> 226 us at
+    // 128^3, p = 8).  Step 1: SpMM and third sweep forwards, first-pass dots
+    // backwards; later steps, after the fused SpMM + dots (forwards): second
+    // sweep backwards, third forwards.
     static constexpr bool alt_dir = true;
     // sweeps 1a and 1b fused into one pass (real FP64 on matrix cores)
     bool fuse_dots = false;
@@ -1199,7 +1201,9 @@ struct Seq final : bgcr_sequence {
                     if (narrow) return narrow_sweep<T>(st, n, Wb, QB, nq + 1, S1, nullptr, part, na, ctl, true);
                 }
                 if constexpr (!std::is_same<T, zd>::value) {
-                    if (mx_upd) return mfma_proj_dot<T, TB>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip);
+                    if (mx_upd)
+                        return mfma_proj_dot<T, TB>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip,
+                                                    alt_dir && fused);
                 } else {
                     // (P = 16 stores W' in W2, which the SpMM has consumed)
                     if (cx_mx) return cx_proj_dot(st, P, n, Wb, QB, nq + 1, S1, Sr, W2, (double*)part, ctl, na);
@@ -1215,7 +1219,8 @@ struct Seq final : bgcr_sequence {
                 run(BGCR_K_PROJ_GRAM, blkb + vblkb + qbytes, [&] {  // W, V_{j+1}, Q
                     if constexpr (!std::is_same<T, zd>::value) {
                         return mfma_proj_gram<T, TB, TB>(st, P, n, Wb, QB, nq + 1, Sf, vblk(j), part, ctl, na,
-                                                         (const double*)(RinvAll + (size_t)j * P2), j, alt_dir);
+                                                         (const double*)(RinvAll + (size_t)j * P2), j,
+                                                         alt_dir && !fused);
                     }
                     return hipErrorNotSupported;
                 });
@@ -1590,7 +1595,37 @@ struct Seq final : bgcr_sequence {
         for (int i = 0; i < nn; ++i)
             if (!(std::abs(Rg(i, i)) > 0.0)) throw Fail{BGCR_ERR_NUMERICAL};
         const Mat Rgi = dense::tri_inv_upper(Rg);
-        const Mat K = dense::matmul(dense::matmul(dense::adjoint(Qg), M), Rgi);
+        // K = Qg^H M Rg^{-1}.  The columns of M that are unit vectors e_r (its
+        // identity block W_{m+1}^H W_m) give row r of Qg, conjugated, without a
+        // product; the rest are dot products.  Rg^{-1} is upper triangular.
+        const int rows = M.r, mc = M.c;
+        std::vector<int> unit_row(mc, -1);
+        std::vector<int> dense_cols;
+        for (int c = 0; c < mc; ++c) {
+            int r1 = -1, nz = 0;
+            for (int r = 0; r < rows && nz < 2; ++r)
+                if (M(r, c) != cd(0.0, 0.0)) {
+                    ++nz;
+                    r1 = r;
+                }
+            if (nz == 1 && M(r1, c) == cd(1.0, 0.0))
+                unit_row[c] = r1;
+            else
+                dense_cols.push_back(c);
+        }
+        Mat K1(nn, mc);
+        for (int c = 0; c < mc; ++c)
+            if (unit_row[c] >= 0)
+                for (int i = 0; i < nn; ++i) K1(i, c) = std::conj(Qg(unit_row[c], i));
+        if (!dense_cols.empty()) {
+            Mat Md(rows, (int)dense_cols.size());
+            for (int j = 0; j < (int)dense_cols.size(); ++j)
+                for (int r = 0; r < rows; ++r) Md(r, j) = M(r, dense_cols[j]);
+            const Mat Kd = dense::matmul(dense::adjoint(Qg), Md);
+            for (int j = 0; j < (int)dense_cols.size(); ++j)
+                for (int i = 0; i < nn; ++i) K1(i, dense_cols[j]) = Kd(i, j);
+        }
+        const Mat K = dense::matmul_upper(K1, Rgi);
         std::vector<std::vector<cd>> svecs;
         eig_select(K, true, kt, robust, theta, sel, svecs);
         vecs.clear();
