@@ -678,9 +678,25 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
     // column (its lower block enters unreflected) and the finished upper block
     // of each window is written to Rh
     for (int e = t; e < P2 * P; e += NT) X[e] = hcol(e / P, e % P);
+    // the reflector products of earlier columns come from memory one after the
+    // other: the next one is loaded into registers while the current one is
+    // applied
+    constexpr int QPT = (P2 * P2 + NT - 1) / NT;
+    A qn[QPT];
+    auto qload = [&](int i) {
+#pragma unroll
+        for (int u = 0; u < QPT; ++u) {
+            const int e = t + u * NT;
+            qn[u] = e < P2 * P2 ? QH[(int64_t)(i - 1) * P2 * P2 + e] : zero<A>();
+        }
+    };
+    if (j > 1) qload(1);
     for (int i = 1; i < j; ++i) {
-        for (int e = t; e < P2 * P2; e += NT) Qs[e] = QH[(int64_t)(i - 1) * P2 * P2 + e];
+#pragma unroll
+        for (int u = 0; u < QPT; ++u)
+            if (t + u * NT < P2 * P2) Qs[t + u * NT] = qn[u];
         __syncthreads();
+        if (i + 1 < j) qload(i + 1);
         for (int e = t; e < P2 * P; e += NT) {
             const int rr = e / P, bb = e % P;
             A s = zero<A>();
@@ -700,21 +716,28 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
     const int r0 = (j - 1) * P;
     for (int e = t; e < P2 * P2; e += NT) M[e] = from_real<A>((e / P2) == (e % P2) ? 1.0 : 0.0);
     __syncthreads();
+    static_assert(P2 <= 64, "one lane of the first wave per row of the 2P x P block");
     for (int c = 0; c < P; ++c) {
-        if (t == 0) {
-            double al = 0.0;
-            for (int l = c; l < P2; ++l) al += absq(X[l * P + c]);
-            al = sqrt(al);
+        // reflector of column c by the first wave, one lane per row: norms by
+        // a butterfly over the wave (every lane ends with the same sum)
+        if (t < 64) {
+            const int l = t;
+            const A xl = (l >= c && l < P2) ? X[l * P + c] : zero<A>();
+            double a2 = absq(xl);
+            for (int off = 32; off > 0; off >>= 1) a2 += __shfl_xor(a2, off);
+            const double al = sqrt(a2);
             double s2 = 0.0;
             if (al > 0.0) {
                 const A x0 = X[c * P + c];
                 const double ax = dabs(x0);
                 const A ph = ax > 0.0 ? scale_by(1.0 / ax, x0) : from_real<A>(1.0);
                 const A beta = scale_by(-al, ph);
-                for (int l = 0; l < P2; ++l) V[l] = l < c ? zero<A>() : (l == c ? x0 - beta : X[l * P + c]);
-                for (int l = c; l < P2; ++l) s2 += absq(V[l]);
+                const A vl = l < c ? zero<A>() : (l == c ? x0 - beta : xl);
+                if (l < P2) V[l] = vl;
+                s2 = absq(vl);
+                for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
             }
-            vv = s2;
+            if (l == 0) vv = s2;
         }
         __syncthreads();
         if (vv > 0.0) {
