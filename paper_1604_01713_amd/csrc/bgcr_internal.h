@@ -234,19 +234,21 @@ hipError_t copy_block(hipStream_t st, int64_t n, int p, const TI* in, int64_t ld
 
 // The three block-CGS sweeps of complex128 blocks of P = 8 or 16 columns on
 // the FP64 matrix cores, the blocks seen as real blocks of 2P interleaved
-// (re, im) columns; nwg workgroups (mfma_nwg); at most cx_mfma_max_blocks(P)
-// blocks in Q, hipErrorNotSupported otherwise.  Partials are the real
-// products part[wg][r 2P + s] of the 2q x 2P real view (q = nq P), which
-// cx_reduce contracts into the complex q x P result.
-int cx_mfma_max_blocks(int P);
+// (re, im) columns; nwg workgroups (mfma_nwg); at most cx_mfma_max_blocks(P,
+// pip) blocks in Q (pip: the sweeps of the PIP order, second pass with the
+// Gram of W', third pass normalising), hipErrorNotSupported otherwise.
+// Partials are the real products part[wg][r 2P + s] of the 2q x 2P real view
+// (q = nq P), which cx_reduce contracts into the complex q x P result.
+int cx_mfma_max_blocks(int P, bool pip);
 // partial Q^T W
 hipError_t cx_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, double* part,
                   const Ctl* ctl, int nwg, bool rev);
-// W' = W - Q S (S complex q x P) and partial Q^T W'; Sr (4 q P doubles)
-// holds the real form of S (P = 8); Wtmp (n x P) receives W' for P = 16 with
-// more than 10 blocks in Q
+// W' = W - Q S (S complex q x P) and partial Q^T W', with gram followed by
+// the partial real Gram of W' (2P x 2P, per-workgroup stride 4 q P + 4 P P);
+// Sr (4 q P doubles) holds the real form of S (P = 8); Wtmp (n x P) receives
+// W' for P = 16 with more than 10 blocks in Q (no Gram then)
 hipError_t cx_proj_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
-                       double* Sr, zd* Wtmp, double* part, const Ctl* ctl, int nwg);
+                       double* Sr, zd* Wtmp, double* part, const Ctl* ctl, int nwg, bool gram, bool rev);
 // W'' = W - Q S stored in Wout with its partial real Gram (part[wg][r 2P + s],
 // 2P x 2P); runs while the cycle is active and for block step `step` if it
 // just stopped there
@@ -257,10 +259,20 @@ hipError_t cx_proj_gram(hipStream_t st, int P, int64_t n, const zd* W, const Blo
 // first `accumulate` output blocks are accumulated
 hipError_t cx_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
                       const zd* coef, int accumulate, int nwg);
+// V = (W - Q S) R^{-1} stored in Vout (Rinv complex P x P); Sr holds
+// 4 q P + 4 P P doubles (the real forms of S and R^{-1}, P = 8); runs while
+// the cycle is active and for block step `step` if it just stopped there
+hipError_t cx_proj_norm(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
+                        double* Sr, const zd* Rinv, zd* Vout, double* part, const Ctl* ctl, int nwg, int step,
+                        bool rev);
 // out = I - M for a complex P x P matrix (the update form of a right
 // multiplication, W M = W - W (I - M))
 hipError_t cx_i_minus(hipStream_t st, const zd* M, zd* out, int P);
 // out (q x P) = add (or 0) + contraction of the summed real partials
+// part[wg stride + off ..]
+hipError_t cx_reduce_at(hipStream_t st, const double* part, int nwg, int64_t stride, int64_t off, int q, int P,
+                        const zd* add, zd* out, const Ctl* ctl);
+// the same with stride 4 q P and no offset
 hipError_t cx_reduce(hipStream_t st, const double* part, int nwg, int q, int P, const zd* add, zd* out,
                      const Ctl* ctl);
 

@@ -24,7 +24,9 @@ namespace mx {
 // ---------------------------------------------------------------------------
 // Update sweep of 32-column FP64 blocks (complex P = 16): W'' = W - Q S with
 // S complex (nq 16 x 16 blocks), stored (Wout non-null, in place allowed);
-// with GRAM the partial 32 x 32 Gram W''^T W'' in part[wg][i 32 + j].  As
+// with GRAM the partial 32 x 32 Gram W''^T W'' in part[wg][i 32 + j]; with
+// NORM (Rinv, the complex 16 x 16 R^{-1}) V = W'' R^{-1} is stored instead,
+// and there is no Gram.  As
 // the 16-column update sweep with the D tile (W^T, 16 columns x 16 rows per
 // wave) doubled: tile g holds columns 16 g .. 16 g + 15, and both share the
 // Q operand loads (column-major, straight into registers).
@@ -32,10 +34,12 @@ namespace mx {
 // block offset) and w = 16 g + l % 16: the lane reads the real or imaginary
 // part of the complex entry (c / 2, w / 2) and applies its sign.
 // ---------------------------------------------------------------------------
-template <int NQ, bool GRAM>
+template <int NQ, bool GRAM, bool NORM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQ <= 4 ? 1 : 2))) void k_update_wide(int64_t n, const double* Win, BlockPtrs Q, int nq,
                                                      const zd* __restrict__ S, double* Wout,
-                                                     double* __restrict__ part, const Ctl* ctl, int step, int rev) {
+                                                     double* __restrict__ part, const zd* __restrict__ Rinv,
+                                                     const Ctl* ctl, int step, int rev) {
+    static_assert(!(GRAM && NORM), "a normalising sweep takes no Gram");
     using M = MX<double>;
     constexpr int P = 32, KK = 8, NQA = NQ > 0 ? NQ : 1, NQV = NQ * KK;
     if (ctl && ctl->active == 0 && !(ctl->meff == step && ctl->status == 0)) return;
@@ -55,6 +59,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQ <= 4 ? 1
     const double* qb[NQA];
 #pragma unroll
     for (int blk = 0; blk < NQA; ++blk) qb[blk] = (const double*)(blk < nq ? Q.p[blk] : Q.p[0]);
+    // NORM: A operands (R^{-1}_r)^T[16 g + l % 16][4 kk + l / 16] = R^{-1}_r[4 kk + l / 16][16 g + l % 16],
+    // the real form of the complex R^{-1} (real part where row and column have the same parity, else the
+    // imaginary part, negated for (odd row, even column))
+    double ra[2][KK];
+    if constexpr (NORM) {
+        const double* Rd = (const double*)Rinv;
+        const double rsg = ((rq & 1) && !(bl & 1)) ? -1.0 : 1.0;
+#pragma unroll
+        for (int g = 0; g < 2; ++g)
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk)
+                ra[g][kk] = rsg * Rd[2 * ((2 * kk + (rq >> 1)) * 16 + 8 * g + (bl >> 1)) + ol];
+    }
     d4v gacc[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -123,7 +140,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NQ <= 4 ? 1
         const int64_t row = rbase + bl;
 #pragma unroll
         for (int g = 0; g < 2; ++g) zero_tail<double>(d[g], rbase, n, lane);
-        if (Wout && row < n) {
+        if constexpr (NORM) {
+            // V^T = (R^{-1}_r)^T W''^T: B operand W''^T[4 kk + l/16][row l % 16] from the tile in LDS
+#pragma unroll
+            for (int g = 0; g < 2; ++g)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) mytr[bl * P + 16 * g + M::drow(lane, v)] = d[g][v];
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                d4v dv = d4v{0, 0, 0, 0};
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) dv = M::mma(ra[g][kk], mytr[bl * P + 4 * kk + rq], dv);
+                if (row < n) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Wout[row * P + 16 * g + M::drow(lane, v)] = dv[v];
+                }
+            }
+        } else if (Wout && row < n) {
 #pragma unroll
             for (int g = 0; g < 2; ++g)
 #pragma unroll
@@ -268,7 +301,7 @@ __global__ __launch_bounds__(256) void k_dot_wide(int64_t n, const double* __res
 // The next tile's operands are loaded while the current one waits at the
 // barrier and takes its dots.
 // ---------------------------------------------------------------------------
-template <int NQ>
+template <int NQ, bool GRAM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_proj_dot_wide(
     int64_t n, const double* __restrict__ Win, BlockPtrs Q, int nq, const zd* __restrict__ S,
     double* __restrict__ part, const Ctl* ctl, int rev) {
@@ -305,6 +338,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int g = 0; g < 2; ++g)
 #pragma unroll
         for (int i = 0; i < NCW; ++i) acc[g][i] = d4v{0, 0, 0, 0};
+    // GRAM: wave w takes the tile (w / 2, w % 2) of the 32 x 32 Gram W'^T W'
+    d4v gacc = d4v{0, 0, 0, 0};
+    const int g1 = wave >> 1, g2 = wave & 1;
     const int lw = logical_wg();
     int64_t t0, t1;
     tile_span((n + 15) / 16, lw, t0, t1);
@@ -391,10 +427,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
                     for (int g = 0; g < 2; ++g) acc[g][i] = M::mma(wa[ks][g], qr[i][ks], acc[g][i]);
             }
+        if constexpr (GRAM) {
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+                gacc = M::mma(g1 ? wa[ks][1] : wa[ks][0], g2 ? wa[ks][1] : wa[ks][0], gacc);
+        }
     }
     // accumulator [g][i] element v: W column 16 g + drow(l, v), Q column 16 ch_i + l % 16
     (void)red;
-    const int64_t nout = (int64_t)q * P;
+    const int64_t nout = (int64_t)q * P, stride = nout + (GRAM ? P * P : 0);
 #pragma unroll
     for (int i = 0; i < NCW; ++i) {
         const int c = 16 * chw[i] + bl;
@@ -402,8 +443,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int g = 0; g < 2; ++g)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) part[(int64_t)lw * nout + (int64_t)c * P + 16 * g + M::drow(lane, v)] = acc[g][i][v];
+                for (int v = 0; v < 4; ++v) part[(int64_t)lw * stride + (int64_t)c * P + 16 * g + M::drow(lane, v)] = acc[g][i][v];
         }
+    }
+    // Gram tile (g1, g2) element v: row 16 g1 + drow(l, v), column 16 g2 + l % 16, after the dots
+    if constexpr (GRAM) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            part[(int64_t)lw * stride + nout + (16 * g1 + M::drow(lane, v)) * P + 16 * g2 + bl] = gacc[v];
     }
 }
 
@@ -421,21 +468,20 @@ __global__ void k_cx_expand(const zd* __restrict__ S, int q, int P, double* __re
 }
 
 // out (q x P complex) = (add ? add : 0) + sum over the nwg workgroup partials
-// of the contraction of their real 2q x 2P matrices (part[wg][r 2P + s]),
-// the complex entries summed over the workgroups in a fixed order
-__global__ __launch_bounds__(256) void k_cx_reduce(const double* __restrict__ part, int nwg, int q, int P,
-                                                   const zd* __restrict__ add, zd* out, const Ctl* ctl) {
+// of the contraction of their real 2q x 2P matrices (part[wg stride + off +
+// r 2P + s]), the complex entries summed over the workgroups in a fixed order
+__global__ __launch_bounds__(256) void k_cx_reduce(const double* __restrict__ part, int nwg, int64_t stride, int64_t off,
+                                                   int q, int P, const zd* __restrict__ add, zd* out, const Ctl* ctl) {
     if (ctl && ctl->active == 0) return;
     __shared__ zd red[256];
     const int t = threadIdx.x, o = blockIdx.x * 16 + (t % 16), g = t / 16;
     const int nout = q * P, P2 = 2 * P;
-    const int64_t stride = (int64_t)4 * q * P;
     zd s = {0.0, 0.0};
     if (o < nout) {
         const int c = o / P, b = o % P;
         const int64_t i00 = (int64_t)(2 * c) * P2 + 2 * b, i10 = i00 + P2;
         for (int w = g; w < nwg; w += 16) {
-            const double* d = part + (int64_t)w * stride;
+            const double* d = part + (int64_t)w * stride + off;
             s.x += d[i00] + d[i10 + 1];
             s.y += d[i00 + 1] - d[i10];
         }
@@ -450,15 +496,16 @@ __global__ __launch_bounds__(256) void k_cx_reduce(const double* __restrict__ pa
 }
 
 // ---------------------------------------------------------------------------
-template <bool GRAM>
+template <bool GRAM, bool NORM = false>
 hipError_t launch_update_wide_t(hipStream_t st, int64_t n, const double* Win, const BlockPtrs& Q, int nq,
-                                const zd* S, double* Wout, double* part, int nwg, const Ctl* ctl, int step, bool rev) {
+                                const zd* S, double* Wout, double* part, int nwg, const Ctl* ctl, int step, bool rev,
+                                const zd* Rinv = nullptr) {
 #define L(NQ)                                                                                                      \
     case NQ: {                                                                                                     \
         const size_t lds = std::max((size_t)((NQ > 0 ? NQ : 1) * 512 + 4 * 16 * 32) * sizeof(double),             \
                                     (size_t)1024 * sizeof(double));                                                \
-        hipLaunchKernelGGL((k_update_wide<NQ, GRAM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, Wout, part, \
-                           ctl, step, (int)rev);                                                                   \
+        hipLaunchKernelGGL((k_update_wide<NQ, GRAM, NORM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, Wout, \
+                           part, Rinv, ctl, step, (int)rev);                                                       \
         break;                                                                                                     \
     }
     switch (nq) {
@@ -469,14 +516,15 @@ hipError_t launch_update_wide_t(hipStream_t st, int64_t n, const double* Win, co
     return hipGetLastError();
 }
 
-inline hipError_t launch_proj_dot_wide(hipStream_t st, int64_t n, const double* Win, const BlockPtrs& Q, int nq,
-                                       const zd* S, double* part, int nwg, const Ctl* ctl, bool rev) {
+template <bool GRAM>
+hipError_t launch_proj_dot_wide(hipStream_t st, int64_t n, const double* Win, const BlockPtrs& Q, int nq,
+                                const zd* S, double* part, int nwg, const Ctl* ctl, bool rev) {
 #define L(NQ)                                                                                                      \
     case NQ: {                                                                                                     \
         const size_t lds = (size_t)(NQ * 512 + 2 * 4 * 512 + 4 * 16 * 17) * sizeof(double);                       \
         static std::once_flag fl;                                                                                  \
-        std::call_once(fl, [] { allow_lds(k_proj_dot_wide<NQ>); });                                                \
-        hipLaunchKernelGGL((k_proj_dot_wide<NQ>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, part, ctl,      \
+        std::call_once(fl, [] { allow_lds(k_proj_dot_wide<NQ, GRAM>); });                                          \
+        hipLaunchKernelGGL((k_proj_dot_wide<NQ, GRAM>), dim3(nwg), dim3(256), lds, st, n, Win, Q, nq, S, part, ctl, \
                            (int)rev);                                                                              \
         break;                                                                                                     \
     }

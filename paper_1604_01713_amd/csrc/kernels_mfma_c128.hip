@@ -13,10 +13,11 @@ extern template hipError_t mfma_proj_gram<double>(hipStream_t, int, int64_t, con
                                                   const double*, double*, double*, const Ctl*, int, const double*,
                                                   int, bool);
 
-int cx_mfma_max_blocks(int P) {
+int cx_mfma_max_blocks(int P, bool pip) {
     // P = 8: the 16-column real sweeps (their second pass holds at most 14
-    // chunks of Q in LDS); P = 16: the 32-column sweeps, dispatched up to 12
-    return P == 8 ? 14 : (P == 16 ? 12 : 0);
+    // chunks of Q in LDS); P = 16: the 32-column sweeps, dispatched up to 12,
+    // the fused second pass (which the PIP order needs) up to 10
+    return P == 8 ? 14 : (P == 16 ? (pip ? 10 : 12) : 0);
 }
 
 static hipError_t expand(hipStream_t st, const zd* S, int q, int P, double* Sr, const Ctl* ctl) {
@@ -26,7 +27,7 @@ static hipError_t expand(hipStream_t st, const zd* S, int q, int P, double* Sr, 
 
 hipError_t cx_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, double* part,
                   const Ctl* ctl, int nwg, bool rev) {
-    if (nq < 1 || nq > cx_mfma_max_blocks(P)) return hipErrorNotSupported;
+    if (nq < 1 || nq > cx_mfma_max_blocks(P, false)) return hipErrorNotSupported;
     if (P == 8) {
         BlockPtrs Wp{};
         Wp.p[0] = W;
@@ -36,17 +37,18 @@ hipError_t cx_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs
 }
 
 hipError_t cx_proj_dot(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
-                       double* Sr, zd* Wtmp, double* part, const Ctl* ctl, int nwg) {
-    if (nq < 1 || nq > cx_mfma_max_blocks(P)) return hipErrorNotSupported;
+                       double* Sr, zd* Wtmp, double* part, const Ctl* ctl, int nwg, bool gram, bool rev) {
+    if (nq < 1 || nq > cx_mfma_max_blocks(P, gram)) return hipErrorNotSupported;
     if (P == 8) {
         const hipError_t e = expand(st, S, nq * P, P, Sr, ctl);
         if (e != hipSuccess) return e;
-        return mfma_proj_dot<double>(st, 16, n, (const double*)W, Q, nq, Sr, part, ctl, nwg, false, false);
+        return mfma_proj_dot<double>(st, 16, n, (const double*)W, Q, nq, Sr, part, ctl, nwg, gram, rev);
     }
     // one fused sweep up to 10 blocks in Q; beyond, W' is stored and dotted
-    // in a second sweep
-    const hipError_t f = mx::launch_proj_dot_wide(st, n, (const double*)W, Q, nq, S, part, nwg, ctl, true);
-    if (f != hipErrorNotSupported) return f;
+    // in a second sweep (no Gram)
+    const hipError_t f = gram ? mx::launch_proj_dot_wide<true>(st, n, (const double*)W, Q, nq, S, part, nwg, ctl, rev)
+                              : mx::launch_proj_dot_wide<false>(st, n, (const double*)W, Q, nq, S, part, nwg, ctl, rev);
+    if (f != hipErrorNotSupported || gram) return f;
     const hipError_t e = mx::launch_update_wide_t<false>(st, n, (const double*)W, Q, nq, S, (double*)Wtmp, nullptr,
                                                          nwg, ctl, -1, false);
     if (e != hipSuccess) return e;
@@ -55,7 +57,7 @@ hipError_t cx_proj_dot(hipStream_t st, int P, int64_t n, const zd* W, const Bloc
 
 hipError_t cx_proj_gram(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
                         double* Sr, zd* Wout, double* part, const Ctl* ctl, int nwg, int step) {
-    if (nq < 1 || nq > cx_mfma_max_blocks(P)) return hipErrorNotSupported;
+    if (nq < 1 || nq > cx_mfma_max_blocks(P, false)) return hipErrorNotSupported;
     if (P == 8) {
         const hipError_t e = expand(st, S, nq * P, P, Sr, ctl);
         if (e != hipSuccess) return e;
@@ -64,6 +66,25 @@ hipError_t cx_proj_gram(hipStream_t st, int P, int64_t n, const zd* W, const Blo
     }
     return mx::launch_update_wide_t<true>(st, n, (const double*)W, Q, nq, S, (double*)Wout, part, nwg, ctl, step,
                                           false);
+}
+
+hipError_t cx_proj_norm(hipStream_t st, int P, int64_t n, const zd* W, const BlockPtrs& Q, int nq, const zd* S,
+                        double* Sr, const zd* Rinv, zd* Vout, double* part, const Ctl* ctl, int nwg, int step,
+                        bool rev) {
+    if (nq < 1 || nq > cx_mfma_max_blocks(P, true)) return hipErrorNotSupported;
+    if (P == 8) {
+        // S and R^{-1} in real form: S_r, then the 16 x 16 R^{-1}_r after it
+        // (expanded whatever the control block says: the sweep also runs
+        // after the step that stopped the cycle, to store its V_{j+1})
+        double* Rr = Sr + (size_t)4 * nq * P * P;
+        hipError_t e = expand(st, S, nq * P, P, Sr, nullptr);
+        if (e == hipSuccess) e = expand(st, Rinv, P, P, Rr, nullptr);
+        if (e != hipSuccess) return e;
+        return mfma_proj_gram<double>(st, 16, n, (const double*)W, Q, nq, Sr, (double*)Vout, part, ctl, nwg, Rr, step,
+                                      rev);
+    }
+    return mx::launch_update_wide_t<false, true>(st, n, (const double*)W, Q, nq, S, (double*)Vout, nullptr, nwg, ctl,
+                                                 step, rev, Rinv);
 }
 
 hipError_t cx_combine(hipStream_t st, int P, int64_t n, const BlockPtrs& in, int nin, const BlockPtrs& out, int nout,
@@ -83,11 +104,17 @@ hipError_t cx_i_minus(hipStream_t st, const zd* M, zd* out, int P) {
     return hipGetLastError();
 }
 
+hipError_t cx_reduce_at(hipStream_t st, const double* part, int nwg, int64_t stride, int64_t off, int q, int P,
+                        const zd* add, zd* out, const Ctl* ctl) {
+    if (q * P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mx::k_cx_reduce, dim3((q * P + 15) / 16), dim3(256), 0, st, part, nwg, stride, off, q, P, add,
+                       out, ctl);
+    return hipGetLastError();
+}
+
 hipError_t cx_reduce(hipStream_t st, const double* part, int nwg, int q, int P, const zd* add, zd* out,
                      const Ctl* ctl) {
-    if (q * P <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mx::k_cx_reduce, dim3((q * P + 15) / 16), dim3(256), 0, st, part, nwg, q, P, add, out, ctl);
-    return hipGetLastError();
+    return cx_reduce_at(st, part, nwg, (int64_t)4 * q * P, 0, q, P, add, out, ctl);
 }
 
 }  // namespace bgcr

@@ -102,8 +102,8 @@ size_t part_outputs(int P, int KB, int qmax, bool cplx) {
     // the second pass of a block step writes its dots and the new block's Gram
     const size_t o = std::max({(size_t)qmax * P + (size_t)P * P, (size_t)KB * P * P, wg * qmax * P});
     // complex sweeps on matrix cores write the real 2q x 2P products (twice
-    // the complex entries)
-    return cplx ? std::max(o, 2 * (size_t)qmax * P) : o;
+    // the complex entries), the second pass followed by the real Gram
+    return cplx ? std::max(o, 2 * ((size_t)qmax * P + (size_t)P * P)) : o;
 }
 
 Sizes sizes_of(const bgcr_params* prm, int64_t n) {
@@ -128,7 +128,7 @@ Sizes sizes_of(const bgcr_params* prm, int64_t n) {
                        m1p * z.P + (size_t)(z.m + 1) * z.P * z.P + 2 * (size_t)z.P * z.P +
                        (size_t)(2 * z.KB + z.m + 1) * z.P * (2 * std::max(z.KP, z.P) + 2 * z.P)) +
                sizeof(double) * ((size_t)z.m + (size_t)NWG_MAX * 2 * z.P) + sizeof(Ctl) +
-               (cplx ? sizeof(double) * 4 * (size_t)(z.KB + z.m) * z.P * z.P : 0);
+               (cplx ? sizeof(double) * 4 * (size_t)(z.KB + z.m + 1) * z.P * z.P : 0);
     const bool enlarged = z.P > prm->p;
     z.total_fixed = z.basis + 3 * (size_t)n * z.P * z.sw /* W2, Wb, R */ +
                     (size_t)n * z.P * z.sa * (enlarged ? 2 : 1) /* X (and B padded) */ + z.recyc + z.part + z.small_;
@@ -169,6 +169,7 @@ struct Seq final : bgcr_sequence {
     bool mx_dot = false; // dot sweeps on matrix cores (also narrow real blocks, P < 8)
     bool mx_upd = false; // update sweeps on matrix cores (also P = 4, without the PIP step order)
     bool cx_mx = false;  // complex block-CGS sweeps on the FP64 matrix cores (P = 8 or 16)
+    bool pip_order = false;  // block steps in the PIP order (V_{j+1} stored normalised by the third sweep)
     double* Sr = nullptr;  // real form of a complex coefficient matrix (cx_mx, P = 8)
     bool mixed, cplx;
     hipStream_t st;
@@ -313,7 +314,8 @@ struct Seq final : bgcr_sequence {
         mx_dot = use_mx || (realb && !off && P < 8);
         mx_upd = use_mx || (realb && !off && P == 4 && (KB + m) * P <= 256);
         fuse_dots = use_mx && std::is_same<T, double>::value && !half;
-        cx_mx = !off && std::is_same<T, zd>::value && (P == 8 || P == 16) && KB + m <= cx_mfma_max_blocks(P);
+        cx_mx = !off && std::is_same<T, zd>::value && (P == 8 || P == 16) && KB + m <= cx_mfma_max_blocks(P, false);
+        pip_order = use_mx || (cx_mx && KB + m <= cx_mfma_max_blocks(P, true));
         // BF16 basis blocks have matrix-core kernels only; every basis
         // combination has to fit one launch (at most 64 output columns)
         if (half && (!use_mx || 2 * KP > 64 ||
@@ -363,7 +365,7 @@ struct Seq final : bgcr_sequence {
         S1 = dalloc<A>((size_t)qmax * P);
         dots_cap = (size_t)qmax * P * std::max(KB, 1);
         Sf = dalloc<A>((size_t)qmax * P + (size_t)P * P);  // [S1 + S2 | W'^H W']
-        if (cx_mx) Sr = dalloc<double>(4 * (size_t)(KB + m) * P * P);
+        if (cx_mx) Sr = dalloc<double>(4 * (size_t)(KB + m + 1) * P * P);  // S_r, then R^{-1}_r
         const size_t mp = (size_t)m * P, m1p = (size_t)(m + 1) * P;
         // everything the host reads at the end of a cycle, contiguous so that
         // one copy brings it over: control block, H and its triangular factor,
@@ -562,7 +564,7 @@ struct Seq final : bgcr_sequence {
             const int wn = std::min(wg, nw - w0);
             const int ng = (wn * P + 15) / 16;
             const int chunk = mxd   ? std::max(1, std::min((ng == 2 ? 9 : 16) * 16 / P, MAXB))
-                              : cxd ? cx_mfma_max_blocks(P)
+                              : cxd ? cx_mfma_max_blocks(P, false)
                                     : std::max(1, (MAXI * NT) / (P * P));
             for (int q0 = 0; q0 < nq; q0 += chunk) {
                 const int qn = std::min(chunk, nq - q0);
@@ -1101,7 +1103,7 @@ struct Seq final : bgcr_sequence {
         // (W''^H W'' = W'^H W' - S2^H S2), so its Cholesky factor is known
         // before sweep 3, which then stores V_{j+1} = W'' R_j^{-1} directly;
         // the SpMM of the next step gathers V_{j+1} without normalising.
-        const bool pip = use_mx;
+        const bool pip = pip_order;
         for (int j = 1; j <= m; ++j) {
             cur_step = j;
             std::vector<const void*> Q;
@@ -1184,7 +1186,7 @@ struct Seq final : bgcr_sequence {
                 if constexpr (!std::is_same<T, zd>::value) {
                     if (mx_dot) return mfma_dot<T, T, TB>(st, P, n, bp({Wb}), 1, QB, nq + 1, part, ctl, na, alt_dir && pip);
                 } else {
-                    if (cx_mx) return cx_dot(st, P, n, Wb, QB, nq + 1, (double*)part, ctl, na, false);
+                    if (cx_mx) return cx_dot(st, P, n, Wb, QB, nq + 1, (double*)part, ctl, na, alt_dir && pip);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, nullptr, nullptr, nullptr, 1, 0, part, na, ctl, 0);
             });
@@ -1205,14 +1207,27 @@ struct Seq final : bgcr_sequence {
                         return mfma_proj_dot<T, TB>(st, P, n, Wb, QB, nq + 1, S1, part, ctl, na, pip,
                                                     alt_dir && fused);
                 } else {
-                    // (P = 16 stores W' in W2, which the SpMM has consumed)
-                    if (cx_mx) return cx_proj_dot(st, P, n, Wb, QB, nq + 1, S1, Sr, W2, (double*)part, ctl, na);
+                    // (P = 16 with more than 10 blocks in Q stores W' in W2, which
+                    // the SpMM has consumed)
+                    if (cx_mx)
+                        return cx_proj_dot(st, P, n, Wb, QB, nq + 1, S1, Sr, W2, (double*)part, ctl, na, pip, false);
                 }
                 return L::update_dot(st, P, n, Wb, QB, nq + 1, S1, nullptr, nullptr, 1, 0, part, na, ctl, 1);
             });
             if (pip) {
                 run(BGCR_K_SMALL, 0.0, [&] {
-                    HIPCHK(reduce_partials<A>(st, part, na, nout + P2, S1, Sf, ctl, nout));
+                    bool done = false;
+                    if constexpr (std::is_same<A, zd>::value) {
+                        if (cx_mx) {
+                            // real partials [dots 4 q P | Gram 4 P P] per workgroup
+                            const int64_t qd = (int64_t)(nq + 1) * P, stride = 4 * qd * P + 4 * (int64_t)P2;
+                            HIPCHK(cx_reduce_at(st, (const double*)part, na, stride, 0, (int)qd, P, S1, Sf, ctl));
+                            HIPCHK(cx_reduce_at(st, (const double*)part, na, stride, 4 * qd * P, P, P, nullptr,
+                                                Sf + nout, ctl));
+                            done = true;
+                        }
+                    }
+                    if (!done) HIPCHK(reduce_partials<A>(st, part, na, nout + P2, S1, Sf, ctl, nout));
                     return step_small<A>(st, P, Sf + nout, Sf, S1, ncb * P, j, m, H, F, Rh, QH, g, RinvAll, rho, ctl,
                                          thresh);
                 });
@@ -1221,8 +1236,10 @@ struct Seq final : bgcr_sequence {
                         return mfma_proj_gram<T, TB, TB>(st, P, n, Wb, QB, nq + 1, Sf, vblk(j), part, ctl, na,
                                                          (const double*)(RinvAll + (size_t)j * P2), j,
                                                          alt_dir && !fused);
+                    } else {
+                        return cx_proj_norm(st, P, n, Wb, QB, nq + 1, Sf, Sr, RinvAll + (size_t)j * P2, vblk(j),
+                                            (double*)part, ctl, na, j, alt_dir);
                     }
-                    return hipErrorNotSupported;
                 });
                 continue;
             }
@@ -1263,7 +1280,7 @@ struct Seq final : bgcr_sequence {
         // blocks (see norm_first) and becomes the cycle's last block; when the
         // cycle stopped earlier, the block of that step is stored after the
         // copy below.
-        const bool norm_last = std::is_same<T, A>::value && !use_mx && P > 1;
+        const bool norm_last = std::is_same<T, A>::value && !pip && P > 1;
         if constexpr (std::is_same<T, A>::value) {
             if (norm_last)
                 run(BGCR_K_COMBINE, vblkb + blkb, [&] {
@@ -1277,7 +1294,7 @@ struct Seq final : bgcr_sequence {
             for (int b = 0; b < KB; ++b) Qs.push_back(ublk(cur, b));
             for (int b = 0; b < KB; ++b) Qs.push_back(cblk(cur, b));
             for (int i = 0; i < m; ++i) Qs.push_back(vblk(i));
-            Qs.push_back((use_mx || norm_last) ? (const void*)vblk(m) : (const void*)W2);
+            Qs.push_back((pip || norm_last) ? (const void*)vblk(m) : (const void*)W2);
             for (int b = 0; b < KB; ++b) Ws.push_back(ublk(cur, b));
             spec = dot_enqueue(Qs, Ws);
         }
@@ -1322,7 +1339,7 @@ struct Seq final : bgcr_sequence {
             for (int i = 0; i < KP; ++i)
                 for (int j = 0; j < mp; ++j) co.F(i, j) = to_cd(hF[(size_t)i * ldH + j]);
         co.RinvLast = Mat(P, P);
-        if (use_mx) {
+        if (pip) {
             // V_{meff+1} was stored normalised by sweep 3 of step meff (or of the last good step)
             co.last = vblk(me);
             co.RinvLast = Mat::eye(P);
@@ -1882,10 +1899,10 @@ struct Seq final : bgcr_sequence {
         auto enqueue = [&] {
             residual_enqueue(Am, B, ldb, nullptr);
             queued = true;
-            // the prologue writes the start block into W2, which off matrix
-            // cores still holds V_{m+1} for the refresh, and an enlarged start
-            // block is projected against the refreshed C: there it waits
-            if (use_mx && P == pu) {
+            // the prologue writes the start block into W2, which off the PIP
+            // order may still hold V_{m+1} for the refresh, and an enlarged
+            // start block is projected against the refreshed C: there it waits
+            if (pip_order && P == pu) {
                 cycle_prologue(false);  // wasted once per system, on the converged cycle
                 prologued = true;
             }
