@@ -57,6 +57,25 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def stream_ceiling(torch, bg, dev, count, reads, writes, reps=20):
+    """Streaming rate (GB/s) that the memory system sustains for `reads` read
+    and `writes` written FP64 blocks of `count` elements, with the row-tile
+    schedule of the sweeps (library probe; HIP events on the launch stream)."""
+    ins = [torch.ones(count, dtype=torch.float64, device=dev) for _ in range(reads)]
+    outs = [torch.empty(count, dtype=torch.float64, device=dev) for _ in range(writes)]
+    for _ in range(3):
+        bg.bgcr_stream_probe(ins, outs)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        bg.bgcr_stream_probe(ins, outs)
+    e1.record()
+    e1.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    del ins, outs
+    return round(8.0 * count * (reads + writes) / (us * 1e3), 1)
+
+
 def load_traffic(kernel, workload):
     """HBM traffic per launch from the committed rocprofv3 PMC summary, if it was
     taken on the current kernel source."""
@@ -749,6 +768,7 @@ def main():
 
     roof = None
     arnoldi = None
+    stream = None
     if prof_sum:
         dom = max(ARNOLDI, key=lambda c: prof_sum[c]["ms"])
         d = prof_sum[dom]
@@ -758,6 +778,15 @@ def main():
                 "kernel": KERNEL_SYMBOL[dom], "launches": d["launches"],
                 "avg_launch_us": round(1e3 * d["ms"] / max(1, d["launches"]), 2),
                 "alg_bytes_per_launch": round(d["bytes"] / max(1, d["launches"]))}
+        # what a plain streaming kernel with the same schedule sustains for the
+        # dominant kernel's mix of read and written n x p blocks
+        blk = 8.0 * n * w.p
+        wr = 1
+        rd = max(1, min(16, int(round(roof["alg_bytes_per_launch"] / blk)) - wr))
+        ceil_rw = stream_ceiling(torch, bg, dev, n * w.p, rd, wr)
+        stream = {"reads": rd, "writes": wr, "GBs": ceil_rw,
+                  "kernel_frac_of_stream": round(ach / ceil_rw, 4) if ceil_rw > 0 else None,
+                  "read_only_GBs": stream_ceiling(torch, bg, dev, n * w.p, rd, 0)}
         tb = sum(prof_sum[c]["bytes"] for c in ARNOLDI)
         tm = sum(prof_sum[c]["ms"] for c in ARNOLDI)
         gpu = {c: v for c, v in prof_sum.items() if not c.startswith("host")}
@@ -799,6 +828,7 @@ def main():
         "max_rel_res_fp64_check": worst,
         "arnoldi_hbm": arnoldi,
         "roofline": roof,
+        "stream_ceiling": stream,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

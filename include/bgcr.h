@@ -287,6 +287,20 @@ int bgcr_set_profiling(bgcr_sequence* s, int on);
 int bgcr_get_profile(const bgcr_sequence* s, double* ms, double* bytes, int64_t* launches,
                      int32_t nclass);
 
+/* Measurement aid (not a step of the method): the streaming rate the memory
+ * system sustains for a mix of read and written FP64 blocks, with the row-tile
+ * schedule of the block-step sweeps (XCD-aware contiguous row spans, 16-byte
+ * accesses).  Every out[o][i] = sum over b of in[b][i], for i < count.
+ *   in:    host array of nin device pointers (1 <= nin <= 16), 16-byte aligned.
+ *   out:   host array of nout device pointers (0 <= nout <= 4), 16-byte aligned,
+ *          not aliasing any input; may be NULL when nout is 0.
+ *   count: doubles per block, even (0: nothing is launched).
+ *   nwg:   workgroups (0: 512, the grid of the sweeps); capped at the tile count.
+ * Asynchronous on hip_stream (may be NULL).  INVALID for bad arguments, HIP
+ * when the launch fails. */
+int bgcr_stream_probe(const double* const* in, int32_t nin, double* const* out, int32_t nout,
+                      int64_t count, int32_t nwg, void* hip_stream);
+
 /* Human-readable text of a status code (static storage). */
 const char* bgcr_strerror(int status);
 

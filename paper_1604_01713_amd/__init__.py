@@ -18,7 +18,7 @@ __all__ = [
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_strerror",
     "bgcr_set_profiling", "bgcr_get_profile", "bgcr_apply_projected", "bgcr_apply_projected_work_bytes",
-    "bgcr_apply_projected_noalloc", "BGCR_NOALLOC_SCRATCH_BYTES", "KERNEL_CLASSES",
+    "bgcr_apply_projected_noalloc", "bgcr_stream_probe", "BGCR_NOALLOC_SCRATCH_BYTES", "KERNEL_CLASSES",
     "DeviceCSR", "Sequence", "EXPORTED_SYMBOLS",
 ]
 
@@ -44,7 +44,7 @@ EXPORTED_SYMBOLS = [
     "bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_footprint_bytes", "bgcr_recycle_dim",
     "bgcr_get_recycle", "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_set_profiling",
     "bgcr_get_profile", "bgcr_strerror", "bgcr_apply_projected", "bgcr_apply_projected_work_bytes",
-    "bgcr_apply_projected_noalloc",
+    "bgcr_apply_projected_noalloc", "bgcr_stream_probe",
 ]
 
 # bytes of the library's own workspace of bgcr_apply_projected_noalloc (bgcr.h)
@@ -115,11 +115,14 @@ def lib():
         L.bgcr_set_profiling.argtypes = [c.c_void_p, c.c_int]
         L.bgcr_get_profile.argtypes = [c.c_void_p, c.POINTER(c.c_double), c.POINTER(c.c_double),
                                        c.POINTER(c.c_int64), c.c_int32]
+        L.bgcr_stream_probe.argtypes = [c.POINTER(c.c_void_p), c.c_int32, c.POINTER(c.c_void_p), c.c_int32,
+                                        c.c_int64, c.c_int32, c.c_void_p]
         L.bgcr_strerror.argtypes = [c.c_int]
         L.bgcr_strerror.restype = c.c_char_p
         for name in ["bgcr_create_sequence", "bgcr_solve", "bgcr_release", "bgcr_recycle_dim", "bgcr_get_recycle",
                      "bgcr_set_recycle", "bgcr_get_cycle_log", "bgcr_spmm", "bgcr_set_profiling",
-                     "bgcr_get_profile", "bgcr_apply_projected", "bgcr_apply_projected_noalloc"]:
+                     "bgcr_get_profile", "bgcr_apply_projected", "bgcr_apply_projected_noalloc",
+                     "bgcr_stream_probe"]:
             getattr(L, name).restype = c.c_int
         _lib = L
     return _lib
@@ -224,6 +227,20 @@ def bgcr_apply_projected_noalloc(A: "DeviceCSR", C, V, W, variant: int, stream=N
     _check(lib().bgcr_apply_projected_noalloc(ctypes.byref(A.csr), p, kc, None if C is None else _ptr(C), _ptr(V),
                                               _ptr(W), int(variant), _stream_handle(stream)),
            "bgcr_apply_projected_noalloc")
+
+
+def bgcr_stream_probe(ins, outs, nwg: int = 0, stream=None):
+    """Streaming-rate probe (a measurement aid): every tensor of outs receives
+    the elementwise sum of the tensors of ins; all are contiguous FP64 device
+    tensors of one even number of elements."""
+    count = int(ins[0].numel())
+    for t in list(ins) + list(outs):
+        if t.dtype.itemsize != 8 or t.is_complex() or not t.is_contiguous() or int(t.numel()) != count:
+            raise ValueError("bgcr_stream_probe: contiguous FP64 tensors of one size")
+    ip = (ctypes.c_void_p * len(ins))(*[t.data_ptr() for t in ins])
+    op = (ctypes.c_void_p * max(1, len(outs)))(*([t.data_ptr() for t in outs] or [0]))
+    _check(lib().bgcr_stream_probe(ip, len(ins), op if outs else None, len(outs), count, int(nwg),
+                                   _stream_handle(stream)), "bgcr_stream_probe")
 
 
 def bgcr_set_profiling(seq, on: bool):

@@ -27,7 +27,7 @@ HIP_FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", "-fcx-limit
 CXX_FLAGS = ["-O3", "-fPIC", "-std=c++17", "-march=x86-64-v3", "-fcx-limited-range", "-fopenmp", "-I", INCLUDE, "-I", CSRC]
 
 HIP_SOURCES = ["kernels.hip", "kernels_mfma_f64.hip", "kernels_mfma_f32.hip", "kernels_mfma_bf16.hip",
-               "kernels_mfma_c128.hip", "ilu.hip",
+               "kernels_mfma_c128.hip", "ilu.hip", "stream_probe.hip",
                "solver.cpp"]
 CXX_SOURCES = ["dense.cpp"]
 

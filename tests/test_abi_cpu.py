@@ -189,3 +189,23 @@ def test_generators_follow_their_recipes():
     H = problems.helmholtz2d(8, 20.0)
     assert H.dtype == np.complex128
     assert H[0, 0] == pytest.approx(4 * 81 - 400 * (1 - 0.5j))
+
+
+def test_stream_probe_arguments_without_gpu(lib):
+    """The streaming-rate probe validates its arguments before any device call:
+    1..16 inputs, 0..4 outputs, an even element count, 16-byte alignment."""
+    sp = lib.bgcr_stream_probe
+    P = ctypes.c_void_p
+    ins = (P * 2)(P(0x1000), P(0x2000))
+    outs = (P * 1)(P(0x3000))
+    assert sp(None, 1, None, 0, 16, 0, None) == bg.BGCR_ERR_INVALID
+    assert sp(ins, 0, None, 0, 16, 0, None) == bg.BGCR_ERR_INVALID
+    assert sp(ins, 17, None, 0, 16, 0, None) == bg.BGCR_ERR_INVALID
+    assert sp(ins, 2, outs, 5, 16, 0, None) == bg.BGCR_ERR_INVALID
+    assert sp(ins, 2, None, 1, 16, 0, None) == bg.BGCR_ERR_INVALID
+    assert sp(ins, 2, outs, 1, 15, 0, None) == bg.BGCR_ERR_INVALID
+    assert sp(ins, 2, outs, 1, 16, -1, None) == bg.BGCR_ERR_INVALID
+    odd = (P * 1)(P(0x1008))
+    assert sp(odd, 1, outs, 1, 16, 0, None) == bg.BGCR_ERR_INVALID
+    # nothing to stream: accepted without a launch
+    assert sp(ins, 2, outs, 1, 0, 0, None) == bg.BGCR_OK
