@@ -42,12 +42,14 @@ def log(*a):
 # the device sources of the real FP64 block-step sweeps of the headline
 # workload (the SpMM, the fused SpMM + dots and the matrix-core sweeps are
 # defined in these files; the others only instantiate them)
-FP64_KERNEL_SOURCES = ("bgcr_internal.h", "kernels_mfma_f64.hip", "mfma_sweeps.h", "spmm_sweep.h")
+FP64_KERNEL_SOURCES = ("bgcr_internal.h", "kernels_mfma_f64.hip", "mfma_sweeps.h", "spmm_sweep.h", "solver.cpp")
 
 
 def kernel_source_hash():
-    """Hash of the device sources of the real FP64 block-step kernels; a
-    committed PMC traffic figure is used only while it matches."""
+    """Hash of the sources of the real FP64 block-step kernels and of the
+    cycle driver that sets their launch mix (the per-launch traffic is an
+    average over it); a committed PMC traffic figure is used only while it
+    matches."""
     h = hashlib.sha256()
     cs = os.path.join(ROOT, "paper_1604_01713_amd", "csrc")
     for f in FP64_KERNEL_SOURCES:

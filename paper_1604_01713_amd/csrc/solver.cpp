@@ -1125,11 +1125,18 @@ struct Seq final : bgcr_sequence {
             // (A W2) R^{-1} would satisfy the Arnoldi relation only to rounding
             // times cond(R_{j-1}), which an almost rank-deficient block makes
             // large (complex Helmholtz: |A U - C| / |C| 1e-10 against the
-            // oracle's 5e-14).  Step 1 keeps the scaled SpMM: its factor is the
-            // second CholQR2 pass, close to the identity.
+            // oracle's 5e-14).  Step 1 off the fused sweep keeps the scaled
+            // SpMM: its factor is the second CholQR2 pass, close to the identity.
             const bool norm_first = std::is_same<T, A>::value && !pip && j > 1 && P > 1;
+            // sweeps 1a and 1b in one pass (FP64 on matrix cores): from step 2
+            // V_j is stored, normalised, by the previous step's third sweep; at
+            // step 1, V_1 = W2 R^{-1} is stored first
+            std::vector<const void*> Qd(Q);
+            Qd.push_back(vblk(j - 1));
+            const double qbytes = sB * n * (kc + (double)j * P);
+            const bool fused = fuse_dots && pip && ((int)Qd.size() * P + 15) / 16 <= 12;
             if constexpr (std::is_same<T, A>::value) {
-                if (pc || norm_first) {
+                if (pc || norm_first || (fused && j == 1)) {
                     // V_j as a stored block (off matrix cores, and at j = 1, it
                     // is W2 R^{-1}); with a preconditioner then M^{-1} V_j into
                     // Zb, which the SpMM reads
@@ -1141,12 +1148,6 @@ struct Seq final : bgcr_sequence {
                     if (pc) apply_minv((const T*)vblk(j - 1), ctl);
                 }
             }
-            // sweeps 1a and 1b in one pass (FP64 on matrix cores, from step 2:
-            // V_j is stored, normalised, by the previous step's third sweep)
-            std::vector<const void*> Qd(Q);
-            Qd.push_back(vblk(j - 1));
-            const double qbytes = sB * n * (kc + (double)j * P);
-            const bool fused = fuse_dots && pip && j > 1 && ((int)Qd.size() * P + 15) / 16 <= 12;
             if (fused) {
                 run(BGCR_K_ARN_SPMM_DOT, abytes + vblkb + blkb + qbytes, [&] {
                     if constexpr (std::is_same<T, double>::value && !half) {
