@@ -196,6 +196,7 @@ struct Seq final : bgcr_sequence {
     unsigned char* hbuf = nullptr;
     size_t hcap = 0, hoff = 0;
     double* rbuf = nullptr;  // pinned: residual partials copied back while the host works
+    hipEvent_t ev_res = nullptr;  // recorded after the copy of the residual partials
     int cur = 0, keff = 0;
     // per-solve counters
     int n_spmm = 0, n_steps = 0, n_cycles = 0, n_refine = 0;
@@ -331,6 +332,7 @@ struct Seq final : bgcr_sequence {
             (void)hipEventDestroy(q.b);
         }
         for (hipEvent_t e : evfree) (void)hipEventDestroy(e);
+        if (ev_res) (void)hipEventDestroy(ev_res);
         for (void* p : allocs) (void)hipFree(p);
         if (hbuf) (void)hipHostFree(hbuf);
         if (rbuf) (void)hipHostFree(rbuf);
@@ -632,10 +634,15 @@ struct Seq final : bgcr_sequence {
                                   dpart, nwg);
         });
         HIPCHK(hipMemcpyAsync(rbuf, dpart, (size_t)nwg * 2 * P * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (!ev_res) HIPCHK(hipEventCreateWithFlags(&ev_res, hipEventDisableTiming));
+        HIPCHK(hipEventRecord(ev_res, st));
         ++n_spmm;
     }
+    // waits for the partials only: work queued after them (the refresh
+    // combination, the next prologue) keeps the device busy while the host
+    // decides and queues the next cycle
     void residual_collect(std::vector<double>& rn2, std::vector<double>& bn2) {
-        sync();
+        HIPCHK(hipEventSynchronize(ev_res));
         rn2.assign(P, 0.0);
         bn2.assign(P, 0.0);
         for (int w = 0; w < nwg; ++w)
