@@ -197,6 +197,8 @@ struct Seq final : bgcr_sequence {
     size_t hcap = 0, hoff = 0;
     double* rbuf = nullptr;  // pinned: residual partials copied back while the host works
     hipEvent_t ev_res = nullptr;  // recorded after the copy of the residual partials
+    A* dbuf = nullptr;               // pinned: the refresh dots, copied back after the steps' results
+    hipEvent_t ev_cyc = nullptr, ev_dots = nullptr;  // after the copies of the steps' results, of the dots
     int cur = 0, keff = 0;
     // per-solve counters
     int n_spmm = 0, n_steps = 0, n_cycles = 0, n_refine = 0;
@@ -333,6 +335,9 @@ struct Seq final : bgcr_sequence {
         }
         for (hipEvent_t e : evfree) (void)hipEventDestroy(e);
         if (ev_res) (void)hipEventDestroy(ev_res);
+        if (ev_cyc) (void)hipEventDestroy(ev_cyc);
+        if (ev_dots) (void)hipEventDestroy(ev_dots);
+        if (dbuf) (void)hipHostFree(dbuf);
         for (void* p : allocs) (void)hipFree(p);
         if (hbuf) (void)hipHostFree(hbuf);
         if (rbuf) (void)hipHostFree(rbuf);
@@ -407,6 +412,10 @@ struct Seq final : bgcr_sequence {
         }
         hcap = std::max({(size_t)4 << 20, 2 * coef_cap * sizeof(A) + (64 << 10), hr_bytes + (64 << 10)});
         if (hipHostMalloc((void**)&hbuf, hcap, hipHostMallocDefault) != hipSuccess) throw Fail{BGCR_ERR_NOMEM};
+        if (hipHostMalloc((void**)&dbuf, std::max<size_t>(1, dots_cap) * sizeof(A), hipHostMallocDefault) != hipSuccess)
+            throw Fail{BGCR_ERR_NOMEM};
+        HIPCHK(hipEventCreateWithFlags(&ev_cyc, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev_dots, hipEventDisableTiming));
         if (hipHostMalloc((void**)&rbuf, (size_t)NWG_MAX * 2 * P * sizeof(double), hipHostMallocDefault) != hipSuccess)
             throw Fail{BGCR_ERR_NOMEM};
         HIPCHK(hipMemsetAsync(ctl, 0, sizeof(Ctl), st));
@@ -893,7 +902,7 @@ struct Seq final : bgcr_sequence {
         int meff = 0;
         bool breakdown = false;
         bool has_dots = false;  // refresh dots [U, C, V_1..V_m, V_{m+1}]^H U taken with the cycle
-        Mat Dm;
+        DotJob spec;            // their layout; the values arrive in dbuf (event ev_dots)
         Mat H, F, Y, RinvLast;
         const void* last = nullptr;  // block holding V_{meff+1} up to RinvLast
     };
@@ -1295,6 +1304,14 @@ struct Seq final : bgcr_sequence {
                     return rows_times<T>(st, P, n, (const T*)W2, RinvAll + (size_t)m * P2, (T*)vblk(m), nullptr);
                 });
         }
+        // The steps' results are copied back first and the dots after them, into
+        // a buffer of their own: the host reads the results and queues the
+        // solution update while the dots run, and waits for the dots only when
+        // the refresh needs them.  (Stream order puts the first copy after
+        // every staged upload that reads hbuf; nothing is staged between the
+        // copy and its event.)
+        HIPCHK(hipMemcpyAsync(hbuf, hr, off_dots, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(ev_cyc, st));
         DotJob spec;
         if (withC && k > 0) {
             std::vector<const void*> Qs;
@@ -1305,11 +1322,10 @@ struct Seq final : bgcr_sequence {
             Qs.push_back((pip || norm_last) ? (const void*)vblk(m) : (const void*)W2);
             for (int b = 0; b < KB; ++b) Ws.push_back(ublk(cur, b));
             spec = dot_enqueue(Qs, Ws);
+            HIPCHK(hipMemcpyAsync(dbuf, dots, spec.total * sizeof(A), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(ev_dots, st));
         }
-        // (stream order puts the copy after every staged upload that reads hbuf)
-        const size_t nread = off_dots + (spec.valid ? spec.total * sizeof(A) : 0);
-        HIPCHK(hipMemcpyAsync(hbuf, hr, nread, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipEventSynchronize(ev_cyc));
         hoff = 0;
         Ctl hc;
         std::memcpy(&hc, hbuf, sizeof(Ctl));
@@ -1330,7 +1346,7 @@ struct Seq final : bgcr_sequence {
         const int me = co.meff, mp = me * P, ldH = m * P;
         HostPhase hp(this, BGCR_K_HOST);
         if (spec.valid && me == m && !co.breakdown) {
-            co.Dm = dot_collect(spec, (const A*)(hbuf + off_dots));
+            co.spec = spec;
             co.has_dots = true;
         }
         co.H = Mat((me + 1) * P, mp);
@@ -1694,7 +1710,13 @@ struct Seq final : bgcr_sequence {
         for (int i = 0; i < me; ++i) Q.push_back(vblk(i));
         Q.push_back(co.last);
         for (int b = 0; b < KB; ++b) W.push_back(ublk(cur, b));
-        const Mat Dm = co.has_dots ? co.Dm : multi_dot(Q, W);
+        Mat Dm;
+        if (co.has_dots) {
+            HIPCHK(hipEventSynchronize(ev_dots));
+            Dm = dot_collect(co.spec, dbuf);
+        } else {
+            Dm = multi_dot(Q, W);
+        }
         std::unique_ptr<HostPhase> hp(new HostPhase(this, BGCR_K_HOST));
         const int ke = keff;
         std::vector<double> d(ke);
