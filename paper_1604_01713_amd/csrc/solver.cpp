@@ -1628,14 +1628,33 @@ struct Seq final : bgcr_sequence {
     // theta = 1/mu, t = Rg^{-1} s.  G = [[D, F], [0, H_m]] (or H_m) has lower
     // bandwidth P: D is diagonal and the subdiagonal blocks R_j of the block
     // Hessenberg H_m are upper triangular.
+    // QR of G (lower bandwidth p) and the inverse of its triangular factor
+    struct GFactor {
+        Mat Qg, Rgi;
+    };
+    GFactor factor_g(const Mat& G) {
+        GFactor f;
+        Mat Rg;
+        dense::qr_pos(G, f.Qg, Rg, P);
+        for (int i = 0; i < G.c; ++i)
+            if (!(std::abs(Rg(i, i)) > 0.0)) throw Fail{BGCR_ERR_NUMERICAL};
+        f.Rgi = dense::tri_inv_upper(Rg);
+        return f;
+    }
+
     void gen_harmonic(const Mat& G, const Mat& M, int kt, std::vector<cd>& theta, dense::Selection& sel,
                       std::vector<std::vector<cd>>& vecs, bool robust) {
-        Mat Qg, Rg;
-        dense::qr_pos(G, Qg, Rg, P);
-        const int nn = G.c;
-        for (int i = 0; i < nn; ++i)
-            if (!(std::abs(Rg(i, i)) > 0.0)) throw Fail{BGCR_ERR_NUMERICAL};
-        const Mat Rgi = dense::tri_inv_upper(Rg);
+        gen_harmonic(factor_g(G), M, nullptr, kt, theta, sel, vecs, robust);
+    }
+
+    // With `colscale`, G = G' diag(colscale^{-1}, 1, ..) is given by the factors
+    // of G' and M by M diag(colscale, 1, ..) (its leading columns unscaled):
+    // K is the same matrix, and t = diag(colscale, 1, ..) R'^{-1} s.
+    void gen_harmonic(const GFactor& gf, const Mat& M, const std::vector<double>* colscale, int kt,
+                      std::vector<cd>& theta, dense::Selection& sel, std::vector<std::vector<cd>>& vecs, bool robust) {
+        const Mat& Qg = gf.Qg;
+        const Mat& Rgi = gf.Rgi;
+        const int nn = Rgi.c;
         // K = Qg^H M Rg^{-1}.  The columns of M that are unit vectors e_r (its
         // identity block W_{m+1}^H W_m) give row r of Qg, conjugated, without a
         // product; the rest are dot products.  Rg^{-1} is upper triangular.
@@ -1674,6 +1693,8 @@ struct Seq final : bgcr_sequence {
             std::vector<cd> tv(nn, cd(0.0, 0.0));
             for (int r = 0; r < nn; ++r)
                 for (int c = r; c < nn; ++c) tv[r] += Rgi(r, c) * sv[c];
+            if (colscale)
+                for (size_t r = 0; r < colscale->size(); ++r) tv[r] *= (*colscale)[r];
             vecs.push_back(tv);
         }
     }
@@ -1710,6 +1731,22 @@ struct Seq final : bgcr_sequence {
         for (int i = 0; i < me; ++i) Q.push_back(vblk(i));
         Q.push_back(co.last);
         for (int b = 0; b < KB; ++b) W.push_back(ublk(cur, b));
+        const int ke = keff;
+        const int rows = ke + (me + 1) * P, cols = ke + mp;
+        const bool harmonic = !prm.ritz_vectors;
+        // G = [D F; 0 H] = [I F; 0 H] diag(D, I) with D = diag(1 / |u_i|): the
+        // QR of the first factor needs no dots, so it is taken while they are
+        // on their way (the harmonic problem then uses M diag(D^{-1}, I))
+        GFactor gf;
+        if (harmonic) {
+            HostPhase hp0(this, BGCR_K_HOST);
+            Mat G1(rows, cols);
+            for (int i = 0; i < ke; ++i) G1(i, i) = 1.0;
+            for (int i = 0; i < ke; ++i)
+                for (int j = 0; j < mp; ++j) G1(i, ke + j) = co.F(i, j);
+            G1.set_block(ke, ke, co.H);
+            gf = factor_g(G1);
+        }
         Mat Dm;
         if (co.has_dots) {
             HIPCHK(hipEventSynchronize(ev_dots));
@@ -1718,28 +1755,29 @@ struct Seq final : bgcr_sequence {
             Dm = multi_dot(Q, W);
         }
         std::unique_ptr<HostPhase> hp(new HostPhase(this, BGCR_K_HOST));
-        const int ke = keff;
-        std::vector<double> d(ke);
+        std::vector<double> d(ke), unorm(ke);
         for (int i = 0; i < ke; ++i) {
             const double nu = std::sqrt(std::max(Dm(i, i).real(), 0.0));
             if (!(nu > 0.0)) throw Fail{BGCR_ERR_NUMERICAL};
+            unorm[i] = nu;
             d[i] = 1.0 / nu;
         }
-        const int rows = ke + (me + 1) * P, cols = ke + mp;
         Mat G(rows, cols), M(rows, cols);
         for (int i = 0; i < ke; ++i) G(i, i) = d[i];
         for (int i = 0; i < ke; ++i)
             for (int j = 0; j < mp; ++j) G(i, ke + j) = co.F(i, j);
         G.set_block(ke, ke, co.H);
-        // M = [C W_{m+1}]^H [U D  W_m] using C^H W = 0 and W^H W = I
+        // M = [C W_{m+1}]^H [U D  W_m] using C^H W = 0 and W^H W = I (for the
+        // harmonic problem with its leading columns unscaled, M diag(D^{-1}, I))
+        auto msc = [&](int j) { return harmonic ? 1.0 : d[j]; };
         for (int i = 0; i < ke; ++i)
-            for (int j = 0; j < ke; ++j) M(i, j) = Dm(KP + i, j) * d[j];
+            for (int j = 0; j < ke; ++j) M(i, j) = Dm(KP + i, j) * msc(j);
         for (int i = 0; i < mp; ++i)
-            for (int j = 0; j < ke; ++j) M(ke + i, j) = Dm(2 * KP + i, j) * d[j];
+            for (int j = 0; j < ke; ++j) M(ke + i, j) = Dm(2 * KP + i, j) * msc(j);
         Mat WlU = Dm.block(2 * KP + mp, 0, P, ke);
         Mat VlU = dense::matmul(dense::adjoint(co.RinvLast), WlU);
         for (int i = 0; i < P; ++i)
-            for (int j = 0; j < ke; ++j) M(ke + mp + i, j) = VlU(i, j) * d[j];
+            for (int j = 0; j < ke; ++j) M(ke + mp + i, j) = VlU(i, j) * msc(j);
         for (int i = 0; i < mp; ++i) M(ke + i, ke + i) = 1.0;
         const int kt = std::min(k, cols);
         std::vector<cd> theta;
@@ -1765,7 +1803,7 @@ struct Seq final : bgcr_sequence {
             if (prm.ritz_vectors)
                 gen_ritz(Ah, Bh, kt, theta, sel, vecs, attempt == 1);
             else
-                gen_harmonic(G, M, kt, theta, sel, vecs, attempt == 1);
+                gen_harmonic(gf, M, &unorm, kt, theta, sel, vecs, attempt == 1);
             ritz_basis(sel, vecs, Pm);
             dense::qr_pos(dense::matmul(G, Pm), Qg, rg);
             if (well_conditioned_r(rg)) break;
