@@ -741,19 +741,26 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
         }
         __syncthreads();
         if (vv > 0.0) {
+            // apply the reflector to the window (its columns c..P-1) and to M:
+            // one entry per thread, the rows of a column on 2P consecutive
+            // lanes, whose v^H x sum is a butterfly over those lanes (rows
+            // above c have v = 0)
             const double f = 2.0 / vv;
-            if (t < P) {
-                const int col = t;
-                if (col >= c) {
-                    A w = zero<A>();
-                    for (int l = c; l < P2; ++l) w += cj(V[l]) * X[l * P + col];
-                    for (int l = c; l < P2; ++l) X[l * P + col] -= scale_by(f, V[l] * w);
-                }
-            } else if (t < P + P2) {
-                const int col = t - P;
-                A w = zero<A>();
-                for (int l = c; l < P2; ++l) w += cj(V[l]) * M[l * P2 + col];
-                for (int l = c; l < P2; ++l) M[l * P2 + col] -= scale_by(f, V[l] * w);
+            for (int e = t; e < P * P2; e += NT) {
+                const int col = e / P2, r = e % P2;
+                const A x = X[r * P + col];
+                A w = cj(V[r]) * x;
+#pragma unroll
+                for (int off = 1; off < P2; off <<= 1) w += sp::shfl_t(w, (t & 63) ^ off);
+                if (col >= c) X[r * P + col] = x - scale_by(f, V[r] * w);
+            }
+            for (int e = t; e < P2 * P2; e += NT) {
+                const int col = e / P2, r = e % P2;
+                const A x = M[r * P2 + col];
+                A w = cj(V[r]) * x;
+#pragma unroll
+                for (int off = 1; off < P2; off <<= 1) w += sp::shfl_t(w, (t & 63) ^ off);
+                M[r * P2 + col] = x - scale_by(f, V[r] * w);
             }
         }
         __syncthreads();
