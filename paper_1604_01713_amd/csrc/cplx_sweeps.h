@@ -476,16 +476,35 @@ __global__ __launch_bounds__(256) void k_cx_reduce(const double* __restrict__ pa
     __shared__ zd red[256];
     const int t = threadIdx.x, o = blockIdx.x * 16 + (t % 16), g = t / 16;
     const int nout = q * P, P2 = 2 * P;
-    zd s = {0.0, 0.0};
+    // four partial sums per thread: four partials' loads in flight at once
+    zd s4[4] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
     if (o < nout) {
         const int c = o / P, b = o % P;
         const int64_t i00 = (int64_t)(2 * c) * P2 + 2 * b, i10 = i00 + P2;
-        for (int w = g; w < nwg; w += 16) {
+        int w = g;
+        for (; w + 16 * 3 < nwg; w += 16 * 4) {
+            double a[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const double* d = part + (int64_t)(w + 16 * u) * stride + off;
+                a[u][0] = d[i00];
+                a[u][1] = d[i10 + 1];
+                a[u][2] = d[i00 + 1];
+                a[u][3] = d[i10];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                s4[u].x += a[u][0] + a[u][1];
+                s4[u].y += a[u][2] - a[u][3];
+            }
+        }
+        for (; w < nwg; w += 16) {
             const double* d = part + (int64_t)w * stride + off;
-            s.x += d[i00] + d[i10 + 1];
-            s.y += d[i00 + 1] - d[i10];
+            s4[0].x += d[i00] + d[i10 + 1];
+            s4[0].y += d[i00 + 1] - d[i10];
         }
     }
+    const zd s = {(s4[0].x + s4[1].x) + (s4[2].x + s4[3].x), (s4[0].y + s4[1].y) + (s4[2].y + s4[3].y)};
     red[t] = s;
     __syncthreads();
     if (t < 16 && o < nout) {

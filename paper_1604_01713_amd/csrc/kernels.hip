@@ -442,16 +442,24 @@ __global__ __launch_bounds__(256) void k_reduce(const A* __restrict__ part, int 
     const int t = threadIdx.x;
     const int o = blockIdx.x * 16 + (t % 16);
     const int g = t / 16;
-    A s0 = zero<A>(), s1 = zero<A>();
+    // eight partial sums per thread, so that eight loads are in flight
+    // before the first add waits (the partials come from L2, and one chain of
+    // dependent loads would be latency bound)
+    A s[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = zero<A>();
     if (o < nout) {
         int w = g;
-        for (; w + 16 < nwg; w += 32) {
-            s0 += part[(int64_t)w * nout + o];
-            s1 += part[(int64_t)(w + 16) * nout + o];
+        for (; w + 16 * 7 < nwg; w += 16 * 8) {
+            A v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(w + 16 * u) * nout + o];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s[u] += v[u];
         }
-        if (w < nwg) s0 += part[(int64_t)w * nout + o];
+        for (; w < nwg; w += 16) s[0] += part[(int64_t)w * nout + o];
     }
-    red[t] = s0 + s1;
+    red[t] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
     __syncthreads();
     if (t < 16 && o < nout) {
         A s = (add && o < nadd) ? add[o] : zero<A>();
