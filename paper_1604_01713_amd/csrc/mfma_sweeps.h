@@ -343,13 +343,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
             wn = load_wt<T, P>(Win, rbase + dstep, n, lane);
         }
         // D = W^T + (-S)^T Q^T over the columns of Q, 4 per instruction
-        // (A rows past P repeat row b % P; those D rows are never stored)
+        // (A rows past P repeat row b % P; those D rows are never stored).
+        // FP64 blocks of 8 columns take two 4x4x4 MFMAs (four 4 x 4 blocks
+        // each, one per group of 4 rows) per step instead, one for W columns
+        // 0..3 and one for 4..7: the same B operand and D elements 0 and 1 of
+        // the 16 x 16 layout, without its repeated half.
+        constexpr bool DUAL4 = std::is_same<T, double>::value && P == 8;
+        if constexpr (DUAL4) {
+            double d0 = d[0], d1 = d[1];
 #pragma unroll
-        for (int blk = 0; blk < NQ; ++blk) {
+            for (int blk = 0; blk < NQ; ++blk) {
 #pragma unroll
-            for (int kk = 0; kk < KK; ++kk) {
-                const int c = blk * P + 4 * kk + rq;
-                d = M::mma(Ss[c * P + bc], myQ[qsw<QLD>(bl, c)], d);
+                for (int kk = 0; kk < KK; ++kk) {
+                    const int c = blk * P + 4 * kk + rq;
+                    const double qv = myQ[qsw<QLD>(bl, c)];
+                    d0 = __builtin_amdgcn_mfma_f64_4x4x4f64(Ss[c * P + (lane & 3)], qv, d0, 0, 0, 0);
+                    d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(Ss[c * P + 4 + (lane & 3)], qv, d1, 0, 0, 0);
+                }
+            }
+            d[0] = d0;
+            d[1] = d1;
+        } else {
+#pragma unroll
+            for (int blk = 0; blk < NQ; ++blk) {
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) {
+                    const int c = blk * P + 4 * kk + rq;
+                    d = M::mma(Ss[c * P + bc], myQ[qsw<QLD>(bl, c)], d);
+                }
             }
         }
         zero_tail<T>(d, rbase, n, lane);
@@ -358,8 +379,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((sizeof(T) 
         for (int ks = 0; ks < 4; ++ks) {
             const int rl = 4 * ks + rq;
             const T wv = myW[rl * P + bc];
+            if constexpr (DUAL4) {
+                // A operand W'[rl][4 h + l % 4] for W column group h
+                const double w0 = myW[rl * P + (lane & 3)], w1 = myW[rl * P + 4 + (lane & 3)];
 #pragma unroll
-            for (int ch = 0; ch < NC; ++ch) acc[ch] = M::mma(wv, myQ[qsw<QLD>(rl, 16 * ch + bl)], acc[ch]);
+                for (int ch = 0; ch < NC; ++ch) {
+                    const double qv = myQ[qsw<QLD>(rl, 16 * ch + bl)];
+                    acc[ch][0] = __builtin_amdgcn_mfma_f64_4x4x4f64(w0, qv, acc[ch][0], 0, 0, 0);
+                    acc[ch][1] = __builtin_amdgcn_mfma_f64_4x4x4f64(w1, qv, acc[ch][1], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch) acc[ch] = M::mma(wv, myQ[qsw<QLD>(rl, 16 * ch + bl)], acc[ch]);
+            }
             if constexpr (GRAM) gacc = MX<double>::mma((double)wv, (double)wv, gacc);
         }
     }
