@@ -437,10 +437,15 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* Win,
     tile_span((n + MROWS - 1) / MROWS, lw, t0, t1);
     T* mytr = tr + wave * 16 * P;
     // NORM: A operands (R^{-1})^T[b'][b] for b = 4 kk + l/16, b' = l % 16
-    T ra[KK];
+    // (FP64 blocks of 8 columns: the 4x4x4 operands for b' = l % 4 and 4 + l % 4)
+    constexpr bool DUAL4 = std::is_same<T, double>::value && P == 8;
+    T ra[KK], rb[KK];
     if constexpr (NORM) {
 #pragma unroll
-        for (int kk = 0; kk < KK; ++kk) ra[kk] = (T)Rinv[(4 * kk + rq) * P + bc];
+        for (int kk = 0; kk < KK; ++kk) {
+            ra[kk] = (T)Rinv[(4 * kk + rq) * P + (DUAL4 ? (lane & 3) : bc)];
+            rb[kk] = DUAL4 ? (T)Rinv[(4 * kk + rq) * P + 4 + (lane & 3)] : ra[kk];
+        }
     }
     // column-major operands: [blk*KK + kk] holds Q_blk[rbase + l % 16][4 kk + l / 16]
     auto load_cr = [&](T(&qv)[NQA * KK], int64_t rbase) {
@@ -468,10 +473,28 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* Win,
 #pragma unroll
             for (int e = 0; e < NQV; ++e) qc[e] = qn[e];
             if (k + 1 < cnt) load_cr(qn, rbase + dstep);
+            if constexpr (DUAL4) {
+                // two four-block 4x4x4 MFMAs per step (W columns 0..3, 4..7):
+                // D elements 0 and 1 of the 16x16x4 layout without its repeats
+                double d0 = d[0], d1 = d[1];
 #pragma unroll
-            for (int blk = 0; blk < NQ; ++blk) {
+                for (int blk = 0; blk < NQ; ++blk) {
 #pragma unroll
-                for (int kk = 0; kk < KK; ++kk) d = M::mma(Ss[(blk * P + 4 * kk + rq) * P + bc], qc[blk * KK + kk], d);
+                    for (int kk = 0; kk < KK; ++kk) {
+                        const T* sr = Ss + (blk * P + 4 * kk + rq) * P;
+                        d0 = __builtin_amdgcn_mfma_f64_4x4x4f64(sr[lane & 3], qc[blk * KK + kk], d0, 0, 0, 0);
+                        d1 = __builtin_amdgcn_mfma_f64_4x4x4f64(sr[4 + (lane & 3)], qc[blk * KK + kk], d1, 0, 0, 0);
+                    }
+                }
+                d[0] = d0;
+                d[1] = d1;
+            } else {
+#pragma unroll
+                for (int blk = 0; blk < NQ; ++blk) {
+#pragma unroll
+                    for (int kk = 0; kk < KK; ++kk)
+                        d = M::mma(Ss[(blk * P + 4 * kk + rq) * P + bc], qc[blk * KK + kk], d);
+                }
             }
         }
         if (k + 1 < cnt) wn = load_wt<T, P>(Win, rbase + dstep, n, lane);
@@ -481,8 +504,20 @@ __global__ __launch_bounds__(256) void k_proj_gram_mfma(int64_t n, const T* Win,
             // V^T = (R^{-1})^T W''^T: B operand W''^T[4 kk + l/16][row l % 16] from the tile in LDS
             d_to_lds<T, P>(d, mytr, lane);
             typename M::acc dv = typename M::acc{0, 0, 0, 0};
+            if constexpr (DUAL4) {
+                double v0 = 0.0, v1 = 0.0;
 #pragma unroll
-            for (int kk = 0; kk < KK; ++kk) dv = M::mma(ra[kk], mytr[bl * P + 4 * kk + rq], dv);
+                for (int kk = 0; kk < KK; ++kk) {
+                    const double wv = mytr[bl * P + 4 * kk + rq];
+                    v0 = __builtin_amdgcn_mfma_f64_4x4x4f64(ra[kk], wv, v0, 0, 0, 0);
+                    v1 = __builtin_amdgcn_mfma_f64_4x4x4f64(rb[kk], wv, v1, 0, 0, 0);
+                }
+                dv[0] = v0;
+                dv[1] = v1;
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KK; ++kk) dv = M::mma(ra[kk], mytr[bl * P + 4 * kk + rq], dv);
+            }
             if (row < n) {
 #pragma unroll
                 for (int v = 0; v < M::template vn<P>(); ++v) {
