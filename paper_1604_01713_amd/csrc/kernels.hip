@@ -616,6 +616,32 @@ __global__ void k_cholqr_second(const A* gram, const A* Z1, A* Rinv0, A* g, int 
     }
 }
 
+// Sum over each aligned group of W lanes (W a power of two up to 32), the same
+// value on every lane of the group: rotations and mirrors within 16-lane rows
+// and quad permutations (DPP moves, a few cycles each) pair the lanes
+// symmetrically, and one cross-lane exchange joins two rows for W = 32.
+template <int CTRL>
+__device__ inline double dpp_mov(double x) {
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(v >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int W>
+__device__ inline double group_sum(double x) {
+    static_assert(W >= 1 && W <= 32 && (W & (W - 1)) == 0, "groups of 1 .. 32 lanes");
+    if constexpr (W >= 32) x += __shfl_xor(x, 16);
+    if constexpr (W >= 16) x += dpp_mov<0x128>(x);  // row_ror:8
+    if constexpr (W >= 8) x += dpp_mov<0x141>(x);   // row_half_mirror
+    if constexpr (W >= 2) x += dpp_mov<0xB1>(x);    // quad_perm 1,0,3,2
+    if constexpr (W >= 4) x += dpp_mov<0x4E>(x);    // quad_perm 2,3,0,1
+    return x;
+}
+template <int W>
+__device__ inline zd group_sum(zd x) {
+    return zd{group_sum<W>(x.x), group_sum<W>(x.y)};
+}
+
 // Per block step j (1-based): CholQR factor of W'' from its Gram partials,
 // new column block of the block Hessenberg H (and of F = C^H A W), and the
 // progressive block-Householder triangularisation of H with the right-hand
@@ -727,12 +753,12 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
     static_assert(P2 <= 64, "one lane of the first wave per row of the 2P x P block");
     for (int c = 0; c < P; ++c) {
         // reflector of column c by the first wave, one lane per row: norms by
-        // a butterfly over the wave (every lane ends with the same sum)
+        // group sums over the 2P lanes of the rows (every lane of the group
+        // ends with the same sum)
         if (t < 64) {
             const int l = t;
             const A xl = (l >= c && l < P2) ? X[l * P + c] : zero<A>();
-            double a2 = absq(xl);
-            for (int off = 32; off > 0; off >>= 1) a2 += __shfl_xor(a2, off);
+            const double a2 = group_sum<P2>(absq(xl));
             const double al = sqrt(a2);
             double s2 = 0.0;
             if (al > 0.0) {
@@ -742,8 +768,7 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
                 const A beta = scale_by(-al, ph);
                 const A vl = l < c ? zero<A>() : (l == c ? x0 - beta : xl);
                 if (l < P2) V[l] = vl;
-                s2 = absq(vl);
-                for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off);
+                s2 = group_sum<P2>(absq(vl));
             }
             if (l == 0) vv = s2;
         }
@@ -751,23 +776,18 @@ __global__ __launch_bounds__(NT) void k_step_small(const A* gram, const A* S, co
         if (vv > 0.0) {
             // apply the reflector to the window (its columns c..P-1) and to M:
             // one entry per thread, the rows of a column on 2P consecutive
-            // lanes, whose v^H x sum is a butterfly over those lanes (rows
-            // above c have v = 0)
+            // lanes, whose v^H x is their group sum (rows above c have v = 0)
             const double f = 2.0 / vv;
             for (int e = t; e < P * P2; e += NT) {
                 const int col = e / P2, r = e % P2;
                 const A x = X[r * P + col];
-                A w = cj(V[r]) * x;
-#pragma unroll
-                for (int off = 1; off < P2; off <<= 1) w += sp::shfl_t(w, (t & 63) ^ off);
+                const A w = group_sum<P2>(cj(V[r]) * x);
                 if (col >= c) X[r * P + col] = x - scale_by(f, V[r] * w);
             }
             for (int e = t; e < P2 * P2; e += NT) {
                 const int col = e / P2, r = e % P2;
                 const A x = M[r * P2 + col];
-                A w = cj(V[r]) * x;
-#pragma unroll
-                for (int off = 1; off < P2; off <<= 1) w += sp::shfl_t(w, (t & 63) ^ off);
+                const A w = group_sum<P2>(cj(V[r]) * x);
                 M[r * P2 + col] = x - scale_by(f, V[r] * w);
             }
         }
